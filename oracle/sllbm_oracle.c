@@ -1,0 +1,656 @@
+/*
+ * Plain CPU reference ("oracle") of the 3-D compressible semi-Lagrangian
+ * lattice Boltzmann method (SLLBM) of Wilde, Kraemer, Reith & Foysi,
+ * "High-order semi-Lagrangian kinetic scheme for compressible turbulence"
+ * (arXiv:2012.05537).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may call, link or
+ * load this file; only the test-suite, the smoke check and the CPU-baseline
+ * leg of the benchmark use it.  It shares no code, header, table or constant
+ * generator with the GPU library.
+ *
+ * Everything is done the slow, literal way, in FP64:
+ *   - the equilibrium is the full tensor contraction over all 3^n components
+ *     of the Hermite series (Sec. II A, Eq. (6); App. A moments; App. B
+ *     Hermite tensors);
+ *   - the quasi-equilibrium term builds the centred third moment of h and of
+ *     h^eq and contracts their difference with all 27 components of H^(3)
+ *     (App. D);
+ *   - streaming traces every (node, velocity) pair back to x - xi*dt, finds
+ *     the enclosing cell with floor(), and sums the (p+1)^3 tensor-product
+ *     Lagrange basis values over that cell's support points (Eqs. (8)-(9)).
+ *     No per-axis factorisation and no precomputed tables are used.
+ *
+ * The file is compiled twice: once with R = double (symbols oracle_*), and
+ * once with -DORACLE_COMPLEX, R = double complex (symbols oracle_cs_*).  The
+ * complex build is used for complex-step derivatives (Squire & Trapp 1998):
+ * every state-dependent operation below is analytic, and the only floor() is
+ * applied to the state-independent departure position.
+ *
+ * Readings of the paper taken here (see the design notes of the repository):
+ *   c_s = 1, T0 = 1, theta = T (lattice units); D = 3; C_v = 1/(gamma-1).
+ *   T from 2 rho E = rho |u|^2 + 2 C_v rho T (the energy of the equilibria).
+ *   Sutherland numerator 1 + S with S = 0.40417, so that mu(T=1) = mu_inf.
+ *   Quasi-equilibrium h* carries the 1/3! of the third Hermite term; each
+ *   population uses its own centred third moment.
+ *   Velocity set: the degree-9 icosahedral D3Q45 rule (origin, two
+ *   icosahedra of radii sqrt(3) and sqrt(15), one dodecahedron of radius 3).
+ *   GLC support points t_k = (1 - cos(pi k / p))/2 per cell, unique periodic
+ *   nodes (n_el * p per axis).
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef ORACLE_COMPLEX
+#include <complex.h>
+typedef double complex R;
+#define RSQRT(x) csqrt(x)
+#define FN(name) oracle_cs_##name
+#else
+typedef double R;
+#define RSQRT(x) sqrt(x)
+#define FN(name) oracle_##name
+#endif
+
+#define Q 45
+#define DIM 3
+
+typedef struct {
+    int n_el[3];           /* cells per axis (periodic) */
+    int p;                 /* interpolation order (GLC points per cell edge - 1) */
+    double length[3];      /* domain edge lengths */
+    double dt;             /* time step */
+    double gamma;          /* heat capacity ratio */
+    double prandtl;        /* target Prandtl number of the quasi-equilibrium term */
+    double mu_inf;         /* dynamic viscosity at T = 1 */
+    double mu_inf_im;      /* imaginary part of mu_inf (complex build only) */
+    int viscosity_law;     /* 0 = Sutherland, 1 = constant mu = mu_inf */
+} oracle_cfg;
+
+/* ------------------------------------------------------------------------- */
+/* Velocity set (Sec. II B: degree-nine D3Q45 cubature with icosahedral      */
+/* symmetry).  Built from the orbit directions and closed-form weights.      */
+/* ------------------------------------------------------------------------- */
+
+static int lex_less(const double *a, const double *b)
+{
+    for (int k = 0; k < 3; ++k) {
+        if (fabs(a[k] - b[k]) > 1e-9) return a[k] < b[k];
+    }
+    return 0;
+}
+
+static void sort_dirs(double (*v)[3], int n)
+{
+    for (int i = 1; i < n; ++i) {           /* insertion sort, lexicographic */
+        double t[3] = {v[i][0], v[i][1], v[i][2]};
+        int j = i - 1;
+        while (j >= 0 && lex_less(t, v[j])) {
+            v[j + 1][0] = v[j][0]; v[j + 1][1] = v[j][1]; v[j + 1][2] = v[j][2];
+            --j;
+        }
+        v[j + 1][0] = t[0]; v[j + 1][1] = t[1]; v[j + 1][2] = t[2];
+    }
+}
+
+/* all sign variants of the three cyclic permutations of (a, b, c), deduplicated */
+static int cyclic_signed(double a, double b, double c, double (*out)[3], int n)
+{
+    double base[3][3] = {{a, b, c}, {b, c, a}, {c, a, b}};
+    for (int r = 0; r < 3; ++r) {
+        for (int s = 0; s < 8; ++s) {
+            double v[3];
+            for (int k = 0; k < 3; ++k) v[k] = ((s >> k) & 1) ? -base[r][k] : base[r][k];
+            int dup = 0;
+            for (int m = 0; m < n; ++m) {
+                if (fabs(out[m][0] - v[0]) < 1e-12 && fabs(out[m][1] - v[1]) < 1e-12 &&
+                    fabs(out[m][2] - v[2]) < 1e-12) { dup = 1; break; }
+            }
+            if (!dup) { out[n][0] = v[0]; out[n][1] = v[1]; out[n][2] = v[2]; ++n; }
+        }
+    }
+    return n;
+}
+
+int oracle_velocity_set(double *xi, double *w)
+{
+    const double phi = 0.5 * (1.0 + sqrt(5.0));
+    double ico[12][3], dod[20][3];
+    int ni = cyclic_signed(0.0, 1.0, phi, ico, 0);
+    int nd = cyclic_signed(1.0, 1.0, 1.0, dod, 0);
+    nd = cyclic_signed(0.0, phi, 1.0 / phi, dod, nd);
+    if (ni != 12 || nd != 20) return -1;
+    for (int m = 0; m < 12; ++m) {
+        double r = sqrt(ico[m][0] * ico[m][0] + ico[m][1] * ico[m][1] + ico[m][2] * ico[m][2]);
+        for (int k = 0; k < 3; ++k) ico[m][k] /= r;
+    }
+    for (int m = 0; m < 20; ++m) {
+        double r = sqrt(dod[m][0] * dod[m][0] + dod[m][1] * dod[m][1] + dod[m][2] * dod[m][2]);
+        for (int k = 0; k < 3; ++k) dod[m][k] /= r;
+    }
+    sort_dirs(ico, 12);
+    sort_dirs(dod, 20);
+    int q = 0;
+    xi[0] = xi[1] = xi[2] = 0.0; w[q++] = 28.0 / 135.0;
+    for (int m = 0; m < 12; ++m, ++q) {
+        for (int k = 0; k < 3; ++k) xi[3 * q + k] = sqrt(3.0) * ico[m][k];
+        w[q] = 25.0 / 432.0;
+    }
+    for (int m = 0; m < 12; ++m, ++q) {
+        for (int k = 0; k < 3; ++k) xi[3 * q + k] = sqrt(15.0) * ico[m][k];
+        w[q] = 1.0 / 2160.0;
+    }
+    for (int m = 0; m < 20; ++m, ++q) {
+        for (int k = 0; k < 3; ++k) xi[3 * q + k] = 3.0 * dod[m][k];
+        w[q] = 1.0 / 216.0;
+    }
+    return q;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Support points, Lagrange basis, Clenshaw-Curtis node weights (Sec. II A,  */
+/* Eq. (8): cell-oriented interpolation on Gauss-Lobatto-Chebyshev points).  */
+/* ------------------------------------------------------------------------- */
+
+void oracle_glc_nodes(int p, double *t)
+{
+    for (int k = 0; k <= p; ++k) t[k] = 0.5 * (1.0 - cos(M_PI * (double)k / (double)p));
+}
+
+/* l_k(s) = prod_{m != k} (s - t_m) / (t_k - t_m) */
+void oracle_lagrange(int p, double s, double *ell)
+{
+    double t[16];
+    oracle_glc_nodes(p, t);
+    for (int k = 0; k <= p; ++k) {
+        double v = 1.0;
+        for (int m = 0; m <= p; ++m) {
+            if (m != k) v *= (s - t[m]) / (t[k] - t[m]);
+        }
+        ell[k] = v;
+    }
+}
+
+/* d l_k / ds at s */
+void oracle_lagrange_deriv(int p, double s, double *dell)
+{
+    double t[16];
+    oracle_glc_nodes(p, t);
+    for (int k = 0; k <= p; ++k) {
+        double sum = 0.0;
+        for (int j = 0; j <= p; ++j) {
+            if (j == k) continue;
+            double v = 1.0 / (t[k] - t[j]);
+            for (int m = 0; m <= p; ++m) {
+                if (m != k && m != j) v *= (s - t[m]) / (t[k] - t[m]);
+            }
+            sum += v;
+        }
+        dell[k] = sum;
+    }
+}
+
+/* Clenshaw-Curtis weights of the Chebyshev extrema on [-1, 1] (sum = 2). */
+void oracle_cc_weights(int p, double *wcc)
+{
+    for (int k = 0; k <= p; ++k) {
+        double s = 0.0;
+        for (int j = 1; j <= p / 2; ++j) {
+            double b = (2 * j == p) ? 1.0 : 2.0;
+            s += b / (4.0 * j * j - 1.0) * cos(2.0 * M_PI * j * k / p);
+        }
+        double c = (k == 0 || k == p) ? 1.0 : 2.0;
+        wcc[k] = c / p * (1.0 - s);
+    }
+}
+
+/* position of unique node g (= e*p + l) along an axis */
+static double node_pos(int g, int p, double h)
+{
+    int e = g / p, l = g % p;
+    return e * h + h * 0.5 * (1.0 - cos(M_PI * (double)l / (double)p));
+}
+
+void oracle_node_coords(const oracle_cfg *c, double *x, double *y, double *z)
+{
+    double *out[3] = {x, y, z};
+    for (int a = 0; a < 3; ++a) {
+        int n = c->n_el[a] * c->p;
+        double h = c->length[a] / c->n_el[a];
+        for (int g = 0; g < n; ++g) out[a][g] = node_pos(g, c->p, h);
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Hermite tensors (App. B) and equilibrium moments (App. A).                */
+/* Full tensors of rank n, stored flat over 3^n components.                  */
+/* ------------------------------------------------------------------------- */
+
+static double kd(int a, int b) { return a == b ? 1.0 : 0.0; }
+
+/* H^(n)(xi) for n = 0..4 at one abscissa (c_s = 1). */
+static void hermite_tensors(const double *x, double *H1, double *H2, double *H3, double *H4)
+{
+    for (int a = 0; a < 3; ++a) {
+        H1[a] = x[a];
+        for (int b = 0; b < 3; ++b) {
+            H2[3 * a + b] = x[a] * x[b] - kd(a, b);
+            for (int c = 0; c < 3; ++c) {
+                H3[9 * a + 3 * b + c] = x[a] * x[b] * x[c]
+                    - (x[a] * kd(b, c) + x[b] * kd(a, c) + x[c] * kd(a, b));
+                for (int d = 0; d < 3; ++d) {
+                    double Tsum = x[a] * x[b] * kd(c, d) + x[a] * x[c] * kd(b, d) + x[a] * x[d] * kd(b, c)
+                                + x[b] * x[c] * kd(a, d) + x[b] * x[d] * kd(a, c) + x[c] * x[d] * kd(a, b);
+                    double dd = kd(a, b) * kd(c, d) + kd(a, c) * kd(b, d) + kd(a, d) * kd(b, c);
+                    H4[27 * a + 9 * b + 3 * c + d] = x[a] * x[b] * x[c] * x[d] - Tsum + dd;
+                }
+            }
+        }
+    }
+}
+
+/* a^(n)_eq for n = 0..4 (App. A, T0 = 1, theta - 1 = T - 1). */
+static void eq_moments(R rho, const R *u, R T, R *a0, R *a1, R *a2, R *a3, R *a4)
+{
+    R th = T - 1.0;
+    *a0 = rho;
+    for (int a = 0; a < 3; ++a) {
+        a1[a] = rho * u[a];
+        for (int b = 0; b < 3; ++b) {
+            a2[3 * a + b] = rho * (u[a] * u[b] + th * kd(a, b));
+            for (int c = 0; c < 3; ++c) {
+                a3[9 * a + 3 * b + c] = rho * (u[a] * u[b] * u[c]
+                    + th * (kd(a, b) * u[c] + kd(a, c) * u[b] + kd(b, c) * u[a]));
+                for (int d = 0; d < 3; ++d) {
+                    R dd = kd(a, b) * kd(c, d) + kd(a, c) * kd(b, d) + kd(a, d) * kd(b, c);
+                    R du = kd(a, b) * u[c] * u[d] + kd(a, c) * u[b] * u[d] + kd(a, d) * u[b] * u[c]
+                         + kd(b, c) * u[a] * u[d] + kd(b, d) * u[a] * u[c] + kd(c, d) * u[a] * u[b];
+                    a4[27 * a + 9 * b + 3 * c + d] = rho * (u[a] * u[b] * u[c] * u[d] + th * (dd * th + du));
+                }
+            }
+        }
+    }
+}
+
+/* f_i^eq = w_i sum_{n<=4} (1/n!) a^(n)_eq : H^(n)_i   (Eq. (6)), all 3^n terms. */
+void FN(equilibrium)(R rho, const R *u, R T, R *feq)
+{
+    double xi[3 * Q], w[Q];
+    oracle_velocity_set(xi, w);
+    R a0, a1[3], a2[9], a3[27], a4[81];
+    eq_moments(rho, u, T, &a0, a1, a2, a3, a4);
+    for (int i = 0; i < Q; ++i) {
+        double H1[3], H2[9], H3[27], H4[81];
+        hermite_tensors(&xi[3 * i], H1, H2, H3, H4);
+        R s0 = a0, s1 = 0, s2 = 0, s3 = 0, s4 = 0;
+        for (int m = 0; m < 3; ++m) s1 += a1[m] * H1[m];
+        for (int m = 0; m < 9; ++m) s2 += a2[m] * H2[m];
+        for (int m = 0; m < 27; ++m) s3 += a3[m] * H3[m];
+        for (int m = 0; m < 81; ++m) s4 += a4[m] * H4[m];
+        feq[i] = w[i] * (s0 + s1 + s2 / 2.0 + s3 / 6.0 + s4 / 24.0);
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Collision (Eq. (5) with the quasi-equilibrium extension of App. D).       */
+/* f, g: the 45 populations of one node.                                     */
+/* ------------------------------------------------------------------------- */
+
+static R mu_of_T(const oracle_cfg *c, R T)
+{
+    R mu_inf = c->mu_inf;
+#ifdef ORACLE_COMPLEX
+    mu_inf += c->mu_inf_im * I;
+#endif
+    if (c->viscosity_law == 1) return mu_inf;
+    const double S = 0.40417;                       /* Sutherland law, Sec. III C */
+    return mu_inf * (1.0 + S) * T * RSQRT(T) / (T + S);
+}
+
+/* Density, velocity, temperature from Eq. (7) (T0 = 1, R = 1). */
+static void node_macro(const oracle_cfg *c, const double *xi, const R *f, const R *g,
+                       R *rho, R *u, R *T)
+{
+    double Cv = 1.0 / (c->gamma - 1.0);
+    R r = 0, j[3] = {0, 0, 0}, twoE = 0;
+    for (int i = 0; i < Q; ++i) {
+        const double *x = &xi[3 * i];
+        double x2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
+        r += f[i];
+        for (int a = 0; a < 3; ++a) j[a] += f[i] * x[a];
+        twoE += f[i] * x2 + g[i];
+    }
+    R uu = 0;
+    for (int a = 0; a < 3; ++a) { u[a] = j[a] / r; uu += u[a] * u[a]; }
+    *rho = r;
+    *T = (twoE / r - uu) / (2.0 * Cv);
+}
+
+/* centred third moment  Q_abc = sum_i h_i (xi_i - u)_a (xi_i - u)_b (xi_i - u)_c */
+static void centred_third(const double *xi, const R *h, const R *u, R *Qt)
+{
+    for (int m = 0; m < 27; ++m) Qt[m] = 0;
+    for (int i = 0; i < Q; ++i) {
+        R d[3];
+        for (int a = 0; a < 3; ++a) d[a] = xi[3 * i + a] - u[a];
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b)
+                for (int cc = 0; cc < 3; ++cc) Qt[9 * a + 3 * b + cc] += h[i] * d[a] * d[b] * d[cc];
+    }
+}
+
+void FN(collide_node)(const oracle_cfg *c, const R *f, const R *g, R *fo, R *go)
+{
+    double xi[3 * Q], w[Q];
+    oracle_velocity_set(xi, w);
+    double Cv = 1.0 / (c->gamma - 1.0);
+    R rho, u[3], T;
+    node_macro(c, xi, f, g, &rho, u, &T);
+    R P = rho * T;                                         /* P = rho T */
+    R mu = mu_of_T(c, T);
+    R tau = mu / (P * c->dt) + 0.5;                        /* tau = mu/(P c_s dt) + 1/2 */
+    R tau_pr = (tau - 0.5) / c->prandtl + 0.5;             /* App. D */
+
+    R feq[Q], geq[Q];
+    FN(equilibrium)(rho, u, T, feq);
+    for (int i = 0; i < Q; ++i) geq[i] = (2.0 * Cv - DIM) * T * feq[i];
+
+    R Qf[27], Qfeq[27], Qg[27], Qgeq[27];
+    centred_third(xi, f, u, Qf);
+    centred_third(xi, feq, u, Qfeq);
+    centred_third(xi, g, u, Qg);
+    centred_third(xi, geq, u, Qgeq);
+
+    for (int i = 0; i < Q; ++i) {
+        double H1[3], H2[9], H3[27], H4[81];
+        hermite_tensors(&xi[3 * i], H1, H2, H3, H4);
+        R fs = 0, gs = 0;
+        for (int m = 0; m < 27; ++m) {
+            fs += (Qf[m] - Qfeq[m]) * H3[m];
+            gs += (Qg[m] - Qgeq[m]) * H3[m];
+        }
+        fs *= w[i] / 6.0;
+        gs *= w[i] / 6.0;
+        fo[i] = f[i] - (f[i] - feq[i]) / tau + (1.0 / tau - 1.0 / tau_pr) * fs;
+        go[i] = g[i] - (g[i] - geq[i]) / tau + (1.0 / tau - 1.0 / tau_pr) * gs;
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Whole-grid operations.  Populations are stored [45][N] with the node      */
+/* index (gz * Ny + gy) * Nx + gx (x fastest).                               */
+/* ------------------------------------------------------------------------- */
+
+static long n_nodes(const oracle_cfg *c)
+{
+    return (long)c->n_el[0] * c->p * (long)c->n_el[1] * c->p * (long)c->n_el[2] * c->p;
+}
+
+long oracle_num_nodes(const oracle_cfg *c) { return n_nodes(c); }
+
+void FN(init_equilibrium)(const oracle_cfg *c, const R *rho, const R *u, const R *T, R *f, R *g)
+{
+    long N = n_nodes(c);
+    double Cv = 1.0 / (c->gamma - 1.0);
+#pragma omp parallel for schedule(static)
+    for (long n = 0; n < N; ++n) {
+        R uu[3] = {u[n], u[N + n], u[2 * N + n]};
+        R feq[Q];
+        FN(equilibrium)(rho[n], uu, T[n], feq);
+        for (int i = 0; i < Q; ++i) {
+            f[(long)i * N + n] = feq[i];
+            g[(long)i * N + n] = (2.0 * Cv - DIM) * T[n] * feq[i];
+        }
+    }
+}
+
+void FN(collide)(const oracle_cfg *c, R *f, R *g)
+{
+    long N = n_nodes(c);
+#pragma omp parallel for schedule(static)
+    for (long n = 0; n < N; ++n) {
+        R fn[Q], gn[Q], fo[Q], go[Q];
+        for (int i = 0; i < Q; ++i) { fn[i] = f[(long)i * N + n]; gn[i] = g[(long)i * N + n]; }
+        FN(collide_node)(c, fn, gn, fo, go);
+        for (int i = 0; i < Q; ++i) { f[(long)i * N + n] = fo[i]; g[(long)i * N + n] = go[i]; }
+    }
+}
+
+/* Value of population i at the departure point of node (gx, gy, gz):
+ * cell found by floor(), then the (p+1)^3 tensor Lagrange sum over it. */
+static void departure_value(const oracle_cfg *c, const double *xi, int i, int gx, int gy, int gz,
+                            const R *f, const R *g, R *fv, R *gv)
+{
+    int p = c->p;
+    int N[3], base[3];
+    double ell[3][16];
+    int gidx[3] = {gx, gy, gz};
+    for (int a = 0; a < 3; ++a) {
+        N[a] = c->n_el[a] * p;
+        double h = c->length[a] / c->n_el[a];
+        double X = node_pos(gidx[a], p, h) - xi[3 * i + a] * c->dt;   /* departure point */
+        double s = X / h;
+        double E = floor(s);
+        double t = s - E;                                            /* local coordinate in [0,1) */
+        long Ei = (long)E % c->n_el[a];
+        if (Ei < 0) Ei += c->n_el[a];
+        base[a] = (int)(Ei * p);
+        oracle_lagrange(p, t, ell[a]);
+    }
+    long Nl = (long)N[0] * N[1] * N[2];
+    R sf = 0, sg = 0;
+    for (int kz = 0; kz <= p; ++kz) {
+        int zz = (base[2] + kz) % N[2];
+        for (int ky = 0; ky <= p; ++ky) {
+            int yy = (base[1] + ky) % N[1];
+            for (int kx = 0; kx <= p; ++kx) {
+                int xx = (base[0] + kx) % N[0];
+                double psi = ell[0][kx] * ell[1][ky] * ell[2][kz];
+                long src = (long)i * Nl + ((long)zz * N[1] + yy) * N[0] + xx;
+                sf += psi * f[src];
+                sg += psi * g[src];
+            }
+        }
+    }
+    *fv = sf;
+    *gv = sg;
+}
+
+void FN(stream)(const oracle_cfg *c, const R *f, const R *g, R *fo, R *go)
+{
+    double xi[3 * Q], w[Q];
+    oracle_velocity_set(xi, w);
+    int Nx = c->n_el[0] * c->p, Ny = c->n_el[1] * c->p, Nz = c->n_el[2] * c->p;
+    long N = n_nodes(c);
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int i = 0; i < Q; ++i) {
+        for (int gz = 0; gz < Nz; ++gz) {
+            for (int gy = 0; gy < Ny; ++gy) {
+                for (int gx = 0; gx < Nx; ++gx) {
+                    long n = ((long)gz * Ny + gy) * Nx + gx;
+                    departure_value(c, xi, i, gx, gy, gz, f, g, &fo[(long)i * N + n], &go[(long)i * N + n]);
+                }
+            }
+        }
+    }
+}
+
+/* n time steps of Eq. (5): collide, then stream (state = pre-collision populations). */
+int FN(step)(const oracle_cfg *c, R *f, R *g, int nsteps)
+{
+    long N = n_nodes(c);
+    R *tf = (R *)malloc(sizeof(R) * Q * N);
+    R *tg = (R *)malloc(sizeof(R) * Q * N);
+    if (!tf || !tg) { free(tf); free(tg); return -1; }
+    for (int s = 0; s < nsteps; ++s) {
+        FN(collide)(c, f, g);
+        FN(stream)(c, f, g, tf, tg);
+        memcpy(f, tf, sizeof(R) * Q * N);
+        memcpy(g, tg, sizeof(R) * Q * N);
+    }
+    free(tf);
+    free(tg);
+    return 0;
+}
+
+/* One step evaluated only at the listed nodes: out[45] f then out[45] g per
+ * sample.  Every source point of every departure stencil is collided from
+ * the full pre-collision state, exactly as the whole-grid step would. */
+void FN(step_at_nodes)(const oracle_cfg *c, const R *f, const R *g, int nsamp, const long *nodes,
+                       R *fo, R *go)
+{
+    double xi[3 * Q], w[Q];
+    oracle_velocity_set(xi, w);
+    int p = c->p;
+    int N[3] = {c->n_el[0] * p, c->n_el[1] * p, c->n_el[2] * p};
+    long Nl = (long)N[0] * N[1] * N[2];
+#pragma omp parallel for schedule(dynamic)
+    for (int s = 0; s < nsamp; ++s) {
+        long n = nodes[s];
+        int gidx[3] = {(int)(n % N[0]), (int)((n / N[0]) % N[1]), (int)(n / ((long)N[0] * N[1]))};
+        for (int i = 0; i < Q; ++i) {
+            int base[3];
+            double ell[3][16];
+            for (int a = 0; a < 3; ++a) {
+                double h = c->length[a] / c->n_el[a];
+                double X = node_pos(gidx[a], p, h) - xi[3 * i + a] * c->dt;
+                double sx = X / h;
+                double E = floor(sx);
+                long Ei = (long)E % c->n_el[a];
+                if (Ei < 0) Ei += c->n_el[a];
+                base[a] = (int)(Ei * p);
+                oracle_lagrange(p, sx - E, ell[a]);
+            }
+            R sf = 0, sg = 0;
+            for (int kz = 0; kz <= p; ++kz)
+                for (int ky = 0; ky <= p; ++ky)
+                    for (int kx = 0; kx <= p; ++kx) {
+                        long src = ((long)((base[2] + kz) % N[2]) * N[1] + (base[1] + ky) % N[1]) * N[0]
+                                 + (base[0] + kx) % N[0];
+                        R fn[Q], gn[Q], fc[Q], gc[Q];
+                        for (int j = 0; j < Q; ++j) { fn[j] = f[(long)j * Nl + src]; gn[j] = g[(long)j * Nl + src]; }
+                        FN(collide_node)(c, fn, gn, fc, gc);
+                        double psi = ell[0][kx] * ell[1][ky] * ell[2][kz];
+                        sf += psi * fc[i];
+                        sg += psi * gc[i];
+                    }
+            fo[(long)s * Q + i] = sf;
+            go[(long)s * Q + i] = sg;
+        }
+    }
+}
+
+/* rho, u (stored [3][N]) and T at every node, Eq. (7). */
+void FN(moments)(const oracle_cfg *c, const R *f, const R *g, R *rho, R *u, R *T)
+{
+    double xi[3 * Q], w[Q];
+    oracle_velocity_set(xi, w);
+    long N = n_nodes(c);
+#pragma omp parallel for schedule(static)
+    for (long n = 0; n < N; ++n) {
+        R fn[Q], gn[Q], uu[3];
+        for (int i = 0; i < Q; ++i) { fn[i] = f[(long)i * N + n]; gn[i] = g[(long)i * N + n]; }
+        node_macro(c, xi, fn, gn, &rho[n], uu, &T[n]);
+        for (int a = 0; a < 3; ++a) u[(long)a * N + n] = uu[a];
+    }
+}
+
+/* Quadrature weight of unique node g along one axis: Clenshaw-Curtis weight of
+ * its local point, mapped to a cell of width h; cell end points are shared by
+ * two cells, so their weights add. */
+static double node_weight(int g, int p, double h)
+{
+    double wcc[16];
+    oracle_cc_weights(p, wcc);
+    int l = g % p;
+    double wl = (l == 0) ? wcc[0] + wcc[p] : wcc[l];
+    return 0.5 * h * wl;
+}
+
+/* Domain integrals of rho, rho u (3) and rho E (Eq. (7)), summed in node order. */
+void FN(totals)(const oracle_cfg *c, const R *f, const R *g, R *out)
+{
+    double xi[3 * Q], w[Q];
+    oracle_velocity_set(xi, w);
+    int p = c->p;
+    int Nx = c->n_el[0] * p, Ny = c->n_el[1] * p, Nz = c->n_el[2] * p;
+    long N = n_nodes(c);
+    double h[3] = {c->length[0] / c->n_el[0], c->length[1] / c->n_el[1], c->length[2] / c->n_el[2]};
+    for (int k = 0; k < 5; ++k) out[k] = 0;
+    for (int gz = 0; gz < Nz; ++gz)
+        for (int gy = 0; gy < Ny; ++gy)
+            for (int gx = 0; gx < Nx; ++gx) {
+                long n = ((long)gz * Ny + gy) * Nx + gx;
+                double W = node_weight(gx, p, h[0]) * node_weight(gy, p, h[1]) * node_weight(gz, p, h[2]);
+                R r = 0, j[3] = {0, 0, 0}, twoE = 0;
+                for (int i = 0; i < Q; ++i) {
+                    R fi = f[(long)i * N + n];
+                    const double *x = &xi[3 * i];
+                    r += fi;
+                    for (int a = 0; a < 3; ++a) j[a] += fi * x[a];
+                    twoE += fi * (x[0] * x[0] + x[1] * x[1] + x[2] * x[2]) + g[(long)i * N + n];
+                }
+                out[0] += W * r;
+                for (int a = 0; a < 3; ++a) out[1 + a] += W * j[a];
+                out[4] += W * 0.5 * twoE;
+            }
+}
+
+/* Flow functional used for gradients:
+ *   L = sum over cells of the tensor Clenshaw-Curtis quadrature of
+ *       (1/2) rho |u|^2 + (div u)^2,
+ * with div u from the derivative of each cell's own interpolation polynomial
+ * (so it is discontinuous across cell faces, as in Sec. III C). */
+R FN(loss)(const oracle_cfg *c, const R *f, const R *g)
+{
+    int p = c->p;
+    int N[3] = {c->n_el[0] * p, c->n_el[1] * p, c->n_el[2] * p};
+    long Nl = (long)N[0] * N[1] * N[2];
+    R *rho = (R *)malloc(sizeof(R) * Nl), *u = (R *)malloc(sizeof(R) * 3 * Nl), *T = (R *)malloc(sizeof(R) * Nl);
+    FN(moments)(c, f, g, rho, u, T);
+    double t[16], wcc[16], Dm[16][16];
+    oracle_glc_nodes(p, t);
+    oracle_cc_weights(p, wcc);
+    for (int k = 0; k <= p; ++k) {
+        double dl[16];
+        oracle_lagrange_deriv(p, t[k], dl);
+        for (int m = 0; m <= p; ++m) Dm[k][m] = dl[m];     /* d l_m / ds at s = t_k */
+    }
+    double h[3] = {c->length[0] / c->n_el[0], c->length[1] / c->n_el[1], c->length[2] / c->n_el[2]};
+    R L = 0;
+    for (int ez = 0; ez < c->n_el[2]; ++ez)
+        for (int ey = 0; ey < c->n_el[1]; ++ey)
+            for (int ex = 0; ex < c->n_el[0]; ++ex)
+                for (int kz = 0; kz <= p; ++kz)
+                    for (int ky = 0; ky <= p; ++ky)
+                        for (int kx = 0; kx <= p; ++kx) {
+                            int k3[3] = {kx, ky, kz}, e3[3] = {ex, ey, ez};
+                            long n = ((long)((ez * p + kz) % N[2]) * N[1] + (ey * p + ky) % N[1]) * N[0]
+                                   + (ex * p + kx) % N[0];
+                            R div = 0;
+                            for (int a = 0; a < 3; ++a) {
+                                /* d u_a / d x_a along axis a inside this cell */
+                                R d = 0;
+                                for (int m = 0; m <= p; ++m) {
+                                    int gg[3] = {e3[0] * p + k3[0], e3[1] * p + k3[1], e3[2] * p + k3[2]};
+                                    gg[a] = e3[a] * p + m;
+                                    long nm = ((long)(gg[2] % N[2]) * N[1] + gg[1] % N[1]) * N[0] + gg[0] % N[0];
+                                    d += Dm[k3[a]][m] * u[(long)a * Nl + nm];
+                                }
+                                div += d / h[a];
+                            }
+                            R ke = 0;
+                            for (int a = 0; a < 3; ++a) ke += u[(long)a * Nl + n] * u[(long)a * Nl + n];
+                            double W = (0.5 * h[0] * wcc[kx]) * (0.5 * h[1] * wcc[ky]) * (0.5 * h[2] * wcc[kz]);
+                            L += W * (0.5 * rho[n] * ke + div * div);
+                        }
+    free(rho); free(u); free(T);
+    return L;
+}
+
+#ifdef ORACLE_COMPLEX
+/* The loss is returned through a pointer in the complex build (ctypes cannot
+ * return a C99 complex by value portably). */
+void oracle_cs_loss_out(const oracle_cfg *c, const R *f, const R *g, R *out) { *out = oracle_cs_loss(c, f, g); }
+#endif

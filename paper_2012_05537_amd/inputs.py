@@ -1,0 +1,132 @@
+"""Seeded synthetic inputs: compressible Taylor-Green-vortex fields and the
+workload table.
+
+This module holds input recipes only (closed-form initial fields, random
+perturbation modes, the conversion of Mach/Reynolds/CFL numbers into the
+time step and viscosity of a run).  It contains none of the method's own
+arithmetic, and it is the only code shared by the GPU path and the oracle.
+
+Units are lattice units: c_s = 1, T0 = 1, rho0 = 1, domain [0, 2 pi]^3.
+Initial condition (Sec. III C, constant-temperature initial condition):
+    u = U (sin x cos y cos z, -cos x sin y cos z, 0)
+    P = rho0 T0 + rho0 U^2 / 16 (cos 2x + cos 2y)(cos 2z + 2),  rho = P / T0,  T = T0
+with U = Ma * sqrt(gamma T0), which reproduces the paper's rho = 1 + C/16(...)
+with C = gamma Ma^2.  mu_inf = rho0 U L / Re with L = 1, and
+dt = CFL * (mean node spacing) / (largest abscissa speed).
+"""
+import math
+
+import numpy as np
+
+# Largest speed |xi| of the 45-velocity set (outer icosahedron shell), used
+# only to turn a CFL number into a time step.
+MAX_SPEED = math.sqrt(15.0)
+
+T0 = 1.0
+RHO0 = 1.0
+
+# The five workloads the implementation is measured and checked on.
+WORKLOADS = {
+    "c1": dict(n_el=4, p=2, Ma=0.5, Re=100.0, gamma=1.4, Pr=0.71, cfl=2.0, steps=10,
+               precision="fp64", modes=None),
+    "c2": dict(n_el=16, p=4, Ma=1.25, Re=1600.0, gamma=1.4, Pr=0.71, cfl=1.0, steps=200,
+               precision="fp64", modes=None),
+    "c3": dict(n_el=32, p=4, Ma=1.25, Re=1600.0, gamma=1.4, Pr=0.71, cfl=5.0, steps=500,
+               precision="fp32", modes=None),
+    "c4": dict(n_el=8, p=3, Ma=0.5, Re=400.0, gamma=1.4, Pr=0.71, cfl=2.0, steps=50,
+               precision="fp64", modes=dict(seed=2012, count=16, scale=0.01), checkpoint=10),
+    "c5": dict(n_el=64, p=4, Ma=1.25, Re=1600.0, gamma=1.4, Pr=0.71, cfl=10.0, steps=200,
+               precision="fp32", modes=dict(seed=2021, count=16, scale=0.01), checkpoint="sqrt"),
+}
+
+
+def velocity_scale(Ma, gamma):
+    """U = Ma * adiabatic sound speed sqrt(gamma T0)."""
+    return Ma * math.sqrt(gamma * T0)
+
+
+def run_parameters(n_el, p, Ma, Re, gamma, cfl, length=2 * math.pi):
+    """(dt, mu_inf) of a run: dt from the CFL number, mu_inf from Re = rho0 U L / mu_inf (L = 1)."""
+    U = velocity_scale(Ma, gamma)
+    mu_inf = RHO0 * U * 1.0 / Re
+    dx = length / (n_el * p)
+    dt = cfl * dx / MAX_SPEED
+    return dt, mu_inf
+
+
+def workload(name, **override):
+    """Workload dict with derived dt, mu_inf and U filled in."""
+    w = dict(WORKLOADS[name])
+    w.update(override)
+    dt, mu_inf = run_parameters(w["n_el"], w["p"], w["Ma"], w["Re"], w["gamma"], w["cfl"])
+    w["dt"] = dt
+    w["mu_inf"] = mu_inf
+    w["U"] = velocity_scale(w["Ma"], w["gamma"])
+    w["name"] = name
+    return w
+
+
+def mesh(xs, ys, zs):
+    """3-D coordinate arrays (flattened, x fastest) from the 1-D node coordinates."""
+    Z, Y, X = np.meshgrid(zs, ys, xs, indexing="ij")
+    return X.ravel(), Y.ravel(), Z.ravel()
+
+
+def tgv_fields(xs, ys, zs, Ma, gamma):
+    """rho (N,), u (3, N), T (N,) of the compressible Taylor-Green vortex."""
+    X, Y, Z = mesh(xs, ys, zs)
+    U = velocity_scale(Ma, gamma)
+    u = np.stack([U * np.sin(X) * np.cos(Y) * np.cos(Z),
+                  -U * np.cos(X) * np.sin(Y) * np.cos(Z),
+                  np.zeros_like(X)])
+    P = RHO0 * T0 + RHO0 * U * U / 16.0 * (np.cos(2 * X) + np.cos(2 * Y)) * (np.cos(2 * Z) + 2.0)
+    rho = P / T0
+    T = np.full_like(X, T0)
+    return rho, u, T
+
+
+def fourier_modes(seed, count, Ma, gamma, scale=0.01, kmax=2):
+    """Seeded divergence-free perturbation modes: list of (k, e, phase, amplitude).
+
+    k in {-kmax..kmax}^3 without 0, e a random unit vector orthogonal to k,
+    phase uniform in [0, 2 pi), amplitude ~ N(0, (scale * U)^2)."""
+    rng = np.random.default_rng(seed)
+    U = velocity_scale(Ma, gamma)
+    modes = []
+    while len(modes) < count:
+        k = rng.integers(-kmax, kmax + 1, size=3)
+        if not k.any():
+            continue
+        v = rng.normal(size=3)
+        kk = k / np.linalg.norm(k)
+        e = v - (v @ kk) * kk
+        e /= np.linalg.norm(e)
+        phase = rng.uniform(0.0, 2 * math.pi)
+        amp = rng.normal(0.0, scale * U)
+        modes.append((k.astype(float), e, phase, amp))
+    return modes
+
+
+def mode_basis(xs, ys, zs, modes):
+    """B (M, 3, N): velocity field of each mode at unit amplitude, e_m sin(k_m . x + phase_m)."""
+    X, Y, Z = mesh(xs, ys, zs)
+    out = np.zeros((len(modes), 3, X.size))
+    for m, (k, e, ph, _) in enumerate(modes):
+        s = np.sin(k[0] * X + k[1] * Y + k[2] * Z + ph)
+        out[m] = e[:, None] * s[None, :]
+    return out
+
+
+def perturbed_tgv(xs, ys, zs, Ma, gamma, modes, amplitudes=None):
+    """TGV fields with the velocity modes added (amplitudes default to the drawn ones)."""
+    rho, u, T = tgv_fields(xs, ys, zs, Ma, gamma)
+    if modes:
+        amps = np.array([m[3] for m in modes]) if amplitudes is None else np.asarray(amplitudes)
+        B = mode_basis(xs, ys, zs, modes)
+        u = u + np.tensordot(amps, B, axes=(0, 0))
+    return rho, u, T
+
+
+def random_populations(shape, seed, scale=1.0):
+    """Seeded standard-normal array (for adjoint seeds and perturbations)."""
+    return np.random.default_rng(seed).normal(0.0, scale, size=shape)
