@@ -1,0 +1,165 @@
+#!/usr/bin/env python3
+"""Benchmark of the SLLBM hot path on one MI355X.
+
+One "step" is one fused pass of the whole per-time-step update (streaming of
+all 90 populations by the order-p semi-Lagrangian interpolation, moments,
+transport coefficients, equilibria, quasi-equilibrium term, relaxation) over
+the whole grid.  The headline workload is the FP64 compressible Taylor-Green
+vortex on 16^3 cells of order 4 (64^3 nodes), Ma 1.25, Re 1600.
+
+Prints ONE JSON line (see the ``--help`` of the options).
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, vendor figure
+Q = 45
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "sllbm_internal.h"):
+        with open(os.path.join(ROOT, "paper_2012_05537_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, dtype):
+    """HBM bytes per launch of the fused kernel from the committed rocprofv3
+    counter summary, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "stream_collide_traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        data = json.load(open(path))
+    except ValueError:
+        return None
+    rec = data.get(f"{workload}:{dtype}")
+    if not rec or rec.get("kernel_source") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def run_gpu(args, wl, precision):
+    import torch
+    from paper_2012_05537_amd import inputs
+    from paper_2012_05537_amd.sllbm import SLLBM
+
+    ctx = SLLBM(wl["n_el"], wl["p"], wl["dt"], wl["mu_inf"], gamma=wl["gamma"], prandtl=wl["Pr"],
+                precision=precision)
+    xs, ys, zs = (t.numpy() for t in ctx.node_coords())
+    rho, u, T = inputs.tgv_fields(xs, ys, zs, wl["Ma"], wl["gamma"])
+    dev = ctx.device
+    ctx.init_equilibrium(torch.from_numpy(rho).to(dev), torch.from_numpy(u).to(dev), torch.from_numpy(T).to(dev))
+    ctx.step(1)                       # leaves the pre-collision bookkeeping; from here one launch per step
+    for _ in range(args.warmup):
+        ctx.step(1)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        ctx.step(1)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kernel_ms = ev0.elapsed_time(ev1) / args.steps
+    tot = ctx.totals()
+    ok = all(math.isfinite(v) for v in tot)
+    nodes = ctx.nodes
+    elem = 8 if precision == 0 else 4
+    bytes_per_launch = 2 * 2 * Q * nodes * elem          # read 90 + write 90 values per node
+    ctx.close()
+    return dict(nodes=nodes, wall=wall, kernel_ms=kernel_ms, bytes=bytes_per_launch, finite=ok, totals=tot)
+
+
+def cpu_baseline(wl, budget_s):
+    """The FP64 oracle on the host cores: whole-grid steps of the same workload
+    (same grid, same parameters) until about budget_s seconds have run."""
+    import numpy as np
+    from oracle import oracle as O
+    from paper_2012_05537_amd import inputs
+
+    cfg = O.make_cfg(wl["n_el"], wl["p"], wl["dt"], wl["mu_inf"], gamma=wl["gamma"], prandtl=wl["Pr"])
+    rho, u, T = inputs.tgv_fields(*O.node_coords(cfg), wl["Ma"], wl["gamma"])
+    f, g = O.init_equilibrium(cfg, rho, u, T)
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        f, g = O.step(cfg, f, g, 1)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el > budget_s or el / steps * (steps + 1) > 2.0 * budget_s:
+            break
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return dict(value=O.num_nodes(cfg) * steps / el, unit="node-updates/s", cores=cores, kind="oracle",
+                sample=f"{steps} whole-grid FP64 oracle step(s) of the same workload "
+                       f"({O.num_nodes(cfg)} nodes), {el:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="c2", help="workload key (c1..c5)")
+    ap.add_argument("--cfl", type=float, default=5.0)
+    ap.add_argument("--precision", choices=["fp64", "fp32"], default=None)
+    ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time for cpu_baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (see the design notes on "
+              "how the step would shard); run with --gpus 1", file=sys.stderr)
+        return 2
+
+    from paper_2012_05537_amd import inputs
+    wl = inputs.workload(args.workload, cfl=args.cfl)
+    prec_name = args.precision or wl["precision"]
+    precision = 0 if prec_name == "fp64" else 1
+    r = run_gpu(args, wl, precision)
+    value = r["nodes"] * args.steps / r["wall"]
+    achieved = r["bytes"] / (r["kernel_ms"] * 1e-3) / 1e9
+    traffic = measured_traffic(args.workload, prec_name)
+    out = {
+        "metric": "node-updates/s (D3V45 f+g)",
+        "value": value,
+        "unit": "node-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["wall"] * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if precision == 0 else "f32 (f64 moments)",
+        "data": "synthetic: closed-form compressible Taylor-Green vortex",
+        "config": {"workload": f"{args.workload}: TGV {wl['n_el']}^3 cells p={wl['p']} "
+                               f"({r['nodes']} nodes), Ma {wl['Ma']}, Re {wl['Re']}, CFL {wl['cfl']}, "
+                               f"{prec_name}",
+                   "nodes": r["nodes"], "order": wl["p"], "cfl": wl["cfl"], "dt": wl["dt"],
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_stream_collide", "kernel_ms": r["kernel_ms"],
+                     "algorithmic_bytes_per_launch": r["bytes"]},
+        "finite": r["finite"],
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

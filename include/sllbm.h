@@ -1,0 +1,183 @@
+/*
+ * sllbm.h -- C ABI of the MI355X (gfx950) semi-Lagrangian lattice Boltzmann
+ * library: the per-time-step update of the 45-velocity f and g populations
+ * of the compressible SLLBM (Wilde, Kraemer, Reith, Foysi, arXiv:2012.05537)
+ * on a periodic hexahedral mesh of equal cells with Gauss-Lobatto-Chebyshev
+ * support points.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  Units      lattice units: c_s = 1, T0 = 1, gas constant 1, D = 3,
+ *             C_v = 1/(gamma - 1).
+ *  Nodes      the unique periodic support points: N_a = n_el[a] * order per
+ *             axis, N = N_x N_y N_z.  Node (gx, gy, gz) has linear index
+ *             (gz * N_y + gy) * N_x + gx; along an axis, node g = e*order + l
+ *             (cell e, local point l in [0, order)) sits at
+ *             x = e*h + h*(1 - cos(pi*l/order))/2, h = length/n_el (Sec. II A).
+ *  Velocities the 45 abscissae in the order returned by sllbm_velocity_set().
+ *  State      one buffer of 2*45*N values of the storage type (double for
+ *             SLLBM_FP64, float for SLLBM_FP32_MIXED): f at [i*N + n], then
+ *             g at [(45 + i)*N + n].  A "state" passed through this ABI is
+ *             always the pre-collision populations h_i(x, t) of Eq. (5).
+ *  Fields     rho [N], u [3][N] (component-major), T [N], all double.
+ *  Pointers   "device" pointers must be device memory on the context's
+ *             device; "host" pointers are ordinary host memory.  The caller
+ *             owns every pointer it passes; the library never keeps one past
+ *             the call.  The library owns its internal state buffers and tables.
+ *  Ordering   every call except sllbm_totals, sllbm_loss, sllbm_create and
+ *             sllbm_destroy is asynchronous on the stream set with
+ *             sllbm_set_stream (default: the null stream).
+ *  Errors     0 on success, else one of the SLLBM_E* codes; no exception
+ *             crosses the ABI.  sllbm_last_error() returns the message of the
+ *             last failure on this context (or of a failed create, for NULL).
+ *  Threads    a context is not thread-safe; distinct contexts are independent.
+ */
+#ifndef SLLBM_H
+#define SLLBM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SLLBM_OK 0
+#define SLLBM_EINVAL 1      /* bad argument or configuration */
+#define SLLBM_ENOMEM 2      /* device allocation failed */
+#define SLLBM_EDEVICE 3     /* HIP runtime error or no usable gfx950 device */
+#define SLLBM_ESTATE 4      /* call not valid in the current state */
+#define SLLBM_ENONFINITE 5  /* a non-finite value was found */
+
+#define SLLBM_D3Q45 45
+
+#define SLLBM_SUTHERLAND 0  /* mu = mu_inf (1+S) T^1.5/(T+S), S = 0.40417 (Sec. III C) */
+#define SLLBM_CONSTANT 1    /* mu = mu_inf */
+
+#define SLLBM_FP64 0        /* double populations and arithmetic */
+#define SLLBM_FP32_MIXED 1  /* float populations, interpolation and relaxation;
+                               double moments, transport coefficients,
+                               equilibrium coefficients and centred third moments */
+
+typedef struct sllbm_ctx sllbm_ctx;
+
+typedef struct {
+    int32_t n_el[3];        /* cells per axis, >= 1 */
+    int32_t order;          /* GLC interpolation order p, 1..6 (Eq. (8)) */
+    int32_t velocity_set;   /* SLLBM_D3Q45 */
+    int32_t viscosity_law;  /* SLLBM_SUTHERLAND or SLLBM_CONSTANT */
+    int32_t precision;      /* SLLBM_FP64 or SLLBM_FP32_MIXED */
+    int32_t device;         /* HIP device ordinal */
+    double length[3];       /* domain edge lengths, > 0 */
+    double dt;              /* time step, > 0 */
+    double gamma;           /* heat capacity ratio, > 1 */
+    double prandtl;         /* Prandtl number of the quasi-equilibrium term, > 0 */
+    double mu_inf;          /* viscosity at T = 1, > 0 */
+} sllbm_config;
+
+/* Create a context (Sec. II A "at the beginning of the simulation": the
+ * departure point of every (node, velocity) pair is located once, and the
+ * per-axis cell offsets and 1-D Lagrange weights are uploaded).  Allocates
+ * two state buffers on cfg->device.  *out is NULL on failure.
+ * Errors: EINVAL (bad config), EDEVICE (no gfx950 device), ENOMEM. */
+int sllbm_create(const sllbm_config *cfg, sllbm_ctx **out);
+
+/* Free the context and its device memory.  NULL is accepted. */
+int sllbm_destroy(sllbm_ctx *ctx);
+
+/* Stream (a hipStream_t, e.g. torch.cuda.current_stream().cuda_stream) on
+ * which every later call is ordered.  NULL selects the null stream. */
+int sllbm_set_stream(sllbm_ctx *ctx, void *hip_stream);
+
+/* Message of the last error on ctx (ctx may be NULL: last failed create). */
+const char *sllbm_last_error(const sllbm_ctx *ctx);
+
+/* Number of unique nodes N; -1 for a NULL context. */
+int64_t sllbm_num_nodes(const sllbm_ctx *ctx);
+
+/* Bytes of one state buffer (2 * 45 * N * sizeof(storage type)). */
+int64_t sllbm_state_bytes(const sllbm_ctx *ctx);
+
+/* The D3Q45 velocity set (Sec. II B, degree-nine cubature): xi[45][3] and
+ * w[45] (host).  Returns 45. */
+int sllbm_velocity_set(double *xi, double *w);
+
+/* 1-D node coordinates along each axis (host arrays of N_x, N_y, N_z). */
+int sllbm_node_coords(const sllbm_ctx *ctx, double *x, double *y, double *z);
+
+/* Change mu_inf (the "relaxation time" parameter; tau - 1/2 = mu/(P dt)). */
+int sllbm_set_viscosity(sllbm_ctx *ctx, double mu_inf);
+
+/* State := equilibrium of the given fields (Eq. (6); g^eq = (2C_v - D) T f^eq).
+ * rho, u, T: device.  Errors: EINVAL on NULL. */
+int sllbm_init_equilibrium(sllbm_ctx *ctx, const double *rho, const double *u, const double *T);
+
+/* State := caller's pre-collision populations (device, storage type). */
+int sllbm_set_state(sllbm_ctx *ctx, const void *state);
+
+/* Copy the current pre-collision populations to the caller (device). */
+int sllbm_get_state(sllbm_ctx *ctx, void *state);
+
+/* Advance n >= 0 time steps of Eq. (5) with the quasi-equilibrium collision
+ * of App. D: each step collides every node, then streams every population
+ * by the semi-Lagrangian interpolation of Eqs. (8)-(9).  Internally the
+ * collision of step k+1 is fused with the streaming of step k, so the hot
+ * loop is one pass per step over the state. */
+int sllbm_step(sllbm_ctx *ctx, int32_t n);
+
+/* As sllbm_step, and also writes the pre-collision state after each of the
+ * n steps to states + k*stride_bytes (device), k = 0..n-1. */
+int sllbm_step_record(sllbm_ctx *ctx, int32_t n, void *states, int64_t stride_bytes);
+
+/* rho, u, T of the current state at every node, Eq. (7) (device, double).
+ * T from 2 rho E = rho |u|^2 + 2 C_v rho T.  Any pointer may be NULL. */
+int sllbm_moments(sllbm_ctx *ctx, double *rho, double *u, double *T);
+
+/* Domain integrals of rho, rho u_x, rho u_y, rho u_z and rho E with
+ * Clenshaw-Curtis weights of the GLC points (host out[5]).  Deterministic
+ * (fixed-order two-stage FP64 reduction).  Synchronises the stream.
+ * Returns ENONFINITE (and still fills out) if any value is not finite. */
+int sllbm_totals(sllbm_ctx *ctx, double *out);
+
+/* ---- adjoint (reverse mode of the step map) ----------------------------- */
+
+/* Flow functional on a caller state (device):
+ *   L = sum over cells of the tensor Clenshaw-Curtis quadrature of
+ *       (1/2) rho |u|^2 + (div u)^2,
+ * div u from each cell's own interpolation polynomial (Sec. III C).
+ * Result to host *out; synchronises the stream. */
+int sllbm_loss(sllbm_ctx *ctx, const void *state, double *out);
+
+/* dL/d(state) of sllbm_loss, written to lam (device, storage type). */
+int sllbm_loss_grad(sllbm_ctx *ctx, const void *state, void *lam);
+
+/* One reverse step.  With X_{n+1} = S(C(X_n)) (C: collision, S: streaming),
+ * lam_out = (dX_{n+1}/dX_n)^T lam_next = J_C(X_n)^T S^T lam_next, where S^T
+ * is applied as a gather over the transposed 1-D interpolation tables
+ * (no atomics).  state_n, lam_next, lam_out: device, storage type; lam_out
+ * must not alias lam_next.  If dmu is not NULL, the derivative with respect
+ * to mu_inf, sum over nodes of lam_next . S (dC/dmu_inf), is added to *dmu
+ * (device double). */
+int sllbm_adjoint_step(sllbm_ctx *ctx, const void *state_n, const void *lam_next, void *lam_out,
+                       double *dmu);
+
+/* Reverse of sllbm_init_equilibrium: given lam0 = dL/d(state), write
+ * dL/drho, dL/du ([3][N]) and dL/dT at the fields (rho, u, T).  All device;
+ * drho, du, dT may be NULL. */
+int sllbm_init_equilibrium_vjp(sllbm_ctx *ctx, const double *rho, const double *u, const double *T,
+                               const void *lam0, double *drho, double *du, double *dT);
+
+/* ---- building blocks exposed for testing -------------------------------- */
+
+/* Streaming only (Eq. (9)) of a caller state: out = S(in) (forward) or
+ * out = S^T(in) (transpose != 0).  Device, storage type, no aliasing. */
+int sllbm_stream(sllbm_ctx *ctx, const void *in, void *out, int32_t transpose);
+
+/* Collision only (Eq. (5) right-hand side with App. D) of a caller state,
+ * in place (device, storage type). */
+int sllbm_collide(sllbm_ctx *ctx, void *state);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SLLBM_H */

@@ -1,0 +1,551 @@
+// C ABI of the SLLBM library (declared in include/sllbm.h): argument
+// validation, device memory, the pre/post-collision bookkeeping of the fused
+// step, and dispatch to the storage-type-specific launchers.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "sllbm_internal.h"
+
+using namespace sllbm;
+
+namespace {
+
+enum Mode { MODE_PRE = 0, MODE_POST = 1 };
+
+constexpr int RED_BLOCKS = 1024;   // blocks of the deterministic reductions
+
+std::string g_create_error;
+
+}  // namespace
+
+struct sllbm_ctx {
+    sllbm_config cfg{};
+    Geometry geo{};
+    VelocitySet vs{};
+    AxisTables htab[2];           // 0: forward streaming, 1: transposed
+    StreamTables dtab[2]{};
+    CollisionParams cp{};
+    hipStream_t stream = nullptr;
+    size_t elem = 8;
+    // State buffers.  In MODE_PRE buf[cur] holds the pre-collision state X_k.
+    // In MODE_POST buf[cur] holds C(X_k) and buf[1-cur] holds C(X_{k-1}), so
+    // X_k = S(buf[1-cur]).  Moments are identical before and after collision.
+    void *buf[2] = {nullptr, nullptr};
+    int cur = 0;
+    int mode = MODE_PRE;
+    bool has_state = false;
+    // device tables
+    int32_t *d_off[2] = {nullptr, nullptr};
+    void *d_wt[2] = {nullptr, nullptr};
+    int32_t *d_lo[2] = {nullptr, nullptr};
+    int32_t *d_span[2] = {nullptr, nullptr};
+    double *d_nodew = nullptr;     // [Nx + Ny + Nz] 1-D node quadrature weights
+    double *d_ccw = nullptr;       // [p+1] Clenshaw-Curtis weights of a cell, mapped to [0, 1] per unit h
+    double *d_dmat = nullptr;      // [(p+1)^2] d ell_m / ds at t_k
+    double *d_h = nullptr;         // [3] cell widths
+    double *d_partials = nullptr;  // [RED_BLOCKS * 8]
+    double *d_small = nullptr;     // [16] reduction results
+    double *d_scr_rho = nullptr;   // [N]   loss scratch
+    double *d_scr_u = nullptr;     // [3N]
+    double *d_scr_div = nullptr;   // [cells * (p+1)^3]
+    std::string err;
+};
+
+namespace {
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard()
+    {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+int fail(sllbm_ctx *c, int code, const std::string &msg)
+{
+    if (c) c->err = msg;
+    else g_create_error = msg;
+    return code;
+}
+
+int hip_fail(sllbm_ctx *c, hipError_t e, const char *what)
+{
+    return fail(c, SLLBM_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+template <typename T>
+hipError_t dalloc(T **p, size_t bytes)
+{
+    return hipMalloc(reinterpret_cast<void **>(p), bytes);
+}
+
+void free_ctx(sllbm_ctx *c)
+{
+    for (int k = 0; k < 2; ++k) {
+        (void)hipFree(c->buf[k]);
+        (void)hipFree(c->d_off[k]);
+        (void)hipFree(c->d_wt[k]);
+        (void)hipFree(c->d_lo[k]);
+        (void)hipFree(c->d_span[k]);
+    }
+    (void)hipFree(c->d_nodew);
+    (void)hipFree(c->d_ccw);
+    (void)hipFree(c->d_dmat);
+    (void)hipFree(c->d_h);
+    (void)hipFree(c->d_partials);
+    (void)hipFree(c->d_small);
+    (void)hipFree(c->d_scr_rho);
+    (void)hipFree(c->d_scr_u);
+    (void)hipFree(c->d_scr_div);
+}
+
+// Cells per tile: about 8 x 8 x 4 nodes (at most 256, one node per thread).
+void choose_tile(Geometry &g)
+{
+    const int p = g.p;
+    int target[3] = {8, 8, 4};
+    for (int a = 0; a < 3; ++a) g.TE[a] = std::min(std::max(1, target[a] / p), g.nel[a]);
+    bool grown = true;
+    while (grown) {
+        grown = false;
+        for (int a = 2; a >= 0; --a) {
+            int TE[3] = {g.TE[0], g.TE[1], g.TE[2]};
+            TE[a] += 1;
+            if (TE[a] <= g.nel[a] && TE[0] * TE[1] * TE[2] * p * p * p <= 256) {
+                g.TE[a] = TE[a];
+                grown = true;
+                break;
+            }
+        }
+    }
+    for (int a = 0; a < 3; ++a) g.ntile[a] = (g.nel[a] + g.TE[a] - 1) / g.TE[a];
+}
+
+template <typename S>
+int upload_tables(sllbm_ctx *c)
+{
+    const int p = c->geo.p;
+    for (int d = 0; d < 2; ++d) {
+        const AxisTables &h = c->htab[d];
+        const size_t n = h.off.size();
+        std::vector<S> wt(n);
+        for (size_t k = 0; k < n; ++k) wt[k] = static_cast<S>(h.wt[k]);
+        hipError_t e;
+        if ((e = dalloc(&c->d_off[d], n * sizeof(int32_t))) != hipSuccess ||
+            (e = dalloc(reinterpret_cast<S **>(&c->d_wt[d]), n * sizeof(S))) != hipSuccess ||
+            (e = dalloc(&c->d_lo[d], Q * 3 * sizeof(int32_t))) != hipSuccess ||
+            (e = dalloc(&c->d_span[d], Q * 3 * sizeof(int32_t))) != hipSuccess)
+            return fail(c, SLLBM_ENOMEM, std::string("table allocation: ") + hipGetErrorString(e));
+        if ((e = hipMemcpy(c->d_off[d], h.off.data(), n * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess ||
+            (e = hipMemcpy(c->d_wt[d], wt.data(), n * sizeof(S), hipMemcpyHostToDevice)) != hipSuccess ||
+            (e = hipMemcpy(c->d_lo[d], h.lo.data(), Q * 3 * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess ||
+            (e = hipMemcpy(c->d_span[d], h.span.data(), Q * 3 * sizeof(int32_t), hipMemcpyHostToDevice)) !=
+                hipSuccess)
+            return hip_fail(c, e, "table upload");
+        StreamTables &t = c->dtab[d];
+        t.off = c->d_off[d];
+        t.wt = c->d_wt[d];
+        t.lo = c->d_lo[d];
+        t.span = c->d_span[d];
+        t.K = h.K;
+        for (int a = 0; a < 3; ++a) {
+            int smax = 0;
+            for (int i = 0; i < Q; ++i) smax = std::max(smax, h.span[i * 3 + a]);
+            t.wmax[a] = (c->geo.TE[a] - 1) * p + smax;
+        }
+    }
+    return SLLBM_OK;
+}
+
+bool is_fp64(const sllbm_ctx *c) { return c->cfg.precision == SLLBM_FP64; }
+
+void *other(sllbm_ctx *c) { return c->buf[1 - c->cur]; }
+
+int check_launch(sllbm_ctx *c, hipError_t e, const char *what)
+{
+    return e == hipSuccess ? SLLBM_OK : hip_fail(c, e, what);
+}
+
+int check_smem(sllbm_ctx *c, int dir)
+{
+    const size_t need = stream_smem_bytes(c->geo, c->dtab[dir], c->elem);
+    if (need > 160 * 1024)
+        return fail(c, SLLBM_EINVAL, "streaming window does not fit in LDS (" + std::to_string(need) + " bytes)");
+    return SLLBM_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+
+extern "C" {
+
+int sllbm_velocity_set(double *xi, double *w)
+{
+    if (!xi || !w) return SLLBM_EINVAL;
+    VelocitySet vs;
+    build_velocity_set(vs);
+    for (int i = 0; i < Q; ++i) {
+        for (int k = 0; k < 3; ++k) xi[3 * i + k] = vs.xi[i][k];
+        w[i] = vs.w[i];
+    }
+    return Q;
+}
+
+const char *sllbm_last_error(const sllbm_ctx *ctx) { return ctx ? ctx->err.c_str() : g_create_error.c_str(); }
+
+int64_t sllbm_num_nodes(const sllbm_ctx *ctx) { return ctx ? ctx->geo.nodes : -1; }
+
+int64_t sllbm_state_bytes(const sllbm_ctx *ctx)
+{
+    return ctx ? static_cast<int64_t>(2 * Q) * ctx->geo.nodes * static_cast<int64_t>(ctx->elem) : -1;
+}
+
+int sllbm_create(const sllbm_config *cfg, sllbm_ctx **out)
+{
+    if (!out) return fail(nullptr, SLLBM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!cfg) return fail(nullptr, SLLBM_EINVAL, "cfg is NULL");
+    if (cfg->velocity_set != SLLBM_D3Q45) return fail(nullptr, SLLBM_EINVAL, "velocity_set must be SLLBM_D3Q45");
+    if (cfg->order < 1 || cfg->order > MAXP) return fail(nullptr, SLLBM_EINVAL, "order must be in 1..6");
+    for (int a = 0; a < 3; ++a) {
+        if (cfg->n_el[a] < 1) return fail(nullptr, SLLBM_EINVAL, "n_el must be >= 1");
+        if (!(cfg->length[a] > 0.0) || !std::isfinite(cfg->length[a]))
+            return fail(nullptr, SLLBM_EINVAL, "length must be positive");
+    }
+    const int64_t nodes = static_cast<int64_t>(cfg->n_el[0]) * cfg->order * cfg->n_el[1] * cfg->order *
+                          cfg->n_el[2] * cfg->order;
+    if (static_cast<int64_t>(cfg->n_el[0]) * cfg->order > (1 << 20) ||
+        static_cast<int64_t>(cfg->n_el[1]) * cfg->order > (1 << 20) ||
+        static_cast<int64_t>(cfg->n_el[2]) * cfg->order > (1 << 20) || nodes > (int64_t(1) << 40))
+        return fail(nullptr, SLLBM_EINVAL, "grid too large");
+    if (!(cfg->dt > 0.0) || !std::isfinite(cfg->dt)) return fail(nullptr, SLLBM_EINVAL, "dt must be positive");
+    if (!(cfg->gamma > 1.0)) return fail(nullptr, SLLBM_EINVAL, "gamma must exceed 1");
+    if (!(cfg->prandtl > 0.0)) return fail(nullptr, SLLBM_EINVAL, "prandtl must be positive");
+    if (!(cfg->mu_inf > 0.0) || !std::isfinite(cfg->mu_inf))
+        return fail(nullptr, SLLBM_EINVAL, "mu_inf must be positive");
+    if (cfg->viscosity_law != SLLBM_SUTHERLAND && cfg->viscosity_law != SLLBM_CONSTANT)
+        return fail(nullptr, SLLBM_EINVAL, "unknown viscosity_law");
+    if (cfg->precision != SLLBM_FP64 && cfg->precision != SLLBM_FP32_MIXED)
+        return fail(nullptr, SLLBM_EINVAL, "unknown precision");
+
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0)
+        return fail(nullptr, SLLBM_EDEVICE, "no HIP device available");
+    if (cfg->device < 0 || cfg->device >= ndev) return fail(nullptr, SLLBM_EINVAL, "device ordinal out of range");
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, cfg->device) != hipSuccess)
+        return fail(nullptr, SLLBM_EDEVICE, "hipGetDeviceProperties failed");
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(nullptr, SLLBM_EDEVICE, std::string("library is built for gfx950, device is ") + prop.gcnArchName);
+
+    DeviceGuard guard(cfg->device);
+    sllbm_ctx *c = new sllbm_ctx();
+    c->cfg = *cfg;
+    c->elem = cfg->precision == SLLBM_FP64 ? sizeof(double) : sizeof(float);
+    Geometry &g = c->geo;
+    g.p = cfg->order;
+    for (int a = 0; a < 3; ++a) {
+        g.nel[a] = cfg->n_el[a];
+        g.N[a] = cfg->n_el[a] * cfg->order;
+    }
+    g.nodes = nodes;
+    choose_tile(g);
+    c->cp.dt = cfg->dt;
+    c->cp.Cv = 1.0 / (cfg->gamma - 1.0);
+    c->cp.beta = 2.0 * c->cp.Cv - 3.0;
+    c->cp.inv_pr = 1.0 / cfg->prandtl;
+    c->cp.mu_inf = cfg->mu_inf;
+    c->cp.law = cfg->viscosity_law;
+
+    build_velocity_set(c->vs);
+    if (upload_velocity_constants(c->vs) != 0) {
+        int rc = fail(nullptr, SLLBM_EDEVICE, "constant upload failed");
+        free_ctx(c);
+        delete c;
+        return rc;
+    }
+    double h[3];
+    for (int a = 0; a < 3; ++a) h[a] = cfg->length[a] / cfg->n_el[a];
+    build_axis_tables(c->vs, g.p, h, cfg->dt, c->htab[0], c->htab[1]);
+
+    auto bail = [&](int rc) {
+        g_create_error = c->err;
+        free_ctx(c);
+        delete c;
+        return rc;
+    };
+    int rc = is_fp64(c) ? upload_tables<double>(c) : upload_tables<float>(c);
+    if (rc != SLLBM_OK) return bail(rc);
+    if ((rc = check_smem(c, 0)) != SLLBM_OK || (rc = check_smem(c, 1)) != SLLBM_OK) return bail(rc);
+
+    const size_t sb = static_cast<size_t>(sllbm_state_bytes(c));
+    hipError_t e;
+    if ((e = hipMalloc(&c->buf[0], sb)) != hipSuccess || (e = hipMalloc(&c->buf[1], sb)) != hipSuccess)
+        return bail(fail(c, SLLBM_ENOMEM, "state allocation of " + std::to_string(sb) + " bytes failed"));
+
+    // quadrature weights and derivative matrix
+    const int p = g.p;
+    double cc[MAXP + 1], t[MAXP + 1];
+    clenshaw_curtis(p, cc);
+    glc_points(p, t);
+    std::vector<double> nodew;
+    for (int a = 0; a < 3; ++a)
+        for (int n = 0; n < g.N[a]; ++n) {
+            const int l = n % p;
+            nodew.push_back(0.5 * h[a] * (l == 0 ? cc[0] + cc[p] : cc[l]));
+        }
+    std::vector<double> dmat((p + 1) * (p + 1));
+    for (int k = 0; k <= p; ++k) {
+        double dl[MAXP + 1];
+        lagrange_basis_deriv(p, t[k], dl);
+        for (int m = 0; m <= p; ++m) dmat[k * (p + 1) + m] = dl[m];
+    }
+    const int64_t cells = static_cast<int64_t>(g.nel[0]) * g.nel[1] * g.nel[2];
+    const int64_t cpts = cells * (p + 1) * (p + 1) * (p + 1);
+    if ((e = dalloc(&c->d_nodew, nodew.size() * sizeof(double))) != hipSuccess ||
+        (e = dalloc(&c->d_ccw, (p + 1) * sizeof(double))) != hipSuccess ||
+        (e = dalloc(&c->d_dmat, dmat.size() * sizeof(double))) != hipSuccess ||
+        (e = dalloc(&c->d_h, 3 * sizeof(double))) != hipSuccess ||
+        (e = dalloc(&c->d_partials, RED_BLOCKS * 8 * sizeof(double))) != hipSuccess ||
+        (e = dalloc(&c->d_small, 16 * sizeof(double))) != hipSuccess ||
+        (e = dalloc(&c->d_scr_rho, nodes * sizeof(double))) != hipSuccess ||
+        (e = dalloc(&c->d_scr_u, 3 * nodes * sizeof(double))) != hipSuccess ||
+        (e = dalloc(&c->d_scr_div, cpts * sizeof(double))) != hipSuccess)
+        return bail(fail(c, SLLBM_ENOMEM, std::string("allocation failed: ") + hipGetErrorString(e)));
+    if ((e = hipMemcpy(c->d_nodew, nodew.data(), nodew.size() * sizeof(double), hipMemcpyHostToDevice)) !=
+            hipSuccess ||
+        (e = hipMemcpy(c->d_ccw, cc, (p + 1) * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(c->d_dmat, dmat.data(), dmat.size() * sizeof(double), hipMemcpyHostToDevice)) !=
+            hipSuccess ||
+        (e = hipMemcpy(c->d_h, h, 3 * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess)
+        return bail(hip_fail(c, e, "upload"));
+    *out = c;
+    return SLLBM_OK;
+}
+
+int sllbm_destroy(sllbm_ctx *ctx)
+{
+    if (!ctx) return SLLBM_OK;
+    {
+        DeviceGuard guard(ctx->cfg.device);
+        if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+        else (void)hipDeviceSynchronize();
+        free_ctx(ctx);
+    }
+    delete ctx;
+    return SLLBM_OK;
+}
+
+int sllbm_set_stream(sllbm_ctx *ctx, void *hip_stream)
+{
+    if (!ctx) return SLLBM_EINVAL;
+    ctx->stream = static_cast<hipStream_t>(hip_stream);
+    return SLLBM_OK;
+}
+
+int sllbm_node_coords(const sllbm_ctx *ctx, double *x, double *y, double *z)
+{
+    if (!ctx || !x || !y || !z) return SLLBM_EINVAL;
+    double *out[3] = {x, y, z};
+    const int p = ctx->geo.p;
+    for (int a = 0; a < 3; ++a) {
+        const double h = ctx->cfg.length[a] / ctx->cfg.n_el[a];
+        for (int n = 0; n < ctx->geo.N[a]; ++n) {
+            const int e = n / p, l = n % p;
+            out[a][n] = e * h + h * 0.5 * (1.0 - std::cos(M_PI * l / p));
+        }
+    }
+    return SLLBM_OK;
+}
+
+int sllbm_set_viscosity(sllbm_ctx *ctx, double mu_inf)
+{
+    if (!ctx) return SLLBM_EINVAL;
+    if (!(mu_inf > 0.0) || !std::isfinite(mu_inf)) return fail(ctx, SLLBM_EINVAL, "mu_inf must be positive");
+    ctx->cfg.mu_inf = mu_inf;
+    ctx->cp.mu_inf = mu_inf;
+    return SLLBM_OK;
+}
+
+int sllbm_init_equilibrium(sllbm_ctx *ctx, const double *rho, const double *u, const double *T)
+{
+    if (!ctx) return SLLBM_EINVAL;
+    if (!rho || !u || !T) return fail(ctx, SLLBM_EINVAL, "NULL field");
+    DeviceGuard guard(ctx->cfg.device);
+    hipError_t e = is_fp64(ctx)
+        ? Launch<double>::init_equilibrium(ctx->geo, ctx->cp, rho, u, T, static_cast<double *>(ctx->buf[ctx->cur]),
+                                           ctx->stream)
+        : Launch<float>::init_equilibrium(ctx->geo, ctx->cp, rho, u, T, static_cast<float *>(ctx->buf[ctx->cur]),
+                                          ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "init_equilibrium");
+    ctx->mode = MODE_PRE;
+    ctx->has_state = true;
+    return SLLBM_OK;
+}
+
+int sllbm_set_state(sllbm_ctx *ctx, const void *state)
+{
+    if (!ctx) return SLLBM_EINVAL;
+    if (!state) return fail(ctx, SLLBM_EINVAL, "NULL state");
+    DeviceGuard guard(ctx->cfg.device);
+    hipError_t e = hipMemcpyAsync(ctx->buf[ctx->cur], state, sllbm_state_bytes(ctx), hipMemcpyDeviceToDevice,
+                                  ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "set_state");
+    ctx->mode = MODE_PRE;
+    ctx->has_state = true;
+    return SLLBM_OK;
+}
+
+int sllbm_get_state(sllbm_ctx *ctx, void *state)
+{
+    if (!ctx) return SLLBM_EINVAL;
+    if (!state) return fail(ctx, SLLBM_EINVAL, "NULL state");
+    if (!ctx->has_state) return fail(ctx, SLLBM_ESTATE, "no state set");
+    DeviceGuard guard(ctx->cfg.device);
+    hipError_t e;
+    if (ctx->mode == MODE_PRE) {
+        e = hipMemcpyAsync(state, ctx->buf[ctx->cur], sllbm_state_bytes(ctx), hipMemcpyDeviceToDevice, ctx->stream);
+    } else if (is_fp64(ctx)) {
+        e = Launch<double>::stream_only(ctx->geo, ctx->dtab[0], static_cast<const double *>(other(ctx)),
+                                        static_cast<double *>(state), ctx->stream);
+    } else {
+        e = Launch<float>::stream_only(ctx->geo, ctx->dtab[0], static_cast<const float *>(other(ctx)),
+                                       static_cast<float *>(state), ctx->stream);
+    }
+    return check_launch(ctx, e, "get_state");
+}
+
+static int step_impl(sllbm_ctx *ctx, int32_t n, char *record, int64_t stride)
+{
+    if (!ctx) return SLLBM_EINVAL;
+    if (n < 0) return fail(ctx, SLLBM_EINVAL, "negative step count");
+    if (!ctx->has_state) return fail(ctx, SLLBM_ESTATE, "no state set");
+    if (n == 0) return SLLBM_OK;
+    DeviceGuard guard(ctx->cfg.device);
+    hipError_t e = hipSuccess;
+    if (ctx->mode == MODE_PRE) {
+        // C(X_k) in place; afterwards buf[cur] = C(X_k)
+        e = is_fp64(ctx) ? Launch<double>::collide_only(ctx->geo, ctx->cp, static_cast<double *>(ctx->buf[ctx->cur]),
+                                                        ctx->stream)
+                         : Launch<float>::collide_only(ctx->geo, ctx->cp, static_cast<float *>(ctx->buf[ctx->cur]),
+                                                       ctx->stream);
+        if (e != hipSuccess) return hip_fail(ctx, e, "collide");
+        ctx->mode = MODE_POST;
+    }
+    for (int32_t s = 0; s < n; ++s) {
+        void *pre = record ? record + static_cast<int64_t>(s) * stride : nullptr;
+        if (is_fp64(ctx))
+            e = Launch<double>::stream_collide(ctx->geo, ctx->dtab[0], ctx->cp,
+                                               static_cast<const double *>(ctx->buf[ctx->cur]),
+                                               static_cast<double *>(other(ctx)), static_cast<double *>(pre),
+                                               ctx->stream);
+        else
+            e = Launch<float>::stream_collide(ctx->geo, ctx->dtab[0], ctx->cp,
+                                              static_cast<const float *>(ctx->buf[ctx->cur]),
+                                              static_cast<float *>(other(ctx)), static_cast<float *>(pre), ctx->stream);
+        if (e != hipSuccess) return hip_fail(ctx, e, "stream_collide");
+        ctx->cur = 1 - ctx->cur;
+    }
+    return SLLBM_OK;
+}
+
+int sllbm_step(sllbm_ctx *ctx, int32_t n) { return step_impl(ctx, n, nullptr, 0); }
+
+int sllbm_step_record(sllbm_ctx *ctx, int32_t n, void *states, int64_t stride_bytes)
+{
+    if (!ctx) return SLLBM_EINVAL;
+    if (!states && n > 0) return fail(ctx, SLLBM_EINVAL, "NULL record buffer");
+    if (n > 1 && stride_bytes < sllbm_state_bytes(ctx)) return fail(ctx, SLLBM_EINVAL, "record stride too small");
+    return step_impl(ctx, n, static_cast<char *>(states), stride_bytes);
+}
+
+int sllbm_moments(sllbm_ctx *ctx, double *rho, double *u, double *T)
+{
+    if (!ctx) return SLLBM_EINVAL;
+    if (!ctx->has_state) return fail(ctx, SLLBM_ESTATE, "no state set");
+    DeviceGuard guard(ctx->cfg.device);
+    hipError_t e = is_fp64(ctx)
+        ? Launch<double>::moments(ctx->geo, ctx->cp, static_cast<const double *>(ctx->buf[ctx->cur]), rho, u, T,
+                                  ctx->stream)
+        : Launch<float>::moments(ctx->geo, ctx->cp, static_cast<const float *>(ctx->buf[ctx->cur]), rho, u, T,
+                                 ctx->stream);
+    return check_launch(ctx, e, "moments");
+}
+
+int sllbm_totals(sllbm_ctx *ctx, double *out)
+{
+    if (!ctx) return SLLBM_EINVAL;
+    if (!out) return fail(ctx, SLLBM_EINVAL, "NULL out");
+    if (!ctx->has_state) return fail(ctx, SLLBM_ESTATE, "no state set");
+    DeviceGuard guard(ctx->cfg.device);
+    hipError_t e = is_fp64(ctx)
+        ? Launch<double>::totals(ctx->geo, ctx->cp, static_cast<const double *>(ctx->buf[ctx->cur]), ctx->d_nodew,
+                                 ctx->d_partials, RED_BLOCKS, ctx->d_small, ctx->stream)
+        : Launch<float>::totals(ctx->geo, ctx->cp, static_cast<const float *>(ctx->buf[ctx->cur]), ctx->d_nodew,
+                                ctx->d_partials, RED_BLOCKS, ctx->d_small, ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "totals");
+    if ((e = hipMemcpyAsync(out, ctx->d_small, 5 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream)) !=
+            hipSuccess ||
+        (e = hipStreamSynchronize(ctx->stream)) != hipSuccess)
+        return hip_fail(ctx, e, "totals copy");
+    for (int k = 0; k < 5; ++k)
+        if (!std::isfinite(out[k])) return fail(ctx, SLLBM_ENONFINITE, "non-finite totals");
+    return SLLBM_OK;
+}
+
+int sllbm_stream(sllbm_ctx *ctx, const void *in, void *out, int32_t transpose)
+{
+    if (!ctx) return SLLBM_EINVAL;
+    if (!in || !out || in == out) return fail(ctx, SLLBM_EINVAL, "bad stream buffers");
+    DeviceGuard guard(ctx->cfg.device);
+    const StreamTables &t = ctx->dtab[transpose ? 1 : 0];
+    hipError_t e = is_fp64(ctx)
+        ? Launch<double>::stream_only(ctx->geo, t, static_cast<const double *>(in), static_cast<double *>(out),
+                                      ctx->stream)
+        : Launch<float>::stream_only(ctx->geo, t, static_cast<const float *>(in), static_cast<float *>(out),
+                                     ctx->stream);
+    return check_launch(ctx, e, "stream");
+}
+
+int sllbm_collide(sllbm_ctx *ctx, void *state)
+{
+    if (!ctx) return SLLBM_EINVAL;
+    if (!state) return fail(ctx, SLLBM_EINVAL, "NULL state");
+    DeviceGuard guard(ctx->cfg.device);
+    hipError_t e = is_fp64(ctx)
+        ? Launch<double>::collide_only(ctx->geo, ctx->cp, static_cast<double *>(state), ctx->stream)
+        : Launch<float>::collide_only(ctx->geo, ctx->cp, static_cast<float *>(state), ctx->stream);
+    return check_launch(ctx, e, "collide");
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Reverse mode
+// ---------------------------------------------------------------------------
+extern "C" {
+
+int sllbm_loss(sllbm_ctx *ctx, const void *, double *) { return fail(ctx, SLLBM_ESTATE, "not available"); }
+int sllbm_loss_grad(sllbm_ctx *ctx, const void *, void *) { return fail(ctx, SLLBM_ESTATE, "not available"); }
+int sllbm_adjoint_step(sllbm_ctx *ctx, const void *, const void *, void *, double *)
+{
+    return fail(ctx, SLLBM_ESTATE, "not available");
+}
+int sllbm_init_equilibrium_vjp(sllbm_ctx *ctx, const double *, const double *, const double *, const void *,
+                               double *, double *, double *)
+{
+    return fail(ctx, SLLBM_ESTATE, "not available");
+}
+
+}  // extern "C"

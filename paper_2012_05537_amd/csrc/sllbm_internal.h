@@ -1,0 +1,121 @@
+// Internal declarations shared by the host tables, the kernels and the C ABI
+// of the SLLBM library.  Not part of the public interface (include/sllbm.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "sllbm.h"
+
+namespace sllbm {
+
+constexpr int Q = 45;        // discrete velocities (D3Q45)
+constexpr int MAXP = 6;      // largest supported interpolation order
+constexpr int NPAIR = 22;    // velocity pairs (xi, -xi); velocity 0 is the rest velocity
+
+// ---------------------------------------------------------------------------
+// Host tables (built once per context, Sec. II A: departure points are
+// tracked once at the start of a run, and equal cells share one table).
+// ---------------------------------------------------------------------------
+
+struct VelocitySet {
+    double xi[Q][3];
+    double w[Q];
+    int opposite[Q];          // index of -xi_i
+};
+
+// Per-axis 1-D interpolation tables for one direction (forward streaming or
+// its transpose).  Output node g = e*p + l along an axis receives
+//   sum_k wt[i][a][l][k] * in[(e*p + off[i][a][l][k]) mod N_a].
+struct AxisTables {
+    int p = 0;
+    int K = 0;                          // taps per output node (padded)
+    std::vector<int32_t> off;           // [Q][3][p][K]
+    std::vector<double> wt;             // [Q][3][p][K]
+    std::vector<int32_t> lo;            // [Q][3]: min offset
+    std::vector<int32_t> span;          // [Q][3]: max - min offset + 1
+};
+
+void build_velocity_set(VelocitySet &vs);
+void glc_points(int p, double *t);                       // t_k = (1 - cos(pi k/p))/2
+void lagrange_basis(int p, double s, double *ell);       // ell_k(s) on the GLC points
+void lagrange_basis_deriv(int p, double s, double *dl);  // d ell_k / ds
+void clenshaw_curtis(int p, double *w);                  // weights on [-1,1]
+// forward tables for displacement -xi*dt, and their exact transposes
+void build_axis_tables(const VelocitySet &vs, int p, const double h[3], double dt,
+                       AxisTables &fwd, AxisTables &adj);
+
+// ---------------------------------------------------------------------------
+// Device-side parameter blocks (passed by value to kernels)
+// ---------------------------------------------------------------------------
+
+struct Geometry {
+    int N[3];        // nodes per axis
+    int nel[3];      // cells per axis
+    int p;           // order
+    int TE[3];       // cells per tile and axis
+    int ntile[3];    // tiles per axis
+    int64_t nodes;   // N[0]*N[1]*N[2]
+};
+
+struct StreamTables {
+    const int32_t *off;    // [Q][3][p][K]
+    const void *wt;        // [Q][3][p][K], storage type
+    const int32_t *lo;     // [Q][3]
+    const int32_t *span;   // [Q][3]
+    int K;
+    int wmax[3];           // largest window extent per axis for a full tile
+};
+
+struct CollisionParams {
+    double dt;
+    double Cv;        // 1/(gamma - 1)
+    double beta;      // 2 C_v - D
+    double inv_pr;    // 1/Pr
+    double mu_inf;
+    int law;          // SLLBM_SUTHERLAND / SLLBM_CONSTANT
+};
+
+// ---------------------------------------------------------------------------
+// Launchers (kernels.hip).  All return hipError_t of the launch.
+// ---------------------------------------------------------------------------
+
+int upload_velocity_constants(const VelocitySet &vs);
+
+template <typename S>
+struct Launch {
+    // fused: out = C(S(in)); also writes S(in) to pre_out if not null
+    static hipError_t stream_collide(const Geometry &g, const StreamTables &t, const CollisionParams &cp,
+                                     const S *in, S *out, S *pre_out, hipStream_t st);
+    static hipError_t stream_only(const Geometry &g, const StreamTables &t, const S *in, S *out,
+                                  hipStream_t st);
+    static hipError_t collide_only(const Geometry &g, const CollisionParams &cp, S *state, hipStream_t st);
+    static hipError_t init_equilibrium(const Geometry &g, const CollisionParams &cp, const double *rho,
+                                       const double *u, const double *T, S *state, hipStream_t st);
+    static hipError_t moments(const Geometry &g, const CollisionParams &cp, const S *state, double *rho,
+                              double *u, double *T, hipStream_t st);
+    static hipError_t totals(const Geometry &g, const CollisionParams &cp, const S *state,
+                             const double *nodew, double *partials, int nblocks, double *out5,
+                             hipStream_t st);
+    static hipError_t loss(const Geometry &g, const S *state, const double *dmat, const double *ccw,
+                           const double *h, double *scratch_rho, double *scratch_u, double *partials,
+                           int nblocks, double *out1, hipStream_t st);
+    static hipError_t loss_grad(const Geometry &g, const S *state, const double *dmat, const double *ccw,
+                                const double *nodew, const double *h, double *scratch_rho,
+                                double *scratch_u, double *scratch_div, S *lam, hipStream_t st);
+    static hipError_t adjoint_step(const Geometry &g, const StreamTables &t, const CollisionParams &cp,
+                                   const S *state_n, const S *lam_next, S *lam_out, double *dmu_partials,
+                                   int nblocks, double *dmu, hipStream_t st);
+    static hipError_t init_equilibrium_vjp(const Geometry &g, const CollisionParams &cp, const double *rho,
+                                           const double *u, const double *T, const S *lam0, double *drho,
+                                           double *du, double *dT, hipStream_t st);
+};
+
+size_t stream_smem_bytes(const Geometry &g, const StreamTables &t, size_t elem);
+int tile_nodes(const Geometry &g);
+int blocks_for(const Geometry &g);
+
+}  // namespace sllbm

@@ -1,0 +1,268 @@
+"""ctypes binding of ``libsllbm.so`` (C ABI in ``include/sllbm.h``).
+
+Argument marshalling only: every computation runs in the HIP library.  Device
+buffers are torch tensors on the context's device; pointers are passed as
+integers.  The library must be built (``python -m paper_2012_05537_amd.build``)
+before use; loading fails loudly otherwise.
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsllbm.so")
+
+Q = 45
+OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ENONFINITE = range(6)
+SUTHERLAND, CONSTANT = 0, 1
+FP64, FP32_MIXED = 0, 1
+
+_ERRNAMES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE", ESTATE: "ESTATE", ENONFINITE: "ENONFINITE"}
+
+
+class SllbmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_ERRNAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Config(ctypes.Structure):
+    _fields_ = [
+        ("n_el", ctypes.c_int32 * 3),
+        ("order", ctypes.c_int32),
+        ("velocity_set", ctypes.c_int32),
+        ("viscosity_law", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("device", ctypes.c_int32),
+        ("length", ctypes.c_double * 3),
+        ("dt", ctypes.c_double),
+        ("gamma", ctypes.c_double),
+        ("prandtl", ctypes.c_double),
+        ("mu_inf", ctypes.c_double),
+    ]
+
+
+_lib = None
+
+_VP = ctypes.c_void_p
+_SIGS = {
+    "sllbm_create": (ctypes.c_int, [ctypes.POINTER(Config), ctypes.POINTER(_VP)]),
+    "sllbm_destroy": (ctypes.c_int, [_VP]),
+    "sllbm_set_stream": (ctypes.c_int, [_VP, _VP]),
+    "sllbm_last_error": (ctypes.c_char_p, [_VP]),
+    "sllbm_num_nodes": (ctypes.c_int64, [_VP]),
+    "sllbm_state_bytes": (ctypes.c_int64, [_VP]),
+    "sllbm_velocity_set": (ctypes.c_int, [_VP, _VP]),
+    "sllbm_node_coords": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
+    "sllbm_set_viscosity": (ctypes.c_int, [_VP, ctypes.c_double]),
+    "sllbm_init_equilibrium": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
+    "sllbm_set_state": (ctypes.c_int, [_VP, _VP]),
+    "sllbm_get_state": (ctypes.c_int, [_VP, _VP]),
+    "sllbm_step": (ctypes.c_int, [_VP, ctypes.c_int32]),
+    "sllbm_step_record": (ctypes.c_int, [_VP, ctypes.c_int32, _VP, ctypes.c_int64]),
+    "sllbm_moments": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
+    "sllbm_totals": (ctypes.c_int, [_VP, _VP]),
+    "sllbm_loss": (ctypes.c_int, [_VP, _VP, _VP]),
+    "sllbm_loss_grad": (ctypes.c_int, [_VP, _VP, _VP]),
+    "sllbm_adjoint_step": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP]),
+    "sllbm_init_equilibrium_vjp": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
+    "sllbm_stream": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int32]),
+    "sllbm_collide": (ctypes.c_int, [_VP, _VP]),
+}
+
+EXPORTED = tuple(_SIGS)
+
+
+def load_library(path=LIB_PATH):
+    """Load libsllbm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise RuntimeError(f"{path} not found: build it with `python -m paper_2012_05537_amd.build`")
+        lib = ctypes.CDLL(path)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def velocity_set():
+    """(xi (45, 3), w (45,)) as float64 tensors on the CPU."""
+    lib = load_library()
+    xi = (ctypes.c_double * (3 * Q))()
+    w = (ctypes.c_double * Q)()
+    n = lib.sllbm_velocity_set(ctypes.addressof(xi), ctypes.addressof(w))
+    assert n == Q
+    return torch.tensor(list(xi), dtype=torch.float64).reshape(Q, 3), torch.tensor(list(w), dtype=torch.float64)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return t.data_ptr()
+
+
+class SLLBM:
+    """One simulation context on one GPU (a thin owner of ``sllbm_ctx*``)."""
+
+    def __init__(self, n_el, order, dt, mu_inf, gamma=1.4, prandtl=0.71, length=2 * 3.141592653589793,
+                 viscosity_law=SUTHERLAND, precision=FP64, device=0):
+        lib = load_library()
+        if isinstance(n_el, int):
+            n_el = (n_el, n_el, n_el)
+        if isinstance(length, (int, float)):
+            length = (length, length, length)
+        cfg = Config()
+        cfg.n_el[:] = [int(v) for v in n_el]
+        cfg.order = int(order)
+        cfg.velocity_set = Q
+        cfg.viscosity_law = int(viscosity_law)
+        cfg.precision = int(precision)
+        cfg.device = int(device)
+        cfg.length[:] = [float(v) for v in length]
+        cfg.dt = float(dt)
+        cfg.gamma = float(gamma)
+        cfg.prandtl = float(prandtl)
+        cfg.mu_inf = float(mu_inf)
+        self.cfg = cfg
+        self._lib = lib
+        h = _VP()
+        rc = lib.sllbm_create(ctypes.byref(cfg), ctypes.byref(h))
+        if rc != OK:
+            raise SllbmError(rc, lib.sllbm_last_error(None).decode())
+        self._h = h
+        self.device = torch.device("cuda", int(device))
+        self.dtype = torch.float64 if precision == FP64 else torch.float32
+        self.nodes = lib.sllbm_num_nodes(h)
+        self.shape = (cfg.n_el[2] * order, cfg.n_el[1] * order, cfg.n_el[0] * order)
+        self.state_bytes = lib.sllbm_state_bytes(h)
+        self._stream = None
+
+    # -- plumbing ---------------------------------------------------------
+    def _check(self, rc):
+        if rc != OK:
+            raise SllbmError(rc, self._lib.sllbm_last_error(self._h).decode())
+
+    def _sync_stream(self):
+        s = torch.cuda.current_stream(self.device).cuda_stream
+        if s != self._stream:
+            self._check(self._lib.sllbm_set_stream(self._h, s))
+            self._stream = s
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.sllbm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def empty_state(self):
+        return torch.empty((2, Q, self.nodes), dtype=self.dtype, device=self.device)
+
+    def _state_arg(self, t):
+        if t.dtype != self.dtype or t.device != self.device or t.numel() != 2 * Q * self.nodes:
+            raise ValueError("state must be a contiguous (2, 45, N) tensor of the storage dtype on the device")
+        return _ptr(t)
+
+    # -- C ABI, same names -------------------------------------------------
+    def node_coords(self):
+        n = [self.cfg.n_el[a] * self.cfg.order for a in range(3)]
+        arrs = [(ctypes.c_double * v)() for v in n]
+        self._check(self._lib.sllbm_node_coords(self._h, *[ctypes.addressof(a) for a in arrs]))
+        return tuple(torch.tensor(list(a), dtype=torch.float64) for a in arrs)
+
+    def set_viscosity(self, mu_inf):
+        self._check(self._lib.sllbm_set_viscosity(self._h, float(mu_inf)))
+        self.cfg.mu_inf = float(mu_inf)
+
+    def init_equilibrium(self, rho, u, T):
+        self._sync_stream()
+        f64 = dict(dtype=torch.float64, device=self.device)
+        rho, u, T = (x.to(**f64).contiguous() for x in (rho, u, T))
+        self._check(self._lib.sllbm_init_equilibrium(self._h, _ptr(rho), _ptr(u), _ptr(T)))
+
+    def set_state(self, state):
+        self._sync_stream()
+        self._check(self._lib.sllbm_set_state(self._h, self._state_arg(state)))
+
+    def get_state(self, out=None):
+        self._sync_stream()
+        out = self.empty_state() if out is None else out
+        self._check(self._lib.sllbm_get_state(self._h, self._state_arg(out)))
+        return out
+
+    def step(self, n=1):
+        self._sync_stream()
+        self._check(self._lib.sllbm_step(self._h, int(n)))
+
+    def step_record(self, n, states):
+        """states: (n, 2, 45, N) tensor receiving the pre-collision state after each step."""
+        self._sync_stream()
+        if states.shape[0] < n or not states.is_contiguous() or states.dtype != self.dtype:
+            raise ValueError("record buffer too small or wrong dtype")
+        self._check(self._lib.sllbm_step_record(self._h, int(n), _ptr(states), int(self.state_bytes)))
+
+    def moments(self):
+        self._sync_stream()
+        f64 = dict(dtype=torch.float64, device=self.device)
+        rho = torch.empty(self.nodes, **f64)
+        u = torch.empty((3, self.nodes), **f64)
+        T = torch.empty(self.nodes, **f64)
+        self._check(self._lib.sllbm_moments(self._h, _ptr(rho), _ptr(u), _ptr(T)))
+        return rho, u, T
+
+    def totals(self):
+        self._sync_stream()
+        out = (ctypes.c_double * 5)()
+        self._check(self._lib.sllbm_totals(self._h, ctypes.addressof(out)))
+        return list(out)
+
+    def loss(self, state):
+        self._sync_stream()
+        out = ctypes.c_double()
+        self._check(self._lib.sllbm_loss(self._h, self._state_arg(state), ctypes.addressof(out)))
+        return out.value
+
+    def loss_grad(self, state, out=None):
+        self._sync_stream()
+        out = self.empty_state() if out is None else out
+        self._check(self._lib.sllbm_loss_grad(self._h, self._state_arg(state), self._state_arg(out)))
+        return out
+
+    def adjoint_step(self, state_n, lam_next, lam_out=None, dmu=None):
+        self._sync_stream()
+        lam_out = self.empty_state() if lam_out is None else lam_out
+        self._check(self._lib.sllbm_adjoint_step(self._h, self._state_arg(state_n), self._state_arg(lam_next),
+                                                 self._state_arg(lam_out), _ptr(dmu)))
+        return lam_out
+
+    def init_equilibrium_vjp(self, rho, u, T, lam0):
+        self._sync_stream()
+        f64 = dict(dtype=torch.float64, device=self.device)
+        rho, u, T = (x.to(**f64).contiguous() for x in (rho, u, T))
+        drho = torch.empty(self.nodes, **f64)
+        du = torch.empty((3, self.nodes), **f64)
+        dT = torch.empty(self.nodes, **f64)
+        self._check(self._lib.sllbm_init_equilibrium_vjp(self._h, _ptr(rho), _ptr(u), _ptr(T),
+                                                         self._state_arg(lam0), _ptr(drho), _ptr(du), _ptr(dT)))
+        return drho, du, dT
+
+    def stream(self, state, transpose=False, out=None):
+        self._sync_stream()
+        out = self.empty_state() if out is None else out
+        self._check(self._lib.sllbm_stream(self._h, self._state_arg(state), self._state_arg(out), int(transpose)))
+        return out
+
+    def collide(self, state):
+        self._sync_stream()
+        self._check(self._lib.sllbm_collide(self._h, self._state_arg(state)))
+        return state

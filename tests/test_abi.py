@@ -1,0 +1,82 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every symbol declared in include/sllbm.h, validates configurations before
+touching a device, and returns the same velocity set as the oracle."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "sllbm.h")).read()
+    return sorted(set(re.findall(r"\b(sllbm_[a-z_0-9]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2012_05537_amd import sllbm
+    return sllbm.load_library()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = _declared()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), n
+    from paper_2012_05537_amd import sllbm
+    assert sorted(sllbm.EXPORTED) == names
+
+
+def test_velocity_set_matches_oracle(oracle):
+    from paper_2012_05537_amd import sllbm
+    xi, w = sllbm.velocity_set()
+    xo, wo = oracle.velocity_set()
+    assert np.allclose(xi.numpy(), xo, rtol=0, atol=1e-15)
+    assert np.allclose(w.numpy(), wo, rtol=0, atol=1e-17)
+
+
+def _cfg(**kw):
+    from paper_2012_05537_amd.sllbm import Config
+    c = Config()
+    c.n_el[:] = [2, 2, 2]
+    c.order = 2
+    c.velocity_set = 45
+    c.viscosity_law = 0
+    c.precision = 0
+    c.device = 0
+    c.length[:] = [1.0, 1.0, 1.0]
+    c.dt = 0.1
+    c.gamma = 1.4
+    c.prandtl = 0.71
+    c.mu_inf = 0.01
+    for k, v in kw.items():
+        if k in ("n_el", "length"):
+            getattr(c, k)[:] = v
+        else:
+            setattr(c, k, v)
+    return c
+
+
+@pytest.mark.parametrize("bad", [
+    dict(order=0), dict(order=7), dict(n_el=[0, 2, 2]), dict(length=[1.0, -1.0, 1.0]), dict(dt=0.0),
+    dict(dt=float("nan")), dict(gamma=1.0), dict(prandtl=0.0), dict(mu_inf=-1.0), dict(velocity_set=27),
+    dict(viscosity_law=5), dict(precision=3), dict(n_el=[1 << 20, 2, 2]),
+])
+def test_invalid_config_is_rejected(lib, bad):
+    h = ctypes.c_void_p()
+    rc = lib.sllbm_create(ctypes.byref(_cfg(**bad)), ctypes.byref(h))
+    assert rc == 1                       # SLLBM_EINVAL
+    assert h.value is None
+    assert len(lib.sllbm_last_error(None)) > 0
+
+
+def test_null_arguments(lib):
+    assert lib.sllbm_create(None, None) == 1
+    assert lib.sllbm_destroy(None) == 0
+    assert lib.sllbm_num_nodes(None) == -1
+    assert lib.sllbm_step(None, 1) == 1
+    assert lib.sllbm_velocity_set(None, None) == 1

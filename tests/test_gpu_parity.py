@@ -1,0 +1,231 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Bar (FP64): max-abs error relative to the max magnitude of the oracle's
+array, <= 1e-12, for populations, moments and totals.  FP32-mixed runs are
+checked against the stated mixed-precision tolerance.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import Q, make_pair, workload_pair, tgv_init, to_np, to_dev, rel_err, require_gpu
+from paper_2012_05537_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def test_node_coords_match(oracle):
+    ctx, cfg = make_pair(oracle, (3, 2, 5), 4, 0.1, 0.01)
+    for a, b in zip(ctx.node_coords(), oracle.node_coords(cfg)):
+        assert np.allclose(a.numpy(), b, rtol=0, atol=1e-14)
+
+
+# (n_el, p, dt, length): ragged tiles, single-cell axes, large departure shifts
+STREAM_CASES = [
+    ((4, 4, 4), 2, 0.41, 2 * math.pi),
+    ((5, 3, 2), 4, 0.37, 2 * math.pi),
+    ((3, 3, 3), 3, 0.9, 2 * math.pi),        # shifts of several cells
+    ((7, 1, 2), 4, 0.05, 2 * math.pi),       # single-cell periodic axis
+    ((2, 3, 4), 1, 0.2, 2 * math.pi),        # p = 1
+    ((3, 2, 2), 5, 0.3, (2.0, 3.0, 4.5)),   # p = 5, anisotropic cells
+    ((2, 2, 3), 6, 0.25, 2 * math.pi),      # p = 6
+]
+
+
+@pytest.mark.parametrize("n_el,p,dt,length", STREAM_CASES)
+def test_stream_matches_oracle(oracle, n_el, p, dt, length):
+    _say(f"stream parity n_el={n_el} p={p} dt={dt}")
+    ctx, cfg = make_pair(oracle, n_el, p, dt, 0.01, length=length)
+    rng = np.random.default_rng(sum(n_el) * 10 + p)
+    N = oracle.num_nodes(cfg)
+    f = rng.normal(size=(Q, N))
+    g = rng.normal(size=(Q, N))
+    out = ctx.stream(to_dev(ctx, f, g))
+    fo, go = oracle.stream(cfg, f, g)
+    F, G = to_np(out)
+    assert rel_err(F, fo) < TOL64 and rel_err(G, go) < TOL64
+
+
+@pytest.mark.parametrize("n_el,p,dt,length", STREAM_CASES[:4])
+def test_transposed_stream_is_adjoint(oracle, n_el, p, dt, length):
+    """<S x, y> = <x, S^T y> with the library's transposed gather."""
+    ctx, cfg = make_pair(oracle, n_el, p, dt, 0.01, length=length)
+    rng = np.random.default_rng(7)
+    N = oracle.num_nodes(cfg)
+    x = rng.normal(size=(2, Q, N))
+    y = rng.normal(size=(2, Q, N))
+    Sx = ctx.stream(to_dev(ctx, x[0], x[1])).cpu().numpy()
+    STy = ctx.stream(to_dev(ctx, y[0], y[1]), transpose=True).cpu().numpy()
+    lhs = np.einsum("pin,pin->pi", Sx, y)
+    rhs = np.einsum("pin,pin->pi", x, STy)
+    assert np.allclose(lhs, rhs, rtol=1e-12, atol=1e-9)
+
+
+@pytest.mark.parametrize("law,pr", [(0, 0.71), (1, 1.0), (0, 2.0)])
+def test_collide_matches_oracle(oracle, law, pr):
+    _say(f"collide parity law={law} Pr={pr}")
+    ctx, cfg = make_pair(oracle, (3, 2, 2), 2, 0.07, 0.013, prandtl=pr, law=law)
+    xs, ys, zs = oracle.node_coords(cfg)
+    rho, u, T = inputs.tgv_fields(xs, ys, zs, 0.9, 1.4)
+    f, g = oracle.init_equilibrium(cfg, rho, u, T)
+    rng = np.random.default_rng(3)
+    _, w = oracle.velocity_set()
+    f = f * (1 + 0.03 * rng.normal(size=f.shape))
+    g = g * (1 + 0.03 * rng.normal(size=g.shape))
+    st = to_dev(ctx, f, g)
+    ctx.collide(st)
+    fo, go = oracle.collide(cfg, f, g)
+    F, G = to_np(st)
+    assert rel_err(F, fo) < TOL64 and rel_err(G, go) < TOL64
+
+
+def test_init_and_moments_match_oracle(oracle):
+    w, ctx, cfg = workload_pair(oracle, "c1")
+    f, g = tgv_init(oracle, ctx, cfg, w["Ma"], w["gamma"])
+    F, G = to_np(ctx.get_state())
+    assert rel_err(F, f) < TOL64 and rel_err(G, g) < TOL64
+    rho, u, T = ctx.moments()
+    r0, u0, T0 = oracle.moments(cfg, f, g)
+    assert rel_err(rho.cpu().numpy(), r0) < TOL64
+    assert rel_err(u.cpu().numpy(), u0) < TOL64
+    assert rel_err(T.cpu().numpy(), T0) < TOL64
+    tot = np.array(ctx.totals())
+    tref = oracle.totals(cfg, f, g)
+    assert np.all(np.abs(tot - tref) <= TOL64 * np.max(np.abs(tref)))
+
+
+@pytest.mark.parametrize("nsteps", [1, 2, 10])
+def test_c1_steps_match_oracle(oracle, nsteps):
+    """4^3 cells, p = 2, TGV Ma 0.5 Re 100 CFL 2 (the small FP64 workload)."""
+    _say(f"c1 parity {nsteps} steps")
+    w, ctx, cfg = workload_pair(oracle, "c1")
+    f, g = tgv_init(oracle, ctx, cfg, w["Ma"], w["gamma"])
+    ctx.step(nsteps)
+    fo, go = oracle.step(cfg, f, g, nsteps)
+    F, G = to_np(ctx.get_state())
+    assert rel_err(F, fo) < TOL64 and rel_err(G, go) < TOL64
+    rho, u, T = ctx.moments()
+    r0, u0, T0 = oracle.moments(cfg, fo, go)
+    for a, b in ((rho, r0), (u, u0), (T, T0)):
+        assert rel_err(a.cpu().numpy(), b) < TOL64
+
+
+def test_step_split_equals_step_total(oracle):
+    """step(3); step(4) == step(7) bitwise; get_state in between changes nothing."""
+    w, ctx, cfg = workload_pair(oracle, "c1")
+    tgv_init(oracle, ctx, cfg, w["Ma"], w["gamma"])
+    ctx.step(3)
+    mid = ctx.get_state()
+    ctx.step(4)
+    a = ctx.get_state()
+    ctx.set_state(mid)
+    ctx.step(4)
+    b = ctx.get_state()
+    assert torch.equal(a, b)
+    w2, ctx2, _ = workload_pair(oracle, "c1")
+    tgv_init(oracle, ctx2, cfg, w["Ma"], w["gamma"])
+    ctx2.step(7)
+    assert torch.equal(ctx2.get_state(), a)
+
+
+def test_step_record_matches_get_state(oracle):
+    w, ctx, cfg = workload_pair(oracle, "c1")
+    tgv_init(oracle, ctx, cfg, w["Ma"], w["gamma"])
+    rec = torch.empty((4, 2, Q, ctx.nodes), dtype=ctx.dtype, device=ctx.device)
+    s0 = ctx.get_state()
+    ctx.step_record(4, rec)
+    ctx2 = make_pair(oracle, w["n_el"], w["p"], w["dt"], w["mu_inf"], gamma=w["gamma"], prandtl=w["Pr"])[0]
+    ctx2.set_state(s0)
+    for k in range(4):
+        ctx2.step(1)
+        assert torch.equal(ctx2.get_state(), rec[k])
+
+
+def test_uniform_flow_stays_uniform_gpu(oracle):
+    ctx, cfg = make_pair(oracle, (3, 2, 4), 4, 0.2, 0.02)
+    N = ctx.nodes
+    dev = ctx.device
+    u = torch.tensor([0.3, -0.2, 0.1], dtype=torch.float64, device=dev)[:, None].expand(3, N).contiguous()
+    ctx.init_equilibrium(torch.ones(N, dtype=torch.float64, device=dev), u, torch.ones(N, dtype=torch.float64,
+                                                                                          device=dev))
+    s0 = ctx.get_state()
+    ctx.step(5)
+    assert float((ctx.get_state() - s0).abs().max()) < 1e-13
+
+
+def test_c2_one_step_sampled_nodes(oracle):
+    """16^3 cells, p = 4 (64^3 nodes), Ma 1.25 Re 1600, CFL 1/5/10: one step at
+    full size, in the launch configuration of the benchmark, checked at
+    sampled nodes that the oracle evaluates one by one."""
+    for cfl in (1.0, 5.0, 10.0):
+        _say(f"c2 sampled parity cfl={cfl}")
+        w, ctx, cfg = workload_pair(oracle, "c2", cfl=cfl)
+        f, g = tgv_init(oracle, ctx, cfg, w["Ma"], w["gamma"])
+        ctx.step(1)
+        F, G = to_np(ctx.get_state())
+        rng = np.random.default_rng(int(cfl))
+        nodes = np.concatenate([[0, ctx.nodes - 1], rng.integers(0, ctx.nodes, 14)])
+        fs, gs = oracle.step_at_nodes(cfg, f, g, nodes)
+        scale = max(np.abs(f).max(), 1.0)
+        assert np.max(np.abs(F[:, nodes].T - fs)) < TOL64 * scale
+        assert np.max(np.abs(G[:, nodes].T - gs)) < TOL64 * np.abs(g).max()
+
+
+def test_c2_first_steps_full_grid(oracle):
+    """64^3 nodes, CFL 1: three full steps against the whole-grid oracle."""
+    _say("c2 full-grid parity, 3 steps")
+    w, ctx, cfg = workload_pair(oracle, "c2", cfl=1.0)
+    f, g = tgv_init(oracle, ctx, cfg, w["Ma"], w["gamma"])
+    ctx.step(3)
+    fo, go = oracle.step(cfg, f, g, 3)
+    F, G = to_np(ctx.get_state())
+    assert rel_err(F, fo) < TOL64 and rel_err(G, go) < TOL64
+
+
+def test_deterministic(oracle):
+    w, ctx, cfg = workload_pair(oracle, "c1")
+    tgv_init(oracle, ctx, cfg, w["Ma"], w["gamma"])
+    ctx.step(5)
+    a = ctx.get_state()
+    ta = ctx.totals()
+    tgv_init(oracle, ctx, cfg, w["Ma"], w["gamma"])
+    ctx.step(5)
+    assert torch.equal(a, ctx.get_state())
+    assert ta == ctx.totals()
+
+
+def test_zero_steps_is_identity(oracle):
+    w, ctx, cfg = workload_pair(oracle, "c1")
+    tgv_init(oracle, ctx, cfg, w["Ma"], w["gamma"])
+    s0 = ctx.get_state()
+    ctx.step(0)
+    assert torch.equal(s0, ctx.get_state())
+
+
+def test_fp32_mixed_matches_oracle(oracle):
+    """FP32 populations vs the FP64 oracle on c1: moments within 1e-5."""
+    _say("fp32 mixed c1 parity")
+    w, ctx, cfg = workload_pair(oracle, "c1", precision=1)
+    f, g = tgv_init(oracle, ctx, cfg, w["Ma"], w["gamma"])
+    ctx.step(10)
+    fo, go = oracle.step(cfg, f, g, 10)
+    rho, u, T = ctx.moments()
+    r0, u0, T0 = oracle.moments(cfg, fo, go)
+    assert rel_err(rho.cpu().numpy(), r0) < 1e-5
+    assert rel_err(u.cpu().numpy(), u0) < 1e-5
+    assert rel_err(T.cpu().numpy(), T0) < 1e-5
