@@ -113,7 +113,7 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="c2", help="workload key (c1..c5)")
-    ap.add_argument("--cfl", type=float, default=5.0)
+    ap.add_argument("--cfl", type=float, default=1.0)
     ap.add_argument("--precision", choices=["fp64", "fp32"], default=None)
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -30,6 +30,9 @@ struct sllbm_ctx {
     AxisTables htab[2];           // 0: forward streaming, 1: transposed
     StreamTables dtab[2]{};
     CollisionParams cp{};
+    Geometry fgeo{};              // tiling of the fused kernel (compile-time tiles per order)
+    int32_t *d_omin = nullptr, *d_lstar = nullptr;
+    void *d_fw = nullptr;         // fused-table weights, storage type
     hipStream_t stream = nullptr;
     size_t elem = 8;
     // State buffers.  In MODE_PRE buf[cur] holds the pre-collision state X_k.
@@ -98,6 +101,9 @@ void free_ctx(sllbm_ctx *c)
         (void)hipFree(c->d_lo[k]);
         (void)hipFree(c->d_span[k]);
     }
+    (void)hipFree(c->d_omin);
+    (void)hipFree(c->d_lstar);
+    (void)hipFree(c->d_fw);
     (void)hipFree(c->d_nodew);
     (void)hipFree(c->d_ccw);
     (void)hipFree(c->d_dmat);
@@ -130,6 +136,8 @@ void choose_tile(Geometry &g)
     }
     for (int a = 0; a < 3; ++a) g.ntile[a] = (g.nel[a] + g.TE[a] - 1) / g.TE[a];
 }
+
+bool is_fp64_cfg(const sllbm_ctx *c) { return c->cfg.precision == SLLBM_FP64; }
 
 template <typename S>
 int upload_tables(sllbm_ctx *c)
@@ -164,7 +172,38 @@ int upload_tables(sllbm_ctx *c)
             t.wmax[a] = (c->geo.TE[a] - 1) * p + smax;
         }
     }
+    std::vector<int32_t> omin, lstar;
+    std::vector<double> fw;
+    build_fused_tables(c->htab[0], omin, lstar, fw);
+    std::vector<S> fws(fw.begin(), fw.end());
+    hipError_t e;
+    if ((e = dalloc(&c->d_omin, omin.size() * sizeof(int32_t))) != hipSuccess ||
+        (e = dalloc(&c->d_lstar, lstar.size() * sizeof(int32_t))) != hipSuccess ||
+        (e = dalloc(reinterpret_cast<S **>(&c->d_fw), fws.size() * sizeof(S))) != hipSuccess)
+        return fail(c, SLLBM_ENOMEM, std::string("table allocation: ") + hipGetErrorString(e));
+    if ((e = hipMemcpy(c->d_omin, omin.data(), omin.size() * sizeof(int32_t), hipMemcpyHostToDevice)) !=
+            hipSuccess ||
+        (e = hipMemcpy(c->d_lstar, lstar.data(), lstar.size() * sizeof(int32_t), hipMemcpyHostToDevice)) !=
+            hipSuccess ||
+        (e = hipMemcpy(c->d_fw, fws.data(), fws.size() * sizeof(S), hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_fail(c, e, "table upload");
     return SLLBM_OK;
+}
+
+template <typename S>
+FusedTables<S> fused_tables(const sllbm_ctx *c)
+{
+    return FusedTables<S>{c->d_omin, c->d_lstar, static_cast<const S *>(c->d_fw)};
+}
+
+// forward streaming of in into out, with collision (and pre-collision copy) if asked
+hipError_t run_fused(sllbm_ctx *c, const void *in, void *out, void *pre, bool collide)
+{
+    if (is_fp64_cfg(c))
+        return launch_fused<double>(c->fgeo, fused_tables<double>(c), c->cp, static_cast<const double *>(in),
+                                    static_cast<double *>(out), static_cast<double *>(pre), collide, c->stream);
+    return launch_fused<float>(c->fgeo, fused_tables<float>(c), c->cp, static_cast<const float *>(in),
+                               static_cast<float *>(out), static_cast<float *>(pre), collide, c->stream);
 }
 
 bool is_fp64(const sllbm_ctx *c) { return c->cfg.precision == SLLBM_FP64; }
@@ -227,7 +266,7 @@ int sllbm_create(const sllbm_config *cfg, sllbm_ctx **out)
                           cfg->n_el[2] * cfg->order;
     if (static_cast<int64_t>(cfg->n_el[0]) * cfg->order > (1 << 20) ||
         static_cast<int64_t>(cfg->n_el[1]) * cfg->order > (1 << 20) ||
-        static_cast<int64_t>(cfg->n_el[2]) * cfg->order > (1 << 20) || nodes > (int64_t(1) << 40))
+        static_cast<int64_t>(cfg->n_el[2]) * cfg->order > (1 << 20) || nodes >= (int64_t(1) << 31))
         return fail(nullptr, SLLBM_EINVAL, "grid too large");
     if (!(cfg->dt > 0.0) || !std::isfinite(cfg->dt)) return fail(nullptr, SLLBM_EINVAL, "dt must be positive");
     if (!(cfg->gamma > 1.0)) return fail(nullptr, SLLBM_EINVAL, "gamma must exceed 1");
@@ -261,6 +300,9 @@ int sllbm_create(const sllbm_config *cfg, sllbm_ctx **out)
     }
     g.nodes = nodes;
     choose_tile(g);
+    c->fgeo = g;
+    fused_tile(g.p, c->fgeo.TE);
+    for (int a = 0; a < 3; ++a) c->fgeo.ntile[a] = (g.nel[a] + c->fgeo.TE[a] - 1) / c->fgeo.TE[a];
     c->cp.dt = cfg->dt;
     c->cp.Cv = 1.0 / (cfg->gamma - 1.0);
     c->cp.beta = 2.0 * c->cp.Cv - 3.0;
@@ -269,12 +311,6 @@ int sllbm_create(const sllbm_config *cfg, sllbm_ctx **out)
     c->cp.law = cfg->viscosity_law;
 
     build_velocity_set(c->vs);
-    if (upload_velocity_constants(c->vs) != 0) {
-        int rc = fail(nullptr, SLLBM_EDEVICE, "constant upload failed");
-        free_ctx(c);
-        delete c;
-        return rc;
-    }
     double h[3];
     for (int a = 0; a < 3; ++a) h[a] = cfg->length[a] / cfg->n_el[a];
     build_axis_tables(c->vs, g.p, h, cfg->dt, c->htab[0], c->htab[1]);
@@ -416,12 +452,8 @@ int sllbm_get_state(sllbm_ctx *ctx, void *state)
     hipError_t e;
     if (ctx->mode == MODE_PRE) {
         e = hipMemcpyAsync(state, ctx->buf[ctx->cur], sllbm_state_bytes(ctx), hipMemcpyDeviceToDevice, ctx->stream);
-    } else if (is_fp64(ctx)) {
-        e = Launch<double>::stream_only(ctx->geo, ctx->dtab[0], static_cast<const double *>(other(ctx)),
-                                        static_cast<double *>(state), ctx->stream);
     } else {
-        e = Launch<float>::stream_only(ctx->geo, ctx->dtab[0], static_cast<const float *>(other(ctx)),
-                                       static_cast<float *>(state), ctx->stream);
+        e = run_fused(ctx, other(ctx), state, nullptr, false);
     }
     return check_launch(ctx, e, "get_state");
 }
@@ -445,15 +477,7 @@ static int step_impl(sllbm_ctx *ctx, int32_t n, char *record, int64_t stride)
     }
     for (int32_t s = 0; s < n; ++s) {
         void *pre = record ? record + static_cast<int64_t>(s) * stride : nullptr;
-        if (is_fp64(ctx))
-            e = Launch<double>::stream_collide(ctx->geo, ctx->dtab[0], ctx->cp,
-                                               static_cast<const double *>(ctx->buf[ctx->cur]),
-                                               static_cast<double *>(other(ctx)), static_cast<double *>(pre),
-                                               ctx->stream);
-        else
-            e = Launch<float>::stream_collide(ctx->geo, ctx->dtab[0], ctx->cp,
-                                              static_cast<const float *>(ctx->buf[ctx->cur]),
-                                              static_cast<float *>(other(ctx)), static_cast<float *>(pre), ctx->stream);
+        e = run_fused(ctx, ctx->buf[ctx->cur], other(ctx), pre, true);
         if (e != hipSuccess) return hip_fail(ctx, e, "stream_collide");
         ctx->cur = 1 - ctx->cur;
     }
@@ -509,7 +533,8 @@ int sllbm_stream(sllbm_ctx *ctx, const void *in, void *out, int32_t transpose)
     if (!ctx) return SLLBM_EINVAL;
     if (!in || !out || in == out) return fail(ctx, SLLBM_EINVAL, "bad stream buffers");
     DeviceGuard guard(ctx->cfg.device);
-    const StreamTables &t = ctx->dtab[transpose ? 1 : 0];
+    if (!transpose) return check_launch(ctx, run_fused(ctx, in, out, nullptr, false), "stream");
+    const StreamTables &t = ctx->dtab[1];
     hipError_t e = is_fp64(ctx)
         ? Launch<double>::stream_only(ctx->geo, t, static_cast<const double *>(in), static_cast<double *>(out),
                                       ctx->stream)

@@ -1,174 +1,27 @@
-// HIP kernels (gfx950) of the SLLBM hot path: semi-Lagrangian streaming
-// (Eqs. (8)-(9)) fused with the local BGK + quasi-equilibrium collision
-// (Eq. (5), App. A, B, D), plus FP64 moments, totals and the equilibrium
-// initialisation.
+// HIP kernels (gfx950) of the SLLBM library besides the fused forward step
+// (fused.hip): the table-driven streaming used for the transposed operator
+// S^T (any tap count), collision of a whole state, equilibrium
+// initialisation, FP64 moments and deterministic totals.
 //
-// Streaming.  Psi_i = Iz (x) Iy (x) Ix is applied by sum factorisation.  A
-// thread block owns a tile of whole cells; for every velocity it stages the
+// Table-driven streaming.  Psi_i = Iz (x) Iy (x) Ix is applied by sum
+// factorisation: a thread block owns a tile of whole cells, stages the
 // tile's departure window of f_i and g_i in LDS (coalesced loads, x
-// fastest), interpolates along z, then y, then x, and keeps the streamed
-// value of its node in registers.  After all 45 velocities the node's 90
-// pre-collision values are collided in registers and written once.
-//
-// Collision.  Moments, temperature, Sutherland viscosity, tau and tau_Pr are
-// computed in double for both storage types.  The equilibrium uses the
-// scalar form of the fourth-order Hermite series: with c = xi.u,
-//   f_i^eq = w_i rho (A0 + c A1 + c^2 A2 + c^3/6 + c^4/24),
-// where A0..A2 depend on |u|^2, T - 1 and |xi_i|^2 only (equal to the tensor
-// contraction of Eq. (6) term by term).  The quasi-equilibrium term contracts
-// the centred third moment of each population (10 unique components) with
-// (w_i/3!) H^(3)_i; the centred third moment of the equilibrium is zero.
+// fastest), interpolates along z, then y, then x, and keeps the result of
+// its node in registers; every axis row is a list of (offset, weight) taps.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
 
+#include "collision.h"
 #include "sllbm_internal.h"
+#include "velset.h"
 
 namespace sllbm {
-
-__constant__ double c_xi[Q][3];
-__constant__ double c_w[Q];
-__constant__ double c_x2[Q];
-__constant__ double c_h3[Q][10];   // (w_i/6) * multiplicity * H3 component, unique (a<=b<=c) order
-
-constexpr double SUTHERLAND_S = 0.40417;
-
-int upload_velocity_constants(const VelocitySet &vs)
-{
-    double xi[Q][3], w[Q], x2[Q], h3[Q][10];
-    static const int idx[10][3] = {{0, 0, 0}, {0, 0, 1}, {0, 0, 2}, {0, 1, 1}, {0, 1, 2},
-                                   {0, 2, 2}, {1, 1, 1}, {1, 1, 2}, {1, 2, 2}, {2, 2, 2}};
-    static const double mult[10] = {1, 3, 3, 3, 6, 3, 1, 3, 3, 1};
-    for (int i = 0; i < Q; ++i) {
-        const double *x = vs.xi[i];
-        for (int k = 0; k < 3; ++k) xi[i][k] = x[k];
-        w[i] = vs.w[i];
-        x2[i] = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
-        for (int m = 0; m < 10; ++m) {
-            int a = idx[m][0], b = idx[m][1], c = idx[m][2];
-            double h = x[a] * x[b] * x[c] - ((b == c ? x[a] : 0.0) + (a == c ? x[b] : 0.0) + (a == b ? x[c] : 0.0));
-            h3[i][m] = vs.w[i] / 6.0 * mult[m] * h;
-        }
-    }
-    if (hipMemcpyToSymbol(HIP_SYMBOL(c_xi), xi, sizeof(xi)) != hipSuccess) return -1;
-    if (hipMemcpyToSymbol(HIP_SYMBOL(c_w), w, sizeof(w)) != hipSuccess) return -1;
-    if (hipMemcpyToSymbol(HIP_SYMBOL(c_x2), x2, sizeof(x2)) != hipSuccess) return -1;
-    if (hipMemcpyToSymbol(HIP_SYMBOL(c_h3), h3, sizeof(h3)) != hipSuccess) return -1;
-    return 0;
-}
 
 __device__ __forceinline__ int pmod(int x, int n)
 {
     int r = x % n;
     return r < 0 ? r + n : r;
-}
-
-// ---------------------------------------------------------------------------
-// Collision of one node, populations in registers (Eq. (5) + App. D)
-// ---------------------------------------------------------------------------
-
-struct NodeMacro {
-    double rho, ux, uy, uz, T;
-};
-
-template <typename S>
-__device__ __forceinline__ NodeMacro node_macro(const S (&f)[Q], const S (&g)[Q], double Cv)
-{
-    double rho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0, K = 0.0;
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        const double fi = static_cast<double>(f[i]);
-        rho += fi;
-        jx = fma(fi, c_xi[i][0], jx);
-        jy = fma(fi, c_xi[i][1], jy);
-        jz = fma(fi, c_xi[i][2], jz);
-        K = fma(fi, c_x2[i], K) + static_cast<double>(g[i]);
-    }
-    NodeMacro m;
-    const double ir = 1.0 / rho;
-    m.rho = rho;
-    m.ux = jx * ir;
-    m.uy = jy * ir;
-    m.uz = jz * ir;
-    const double u2 = m.ux * m.ux + m.uy * m.uy + m.uz * m.uz;
-    m.T = (K * ir - u2) / (2.0 * Cv);       // 2 rho E = rho |u|^2 + 2 C_v rho T
-    return m;
-}
-
-__device__ __forceinline__ double viscosity(const CollisionParams &cp, double T)
-{
-    if (cp.law == SLLBM_CONSTANT) return cp.mu_inf;
-    return cp.mu_inf * (1.0 + SUTHERLAND_S) * T * sqrt(T) / (T + SUTHERLAND_S);
-}
-
-// equilibrium bracket coefficients (D = 3), see file header
-struct EqCoef {
-    double a0, a1, a2;
-};
-
-__device__ __forceinline__ EqCoef eq_coef(double u2, double th, double x2)
-{
-    EqCoef e;
-    e.a0 = 1.0 - 0.5 * u2 + 0.5 * th * (x2 - 3.0) + 0.125 * u2 * u2 - 0.25 * th * u2 * (x2 - 5.0) +
-           0.125 * th * th * (x2 * x2 - 10.0 * x2 + 15.0);
-    e.a1 = 1.0 - 0.5 * u2 + 0.5 * th * (x2 - 5.0);
-    e.a2 = 0.5 - 0.25 * u2 + 0.25 * th * (x2 - 7.0);
-    return e;
-}
-
-__device__ __forceinline__ double eq_bracket(const EqCoef &e, double c)
-{
-    return fma(c, fma(c, fma(c, fma(c, 1.0 / 24.0, 1.0 / 6.0), e.a2), e.a1), e.a0);
-}
-
-template <typename S>
-__device__ __forceinline__ void collide_node(S (&f)[Q], S (&g)[Q], const CollisionParams &cp)
-{
-    const NodeMacro m = node_macro(f, g, cp.Cv);
-    const double u2 = m.ux * m.ux + m.uy * m.uy + m.uz * m.uz;
-    const double P = m.rho * m.T;
-    const double mu = viscosity(cp, m.T);
-    const double tau = mu / (P * cp.dt) + 0.5;
-    const double tau_pr = (tau - 0.5) * cp.inv_pr + 0.5;
-    const double om = 1.0 / tau;
-    const double kap = om - 1.0 / tau_pr;
-
-    // centred third moments of f and g
-    double qf[10], qg[10];
-#pragma unroll
-    for (int k = 0; k < 10; ++k) qf[k] = qg[k] = 0.0;
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        const double dx = c_xi[i][0] - m.ux, dy = c_xi[i][1] - m.uy, dz = c_xi[i][2] - m.uz;
-        const double dxx = dx * dx, dyy = dy * dy, dzz = dz * dz;
-        const double mono[10] = {dxx * dx, dxx * dy, dxx * dz, dx * dyy, dx * dy * dz,
-                                 dx * dzz, dyy * dy, dyy * dz, dy * dzz, dzz * dz};
-        const double fi = static_cast<double>(f[i]), gi = static_cast<double>(g[i]);
-#pragma unroll
-        for (int k = 0; k < 10; ++k) {
-            qf[k] = fma(fi, mono[k], qf[k]);
-            qg[k] = fma(gi, mono[k], qg[k]);
-        }
-    }
-
-    const double th = m.T - 1.0;
-    const double betaT = cp.beta * m.T;
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        const double c = c_xi[i][0] * m.ux + c_xi[i][1] * m.uy + c_xi[i][2] * m.uz;
-        const EqCoef e = eq_coef(u2, th, c_x2[i]);
-        const double feq = c_w[i] * m.rho * eq_bracket(e, c);
-        const double geq = betaT * feq;
-        double fs = 0.0, gs = 0.0;
-#pragma unroll
-        for (int k = 0; k < 10; ++k) {
-            fs = fma(c_h3[i][k], qf[k], fs);
-            gs = fma(c_h3[i][k], qg[k], gs);
-        }
-        const double fi = static_cast<double>(f[i]), gi = static_cast<double>(g[i]);
-        f[i] = static_cast<S>(fi + om * (feq - fi) + kap * fs);
-        g[i] = static_cast<S>(gi + om * (geq - gi) + kap * gs);
-    }
 }
 
 // ---------------------------------------------------------------------------
@@ -346,10 +199,9 @@ __device__ __forceinline__ void stream_velocity(int i, const Geometry &geo, cons
 // Kernels
 // ---------------------------------------------------------------------------
 
-template <typename S, bool COLLIDE>
-__global__ void __launch_bounds__(256) k_stream_collide(Geometry geo, StreamTables tab, CollisionParams cp,
-                                                        const S *__restrict__ in, S *__restrict__ out,
-                                                        S *__restrict__ pre_out)
+template <typename S>
+__global__ void __launch_bounds__(256) k_stream_tab(Geometry geo, StreamTables tab, const S *__restrict__ in,
+                                                    S *__restrict__ out)
 {
     const TileInfo t = tile_info(geo);
     const StreamSmem<S> sm = carve_smem<S>(geo, tab);
@@ -363,14 +215,6 @@ __global__ void __launch_bounds__(256) k_stream_collide(Geometry geo, StreamTabl
     if (!t.valid) return;
     const int64_t node =
         (static_cast<int64_t>(t.X0[2] + t.lz) * geo.N[1] + (t.X0[1] + t.ly)) * geo.N[0] + t.X0[0] + t.lx;
-    if (pre_out != nullptr) {
-#pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            pre_out[static_cast<int64_t>(i) * N + node] = fv[i];
-            pre_out[static_cast<int64_t>(Q + i) * N + node] = gv[i];
-        }
-    }
-    if constexpr (COLLIDE) collide_node<S>(fv, gv, cp);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         out[static_cast<int64_t>(i) * N + node] = fv[i];
@@ -389,7 +233,7 @@ __global__ void __launch_bounds__(256) k_collide(int64_t N, CollisionParams cp, 
             f[i] = state[static_cast<int64_t>(i) * N + n];
             g[i] = state[static_cast<int64_t>(Q + i) * N + n];
         }
-        collide_node<S>(f, g, cp);
+        collide_regs<S>(f, g, cp);
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
             state[static_cast<int64_t>(i) * N + n] = f[i];
@@ -412,11 +256,30 @@ __global__ void __launch_bounds__(256) k_init_equilibrium(int64_t N, CollisionPa
         const double betaT = cp.beta * Tn;
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            const double c = c_xi[i][0] * ux + c_xi[i][1] * uy + c_xi[i][2] * uz;
-            const double feq = c_w[i] * r * eq_bracket(eq_coef(u2, th, c_x2[i]), c);
+            const double c = vs::T.xi[i][0] * ux + vs::T.xi[i][1] * uy + vs::T.xi[i][2] * uz;
+            const EqShell e = eq_shell(u2, th, vs::T.x2[i]);
+            const double br = fma(c, fma(c, fma(c, fma(c, 1.0 / 24.0, 1.0 / 6.0), e.a2), e.a1), e.a0);
+            const double feq = vs::T.w[i] * r * br;
             state[static_cast<int64_t>(i) * N + n] = static_cast<S>(feq);
             state[static_cast<int64_t>(Q + i) * N + n] = static_cast<S>(betaT * feq);
         }
+    }
+}
+
+// rho, j, 2 rho E of node n (Eq. (7)), in double
+template <typename S>
+__device__ __forceinline__ void node_sums(const S *__restrict__ state, int64_t N, int64_t n, double &rho,
+                                          double &jx, double &jy, double &jz, double &twoE)
+{
+    rho = jx = jy = jz = twoE = 0.0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const double fi = static_cast<double>(state[static_cast<int64_t>(i) * N + n]);
+        rho += fi;
+        jx = fma(fi, vs::T.xi[i][0], jx);
+        jy = fma(fi, vs::T.xi[i][1], jy);
+        jz = fma(fi, vs::T.xi[i][2], jz);
+        twoE = fma(fi, vs::T.x2[i], twoE) + static_cast<double>(state[static_cast<int64_t>(Q + i) * N + n]);
     }
 }
 
@@ -427,20 +290,16 @@ __global__ void __launch_bounds__(256) k_moments(int64_t N, CollisionParams cp, 
 {
     for (int64_t n = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; n < N;
          n += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-        S f[Q], g[Q];
-#pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            f[i] = state[static_cast<int64_t>(i) * N + n];
-            g[i] = state[static_cast<int64_t>(Q + i) * N + n];
-        }
-        const NodeMacro m = node_macro(f, g, cp.Cv);
-        if (rho) rho[n] = m.rho;
+        double r, jx, jy, jz, twoE;
+        node_sums(state, N, n, r, jx, jy, jz, twoE);
+        const double ux = jx / r, uy = jy / r, uz = jz / r;
+        if (rho) rho[n] = r;
         if (u) {
-            u[n] = m.ux;
-            u[N + n] = m.uy;
-            u[2 * N + n] = m.uz;
+            u[n] = ux;
+            u[N + n] = uy;
+            u[2 * N + n] = uz;
         }
-        if (T) T[n] = m.T;
+        if (T) T[n] = (twoE / r - (ux * ux + uy * uy + uz * uz)) / (2.0 * cp.Cv);
     }
 }
 
@@ -480,16 +339,8 @@ __global__ void __launch_bounds__(256) k_totals_partial(Geometry geo, const S *_
         const int gy = static_cast<int>(r % geo.N[1]);
         const int gz = static_cast<int>(r / geo.N[1]);
         const double W = wx[gx] * wy[gy] * wz[gz];
-        double rho = 0, jx = 0, jy = 0, jz = 0, twoE = 0;
-#pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            const double fi = static_cast<double>(state[static_cast<int64_t>(i) * N + n]);
-            rho += fi;
-            jx = fma(fi, c_xi[i][0], jx);
-            jy = fma(fi, c_xi[i][1], jy);
-            jz = fma(fi, c_xi[i][2], jz);
-            twoE = fma(fi, c_x2[i], twoE) + static_cast<double>(state[static_cast<int64_t>(Q + i) * N + n]);
-        }
+        double rho, jx, jy, jz, twoE;
+        node_sums(state, N, n, rho, jx, jy, jz, twoE);
         acc[0] = fma(W, rho, acc[0]);
         acc[1] = fma(W, jx, acc[1]);
         acc[2] = fma(W, jy, acc[2]);
@@ -552,27 +403,13 @@ static hipError_t allow_smem(Kern kern, size_t smem)
 }
 
 template <typename S>
-hipError_t Launch<S>::stream_collide(const Geometry &g, const StreamTables &t, const CollisionParams &cp,
-                                     const S *in, S *out, S *pre_out, hipStream_t st)
-{
-    const size_t smem = stream_smem_bytes(g, t, sizeof(S));
-    hipError_t e = allow_smem(k_stream_collide<S, true>, smem);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_stream_collide<S, true>), dim3(blocks_for(g)), dim3(stream_block(g)), smem, st, g, t,
-                       cp, in, out, pre_out);
-    return hipGetLastError();
-}
-
-template <typename S>
 hipError_t Launch<S>::stream_only(const Geometry &g, const StreamTables &t, const S *in, S *out,
                                   hipStream_t st)
 {
     const size_t smem = stream_smem_bytes(g, t, sizeof(S));
-    hipError_t e = allow_smem(k_stream_collide<S, false>, smem);
+    hipError_t e = allow_smem(k_stream_tab<S>, smem);
     if (e != hipSuccess) return e;
-    CollisionParams cp{};
-    hipLaunchKernelGGL((k_stream_collide<S, false>), dim3(blocks_for(g)), dim3(stream_block(g)), smem, st, g,
-                       t, cp, in, out, static_cast<S *>(nullptr));
+    hipLaunchKernelGGL((k_stream_tab<S>), dim3(blocks_for(g)), dim3(stream_block(g)), smem, st, g, t, in, out);
     return hipGetLastError();
 }
 

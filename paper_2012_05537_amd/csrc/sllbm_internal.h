@@ -70,6 +70,16 @@ struct StreamTables {
     int wmax[3];           // largest window extent per axis for a full tile
 };
 
+// Tables of the fused forward kernel, for each velocity i and axis a:
+// omin = smallest departure-cell offset of the p rows, lstar = first row that
+// uses cell omin + 1 (p if none), w = the p x (p+1) Lagrange weights.
+template <typename S>
+struct FusedTables {
+    const int32_t *omin;    // [Q][3]
+    const int32_t *lstar;   // [Q][3]
+    const S *w;             // [Q][3][p][p+1]
+};
+
 struct CollisionParams {
     double dt;
     double Cv;        // 1/(gamma - 1)
@@ -83,13 +93,9 @@ struct CollisionParams {
 // Launchers (kernels.hip).  All return hipError_t of the launch.
 // ---------------------------------------------------------------------------
 
-int upload_velocity_constants(const VelocitySet &vs);
-
 template <typename S>
 struct Launch {
-    // fused: out = C(S(in)); also writes S(in) to pre_out if not null
-    static hipError_t stream_collide(const Geometry &g, const StreamTables &t, const CollisionParams &cp,
-                                     const S *in, S *out, S *pre_out, hipStream_t st);
+    // table-driven streaming (any tap count; used for the transpose)
     static hipError_t stream_only(const Geometry &g, const StreamTables &t, const S *in, S *out,
                                   hipStream_t st);
     static hipError_t collide_only(const Geometry &g, const CollisionParams &cp, S *state, hipStream_t st);
@@ -113,6 +119,13 @@ struct Launch {
                                            const double *u, const double *T, const S *lam0, double *drho,
                                            double *du, double *dT, hipStream_t st);
 };
+
+template <typename S>
+hipError_t launch_fused(const Geometry &g, const FusedTables<S> &t, const CollisionParams &cp, const S *in, S *out,
+                        S *pre, bool collide, hipStream_t st);
+void fused_tile(int p, int te[3]);
+void build_fused_tables(const AxisTables &fwd, std::vector<int32_t> &omin, std::vector<int32_t> &lstar,
+                        std::vector<double> &w);
 
 size_t stream_smem_bytes(const Geometry &g, const StreamTables &t, size_t elem);
 int tile_nodes(const Geometry &g);

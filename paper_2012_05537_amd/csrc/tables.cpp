@@ -9,82 +9,22 @@
 // tensor product of three 1-D operators, each described by p rows of (p+1)
 // taps; these rows are all that is stored.
 #include <algorithm>
-#include <array>
 #include <cmath>
 
 #include "sllbm_internal.h"
+#include "velset.h"
 
 namespace sllbm {
 
-namespace {
 
-using Vec3 = std::array<double, 3>;
-
-// Sign variants of the cyclic permutations of (a, b, c), without duplicates.
-std::vector<Vec3> signed_cycles(double a, double b, double c)
+// Degree-nine D3Q45 rule (Sec. II B), from the compile-time table shared with
+// the kernels (velset.h).
+void build_velocity_set(VelocitySet &out)
 {
-    std::vector<Vec3> out;
-    const Vec3 rot[3] = {{a, b, c}, {b, c, a}, {c, a, b}};
-    for (const Vec3 &r : rot) {
-        for (int s = 0; s < 8; ++s) {
-            Vec3 v{(s & 1) ? -r[0] : r[0], (s & 2) ? -r[1] : r[1], (s & 4) ? -r[2] : r[2]};
-            bool seen = std::any_of(out.begin(), out.end(), [&](const Vec3 &u) {
-                return std::fabs(u[0] - v[0]) + std::fabs(u[1] - v[1]) + std::fabs(u[2] - v[2]) < 1e-12;
-            });
-            if (!seen) out.push_back(v);
-        }
-    }
-    return out;
-}
-
-void normalise_and_sort(std::vector<Vec3> &dirs)
-{
-    for (Vec3 &v : dirs) {
-        double r = std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
-        for (double &c : v) c /= r;
-    }
-    // lexicographic order, coordinates closer than 1e-9 count as equal
-    std::sort(dirs.begin(), dirs.end(), [](const Vec3 &x, const Vec3 &y) {
-        for (int k = 0; k < 3; ++k)
-            if (std::fabs(x[k] - y[k]) > 1e-9) return x[k] < y[k];
-        return false;
-    });
-}
-
-}  // namespace
-
-// Degree-nine D3Q45 rule (Sec. II B): the origin, an icosahedron at radius
-// sqrt(3), the same icosahedron at radius sqrt(15), and its dual dodecahedron
-// at radius 3, with weights 28/135, 25/432, 1/2160 and 1/216.
-void build_velocity_set(VelocitySet &vs)
-{
-    const double phi = 0.5 * (1.0 + std::sqrt(5.0));
-    std::vector<Vec3> ico = signed_cycles(0.0, 1.0, phi);
-    std::vector<Vec3> dod = signed_cycles(1.0, 1.0, 1.0);
-    std::vector<Vec3> dod2 = signed_cycles(0.0, phi, 1.0 / phi);
-    dod.insert(dod.end(), dod2.begin(), dod2.end());
-    normalise_and_sort(ico);
-    normalise_and_sort(dod);
-    struct Shell { const std::vector<Vec3> *dirs; double radius, weight; };
-    const Shell shells[3] = {{&ico, std::sqrt(3.0), 25.0 / 432.0},
-                             {&ico, std::sqrt(15.0), 1.0 / 2160.0},
-                             {&dod, 3.0, 1.0 / 216.0}};
-    int q = 0;
-    vs.xi[0][0] = vs.xi[0][1] = vs.xi[0][2] = 0.0;
-    vs.w[q++] = 28.0 / 135.0;
-    for (const Shell &s : shells) {
-        for (const Vec3 &d : *s.dirs) {
-            for (int k = 0; k < 3; ++k) vs.xi[q][k] = s.radius * d[k];
-            vs.w[q++] = s.weight;
-        }
-    }
     for (int i = 0; i < Q; ++i) {
-        vs.opposite[i] = -1;
-        for (int j = 0; j < Q; ++j) {
-            double d = std::fabs(vs.xi[i][0] + vs.xi[j][0]) + std::fabs(vs.xi[i][1] + vs.xi[j][1]) +
-                       std::fabs(vs.xi[i][2] + vs.xi[j][2]);
-            if (d < 1e-12) vs.opposite[i] = j;
-        }
+        for (int k = 0; k < 3; ++k) out.xi[i][k] = vs::T.xi[i][k];
+        out.w[i] = vs::T.w[i];
+        out.opposite[i] = vs::T.opp[i];
     }
 }
 
@@ -217,6 +157,31 @@ void build_axis_tables(const VelocitySet &vs, int p, const double h[3], double d
             adj.span[i * 3 + a] = hi - lo + 1;
         }
     }
+}
+
+}  // namespace sllbm
+
+namespace sllbm {
+
+void build_fused_tables(const AxisTables &fwd, std::vector<int32_t> &omin, std::vector<int32_t> &lstar,
+                        std::vector<double> &w)
+{
+    const int p = fwd.p, K = fwd.K;
+    omin.assign(Q * 3, 0);
+    lstar.assign(Q * 3, p);
+    w.assign(Q * 3 * p * (p + 1), 0.0);
+    for (int i = 0; i < Q; ++i)
+        for (int a = 0; a < 3; ++a) {
+            const int base = (i * 3 + a) * p;
+            // departure cell of row l is off[l][0] / p; non-decreasing in l
+            const int o0 = fwd.off[base * K] / p;
+            omin[i * 3 + a] = o0;
+            for (int l = 0; l < p; ++l) {
+                const int o = fwd.off[(base + l) * K] / p - o0;
+                if (o == 1 && lstar[i * 3 + a] == p) lstar[i * 3 + a] = l;
+                for (int k = 0; k <= p; ++k) w[(base + l) * (p + 1) + k] = fwd.wt[(base + l) * K + k];
+            }
+        }
 }
 
 }  // namespace sllbm
