@@ -29,10 +29,6 @@ namespace sllbm {
 
 constexpr double SUTHERLAND_S = 0.40417;
 
-struct NodeState {
-    double rho, ux, uy, uz, T;
-};
-
 __device__ __forceinline__ double viscosity_of(const CollisionParams &cp, double T)
 {
     if (cp.law == SLLBM_CONSTANT) return cp.mu_inf;
@@ -110,94 +106,76 @@ __device__ __forceinline__ EqShell eq_shell(double u2, double th, double x2)
 
 constexpr double SHELL_X2[4] = {0.0, 3.0, 15.0, 9.0};
 
-template <typename S>
-__device__ __forceinline__ NodeState node_state(const RawMoments &rf, double G0, double Cv)
-{
-    NodeState n;
-    n.rho = rf.m0;
-    const double ir = 1.0 / n.rho;
-    n.ux = rf.m1[0] * ir;
-    n.uy = rf.m1[1] * ir;
-    n.uz = rf.m1[2] * ir;
-    const double u2 = n.ux * n.ux + n.uy * n.uy + n.uz * n.uz;
-    const double K = rf.m2[0] + rf.m2[3] + rf.m2[5] + G0;      // 2 rho E
-    n.T = (K * ir - u2) / (2.0 * Cv);
-    return n;
-}
 
+// Collision of one node whose two populations are held by a lane pair: the
+// even lane holds f (is_g = false), the odd lane g.  Each lane forms the raw
+// moments of its own population; the pair exchanges rho, j, and the energy
+// parts (tr M2[f] and M0[g]); each lane then builds Qbar of its own
+// population and relaxes it (g^eq = (2 C_v - D) T f^eq).  Both lanes of a
+// pair must be active.
 template <typename S>
-__device__ __forceinline__ void collide_regs(S (&f)[vs::Q], S (&g)[vs::Q], const CollisionParams &cp)
+__device__ __forceinline__ void collide_half(S (&v)[vs::Q], bool is_g, const CollisionParams &cp)
 {
-    using R = S;   // per-velocity arithmetic type
-    // f moments and Qbar[f]
-    RawMoments rm = raw_moments(f);
-    double G0 = static_cast<double>(g[0]);
-#pragma unroll
-    for (int q = 0; q < 22; ++q) G0 += static_cast<double>(g[vs::PAIRS.a[q]]) + static_cast<double>(g[vs::PAIRS.b[q]]);
-    const NodeState n = node_state<S>(rm, G0, cp.Cv);
-    const double u[3] = {n.ux, n.uy, n.uz};
-    double qf[10];
-    centred_third(rm, u, qf);
-    // g moments and Qbar[g]
-    rm = raw_moments(g);
-    double qg[10];
-    centred_third(rm, u, qg);
+    using R = S;
+    const RawMoments rm = raw_moments(v);
+    const double ktr = rm.m2[0] + rm.m2[3] + rm.m2[5];
+    const double p_m0 = __shfl_xor(rm.m0, 1);
+    const double p_j0 = __shfl_xor(rm.m1[0], 1);
+    const double p_j1 = __shfl_xor(rm.m1[1], 1);
+    const double p_j2 = __shfl_xor(rm.m1[2], 1);
+    const double p_tr = __shfl_xor(ktr, 1);
+    const double rho = is_g ? p_m0 : rm.m0;
+    const double ir = 1.0 / rho;
+    const double u[3] = {(is_g ? p_j0 : rm.m1[0]) * ir, (is_g ? p_j1 : rm.m1[1]) * ir,
+                         (is_g ? p_j2 : rm.m1[2]) * ir};
+    const double K = is_g ? p_tr + rm.m0 : ktr + p_m0;          // 2 rho E
+    const double u2 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    const double T = (K * ir - u2) / (2.0 * cp.Cv);
+    double qb[10];
+    centred_third(rm, u, qb);
 
-    const double u2 = n.ux * n.ux + n.uy * n.uy + n.uz * n.uz;
-    const double P = n.rho * n.T;
-    const double tau = viscosity_of(cp, n.T) / (P * cp.dt) + 0.5;
+    const double P = rho * T;
+    const double tau = viscosity_of(cp, T) / (P * cp.dt) + 0.5;
     const double tau_pr = (tau - 0.5) * cp.inv_pr + 0.5;
     const R om = static_cast<R>(1.0 / tau);
     const R kap = static_cast<R>(1.0 / tau - 1.0 / tau_pr);
-    const double th = n.T - 1.0;
-    const R betaT = static_cast<R>(cp.beta * n.T);
+    const double th = T - 1.0;
+    const R eqs = static_cast<R>(is_g ? cp.beta * T : 1.0);
 
     R A0[4], A1[4], A2[4];
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
         const EqShell e = eq_shell(u2, th, SHELL_X2[s]);
-        A0[s] = static_cast<R>(e.a0 * n.rho);
-        A1[s] = static_cast<R>(e.a1 * n.rho);
-        A2[s] = static_cast<R>(e.a2 * n.rho);
+        A0[s] = static_cast<R>(e.a0 * rho);
+        A1[s] = static_cast<R>(e.a1 * rho);
+        A2[s] = static_cast<R>(e.a2 * rho);
     }
-    const R rho6 = static_cast<R>(n.rho / 6.0), rho24 = static_cast<R>(n.rho / 24.0);
-    R qfr[10], qgr[10];
+    const R rho6 = static_cast<R>(rho / 6.0), rho24 = static_cast<R>(rho / 24.0);
+    R qr[10];
 #pragma unroll
-    for (int m = 0; m < 10; ++m) {
-        qfr[m] = static_cast<R>(qf[m]);
-        qgr[m] = static_cast<R>(qg[m]);
-    }
-    const R ux = static_cast<R>(n.ux), uy = static_cast<R>(n.uy), uz = static_cast<R>(n.uz);
-
-    // rest velocity: c = 0, h* = 0
+    for (int m = 0; m < 10; ++m) qr[m] = static_cast<R>(qb[m]);
+    const R ux = static_cast<R>(u[0]), uy = static_cast<R>(u[1]), uz = static_cast<R>(u[2]);
     {
-        const R feq = static_cast<R>(vs::T.w[0]) * A0[0];
-        const R fi = f[0], gi = g[0];
-        f[0] = fma(om, feq - fi, fi);
-        g[0] = fma(om, betaT * feq - gi, gi);
+        const R heq = eqs * static_cast<R>(vs::T.w[0]) * A0[0];
+        const R vi = v[0];
+        v[0] = fma(om, heq - vi, vi);
     }
 #pragma unroll
     for (int q = 0; q < 22; ++q) {
         const int i = vs::PAIRS.a[q], j = vs::PAIRS.b[q];
         const int s = vs::T.shell[i];
-        const R w = static_cast<R>(vs::T.w[i]);
         const R c = static_cast<R>(vs::T.xi[i][0]) * ux + static_cast<R>(vs::T.xi[i][1]) * uy +
                     static_cast<R>(vs::T.xi[i][2]) * uz;
         const R c2 = c * c;
         const R even = fma(c2, fma(c2, rho24, A2[s]), A0[s]);
         const R odd = c * fma(c2, rho6, A1[s]);
-        const R feq_i = w * (even + odd), feq_j = w * (even - odd);
-        R fs = 0, gs = 0;
+        const R we = eqs * static_cast<R>(vs::T.w[i]);
+        R hs = 0;
 #pragma unroll
-        for (int m = 0; m < 10; ++m) {
-            fs = fma(static_cast<R>(vs::H3.c[i][m]), qfr[m], fs);
-            gs = fma(static_cast<R>(vs::H3.c[i][m]), qgr[m], gs);
-        }
-        const R fi = f[i], fj = f[j], gi = g[i], gj = g[j];
-        f[i] = fma(kap, fs, fma(om, feq_i - fi, fi));
-        f[j] = fma(-kap, fs, fma(om, feq_j - fj, fj));
-        g[i] = fma(kap, gs, fma(om, betaT * feq_i - gi, gi));
-        g[j] = fma(-kap, gs, fma(om, betaT * feq_j - gj, gj));
+        for (int m = 0; m < 10; ++m) hs = fma(static_cast<R>(vs::H3.c[i][m]), qr[m], hs);
+        const R vi = v[i], vj = v[j];
+        v[i] = fma(kap, hs, fma(om, fma(we, even, we * odd) - vi, vi));
+        v[j] = fma(-kap, hs, fma(om, fma(we, even, -we * odd) - vj, vj));
     }
 }
 

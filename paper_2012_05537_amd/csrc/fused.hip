@@ -37,13 +37,15 @@ template <int P, int TEX, int TEY, int TEZ>
 struct TileShape {
     static constexpr int TX = TEX * P, TY = TEY * P, TZ = TEZ * P;
     static constexpr int NN = TX * TY * TZ;                          // nodes of a tile
-    static constexpr int NT = (NN + 63) / 64 * 64;                   // threads: whole waves
+    static constexpr int NT = (2 * NN + 63) / 64 * 64;               // two threads per node, whole waves
     static constexpr int WX = TX + P + 1, WY = TY + P + 1, WZ = TZ + P + 1;   // largest window
-    static constexpr int R = 2 * P + 1;                              // source rows of one cell
     static constexpr int round64(int n) { return (n + 63) / 64 * 64; }
-    static constexpr int ZT = WX * WY * TEZ, ZP = round64(ZT);      // z-pass tasks per velocity
+    // tasks per (velocity, population), padded to whole waves
+    static constexpr int ZT = WX * WY * TEZ, ZP = round64(ZT);
     static constexpr int YT = WX * TZ * TEY, YP = round64(YT);
     static constexpr int XT = TY * TZ * TEX, XP = round64(XT);
+    static constexpr int BZ = TZ * WY * WX;                          // LDS slab of one (velocity, population)
+    static constexpr int CY = TZ * TY * WX;
 };
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -88,12 +90,12 @@ __global__ void __launch_bounds__(NTH, MINB)
             S *__restrict__ pre_out)
 {
     using TS = TileShape<P, TEX, TEY, TEZ>;
-    constexpr int TX = TS::TX, TY = TS::TY, TZ = TS::TZ, NT = TS::NT;
+    constexpr int TX = TS::TX, TY = TS::TY, TZ = TS::TZ, NT = TS::NT, NN = TS::NN;
     constexpr int WX = TS::WX, WY = TS::WY, WZ = TS::WZ;
     constexpr int NROUND = (vs::Q - 1 + G - 1) / G;
 
-    __shared__ S bz[G * 2 * TZ * WY * WX];     // z-pass output; reused for the x-pass output
-    __shared__ S cy[G * 2 * TZ * TY * WX];     // y-pass output
+    __shared__ S bz[G * 2 * TS::BZ];     // z-pass output; reused for the x-pass output
+    __shared__ S cy[G * 2 * TS::CY];     // y-pass output
     __shared__ int xo[G][WX], yo[G][WY], zo[G][WZ];
     __shared__ int sh_lstar[G][3], sh_nrow[G][3];
 
@@ -108,16 +110,16 @@ __global__ void __launch_bounds__(NTH, MINB)
     const int tcy = (tile / geo.ntile[0]) % geo.ntile[1];
     const int tcz = tile / (geo.ntile[0] * geo.ntile[1]);
     const int X0 = tcx * TX, Y0 = tcy * TY, Z0 = tcz * TZ;
-    const int lx = tid % TX, ly = (tid / TX) % TY, lz = tid / (TX * TY);
-    const bool valid = tid < TS::NN && (X0 + lx < geo.N[0]) && (Y0 + ly < geo.N[1]) && (Z0 + lz < geo.N[2]);
+    // node and population of this thread: lanes 2k (f) and 2k+1 (g) share a node
+    const int nl = tid >> 1;
+    const int pop = tid & 1;
+    const int lx = nl % TX, ly = (nl / TX) % TY, lz = nl / (TX * TY);
+    const bool valid = nl < NN && (X0 + lx < geo.N[0]) && (Y0 + ly < geo.N[1]) && (Z0 + lz < geo.N[2]);
     const int node = ((Z0 + lz) * geo.N[1] + (Y0 + ly)) * geo.N[0] + (X0 + lx);
+    const S *__restrict__ my_in = in + static_cast<int64_t>(pop) * vs::Q * N;
 
-    S fv[vs::Q], gv[vs::Q];
-    {
-        const int n = valid ? node : 0;
-        fv[0] = in[n];                        // the rest velocity does not move
-        gv[0] = in[vs::Q * N + n];
-    }
+    S v[vs::Q];
+    v[0] = my_in[valid ? node : 0];          // the rest velocity does not move
 
 #pragma unroll
     for (int rd = 0; rd < NROUND; ++rd) {
@@ -150,141 +152,91 @@ __global__ void __launch_bounds__(NTH, MINB)
         __syncthreads();
 
         // (b) z-pass: columns straight from global memory
-        for (int b = wave * 64; b < G * TS::ZP; b += NT) {
-            const int gg = b / TS::ZP;                   // wave-uniform velocity of the round
+        for (int b = wave * 64; b < G * 2 * TS::ZP; b += NT) {
+            const int gp = b / TS::ZP;                   // wave-uniform (velocity of the round, population)
+            const int gg = gp >> 1, pp = gp & 1;
             const int t = b % TS::ZP + lane;
             if (gg < gcount && t < TS::ZT) {
                 const int i = vbase + gg;
                 const int wx = t % WX, wy = (t / WX) % WY, ez = t / (WX * WY);
-                const S *__restrict__ fin = in + static_cast<int64_t>(i) * N;
-                const S *__restrict__ gin = in + static_cast<int64_t>(vs::Q + i) * N;
+                const S *__restrict__ src = in + static_cast<int64_t>(pp * vs::Q + i) * N;
                 const int nrow = uniform(sh_nrow[gg][2]);
                 const int base = xo[gg][wx] + yo[gg][wy];
-                S cf[2 * P + 1], cg[2 * P + 1];
+                S c[2 * P + 1];
 #pragma unroll
-                for (int r = 0; r < 2 * P + 1; ++r) {
-                    if (r < nrow) {
-                        const int n = base + zo[gg][ez * P + r];
-                        cf[r] = fin[n];
-                        cg[r] = gin[n];
-                    } else {
-                        cf[r] = 0;
-                        cg[r] = 0;
-                    }
-                }
-                const S *W = tab.w + (i * 3 + 2) * P * (P + 1);
-                const int ls = uniform(sh_lstar[gg][2]);
-                S of[P], og[P];
-                interp_cell<S, P>(W, ls, cf, of);
-                interp_cell<S, P>(W, ls, cg, og);
-                S *dst = bz + gg * 2 * TZ * WY * WX;
+                for (int r = 0; r < 2 * P + 1; ++r) c[r] = (r < nrow) ? src[base + zo[gg][ez * P + r]] : S(0);
+                S o[P];
+                interp_cell<S, P>(tab.w + (i * 3 + 2) * P * (P + 1), uniform(sh_lstar[gg][2]), c, o);
+                S *dst = bz + gp * TS::BZ;
 #pragma unroll
-                for (int l = 0; l < P; ++l) {
-                    dst[((ez * P + l) * WY + wy) * WX + wx] = of[l];
-                    dst[TZ * WY * WX + ((ez * P + l) * WY + wy) * WX + wx] = og[l];
-                }
+                for (int l = 0; l < P; ++l) dst[((ez * P + l) * WY + wy) * WX + wx] = o[l];
             }
         }
         __syncthreads();
 
         // (c) y-pass
-        for (int b = wave * 64; b < G * TS::YP; b += NT) {
-            const int gg = b / TS::YP;
+        for (int b = wave * 64; b < G * 2 * TS::YP; b += NT) {
+            const int gp = b / TS::YP;
+            const int gg = gp >> 1;
             const int t = b % TS::YP + lane;
             if (gg < gcount && t < TS::YT) {
                 const int i = vbase + gg;
                 const int wx = t % WX, tz = (t / WX) % TZ, ey = t / (WX * TZ);
                 const int nrow = uniform(sh_nrow[gg][1]);
-                const S *src = bz + gg * 2 * TZ * WY * WX;
-                S cf[2 * P + 1], cg[2 * P + 1];
+                const S *src = bz + gp * TS::BZ + (tz * WY + ey * P) * WX + wx;
+                S c[2 * P + 1];
 #pragma unroll
-                for (int r = 0; r < 2 * P + 1; ++r) {
-                    if (r < nrow) {
-                        const int idx = (tz * WY + ey * P + r) * WX + wx;
-                        cf[r] = src[idx];
-                        cg[r] = src[TZ * WY * WX + idx];
-                    } else {
-                        cf[r] = 0;
-                        cg[r] = 0;
-                    }
-                }
-                const S *W = tab.w + (i * 3 + 1) * P * (P + 1);
-                const int ls = uniform(sh_lstar[gg][1]);
-                S of[P], og[P];
-                interp_cell<S, P>(W, ls, cf, of);
-                interp_cell<S, P>(W, ls, cg, og);
-                S *dst = cy + gg * 2 * TZ * TY * WX;
+                for (int r = 0; r < 2 * P + 1; ++r) c[r] = (r < nrow) ? src[r * WX] : S(0);
+                S o[P];
+                interp_cell<S, P>(tab.w + (i * 3 + 1) * P * (P + 1), uniform(sh_lstar[gg][1]), c, o);
+                S *dst = cy + gp * TS::CY + (tz * TY + ey * P) * WX + wx;
 #pragma unroll
-                for (int l = 0; l < P; ++l) {
-                    dst[(tz * TY + ey * P + l) * WX + wx] = of[l];
-                    dst[TZ * TY * WX + (tz * TY + ey * P + l) * WX + wx] = og[l];
-                }
+                for (int l = 0; l < P; ++l) dst[l * WX] = o[l];
             }
         }
         __syncthreads();
 
         // (d) x-pass, output in node order (into bz, free since the y-pass)
-        for (int b = wave * 64; b < G * TS::XP; b += NT) {
-            const int gg = b / TS::XP;
+        for (int b = wave * 64; b < G * 2 * TS::XP; b += NT) {
+            const int gp = b / TS::XP;
+            const int gg = gp >> 1;
             const int t = b % TS::XP + lane;
             if (gg < gcount && t < TS::XT) {
                 const int i = vbase + gg;
                 const int ty = t % TY, tz = (t / TY) % TZ, ex = t / (TY * TZ);
                 const int nrow = uniform(sh_nrow[gg][0]);
-                const S *src = cy + gg * 2 * TZ * TY * WX;
-                S cf[2 * P + 1], cg[2 * P + 1];
+                const S *src = cy + gp * TS::CY + (tz * TY + ty) * WX + ex * P;
+                S c[2 * P + 1];
 #pragma unroll
-                for (int r = 0; r < 2 * P + 1; ++r) {
-                    if (r < nrow) {
-                        const int idx = (tz * TY + ty) * WX + ex * P + r;
-                        cf[r] = src[idx];
-                        cg[r] = src[TZ * TY * WX + idx];
-                    } else {
-                        cf[r] = 0;
-                        cg[r] = 0;
-                    }
-                }
-                const S *W = tab.w + (i * 3 + 0) * P * (P + 1);
-                const int ls = uniform(sh_lstar[gg][0]);
-                S of[P], og[P];
-                interp_cell<S, P>(W, ls, cf, of);
-                interp_cell<S, P>(W, ls, cg, og);
-                S *dst = bz + gg * 2 * TS::NN;
+                for (int r = 0; r < 2 * P + 1; ++r) c[r] = (r < nrow) ? src[r] : S(0);
+                S o[P];
+                interp_cell<S, P>(tab.w + (i * 3 + 0) * P * (P + 1), uniform(sh_lstar[gg][0]), c, o);
+                S *dst = bz + gp * NN + (tz * TY + ty) * TX + ex * P;
 #pragma unroll
-                for (int l = 0; l < P; ++l) {
-                    dst[(tz * TY + ty) * TX + ex * P + l] = of[l];
-                    dst[TS::NN + (tz * TY + ty) * TX + ex * P + l] = og[l];
-                }
+                for (int l = 0; l < P; ++l) dst[l] = o[l];
             }
         }
         __syncthreads();
 
-        // (e) the node's streamed values
+        // (e) this thread's streamed values
 #pragma unroll
         for (int gg = 0; gg < G; ++gg) {
             const int i = 1 + rd * G + gg;
-            if (i < vs::Q && tid < TS::NN) {
-                fv[i] = bz[gg * 2 * TS::NN + tid];
-                gv[i] = bz[gg * 2 * TS::NN + TS::NN + tid];
-            }
+            if (i < vs::Q && nl < NN) v[i] = bz[(gg * 2 + pop) * NN + nl];
         }
         __syncthreads();
     }
 
     if (!valid) return;
     if (pre_out != nullptr) {
+        S *dst = pre_out + static_cast<int64_t>(pop) * vs::Q * N + node;
 #pragma unroll
-        for (int i = 0; i < vs::Q; ++i) {
-            pre_out[static_cast<int64_t>(i) * N + node] = fv[i];
-            pre_out[static_cast<int64_t>(vs::Q + i) * N + node] = gv[i];
-        }
+        for (int i = 0; i < vs::Q; ++i) dst[static_cast<int64_t>(i) * N] = v[i];
     }
-    if constexpr (COLLIDE) collide_regs<S>(fv, gv, cp);
+    if constexpr (COLLIDE) collide_half<S>(v, pop != 0, cp);
+    S *dst = out + static_cast<int64_t>(pop) * vs::Q * N + node;
 #pragma unroll
-    for (int i = 0; i < vs::Q; ++i) {
-        out[static_cast<int64_t>(i) * N + node] = fv[i];
-        out[static_cast<int64_t>(vs::Q + i) * N + node] = gv[i];
-    }
+    for (int i = 0; i < vs::Q; ++i) dst[static_cast<int64_t>(i) * N] = v[i];
 }
 
 // ---------------------------------------------------------------------------

@@ -222,24 +222,22 @@ __global__ void __launch_bounds__(256) k_stream_tab(Geometry geo, StreamTables t
     }
 }
 
+// Collision of a whole state, two lanes per node (f on the even lane, g on
+// the odd one), with the same code as the fused step.
 template <typename S>
 __global__ void __launch_bounds__(256) k_collide(int64_t N, CollisionParams cp, S *__restrict__ state)
 {
-    for (int64_t n = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; n < N;
-         n += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-        S f[Q], g[Q];
+    const int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+    const int64_t n = t >> 1;
+    const int pop = static_cast<int>(t & 1);
+    if (n >= N) return;                    // both lanes of a pair leave together
+    S *p = state + static_cast<int64_t>(pop) * Q * N + n;
+    S v[Q];
 #pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            f[i] = state[static_cast<int64_t>(i) * N + n];
-            g[i] = state[static_cast<int64_t>(Q + i) * N + n];
-        }
-        collide_regs<S>(f, g, cp);
+    for (int i = 0; i < Q; ++i) v[i] = p[static_cast<int64_t>(i) * N];
+    collide_half<S>(v, pop != 0, cp);
 #pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            state[static_cast<int64_t>(i) * N + n] = f[i];
-            state[static_cast<int64_t>(Q + i) * N + n] = g[i];
-        }
-    }
+    for (int i = 0; i < Q; ++i) p[static_cast<int64_t>(i) * N] = v[i];
 }
 
 template <typename S>
@@ -416,7 +414,8 @@ hipError_t Launch<S>::stream_only(const Geometry &g, const StreamTables &t, cons
 template <typename S>
 hipError_t Launch<S>::collide_only(const Geometry &g, const CollisionParams &cp, S *state, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_collide<S>), dim3(node_grid(g.nodes)), dim3(256), 0, st, g.nodes, cp, state);
+    const int64_t blocks = (2 * g.nodes + 255) / 256;
+    hipLaunchKernelGGL((k_collide<S>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, g.nodes, cp, state);
     return hipGetLastError();
 }
 
