@@ -27,6 +27,8 @@
 // halo of neighbouring tiles in that XCD's L2.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "collision.h"
 #include "sllbm_internal.h"
 #include "velset.h"
@@ -64,44 +66,100 @@ __device__ __forceinline__ int xcd_tile(int b, int nb)
     return xcd < rem ? xcd * (per + 1) + slot : rem * (per + 1) + (xcd - rem) * per + slot;
 }
 
-// One velocity's P output rows from a column c[0..2P]:
-//   out[l] = sum_k W[l][k] c[k + (l >= lstar ? P : 0)]
-template <typename S, int P>
-__device__ __forceinline__ void interp_cell(const S *__restrict__ W, int lstar, const S (&c)[2 * P + 1],
-                                            S (&out)[P])
-{
-#pragma unroll
-    for (int l = 0; l < P; ++l) {
-        S acc = 0;
-        if (l < lstar) {
-#pragma unroll
-            for (int k = 0; k <= P; ++k) acc = fma(W[l * (P + 1) + k], c[k], acc);
-        } else {
-#pragma unroll
-            for (int k = 0; k <= P; ++k) acc = fma(W[l * (P + 1) + k], c[P + k], acc);
-        }
-        out[l] = acc;
-    }
-}
+// Per-block state of the fused kernel.  A block has 8 waves; in each round
+// wave w streams velocity 1 + 4*round + w/2 of population w%2 through its own
+// z-, y- and x-passes in wave-private LDS, so waves proceed independently;
+// one block barrier per round publishes the node-ordered results
+// (double-buffered) to the threads that own the nodes.
+//
+// Source-cell grouping.  Along an axis, node n of the tile (row l = n mod P)
+// reads cell floor(n/P) + o_l, with o_l = omin for l < lstar and omin + 1
+// otherwise.  Equivalently the nodes n = g*P + lstar + j, j = 0..P-1, all
+// read cell g + omin + 1 with row l = (lstar + j) mod P.  A pass therefore
+// works per (column, group g): it loads the P+1 points of one source cell,
+// and writes up to P outputs at an offset that is uniform across the wave
+// (lstar is a property of the velocity), with no per-lane selection.
+template <typename S, int P, int TEX, int TEY, int TEZ>
+struct Fused {
+    using TS = TileShape<P, TEX, TEY, TEZ>;
+    static constexpr int G = 4;                                     // velocities per round
+    static constexpr int NT = 512;                                  // 8 waves = G velocities x 2 populations
+    static constexpr int TX = TS::TX, TY = TS::TY, TZ = TS::TZ, NN = TS::NN;
+    static constexpr int WX = TS::WX, WY = TS::WY, WZ = TS::WZ;
+    static_assert(2 * NN <= NT, "tile too large for the block");
+    static constexpr int NROUND = (vs::Q - 1) / G;
+    static constexpr int ZC = WX * WY, ZK = (ZC + 63) / 64;         // z columns per wave, per lane
+    static constexpr int YC = WX * TZ, YK = (YC + 63) / 64;
+    static constexpr int XC = TY * TZ, XK = (XC + 63) / 64;
+    static constexpr int RS = 2 * TX + 1;                           // padded row of dx (both populations)
 
-template <typename S, int P, int TEX, int TEY, int TEZ, int G, bool COLLIDE, int NTH, int MINB>
-__global__ void __launch_bounds__(NTH, MINB)
+    struct Smem {
+        S bz[2 * G][TZ * WY * WX];          // wave-private z-pass output
+        S cy[2 * G][TZ * TY * WX];          // wave-private y-pass output
+        S dx[2][G][TZ * TY * RS];           // node-ordered streamed values, two buffers
+        int xo[NROUND][G][WX];              // global node offsets of the windows
+        int yo[NROUND][G][WY];
+        int zo[NROUND][G][WZ];
+    };
+
+    using Col = S[TEZ + 1][ZK][P + 1];
+
+    // loads of this wave's z-columns of round rd: group g reads window rows (g+1)P .. (g+1)P + P
+    static __device__ __forceinline__ void prefetch(const Smem &sm, const S *__restrict__ in, int64_t N, int rd,
+                                                    int gg, int pp, int lane, Col &col)
+    {
+        const int i = 1 + rd * G + gg;
+        const S *__restrict__ src = in + static_cast<int64_t>(pp * vs::Q + i) * N;
+#pragma unroll
+        for (int k = 0; k < ZK; ++k) {
+            int t = lane + 64 * k;
+            t = t < ZC ? t : ZC - 1;                          // idle lanes repeat a valid column
+            const int wx = t % WX, wy = t / WX;
+            const unsigned base = static_cast<unsigned>(sm.xo[rd][gg][wx] + sm.yo[rd][gg][wy]);
+            const int *zo = sm.zo[rd][gg];
+#pragma unroll
+            for (int g = 0; g <= TEZ; ++g)
+#pragma unroll
+                for (int r = 0; r <= P; ++r) col[g][k][r] = src[base + static_cast<unsigned>(zo[g * P + r])];
+        }
+    }
+
+    // outputs of group g (g = -1 .. TE-1) along an axis of TE cells: positions
+    // g*P + lstar + j inside [0, TE*P); W = this axis' weights [P][P+1]
+    template <int TE, typename Src, typename Dst>
+    static __device__ __forceinline__ void group_outputs(int g, int lstar, const S *__restrict__ W, const Src &c,
+                                                         Dst &&store)
+    {
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+            const int pos = g * P + lstar + j;
+            if (pos >= 0 && pos < TE * P) {                     // wave-uniform
+                const int l = (lstar + j) % P;
+                const S *w = W + l * (P + 1);
+                S acc = 0;
+#pragma unroll
+                for (int k = 0; k <= P; ++k) acc = fma(w[k], c[k], acc);
+                store(pos, acc);
+            }
+        }
+    }
+};
+
+template <typename S, int P, int TEX, int TEY, int TEZ, bool COLLIDE, int MINB>
+__global__ void __launch_bounds__(512, MINB)
     k_fused(Geometry geo, FusedTables<S> tab, CollisionParams cp, const S *__restrict__ in, S *__restrict__ out,
             S *__restrict__ pre_out)
 {
-    using TS = TileShape<P, TEX, TEY, TEZ>;
-    constexpr int TX = TS::TX, TY = TS::TY, TZ = TS::TZ, NT = TS::NT, NN = TS::NN;
-    constexpr int WX = TS::WX, WY = TS::WY, WZ = TS::WZ;
-    constexpr int NROUND = (vs::Q - 1 + G - 1) / G;
-
-    __shared__ S bz[G * 2 * TS::BZ];     // z-pass output; reused for the x-pass output
-    __shared__ S cy[G * 2 * TS::CY];     // y-pass output
-    __shared__ int xo[G][WX], yo[G][WY], zo[G][WZ];
-    __shared__ int sh_lstar[G][3], sh_nrow[G][3];
+    using F = Fused<S, P, TEX, TEY, TEZ>;
+    constexpr int G = F::G, NT = F::NT, NN = F::NN, RS = F::RS;
+    constexpr int TX = F::TX, TY = F::TY, TZ = F::TZ;
+    constexpr int WX = F::WX, WY = F::WY, WZ = F::WZ;
+    __shared__ typename F::Smem sm;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = uniform(tid >> 6);
+    const int gg = wave >> 1, pp = wave & 1;          // this wave's velocity slot and population
     const int64_t N = geo.nodes;
 
     // tile origin
@@ -110,121 +168,105 @@ __global__ void __launch_bounds__(NTH, MINB)
     const int tcy = (tile / geo.ntile[0]) % geo.ntile[1];
     const int tcz = tile / (geo.ntile[0] * geo.ntile[1]);
     const int X0 = tcx * TX, Y0 = tcy * TY, Z0 = tcz * TZ;
+
+    // global node offsets of every round's windows
+    for (int e = tid; e < F::NROUND * G * (WX + WY + WZ); e += NT) {
+        const int rg = e / (WX + WY + WZ);                 // round * G + velocity slot
+        const int r = e % (WX + WY + WZ);
+        const int i = 1 + rg;
+        if (r < WX) {
+            (&sm.xo[0][0][0])[rg * WX + r] = wrap(X0 + tab.omin[i * 3 + 0] * P + r, geo.N[0]);
+        } else if (r < WX + WY) {
+            const int w = r - WX;
+            (&sm.yo[0][0][0])[rg * WY + w] = wrap(Y0 + tab.omin[i * 3 + 1] * P + w, geo.N[1]) * geo.N[0];
+        } else {
+            const int w = r - WX - WY;
+            (&sm.zo[0][0][0])[rg * WZ + w] = wrap(Z0 + tab.omin[i * 3 + 2] * P + w, geo.N[2]) * geo.N[0] * geo.N[1];
+        }
+    }
+    __syncthreads();
+
     // node and population of this thread: lanes 2k (f) and 2k+1 (g) share a node
     const int nl = tid >> 1;
     const int pop = tid & 1;
     const int lx = nl % TX, ly = (nl / TX) % TY, lz = nl / (TX * TY);
     const bool valid = nl < NN && (X0 + lx < geo.N[0]) && (Y0 + ly < geo.N[1]) && (Z0 + lz < geo.N[2]);
     const int node = ((Z0 + lz) * geo.N[1] + (Y0 + ly)) * geo.N[0] + (X0 + lx);
-    const S *__restrict__ my_in = in + static_cast<int64_t>(pop) * vs::Q * N;
+    const int my_dx = (lz * TY + ly) * RS + lx * 2 + pop;
 
     S v[vs::Q];
-    v[0] = my_in[valid ? node : 0];          // the rest velocity does not move
+    v[0] = in[static_cast<int64_t>(pop) * vs::Q * N + (valid ? node : 0)];   // the rest velocity does not move
 
+    S *bz = sm.bz[wave];
+    S *cy = sm.cy[wave];
+    for (int rd = 0; rd < F::NROUND; ++rd) {
+        const int i = 1 + rd * G + gg;
+        const int lsx = tab.lstar[i * 3 + 0], lsy = tab.lstar[i * 3 + 1], lsz = tab.lstar[i * 3 + 2];
+        const S *wxw = tab.w + (i * 3 + 0) * P * (P + 1);
+        const S *wyw = tab.w + (i * 3 + 1) * P * (P + 1);
+        const S *wzw = tab.w + (i * 3 + 2) * P * (P + 1);
+
+        // z-pass: cell columns straight from global memory
+        typename F::Col col;
+        F::prefetch(sm, in, N, rd, gg, pp, lane, col);
 #pragma unroll
-    for (int rd = 0; rd < NROUND; ++rd) {
-        const int vbase = 1 + rd * G;
-        const int gcount = (vs::Q - vbase) < G ? (vs::Q - vbase) : G;
+        for (int k = 0; k < F::ZK; ++k) {
+            const int t = lane + 64 * k;
+            if (t < F::ZC) {
+                S *dst = bz + t;                                         // (wx, wy) = t
+#pragma unroll
+                for (int g = 0; g <= TEZ; ++g)
+                    F::template group_outputs<TEZ>(g - 1, lsz, wzw, col[g][k],
+                                                   [&](int pos, S val) { dst[pos * WY * WX] = val; });
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
-        // (a) global node offsets of the round's windows, per axis
-        for (int e = tid; e < G * (WX + WY + WZ); e += NT) {
-            const int gg = e / (WX + WY + WZ);
-            const int r = e % (WX + WY + WZ);
-            if (gg < gcount) {
-                const int i = vbase + gg;
-                if (r < WX) {
-                    xo[gg][r] = wrap(X0 + tab.omin[i * 3 + 0] * P + r, geo.N[0]);
-                } else if (r < WX + WY) {
-                    const int w = r - WX;
-                    yo[gg][w] = wrap(Y0 + tab.omin[i * 3 + 1] * P + w, geo.N[1]) * geo.N[0];
-                } else {
-                    const int w = r - WX - WY;
-                    zo[gg][w] = wrap(Z0 + tab.omin[i * 3 + 2] * P + w, geo.N[2]) * geo.N[0] * geo.N[1];
+        // y-pass
+#pragma unroll
+        for (int k = 0; k < F::YK; ++k) {
+            const int t = lane + 64 * k;
+            if (t < F::YC) {
+                const int wx = t % WX, tz = t / WX;
+                const S *src = bz + tz * WY * WX + wx;
+                S *dst = cy + tz * TY * WX + wx;
+#pragma unroll
+                for (int g = 0; g <= TEY; ++g) {
+                    S c[P + 1];
+#pragma unroll
+                    for (int r = 0; r <= P; ++r) c[r] = src[(g * P + r) * WX];
+                    F::template group_outputs<TEY>(g - 1, lsy, wyw, c, [&](int pos, S val) { dst[pos * WX] = val; });
                 }
             }
-            if (e < G * 3 && e / 3 < gcount) {
-                const int i = vbase + e / 3, a = e % 3;
-                const int ls = tab.lstar[i * 3 + a];
-                sh_lstar[e / 3][a] = ls;
-                sh_nrow[e / 3][a] = ls < P ? 2 * P + 1 : P + 1;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+        // x-pass into the node-ordered buffer (both populations interleaved)
+        S *dxw = sm.dx[rd & 1][gg];
+#pragma unroll
+        for (int k = 0; k < F::XK; ++k) {
+            const int t = lane + 64 * k;
+            if (t < F::XC) {
+                const S *src = cy + t * WX;                              // row (ty, tz) = t
+                S *dst = dxw + t * RS + pp;
+#pragma unroll
+                for (int g = 0; g <= TEX; ++g) {
+                    S c[P + 1];
+#pragma unroll
+                    for (int r = 0; r <= P; ++r) c[r] = src[g * P + r];
+                    F::template group_outputs<TEX>(g - 1, lsx, wxw, c, [&](int pos, S val) { dst[pos * 2] = val; });
+                }
             }
         }
         __syncthreads();
 
-        // (b) z-pass: columns straight from global memory
-        for (int b = wave * 64; b < G * 2 * TS::ZP; b += NT) {
-            const int gp = b / TS::ZP;                   // wave-uniform (velocity of the round, population)
-            const int gg = gp >> 1, pp = gp & 1;
-            const int t = b % TS::ZP + lane;
-            if (gg < gcount && t < TS::ZT) {
-                const int i = vbase + gg;
-                const int wx = t % WX, wy = (t / WX) % WY, ez = t / (WX * WY);
-                const S *__restrict__ src = in + static_cast<int64_t>(pp * vs::Q + i) * N;
-                const int nrow = uniform(sh_nrow[gg][2]);
-                const int base = xo[gg][wx] + yo[gg][wy];
-                S c[2 * P + 1];
+        // this round's four values move to the top of v, earlier rounds shift down
 #pragma unroll
-                for (int r = 0; r < 2 * P + 1; ++r) c[r] = (r < nrow) ? src[base + zo[gg][ez * P + r]] : S(0);
-                S o[P];
-                interp_cell<S, P>(tab.w + (i * 3 + 2) * P * (P + 1), uniform(sh_lstar[gg][2]), c, o);
-                S *dst = bz + gp * TS::BZ;
+        for (int q = 1; q + G < vs::Q; ++q) v[q] = v[q + G];
 #pragma unroll
-                for (int l = 0; l < P; ++l) dst[((ez * P + l) * WY + wy) * WX + wx] = o[l];
-            }
-        }
-        __syncthreads();
-
-        // (c) y-pass
-        for (int b = wave * 64; b < G * 2 * TS::YP; b += NT) {
-            const int gp = b / TS::YP;
-            const int gg = gp >> 1;
-            const int t = b % TS::YP + lane;
-            if (gg < gcount && t < TS::YT) {
-                const int i = vbase + gg;
-                const int wx = t % WX, tz = (t / WX) % TZ, ey = t / (WX * TZ);
-                const int nrow = uniform(sh_nrow[gg][1]);
-                const S *src = bz + gp * TS::BZ + (tz * WY + ey * P) * WX + wx;
-                S c[2 * P + 1];
-#pragma unroll
-                for (int r = 0; r < 2 * P + 1; ++r) c[r] = (r < nrow) ? src[r * WX] : S(0);
-                S o[P];
-                interp_cell<S, P>(tab.w + (i * 3 + 1) * P * (P + 1), uniform(sh_lstar[gg][1]), c, o);
-                S *dst = cy + gp * TS::CY + (tz * TY + ey * P) * WX + wx;
-#pragma unroll
-                for (int l = 0; l < P; ++l) dst[l * WX] = o[l];
-            }
-        }
-        __syncthreads();
-
-        // (d) x-pass, output in node order (into bz, free since the y-pass)
-        for (int b = wave * 64; b < G * 2 * TS::XP; b += NT) {
-            const int gp = b / TS::XP;
-            const int gg = gp >> 1;
-            const int t = b % TS::XP + lane;
-            if (gg < gcount && t < TS::XT) {
-                const int i = vbase + gg;
-                const int ty = t % TY, tz = (t / TY) % TZ, ex = t / (TY * TZ);
-                const int nrow = uniform(sh_nrow[gg][0]);
-                const S *src = cy + gp * TS::CY + (tz * TY + ty) * WX + ex * P;
-                S c[2 * P + 1];
-#pragma unroll
-                for (int r = 0; r < 2 * P + 1; ++r) c[r] = (r < nrow) ? src[r] : S(0);
-                S o[P];
-                interp_cell<S, P>(tab.w + (i * 3 + 0) * P * (P + 1), uniform(sh_lstar[gg][0]), c, o);
-                S *dst = bz + gp * NN + (tz * TY + ty) * TX + ex * P;
-#pragma unroll
-                for (int l = 0; l < P; ++l) dst[l] = o[l];
-            }
-        }
-        __syncthreads();
-
-        // (e) this thread's streamed values
-#pragma unroll
-        for (int gg = 0; gg < G; ++gg) {
-            const int i = 1 + rd * G + gg;
-            if (i < vs::Q && nl < NN) v[i] = bz[(gg * 2 + pop) * NN + nl];
-        }
-        __syncthreads();
+        for (int g = 0; g < G; ++g) v[vs::Q - G + g] = sm.dx[rd & 1][g][nl < NN ? my_dx : 0];
     }
 
     if (!valid) return;
@@ -253,22 +295,20 @@ template <typename S, int P, int TEX, int TEY, int TEZ>
 static hipError_t launch_fused_t(const Geometry &g, const FusedTables<S> &t, const CollisionParams &cp,
                                  const S *in, S *out, S *pre, bool collide, hipStream_t st)
 {
-    using TS = TileShape<P, TEX, TEY, TEZ>;
-    constexpr int G = 4;
     constexpr int MB = MinBlocks<S>::value;
     const int nb = g.ntile[0] * g.ntile[1] * g.ntile[2];
     if (collide)
-        hipLaunchKernelGGL((k_fused<S, P, TEX, TEY, TEZ, G, true, TS::NT, MB>), dim3(nb), dim3(TS::NT), 0, st, g, t, cp, in,
-                           out, pre);
+        hipLaunchKernelGGL((k_fused<S, P, TEX, TEY, TEZ, true, MB>), dim3(nb), dim3(512), 0, st, g, t, cp, in, out,
+                           pre);
     else
-        hipLaunchKernelGGL((k_fused<S, P, TEX, TEY, TEZ, G, false, TS::NT, MB>), dim3(nb), dim3(TS::NT), 0, st, g, t, cp,
-                           in, out, pre);
+        hipLaunchKernelGGL((k_fused<S, P, TEX, TEY, TEZ, false, MB>), dim3(nb), dim3(512), 0, st, g, t, cp, in,
+                           out, pre);
     return hipGetLastError();
 }
 
 void fused_tile(int p, int te[3])
 {
-    static const int table[7][3] = {{0, 0, 0}, {8, 8, 4}, {4, 4, 2}, {2, 2, 2}, {2, 2, 1}, {1, 1, 2}, {1, 1, 1}};
+    static const int table[7][3] = {{0, 0, 0}, {8, 8, 4}, {4, 4, 2}, {3, 3, 1}, {2, 2, 1}, {1, 1, 2}, {1, 1, 1}};
     for (int a = 0; a < 3; ++a) te[a] = table[p][a];
 }
 
@@ -279,7 +319,7 @@ hipError_t launch_fused(const Geometry &g, const FusedTables<S> &t, const Collis
     switch (g.p) {
     case 1: return launch_fused_t<S, 1, 8, 8, 4>(g, t, cp, in, out, pre, collide, st);
     case 2: return launch_fused_t<S, 2, 4, 4, 2>(g, t, cp, in, out, pre, collide, st);
-    case 3: return launch_fused_t<S, 3, 2, 2, 2>(g, t, cp, in, out, pre, collide, st);
+    case 3: return launch_fused_t<S, 3, 3, 3, 1>(g, t, cp, in, out, pre, collide, st);
     case 4: return launch_fused_t<S, 4, 2, 2, 1>(g, t, cp, in, out, pre, collide, st);
     case 5: return launch_fused_t<S, 5, 1, 1, 2>(g, t, cp, in, out, pre, collide, st);
     case 6: return launch_fused_t<S, 6, 1, 1, 1>(g, t, cp, in, out, pre, collide, st);
