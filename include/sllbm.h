@@ -160,6 +160,13 @@ int sllbm_loss_grad(sllbm_ctx *ctx, const void *state, void *lam);
 int sllbm_adjoint_step(sllbm_ctx *ctx, const void *state_n, const void *lam_next, void *lam_out,
                        double *dmu);
 
+/* Reverse of sllbm_moments at the current state: given adjoints drho [N],
+ * du [3][N] and dT [N] (device double; any may be NULL = zero), write
+ * lam = (d(rho, u, T)/d(state))^T (drho, du, dT) (device, storage type),
+ * through rho = sum f, rho u = sum f xi and 2 rho E = sum (f |xi|^2 + g)
+ * of Eq. (7).  Requires a state. */
+int sllbm_moments_vjp(sllbm_ctx *ctx, const double *drho, const double *du, const double *dT, void *lam);
+
 /* Reverse of sllbm_init_equilibrium: given lam0 = dL/d(state), write
  * dL/drho, dL/du ([3][N]) and dL/dT at the fields (rho, u, T).  All device;
  * drho, du, dT may be NULL. */

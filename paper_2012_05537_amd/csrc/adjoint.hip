@@ -1,2 +1,613 @@
-// Reverse-mode kernels (placeholder until the adjoint is built).
+// Reverse mode of the SLLBM step (kernels and launchers).
+//
+// One step maps the pre-collision state X_n to X_{n+1} = S(C(X_n)), with C
+// the node-local collision (Eq. (5) with App. D) and S the semi-Lagrangian
+// streaming (Eq. (9)), which is linear.  Its vector-Jacobian product is
+//   lambda_n = J_C(X_n)^T S^T lambda_{n+1}.
+// S^T is applied as a gather over the transposed 1-D tables (kernels.hip);
+// this file holds the collision VJP, the VJP of the equilibrium
+// initialisation, and the flow functional used for gradients with its
+// derivative.  All reverse arithmetic is in double; states are stored in the
+// context's storage type.
+//
+// Collision VJP (per node, f on the even lane of a pair, g on the odd lane).
+// With adjoints alpha_i of the post-collision values of the lane's population
+// (alpha = a for f, b for g) and the forward quantities recomputed from X_n:
+//   h'_i = h_i + omega (s h^eq_i - h_i) + kappa h*_i,  s = 1 (f), beta T (g),
+//   omega = 1/tau, kappa = 1/tau - 1/tau_Pr,
+// the reverse sweep accumulates, per lane, the scalars
+//   sum alpha (s h^eq - h)            -> d omega
+//   sum alpha h*                      -> d kappa
+//   sum alpha s h^eq omega / rho      -> d rho
+//   equilibrium terms in c = xi.u, |u|^2 and theta = T - 1 -> d u, d T
+//   Abar_m = kappa sum_i alpha_i H3c_im  (adjoint of Qbar) -> d h, d u
+// adds them over the pair, pushes them through tau(mu(T), P = rho T),
+// T = (K/rho - |u|^2)/(2 C_v) and u = J/rho, and forms per velocity
+//   lambda_f,k = (1 - omega) a_k + rho_bar + J_bar . xi_k + K_bar |xi_k|^2 + Abar_f : d_k^3
+//   lambda_g,k = (1 - omega) b_k + K_bar + Abar_g : d_k^3,   d_k = xi_k - u.
+// The node's contribution to dL/dmu_inf is mu_bar * (mu / mu_inf).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "collision.h"
 #include "sllbm_internal.h"
+#include "velset.h"
+
+namespace sllbm {
+
+namespace {
+
+__device__ __forceinline__ double pair_sum(double v) { return v + __shfl_xor(v, 1); }
+
+__device__ __forceinline__ double viscosity_factor(const CollisionParams &cp, double T, double &dfac_dT)
+{
+    if (cp.law == SLLBM_CONSTANT) {
+        dfac_dT = 0.0;
+        return 1.0;
+    }
+    // (1 + S) T^1.5 / (T + S)
+    const double sq = sqrt(T);
+    const double den = T + SUTHERLAND_S;
+    const double fac = (1.0 + SUTHERLAND_S) * T * sq / den;
+    dfac_dT = (1.0 + SUTHERLAND_S) * (1.5 * sq / den - T * sq / (den * den));
+    return fac;
+}
+
+// bracket b(c) = a0 + a1 c + a2 c^2 + c^3/6 + c^4/24 and its derivatives
+struct Bracket {
+    double a0, a1, a2;           // value coefficients
+    double d0u, d1u, d2u;        // d a_k / d |u|^2
+    double d0t, d1t, d2t;        // d a_k / d theta
+};
+
+__device__ __forceinline__ Bracket bracket(double u2, double th, double x2)
+{
+    Bracket b;
+    const EqShell e = eq_shell(u2, th, x2);
+    b.a0 = e.a0;
+    b.a1 = e.a1;
+    b.a2 = e.a2;
+    b.d0u = -0.5 + 0.25 * u2 - 0.25 * th * (x2 - 5.0);
+    b.d1u = -0.5;
+    b.d2u = -0.25;
+    b.d0t = 0.5 * (x2 - 3.0) - 0.25 * u2 * (x2 - 5.0) + 0.25 * th * (x2 * x2 - 10.0 * x2 + 15.0);
+    b.d1t = 0.5 * (x2 - 5.0);
+    b.d2t = 0.25 * (x2 - 7.0);
+    return b;
+}
+
+__device__ __forceinline__ double bval(const Bracket &b, double c)
+{
+    return fma(c, fma(c, fma(c, fma(c, 1.0 / 24.0, 1.0 / 6.0), b.a2), b.a1), b.a0);
+}
+
+__device__ __forceinline__ double bder(const Bracket &b, double c)    // d b / d c
+{
+    return fma(c, fma(c, fma(c, 1.0 / 6.0, 0.5), 2.0 * b.a2), b.a1);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Collision VJP: lam = J_C(X)^T mu, two lanes per node.  dmu_part[block]
+// receives the block's sum of dL/dmu_inf.
+// ---------------------------------------------------------------------------
+// Grid-stride over lane pairs; the whole block runs the same number of
+// iterations, so every shuffle partner is live.  mu and lam may be the same
+// buffer: each lane reads its 45 values before writing them.
+template <typename S>
+__global__ void __launch_bounds__(256) k_collide_vjp(int64_t N, CollisionParams cp, const S *__restrict__ X,
+                                                     const S *mu, S *lam, double *__restrict__ dmu_part)
+{
+    __shared__ double red[256];
+    double dmu_acc = 0.0;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    for (int64_t t0 = blockIdx.x * static_cast<int64_t>(blockDim.x); t0 < 2 * N; t0 += stride) {
+    const int64_t t = t0 + threadIdx.x;
+    const int64_t n = t >> 1;
+    const int pop = static_cast<int>(t & 1);
+    const bool is_g = pop != 0;
+    const bool active = n < N;
+    const int64_t nn = active ? n : 0;
+    const int64_t off = static_cast<int64_t>(pop) * vs::Q * N + nn;
+
+    double h[vs::Q], al[vs::Q];
+#pragma unroll
+    for (int i = 0; i < vs::Q; ++i) {
+        h[i] = static_cast<double>(X[off + static_cast<int64_t>(i) * N]);
+        al[i] = static_cast<double>(mu[off + static_cast<int64_t>(i) * N]);
+    }
+
+    // ---- forward quantities (as in collide_half) ----
+    const RawMoments rm = raw_moments(h);
+    const double ktr = rm.m2[0] + rm.m2[3] + rm.m2[5];
+    const double p_m0 = __shfl_xor(rm.m0, 1);
+    const double p_j0 = __shfl_xor(rm.m1[0], 1), p_j1 = __shfl_xor(rm.m1[1], 1), p_j2 = __shfl_xor(rm.m1[2], 1);
+    const double p_tr = __shfl_xor(ktr, 1);
+    const double rho = is_g ? p_m0 : rm.m0;
+    const double J[3] = {is_g ? p_j0 : rm.m1[0], is_g ? p_j1 : rm.m1[1], is_g ? p_j2 : rm.m1[2]};
+    const double ir = 1.0 / rho;
+    const double u[3] = {J[0] * ir, J[1] * ir, J[2] * ir};
+    const double K = is_g ? p_tr + rm.m0 : ktr + p_m0;
+    const double u2 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    const double Cv = cp.Cv;
+    const double T = (K * ir - u2) / (2.0 * Cv);
+    double qb[10];
+    centred_third(rm, u, qb);
+    const double P = rho * T;
+    double dfac;
+    const double fac = viscosity_factor(cp, T, dfac);
+    const double mu_v = cp.mu_inf * fac;
+    const double tau = mu_v / (P * cp.dt) + 0.5;
+    const double tau_pr = (tau - 0.5) * cp.inv_pr + 0.5;
+    const double om = 1.0 / tau;
+    const double kap = 1.0 / tau - 1.0 / tau_pr;
+    const double th = T - 1.0;
+    const double eqs = is_g ? cp.beta * T : 1.0;
+
+    Bracket br[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) br[s] = bracket(u2, th, SHELL_X2[s]);
+
+    // ---- reverse sweep over the velocities (own population) ----
+    double s_om = 0, s_ka = 0, s_heq = 0, s_eqT = 0, s_u2 = 0, s_th = 0;
+    double ubar[3] = {0, 0, 0};
+    double abar[10];
+#pragma unroll
+    for (int m = 0; m < 10; ++m) abar[m] = 0.0;
+    {   // rest velocity: c = 0, h* = 0
+        const double w = vs::T.w[0];
+        const double feq = w * rho * br[0].a0;
+        const double heq = eqs * feq;
+        s_om = fma(al[0], heq - h[0], s_om);
+        s_heq = fma(al[0], heq, s_heq);
+        s_eqT = fma(al[0], feq, s_eqT);
+        s_u2 = fma(al[0] * w * rho * eqs, br[0].d0u, s_u2);
+        s_th = fma(al[0] * w * rho * eqs, br[0].d0t, s_th);
+    }
+#pragma unroll
+    for (int q = 0; q < 22; ++q) {
+        const int i = vs::PAIRS.a[q], j = vs::PAIRS.b[q];
+        const Bracket &b = br[vs::T.shell[i]];
+        const double w = vs::T.w[i];
+        const double c = vs::T.xi[i][0] * u[0] + vs::T.xi[i][1] * u[1] + vs::T.xi[i][2] * u[2];
+        const double feq_i = w * rho * bval(b, c), feq_j = w * rho * bval(b, -c);
+        const double heq_i = eqs * feq_i, heq_j = eqs * feq_j;
+        double hs = 0.0;
+#pragma unroll
+        for (int m = 0; m < 10; ++m) hs = fma(vs::H3.c[i][m], qb[m], hs);
+        const double ai = al[i], aj = al[j];
+        s_om += ai * (heq_i - h[i]) + aj * (heq_j - h[j]);
+        s_ka += (ai - aj) * hs;
+        s_heq += ai * heq_i + aj * heq_j;
+        s_eqT += ai * feq_i + aj * feq_j;
+        const double wre = w * rho * eqs;
+        const double gu = wre * (ai * bder(b, c) - aj * bder(b, -c));      // d/du through c
+        ubar[0] = fma(gu, vs::T.xi[i][0], ubar[0]);
+        ubar[1] = fma(gu, vs::T.xi[i][1], ubar[1]);
+        ubar[2] = fma(gu, vs::T.xi[i][2], ubar[2]);
+        const double sp = ai + aj, sm = ai - aj;
+        s_u2 += wre * (sp * (b.d0u + c * c * b.d2u) + sm * c * b.d1u);
+        s_th += wre * (sp * (b.d0t + c * c * b.d2t) + sm * c * b.d1t);
+#pragma unroll
+        for (int m = 0; m < 10; ++m) abar[m] = fma(sm, vs::H3.c[i][m], abar[m]);
+    }
+#pragma unroll
+    for (int m = 0; m < 10; ++m) abar[m] *= kap;
+
+    // Qbar -> u: -sum_m abar_m (delta_ad C2_bc + delta_bd C2_ac + delta_cd C2_ab), C2 centred second moment
+    double C2[6];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = a; b < 3; ++b)
+            C2[sym2(a, b)] = rm.m2[sym2(a, b)] - u[a] * rm.m1[b] - u[b] * rm.m1[a] + rm.m0 * u[a] * u[b];
+    double uq[3] = {0, 0, 0};
+#pragma unroll
+    for (int m = 0; m < 10; ++m) {
+        const int a = vs::IDX3[m][0], b = vs::IDX3[m][1], c = vs::IDX3[m][2];
+        uq[a] -= abar[m] * C2[sym2(b, c)];
+        uq[b] -= abar[m] * C2[sym2(a, c)];
+        uq[c] -= abar[m] * C2[sym2(a, b)];
+    }
+
+    // ---- pair totals ----
+    const double S_om = pair_sum(s_om), S_ka = pair_sum(s_ka);
+    const double S_heq = pair_sum(om * s_heq);
+    const double S_eqT = pair_sum(is_g ? om * cp.beta * s_eqT : 0.0);
+    const double S_u2 = pair_sum(om * s_u2), S_th = pair_sum(om * s_th);
+    double U[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) U[a] = pair_sum(om * ubar[a] + uq[a]);
+
+    // omega = 1/tau, kappa = 1/tau - 1/tau_pr
+    const double om_bar = S_om + S_ka;
+    const double ompr_bar = -S_ka;
+    const double tau_bar = -om_bar / (tau * tau) - ompr_bar / (tau_pr * tau_pr) * cp.inv_pr;
+    const double mu_bar = tau_bar / (P * cp.dt);
+    const double P_bar = -tau_bar * mu_v / (P * P * cp.dt);
+    double T_bar = mu_bar * cp.mu_inf * dfac + P_bar * rho + S_th + S_eqT;
+    double rho_bar = P_bar * T + S_heq * ir;
+    double ub[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) ub[a] = U[a] + 2.0 * u[a] * S_u2;
+    // T = (K/rho - |u|^2) / (2 C_v)
+    const double K_bar = T_bar / (2.0 * Cv * rho);
+    rho_bar -= T_bar * K * ir * ir / (2.0 * Cv);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) ub[a] -= T_bar * u[a] / Cv;
+    // u = J / rho
+    double J_bar[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) J_bar[a] = ub[a] * ir;
+    rho_bar -= (ub[0] * u[0] + ub[1] * u[1] + ub[2] * u[2]) * ir;
+
+    // ---- per-velocity outputs ----
+    if (active) {
+        const double one_m = 1.0 - om;
+#pragma unroll
+        for (int k = 0; k < vs::Q; ++k) {
+            const double d0 = vs::T.xi[k][0] - u[0], d1 = vs::T.xi[k][1] - u[1], d2 = vs::T.xi[k][2] - u[2];
+            const double dd[3] = {d0, d1, d2};
+            double qterm = 0.0;
+#pragma unroll
+            for (int m = 0; m < 10; ++m)
+                qterm = fma(abar[m], dd[vs::IDX3[m][0]] * dd[vs::IDX3[m][1]] * dd[vs::IDX3[m][2]], qterm);
+            double r = one_m * al[k] + K_bar * (is_g ? 1.0 : vs::T.x2[k]) + qterm;
+            if (!is_g)
+                r += rho_bar + J_bar[0] * vs::T.xi[k][0] + J_bar[1] * vs::T.xi[k][1] + J_bar[2] * vs::T.xi[k][2];
+            lam[off + static_cast<int64_t>(k) * N] = static_cast<S>(r);
+        }
+    }
+
+    // ---- dL/dmu_inf: mu = mu_inf * fac, counted once per node (f lane) ----
+    if (active && !is_g) dmu_acc += mu_bar * fac;
+    }
+    red[threadIdx.x] = dmu_acc;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) dmu_part[blockIdx.x] = red[0];
+}
+
+// Fixed-order sum of n block partials by one block of 256 threads; the
+// result is added to *acc (add != 0) or stored there.  Deterministic.
+__global__ void __launch_bounds__(256) k_accumulate(const double *__restrict__ part, int n, double *__restrict__ acc,
+                                                    int add)
+{
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int b = threadIdx.x; b < n; b += 256) s += part[b];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *acc = add ? *acc + red[0] : red[0];
+}
+
+// ---------------------------------------------------------------------------
+// VJP of the equilibrium initialisation: fields -> (f^eq, g^eq)
+// ---------------------------------------------------------------------------
+template <typename S>
+__global__ void __launch_bounds__(256) k_init_vjp(int64_t N, CollisionParams cp, const double *__restrict__ rho,
+                                                  const double *__restrict__ u, const double *__restrict__ T,
+                                                  const S *__restrict__ lam, double *__restrict__ drho,
+                                                  double *__restrict__ du, double *__restrict__ dT)
+{
+    const int64_t n = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+    if (n >= N) return;
+    const double r = rho[n], uu[3] = {u[n], u[N + n], u[2 * N + n]}, Tn = T[n];
+    const double u2 = uu[0] * uu[0] + uu[1] * uu[1] + uu[2] * uu[2];
+    const double th = Tn - 1.0;
+    const double bT = cp.beta * Tn;
+    double gr = 0, gu[3] = {0, 0, 0}, gu2 = 0, gt = 0;
+#pragma unroll
+    for (int i = 0; i < vs::Q; ++i) {
+        const double a = static_cast<double>(lam[static_cast<int64_t>(i) * N + n]);
+        const double b = static_cast<double>(lam[static_cast<int64_t>(vs::Q + i) * N + n]);
+        const Bracket br = bracket(u2, th, vs::T.x2[i]);
+        const double c = vs::T.xi[i][0] * uu[0] + vs::T.xi[i][1] * uu[1] + vs::T.xi[i][2] * uu[2];
+        const double w = vs::T.w[i];
+        const double e = a + bT * b;                       // adjoint of f^eq_i (through f and g)
+        const double bv = bval(br, c);
+        gr += e * w * bv;
+        const double gc = e * w * r * bder(br, c);
+        gu[0] = fma(gc, vs::T.xi[i][0], gu[0]);
+        gu[1] = fma(gc, vs::T.xi[i][1], gu[1]);
+        gu[2] = fma(gc, vs::T.xi[i][2], gu[2]);
+        gu2 += e * w * r * (br.d0u + c * br.d1u + c * c * br.d2u);
+        gt += e * w * r * (br.d0t + c * br.d1t + c * c * br.d2t) + b * cp.beta * w * r * bv;
+    }
+    if (drho) drho[n] = gr;
+    if (du) {
+        du[n] = gu[0] + 2.0 * uu[0] * gu2;
+        du[N + n] = gu[1] + 2.0 * uu[1] * gu2;
+        du[2 * N + n] = gu[2] + 2.0 * uu[2] * gu2;
+    }
+    if (dT) dT[n] = gt;
+}
+
+// ---------------------------------------------------------------------------
+// VJP of the moments (Eq. (7) with 2 rho E = rho |u|^2 + 2 C_v rho T): given
+// adjoints of rho, u, T at every node, lam = d(rho, u, T)/d(state)^T (...).
+// ---------------------------------------------------------------------------
+template <typename S>
+__global__ void __launch_bounds__(256) k_moments_vjp(int64_t N, CollisionParams cp, const S *__restrict__ st,
+                                                     const double *__restrict__ drho, const double *__restrict__ du,
+                                                     const double *__restrict__ dT, S *__restrict__ lam)
+{
+    const int64_t n = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+    if (n >= N) return;
+    double r = 0, j[3] = {0, 0, 0}, K = 0;
+#pragma unroll
+    for (int i = 0; i < vs::Q; ++i) {
+        const double f = static_cast<double>(st[static_cast<int64_t>(i) * N + n]);
+        const double g = static_cast<double>(st[static_cast<int64_t>(vs::Q + i) * N + n]);
+        r += f;
+        j[0] = fma(f, vs::T.xi[i][0], j[0]);
+        j[1] = fma(f, vs::T.xi[i][1], j[1]);
+        j[2] = fma(f, vs::T.xi[i][2], j[2]);
+        K += fma(f, vs::T.x2[i], g);
+    }
+    const double ir = 1.0 / r;
+    const double u[3] = {j[0] * ir, j[1] * ir, j[2] * ir};
+    const double Tb = dT ? dT[n] : 0.0;
+    double rb = drho ? drho[n] : 0.0;
+    double ub[3] = {du ? du[n] : 0.0, du ? du[N + n] : 0.0, du ? du[2 * N + n] : 0.0};
+    // T = (K/rho - |u|^2) / (2 C_v)
+    const double Kb = Tb / (2.0 * cp.Cv * r);
+    rb -= Tb * K * ir * ir / (2.0 * cp.Cv);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) ub[a] -= Tb * u[a] / cp.Cv;
+    // u = J / rho
+    rb -= (ub[0] * u[0] + ub[1] * u[1] + ub[2] * u[2]) * ir;
+    const double Jb[3] = {ub[0] * ir, ub[1] * ir, ub[2] * ir};
+#pragma unroll
+    for (int i = 0; i < vs::Q; ++i) {
+        lam[static_cast<int64_t>(i) * N + n] = static_cast<S>(rb + Jb[0] * vs::T.xi[i][0] + Jb[1] * vs::T.xi[i][1] +
+                                                              Jb[2] * vs::T.xi[i][2] + Kb * vs::T.x2[i]);
+        lam[static_cast<int64_t>(vs::Q + i) * N + n] = static_cast<S>(Kb);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Flow functional L = sum over cells of the tensor Clenshaw-Curtis quadrature
+// of (1/2) rho |u|^2 + (div u)^2, div u from each cell's own polynomial.
+// ---------------------------------------------------------------------------
+template <typename S>
+__global__ void __launch_bounds__(256) k_rho_u(int64_t N, const S *__restrict__ st, double *__restrict__ rho,
+                                               double *__restrict__ u)
+{
+    const int64_t n = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+    if (n >= N) return;
+    double r = 0, j[3] = {0, 0, 0};
+#pragma unroll
+    for (int i = 0; i < vs::Q; ++i) {
+        const double f = static_cast<double>(st[static_cast<int64_t>(i) * N + n]);
+        r += f;
+        j[0] = fma(f, vs::T.xi[i][0], j[0]);
+        j[1] = fma(f, vs::T.xi[i][1], j[1]);
+        j[2] = fma(f, vs::T.xi[i][2], j[2]);
+    }
+    rho[n] = r;
+    u[n] = j[0] / r;
+    u[N + n] = j[1] / r;
+    u[2 * N + n] = j[2] / r;
+}
+
+struct CellGeo {
+    int N[3], nel[3], p;
+    int64_t nodes;
+    double h[3];
+};
+
+__device__ __forceinline__ int64_t node_of(const CellGeo &g, int gx, int gy, int gz)
+{
+    gx %= g.N[0];
+    gy %= g.N[1];
+    gz %= g.N[2];
+    return (static_cast<int64_t>(gz) * g.N[1] + gy) * g.N[0] + gx;
+}
+
+// per cell point: partial loss; sdiv[c] = 2 W_c div_c (for the gradient)
+__global__ void __launch_bounds__(256) k_loss_cells(CellGeo g, const double *__restrict__ dmat,
+                                                    const double *__restrict__ ccw, const double *__restrict__ rho,
+                                                    const double *__restrict__ u, double *__restrict__ sdiv,
+                                                    double *__restrict__ part)
+{
+    __shared__ double red[256];
+    const int p = g.p, p1 = p + 1;
+    const int64_t ncp = static_cast<int64_t>(g.nel[0]) * g.nel[1] * g.nel[2] * p1 * p1 * p1;
+    double acc = 0.0;
+    for (int64_t c = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; c < ncp;
+         c += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        int64_t r = c;
+        const int kx = static_cast<int>(r % p1); r /= p1;
+        const int ky = static_cast<int>(r % p1); r /= p1;
+        const int kz = static_cast<int>(r % p1); r /= p1;
+        const int ex = static_cast<int>(r % g.nel[0]); r /= g.nel[0];
+        const int ey = static_cast<int>(r % g.nel[1]);
+        const int ez = static_cast<int>(r / g.nel[1]);
+        const int gx = ex * p + kx, gy = ey * p + ky, gz = ez * p + kz;
+        double div = 0.0;
+        for (int m = 0; m <= p; ++m) {
+            div += dmat[kx * p1 + m] * u[node_of(g, ex * p + m, gy, gz)] / g.h[0];
+            div += dmat[ky * p1 + m] * u[g.nodes + node_of(g, gx, ey * p + m, gz)] / g.h[1];
+            div += dmat[kz * p1 + m] * u[2 * g.nodes + node_of(g, gx, gy, ez * p + m)] / g.h[2];
+        }
+        const int64_t n = node_of(g, gx, gy, gz);
+        const double ux = u[n], uy = u[g.nodes + n], uz = u[2 * g.nodes + n];
+        const double W = (0.5 * g.h[0] * ccw[kx]) * (0.5 * g.h[1] * ccw[ky]) * (0.5 * g.h[2] * ccw[kz]);
+        acc += W * (0.5 * rho[n] * (ux * ux + uy * uy + uz * uz) + div * div);
+        if (sdiv) sdiv[c] = 2.0 * W * div;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// dL/d(state) at every node: dL/drho and dL/du gathered from the cell points
+// whose value or derivative stencil contains the node, then chained through
+// rho = sum f and u = sum f xi / rho (g does not enter L).
+template <typename S>
+__global__ void __launch_bounds__(256) k_loss_grad(CellGeo g, const double *__restrict__ dmat,
+                                                   const double *__restrict__ nodew, const double *__restrict__ rho,
+                                                   const double *__restrict__ u, const double *__restrict__ sdiv,
+                                                   S *__restrict__ lam)
+{
+    const int64_t n = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+    if (n >= g.nodes) return;
+    const int p = g.p, p1 = p + 1;
+    const int gi[3] = {static_cast<int>(n % g.N[0]), static_cast<int>((n / g.N[0]) % g.N[1]),
+                       static_cast<int>(n / (static_cast<int64_t>(g.N[0]) * g.N[1]))};
+    const double W = nodew[gi[0]] * nodew[g.N[0] + gi[1]] * nodew[g.N[0] + g.N[1] + gi[2]];
+    const double r = rho[n];
+    const double uu[3] = {u[n], u[g.nodes + n], u[2 * g.nodes + n]};
+    double du[3];
+    // the cell (and local index) containing node index gi along an axis: own cell, and
+    // for a cell end point also the previous cell with local index p
+    int ce[3][2], ck[3][2], nopt[3];
+    for (int a = 0; a < 3; ++a) {
+        const int e = gi[a] / p, l = gi[a] % p;
+        ce[a][0] = e;
+        ck[a][0] = l;
+        nopt[a] = 1;
+        if (l == 0) {
+            ce[a][1] = (e - 1 + g.nel[a]) % g.nel[a];
+            ck[a][1] = p;
+            nopt[a] = 2;
+        }
+    }
+    for (int a = 0; a < 3; ++a) {
+        const int b = (a + 1) % 3, c = (a + 2) % 3;
+        double s = 0.0;
+        for (int oa = 0; oa < nopt[a]; ++oa)             // cell along a and the node's index m in it
+            for (int ob = 0; ob < nopt[b]; ++ob)
+                for (int oc = 0; oc < nopt[c]; ++oc)
+                    for (int ka = 0; ka <= p; ++ka) {      // cell point along a
+                        int E[3], kk[3];
+                        E[a] = ce[a][oa];
+                        kk[a] = ka;
+                        E[b] = ce[b][ob];
+                        kk[b] = ck[b][ob];
+                        E[c] = ce[c][oc];
+                        kk[c] = ck[c][oc];
+                        const int64_t cp = ((static_cast<int64_t>(E[2]) * g.nel[1] + E[1]) * g.nel[0] + E[0]) *
+                                               (p1 * p1 * p1) +
+                                           (kk[2] * p1 + kk[1]) * p1 + kk[0];
+                        s += sdiv[cp] * dmat[ka * p1 + ck[a][oa]];
+                    }
+        du[a] = r * uu[a] * W + s / g.h[a];
+    }
+    const double drho = 0.5 * (uu[0] * uu[0] + uu[1] * uu[1] + uu[2] * uu[2]) * W -
+                        (du[0] * uu[0] + du[1] * uu[1] + du[2] * uu[2]) / r;
+    const double dj[3] = {du[0] / r, du[1] / r, du[2] / r};
+#pragma unroll
+    for (int i = 0; i < vs::Q; ++i) {
+        lam[static_cast<int64_t>(i) * g.nodes + n] =
+            static_cast<S>(drho + dj[0] * vs::T.xi[i][0] + dj[1] * vs::T.xi[i][1] + dj[2] * vs::T.xi[i][2]);
+        lam[static_cast<int64_t>(vs::Q + i) * g.nodes + n] = static_cast<S>(0);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+
+static CellGeo cell_geo(const Geometry &g, const double *hh)
+{
+    CellGeo c;
+    for (int a = 0; a < 3; ++a) {
+        c.N[a] = g.N[a];
+        c.nel[a] = g.nel[a];
+        c.h[a] = hh[a];
+    }
+    c.p = g.p;
+    c.nodes = g.nodes;
+    return c;
+}
+
+template <typename S>
+hipError_t Launch<S>::loss(const Geometry &g, const S *state, const double *dmat, const double *ccw, const double *h,
+                           double *scratch_rho, double *scratch_u, double *partials, int nblocks, double *out1,
+                           hipStream_t st)
+{
+    const unsigned nb = static_cast<unsigned>((g.nodes + 255) / 256);
+    hipLaunchKernelGGL((k_rho_u<S>), dim3(nb), dim3(256), 0, st, g.nodes, state, scratch_rho, scratch_u);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_loss_cells, dim3(nblocks), dim3(256), 0, st, cell_geo(g, h), dmat, ccw, scratch_rho,
+                       scratch_u, static_cast<double *>(nullptr), partials);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_accumulate, dim3(1), dim3(256), 0, st, partials, nblocks, out1, 0);
+    return hipGetLastError();
+}
+
+template <typename S>
+hipError_t Launch<S>::loss_grad(const Geometry &g, const S *state, const double *dmat, const double *ccw,
+                                const double *nodew, const double *h, double *scratch_rho, double *scratch_u,
+                                double *scratch_div, double *partials, int nblocks, S *lam, hipStream_t st)
+{
+    const unsigned nb = static_cast<unsigned>((g.nodes + 255) / 256);
+    hipLaunchKernelGGL((k_rho_u<S>), dim3(nb), dim3(256), 0, st, g.nodes, state, scratch_rho, scratch_u);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_loss_cells, dim3(nblocks), dim3(256), 0, st, cell_geo(g, h), dmat, ccw, scratch_rho,
+                       scratch_u, scratch_div, partials);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL((k_loss_grad<S>), dim3(nb), dim3(256), 0, st, cell_geo(g, h), dmat, nodew, scratch_rho,
+                       scratch_u, scratch_div, lam);
+    return hipGetLastError();
+}
+
+template <typename S>
+hipError_t Launch<S>::adjoint_step(const Geometry &g, const StreamTables &t, const CollisionParams &cp,
+                                   const S *state_n, const S *lam_next, S *lam_out, double *dmu_partials, int nblocks,
+                                   double *dmu, hipStream_t st)
+{
+    // lam_out <- S^T lam_next, then lam_out <- J_C(X_n)^T lam_out in place
+    hipError_t e = stream_only(g, t, lam_next, lam_out, st);
+    if (e != hipSuccess) return e;
+    const int blocks = static_cast<int>(std::min<int64_t>((2 * g.nodes + 255) / 256, nblocks));
+    hipLaunchKernelGGL((k_collide_vjp<S>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, g.nodes, cp,
+                       state_n, lam_out, lam_out, dmu_partials);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (dmu) {
+        hipLaunchKernelGGL(k_accumulate, dim3(1), dim3(256), 0, st, dmu_partials, blocks, dmu, 1);
+        e = hipGetLastError();
+    }
+    return e;
+}
+
+template <typename S>
+hipError_t Launch<S>::init_equilibrium_vjp(const Geometry &g, const CollisionParams &cp, const double *rho,
+                                           const double *u, const double *T, const S *lam0, double *drho, double *du,
+                                           double *dT, hipStream_t st)
+{
+    const unsigned nb = static_cast<unsigned>((g.nodes + 255) / 256);
+    hipLaunchKernelGGL((k_init_vjp<S>), dim3(nb), dim3(256), 0, st, g.nodes, cp, rho, u, T, lam0, drho, du, dT);
+    return hipGetLastError();
+}
+
+template <typename S>
+hipError_t Launch<S>::moments_vjp(const Geometry &g, const CollisionParams &cp, const S *state, const double *drho,
+                                  const double *du, const double *dT, S *lam, hipStream_t st)
+{
+    const unsigned nb = static_cast<unsigned>((g.nodes + 255) / 256);
+    hipLaunchKernelGGL((k_moments_vjp<S>), dim3(nb), dim3(256), 0, st, g.nodes, cp, state, drho, du, dT, lam);
+    return hipGetLastError();
+}
+
+template struct Launch<double>;
+template struct Launch<float>;
+
+}  // namespace sllbm

@@ -18,6 +18,7 @@ namespace {
 enum Mode { MODE_PRE = 0, MODE_POST = 1 };
 
 constexpr int RED_BLOCKS = 1024;   // blocks of the deterministic reductions
+constexpr int ADJ_BLOCKS = 4096;   // largest grid of the collision VJP (grid-stride beyond)
 
 std::string g_create_error;
 
@@ -50,12 +51,13 @@ struct sllbm_ctx {
     double *d_nodew = nullptr;     // [Nx + Ny + Nz] 1-D node quadrature weights
     double *d_ccw = nullptr;       // [p+1] Clenshaw-Curtis weights of a cell, mapped to [0, 1] per unit h
     double *d_dmat = nullptr;      // [(p+1)^2] d ell_m / ds at t_k
-    double *d_h = nullptr;         // [3] cell widths
     double *d_partials = nullptr;  // [RED_BLOCKS * 8]
     double *d_small = nullptr;     // [16] reduction results
     double *d_scr_rho = nullptr;   // [N]   loss scratch
     double *d_scr_u = nullptr;     // [3N]
     double *d_scr_div = nullptr;   // [cells * (p+1)^3]
+    double *d_adj_part = nullptr;  // [ADJ_BLOCKS] dmu_inf partials of the collision VJP
+    double h[3] = {0, 0, 0};       // cell widths (host)
     std::string err;
 };
 
@@ -107,12 +109,12 @@ void free_ctx(sllbm_ctx *c)
     (void)hipFree(c->d_nodew);
     (void)hipFree(c->d_ccw);
     (void)hipFree(c->d_dmat);
-    (void)hipFree(c->d_h);
     (void)hipFree(c->d_partials);
     (void)hipFree(c->d_small);
     (void)hipFree(c->d_scr_rho);
     (void)hipFree(c->d_scr_u);
     (void)hipFree(c->d_scr_div);
+    (void)hipFree(c->d_adj_part);
 }
 
 // Cells per tile: about 8 x 8 x 4 nodes (at most 256, one node per thread).
@@ -312,7 +314,7 @@ int sllbm_create(const sllbm_config *cfg, sllbm_ctx **out)
 
     build_velocity_set(c->vs);
     double h[3];
-    for (int a = 0; a < 3; ++a) h[a] = cfg->length[a] / cfg->n_el[a];
+    for (int a = 0; a < 3; ++a) c->h[a] = h[a] = cfg->length[a] / cfg->n_el[a];
     build_axis_tables(c->vs, g.p, h, cfg->dt, c->htab[0], c->htab[1]);
 
     auto bail = [&](int rc) {
@@ -352,19 +354,18 @@ int sllbm_create(const sllbm_config *cfg, sllbm_ctx **out)
     if ((e = dalloc(&c->d_nodew, nodew.size() * sizeof(double))) != hipSuccess ||
         (e = dalloc(&c->d_ccw, (p + 1) * sizeof(double))) != hipSuccess ||
         (e = dalloc(&c->d_dmat, dmat.size() * sizeof(double))) != hipSuccess ||
-        (e = dalloc(&c->d_h, 3 * sizeof(double))) != hipSuccess ||
         (e = dalloc(&c->d_partials, RED_BLOCKS * 8 * sizeof(double))) != hipSuccess ||
         (e = dalloc(&c->d_small, 16 * sizeof(double))) != hipSuccess ||
         (e = dalloc(&c->d_scr_rho, nodes * sizeof(double))) != hipSuccess ||
         (e = dalloc(&c->d_scr_u, 3 * nodes * sizeof(double))) != hipSuccess ||
-        (e = dalloc(&c->d_scr_div, cpts * sizeof(double))) != hipSuccess)
+        (e = dalloc(&c->d_scr_div, cpts * sizeof(double))) != hipSuccess ||
+        (e = dalloc(&c->d_adj_part, ADJ_BLOCKS * sizeof(double))) != hipSuccess)
         return bail(fail(c, SLLBM_ENOMEM, std::string("allocation failed: ") + hipGetErrorString(e)));
     if ((e = hipMemcpy(c->d_nodew, nodew.data(), nodew.size() * sizeof(double), hipMemcpyHostToDevice)) !=
             hipSuccess ||
         (e = hipMemcpy(c->d_ccw, cc, (p + 1) * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(c->d_dmat, dmat.data(), dmat.size() * sizeof(double), hipMemcpyHostToDevice)) !=
-            hipSuccess ||
-        (e = hipMemcpy(c->d_h, h, 3 * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess)
+            hipSuccess)
         return bail(hip_fail(c, e, "upload"));
     *out = c;
     return SLLBM_OK;
@@ -561,16 +562,84 @@ int sllbm_collide(sllbm_ctx *ctx, void *state)
 // ---------------------------------------------------------------------------
 extern "C" {
 
-int sllbm_loss(sllbm_ctx *ctx, const void *, double *) { return fail(ctx, SLLBM_ESTATE, "not available"); }
-int sllbm_loss_grad(sllbm_ctx *ctx, const void *, void *) { return fail(ctx, SLLBM_ESTATE, "not available"); }
-int sllbm_adjoint_step(sllbm_ctx *ctx, const void *, const void *, void *, double *)
+int sllbm_loss(sllbm_ctx *ctx, const void *state, double *out)
 {
-    return fail(ctx, SLLBM_ESTATE, "not available");
+    if (!ctx) return SLLBM_EINVAL;
+    if (!state || !out) return fail(ctx, SLLBM_EINVAL, "NULL argument");
+    DeviceGuard guard(ctx->cfg.device);
+    hipError_t e = is_fp64(ctx)
+        ? Launch<double>::loss(ctx->geo, static_cast<const double *>(state), ctx->d_dmat, ctx->d_ccw, ctx->h,
+                               ctx->d_scr_rho, ctx->d_scr_u, ctx->d_partials, RED_BLOCKS, ctx->d_small, ctx->stream)
+        : Launch<float>::loss(ctx->geo, static_cast<const float *>(state), ctx->d_dmat, ctx->d_ccw, ctx->h,
+                              ctx->d_scr_rho, ctx->d_scr_u, ctx->d_partials, RED_BLOCKS, ctx->d_small, ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "loss");
+    if ((e = hipMemcpyAsync(out, ctx->d_small, sizeof(double), hipMemcpyDeviceToHost, ctx->stream)) != hipSuccess ||
+        (e = hipStreamSynchronize(ctx->stream)) != hipSuccess)
+        return hip_fail(ctx, e, "loss copy");
+    if (!std::isfinite(*out)) return fail(ctx, SLLBM_ENONFINITE, "non-finite loss");
+    return SLLBM_OK;
 }
-int sllbm_init_equilibrium_vjp(sllbm_ctx *ctx, const double *, const double *, const double *, const void *,
-                               double *, double *, double *)
+
+int sllbm_loss_grad(sllbm_ctx *ctx, const void *state, void *lam)
 {
-    return fail(ctx, SLLBM_ESTATE, "not available");
+    if (!ctx) return SLLBM_EINVAL;
+    if (!state || !lam || state == lam) return fail(ctx, SLLBM_EINVAL, "bad loss_grad buffers");
+    DeviceGuard guard(ctx->cfg.device);
+    hipError_t e = is_fp64(ctx)
+        ? Launch<double>::loss_grad(ctx->geo, static_cast<const double *>(state), ctx->d_dmat, ctx->d_ccw,
+                                    ctx->d_nodew, ctx->h, ctx->d_scr_rho, ctx->d_scr_u, ctx->d_scr_div,
+                                    ctx->d_partials, RED_BLOCKS, static_cast<double *>(lam), ctx->stream)
+        : Launch<float>::loss_grad(ctx->geo, static_cast<const float *>(state), ctx->d_dmat, ctx->d_ccw,
+                                   ctx->d_nodew, ctx->h, ctx->d_scr_rho, ctx->d_scr_u, ctx->d_scr_div,
+                                   ctx->d_partials, RED_BLOCKS, static_cast<float *>(lam), ctx->stream);
+    return check_launch(ctx, e, "loss_grad");
+}
+
+int sllbm_adjoint_step(sllbm_ctx *ctx, const void *state_n, const void *lam_next, void *lam_out, double *dmu)
+{
+    if (!ctx) return SLLBM_EINVAL;
+    if (!state_n || !lam_next || !lam_out) return fail(ctx, SLLBM_EINVAL, "NULL argument");
+    if (lam_out == lam_next || lam_out == state_n) return fail(ctx, SLLBM_EINVAL, "lam_out aliases an input");
+    DeviceGuard guard(ctx->cfg.device);
+    const StreamTables &t = ctx->dtab[1];
+    hipError_t e = is_fp64(ctx)
+        ? Launch<double>::adjoint_step(ctx->geo, t, ctx->cp, static_cast<const double *>(state_n),
+                                       static_cast<const double *>(lam_next), static_cast<double *>(lam_out),
+                                       ctx->d_adj_part, ADJ_BLOCKS, dmu, ctx->stream)
+        : Launch<float>::adjoint_step(ctx->geo, t, ctx->cp, static_cast<const float *>(state_n),
+                                      static_cast<const float *>(lam_next), static_cast<float *>(lam_out),
+                                      ctx->d_adj_part, ADJ_BLOCKS, dmu, ctx->stream);
+    return check_launch(ctx, e, "adjoint_step");
+}
+
+int sllbm_moments_vjp(sllbm_ctx *ctx, const double *drho, const double *du, const double *dT, void *lam)
+{
+    if (!ctx) return SLLBM_EINVAL;
+    if (!lam) return fail(ctx, SLLBM_EINVAL, "NULL lam");
+    if (!ctx->has_state) return fail(ctx, SLLBM_ESTATE, "no state set");
+    DeviceGuard guard(ctx->cfg.device);
+    // the Jacobian of (rho, u, T) depends on the moments only, which collision conserves,
+    // so the held buffer serves in either bookkeeping mode
+    hipError_t e = is_fp64(ctx)
+        ? Launch<double>::moments_vjp(ctx->geo, ctx->cp, static_cast<const double *>(ctx->buf[ctx->cur]), drho, du,
+                                      dT, static_cast<double *>(lam), ctx->stream)
+        : Launch<float>::moments_vjp(ctx->geo, ctx->cp, static_cast<const float *>(ctx->buf[ctx->cur]), drho, du, dT,
+                                     static_cast<float *>(lam), ctx->stream);
+    return check_launch(ctx, e, "moments_vjp");
+}
+
+int sllbm_init_equilibrium_vjp(sllbm_ctx *ctx, const double *rho, const double *u, const double *T,
+                               const void *lam0, double *drho, double *du, double *dT)
+{
+    if (!ctx) return SLLBM_EINVAL;
+    if (!rho || !u || !T || !lam0) return fail(ctx, SLLBM_EINVAL, "NULL argument");
+    DeviceGuard guard(ctx->cfg.device);
+    hipError_t e = is_fp64(ctx)
+        ? Launch<double>::init_equilibrium_vjp(ctx->geo, ctx->cp, rho, u, T, static_cast<const double *>(lam0),
+                                               drho, du, dT, ctx->stream)
+        : Launch<float>::init_equilibrium_vjp(ctx->geo, ctx->cp, rho, u, T, static_cast<const float *>(lam0), drho,
+                                              du, dT, ctx->stream);
+    return check_launch(ctx, e, "init_equilibrium_vjp");
 }
 
 }  // extern "C"

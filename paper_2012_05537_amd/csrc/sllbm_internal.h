@@ -111,10 +111,13 @@ struct Launch {
                            int nblocks, double *out1, hipStream_t st);
     static hipError_t loss_grad(const Geometry &g, const S *state, const double *dmat, const double *ccw,
                                 const double *nodew, const double *h, double *scratch_rho,
-                                double *scratch_u, double *scratch_div, S *lam, hipStream_t st);
+                                double *scratch_u, double *scratch_div, double *partials, int nblocks, S *lam,
+                                hipStream_t st);
     static hipError_t adjoint_step(const Geometry &g, const StreamTables &t, const CollisionParams &cp,
                                    const S *state_n, const S *lam_next, S *lam_out, double *dmu_partials,
                                    int nblocks, double *dmu, hipStream_t st);
+    static hipError_t moments_vjp(const Geometry &g, const CollisionParams &cp, const S *state, const double *drho,
+                                  const double *du, const double *dT, S *lam, hipStream_t st);
     static hipError_t init_equilibrium_vjp(const Geometry &g, const CollisionParams &cp, const double *rho,
                                            const double *u, const double *T, const S *lam0, double *drho,
                                            double *du, double *dT, hipStream_t st);

@@ -66,6 +66,7 @@ _SIGS = {
     "sllbm_loss": (ctypes.c_int, [_VP, _VP, _VP]),
     "sllbm_loss_grad": (ctypes.c_int, [_VP, _VP, _VP]),
     "sllbm_adjoint_step": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP]),
+    "sllbm_moments_vjp": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP]),
     "sllbm_init_equilibrium_vjp": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
     "sllbm_stream": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int32]),
     "sllbm_collide": (ctypes.c_int, [_VP, _VP]),
@@ -244,6 +245,14 @@ class SLLBM:
         self._check(self._lib.sllbm_adjoint_step(self._h, self._state_arg(state_n), self._state_arg(lam_next),
                                                  self._state_arg(lam_out), _ptr(dmu)))
         return lam_out
+
+    def moments_vjp(self, drho=None, du=None, dT=None, out=None):
+        self._sync_stream()
+        f64 = dict(dtype=torch.float64, device=self.device)
+        args = [None if x is None else x.to(**f64).contiguous() for x in (drho, du, dT)]
+        out = self.empty_state() if out is None else out
+        self._check(self._lib.sllbm_moments_vjp(self._h, *[_ptr(a) for a in args], self._state_arg(out)))
+        return out
 
     def init_equilibrium_vjp(self, rho, u, T, lam0):
         self._sync_stream()
