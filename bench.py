@@ -35,7 +35,7 @@ def kernel_source_hash():
 def measured_traffic(workload, dtype):
     """HBM bytes per launch of the fused kernel from the committed rocprofv3
     counter summary, if it was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", "stream_collide_traffic.json")
+    path = os.path.join(ROOT, "profiles", "k_fused_traffic.json")
     if not os.path.exists(path):
         return None
     try:
