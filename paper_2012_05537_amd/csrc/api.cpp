@@ -18,7 +18,8 @@ namespace {
 enum Mode { MODE_PRE = 0, MODE_POST = 1 };
 
 constexpr int RED_BLOCKS = 1024;   // blocks of the deterministic reductions
-constexpr int ADJ_BLOCKS = 4096;   // largest grid of the collision VJP (grid-stride beyond)
+constexpr int ADJ_BLOCKS = 4096;
+constexpr int FUSED_CONCURRENT = 32;  // fused blocks one XCD holds at once (32 CUs, one block each)   // largest grid of the collision VJP (grid-stride beyond)
 
 std::string g_create_error;
 
@@ -305,6 +306,7 @@ int sllbm_create(const sllbm_config *cfg, sllbm_ctx **out)
     c->fgeo = g;
     fused_tile(g.p, c->fgeo.TE);
     for (int a = 0; a < 3; ++a) c->fgeo.ntile[a] = (g.nel[a] + c->fgeo.TE[a] - 1) / c->fgeo.TE[a];
+    fused_bricks(c->fgeo, FUSED_CONCURRENT);
     c->cp.dt = cfg->dt;
     c->cp.Cv = 1.0 / (cfg->gamma - 1.0);
     c->cp.beta = 2.0 * c->cp.Cv - 3.0;

@@ -27,6 +27,8 @@
 // halo of neighbouring tiles in that XCD's L2.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cmath>
 #include <type_traits>
 
 #include "collision.h"
@@ -58,12 +60,34 @@ __device__ __forceinline__ int wrap(int x, int n)
     return r < 0 ? r + n : r;
 }
 
-// tile index of this block: contiguous ranges of tiles per XCD
+// walk index of this block: contiguous ranges of the walk per XCD
 __device__ __forceinline__ int xcd_tile(int b, int nb)
 {
     const int xcd = b & 7, slot = b >> 3;
     const int per = nb >> 3, rem = nb & 7;
     return xcd < rem ? xcd * (per + 1) + slot : rem * (per + 1) + (xcd - rem) * per + slot;
+}
+
+// Tile coordinates of walk index L.  The walk visits bricks of
+// brick[0] x brick[1] x brick[2] tiles (smaller at the far edges) in z-slab,
+// y-row, x order, and the tiles of a brick in x-y-z order, so the blocks one
+// XCD holds at a time cover a compact brick whose halo is shared in L2.
+__device__ __forceinline__ void walk_tile(int L, const Geometry &g, int &tx, int &ty, int &tz)
+{
+    const int nx = g.ntile[0], ny = g.ntile[1], nz = g.ntile[2];
+    const int BX = g.brick[0], BY = g.brick[1], BZ = g.brick[2];
+    const int slab = L / (nx * ny * BZ);
+    const int z0 = slab * BZ, bzs = min(BZ, nz - z0);
+    int r = L - slab * nx * ny * BZ;
+    const int row = r / (nx * BY * bzs);
+    const int y0 = row * BY, bys = min(BY, ny - y0);
+    r -= row * nx * BY * bzs;
+    const int bxi = r / (BX * bys * bzs);
+    const int x0 = bxi * BX, bxs = min(BX, nx - x0);
+    r -= bxi * BX * bys * bzs;
+    tx = x0 + r % bxs;
+    ty = y0 + (r / bxs) % bys;
+    tz = z0 + r / (bxs * bys);
 }
 
 // Per-block state of the fused kernel.  A block has 8 waves; in each round
@@ -163,10 +187,8 @@ __global__ void __launch_bounds__(512, MINB)
     const int64_t N = geo.nodes;
 
     // tile origin
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    const int tcx = tile % geo.ntile[0];
-    const int tcy = (tile / geo.ntile[0]) % geo.ntile[1];
-    const int tcz = tile / (geo.ntile[0] * geo.ntile[1]);
+    int tcx, tcy, tcz;
+    walk_tile(uniform(xcd_tile(blockIdx.x, gridDim.x)), geo, tcx, tcy, tcz);
     const int X0 = tcx * TX, Y0 = tcy * TY, Z0 = tcz * TZ;
 
     // global node offsets of every round's windows
@@ -304,6 +326,34 @@ static hipError_t launch_fused_t(const Geometry &g, const FusedTables<S> &t, con
         hipLaunchKernelGGL((k_fused<S, P, TEX, TEY, TEZ, false, MB>), dim3(nb), dim3(512), 0, st, g, t, cp, in,
                            out, pre);
     return hipGetLastError();
+}
+
+// Brick of about `concurrent` tiles (the blocks one XCD holds at once).  A
+// brick spans whole x rows of tiles when they fit, so its rows are read as
+// full cache lines and its x halo is its own data (periodic); its y and z
+// extents minimise the ratio of the one-cell-wider read window to the
+// brick's own cells.
+void fused_bricks(Geometry &g, int concurrent)
+{
+    const int bx = std::min(g.ntile[0], concurrent);
+    double best = 1e300;
+    int bb[3] = {bx, 1, 1};
+    for (int by = 1; by <= g.ntile[1]; ++by)
+        for (int bz = 1; bz <= g.ntile[2]; ++bz) {
+            if (bx * by * bz > concurrent) break;
+            const double cy = by * g.TE[1], cz = bz * g.TE[2];
+            const double wy = by == g.ntile[1] ? cy : cy + 1, wz = bz == g.ntile[2] ? cz : cz + 1;
+            const double wx = bx == g.ntile[0] ? 1.0 : (bx * g.TE[0] + 1.0) / (bx * g.TE[0]);
+            // fewer tiles than the XCD holds leave CUs idle between bricks: weigh by fill
+            const double fill = static_cast<double>(bx * by * bz) / concurrent;
+            const double ratio = wx * wy * wz / (cy * cz) / std::sqrt(fill);
+            if (ratio < best - 1e-12) {
+                best = ratio;
+                bb[1] = by;
+                bb[2] = bz;
+            }
+        }
+    for (int a = 0; a < 3; ++a) g.brick[a] = bb[a];
 }
 
 void fused_tile(int p, int te[3])

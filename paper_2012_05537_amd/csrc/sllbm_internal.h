@@ -58,6 +58,7 @@ struct Geometry {
     int p;           // order
     int TE[3];       // cells per tile and axis
     int ntile[3];    // tiles per axis
+    int brick[3];    // tiles per brick and axis (tile walk order of the fused kernel)
     int64_t nodes;   // N[0]*N[1]*N[2]
 };
 
@@ -127,6 +128,7 @@ template <typename S>
 hipError_t launch_fused(const Geometry &g, const FusedTables<S> &t, const CollisionParams &cp, const S *in, S *out,
                         S *pre, bool collide, hipStream_t st);
 void fused_tile(int p, int te[3]);
+void fused_bricks(Geometry &g, int concurrent);
 void build_fused_tables(const AxisTables &fwd, std::vector<int32_t> &omin, std::vector<int32_t> &lstar,
                         std::vector<double> &w);
 
