@@ -96,6 +96,46 @@ def run_gpu(args, wl, precision):
     return dict(nodes=nodes, wall=wall, kernel_ms=kernel_ms, bytes=bytes_per_launch, finite=ok, totals=tot)
 
 
+def run_adjoint(wl, precision):
+    """Wall time of a checkpointed rollout gradient of the workload (forward
+    rollout with checkpoints, then the reverse sweep with segment replay), and
+    the ratio backward / forward."""
+    import numpy as np
+    import torch
+    from paper_2012_05537_amd import inputs
+    from paper_2012_05537_amd.adjoint import Rollout
+    from paper_2012_05537_amd.sllbm import SLLBM
+
+    ctx = SLLBM(wl["n_el"], wl["p"], wl["dt"], wl["mu_inf"], gamma=wl["gamma"], prandtl=wl["Pr"],
+                precision=precision)
+    xs, ys, zs = (t.numpy() for t in ctx.node_coords())
+    md = wl.get("modes") or dict(seed=2012, count=16, scale=0.01)
+    modes = inputs.fourier_modes(md["seed"], md["count"], wl["Ma"], wl["gamma"], md["scale"])
+    rho, u, T = inputs.tgv_fields(xs, ys, zs, wl["Ma"], wl["gamma"])
+    B = inputs.mode_basis(xs, ys, zs, modes)
+    steps = wl["steps"]
+    roll = Rollout(ctx, rho, u, T, B, steps, checkpoint=wl.get("checkpoint", 10))
+    del B
+    amps = torch.tensor(np.array([m[3] for m in modes]), dtype=torch.float64, requires_grad=True)
+    mu = torch.tensor(wl["mu_inf"], dtype=torch.float64, requires_grad=True)
+    roll(amps, mu).backward()                     # warm-up (allocations, first launches)
+    amps.grad = None
+    mu.grad = None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    L = roll(amps, mu)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    L.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    ctx.close()
+    return {"workload": f"{wl['name']}: {wl['n_el']}^3 cells p={wl['p']} ({ctx.nodes} nodes), {steps} steps, "
+                        f"{len(modes)} modes + mu_inf, checkpoint {wl.get('checkpoint', 10)}",
+            "forward_s": t1 - t0, "backward_s": t2 - t1, "backward_over_forward": (t2 - t1) / (t1 - t0),
+            "loss": L.item(), "grad_finite": bool(torch.isfinite(amps.grad).all() and math.isfinite(mu.grad.item()))}
+
+
 def cpu_baseline(wl, budget_s):
     """The FP64 oracle on the host cores: whole-grid steps of the same workload
     (same grid, same parameters) until about budget_s seconds have run."""
@@ -130,6 +170,9 @@ def main():
     ap.add_argument("--precision", choices=["fp64", "fp32"], default=None)
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--adjoint-workload", default="c4",
+                    help="workload whose rollout gradient is timed for the adjoint/forward ratio ('none' to skip)")
+    ap.add_argument("--adjoint-cfl", type=float, default=None, help="CFL override of the adjoint workload")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run three plain copies of one state's size first (HBM counter calibration)")
     args = ap.parse_args()
@@ -170,6 +213,10 @@ def main():
                      "algorithmic_bytes_per_launch": r["bytes"]},
         "finite": r["finite"],
     }
+    if args.adjoint_workload != "none":
+        over = {} if args.adjoint_cfl is None else {"cfl": args.adjoint_cfl}
+        wa = inputs.workload(args.adjoint_workload, **over)
+        out["adjoint"] = run_adjoint(wa, 0 if wa["precision"] == "fp64" else 1)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_budget)
     print(json.dumps(out), flush=True)
