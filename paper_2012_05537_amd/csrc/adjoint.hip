@@ -245,6 +245,8 @@ __global__ void __launch_bounds__(256) k_collide_vjp(int64_t N, CollisionParams 
 
     // ---- per-velocity outputs ----
     if (active) {
+        S *lp = lam + off;
+        asm volatile("" : "+v"(lp));      // fresh store addresses (the load addresses are not kept live)
         const double one_m = 1.0 - om;
 #pragma unroll
         for (int k = 0; k < vs::Q; ++k) {
@@ -257,7 +259,7 @@ __global__ void __launch_bounds__(256) k_collide_vjp(int64_t N, CollisionParams 
             double r = one_m * al[k] + K_bar * (is_g ? 1.0 : vs::T.x2[k]) + qterm;
             if (!is_g)
                 r += rho_bar + J_bar[0] * vs::T.xi[k][0] + J_bar[1] * vs::T.xi[k][1] + J_bar[2] * vs::T.xi[k][2];
-            lam[off + static_cast<int64_t>(k) * N] = static_cast<S>(r);
+            lp[static_cast<int64_t>(k) * N] = static_cast<S>(r);
         }
     }
 

@@ -15,8 +15,6 @@ using namespace sllbm;
 
 namespace {
 
-enum Mode { MODE_PRE = 0, MODE_POST = 1 };
-
 constexpr int RED_BLOCKS = 1024;   // blocks of the deterministic reductions
 constexpr int ADJ_BLOCKS = 4096;
 constexpr int FUSED_CONCURRENT = 32;  // fused blocks one XCD holds at once (32 CUs, one block each)   // largest grid of the collision VJP (grid-stride beyond)
@@ -37,12 +35,10 @@ struct sllbm_ctx {
     void *d_fw = nullptr;         // fused-table weights, storage type
     hipStream_t stream = nullptr;
     size_t elem = 8;
-    // State buffers.  In MODE_PRE buf[cur] holds the pre-collision state X_k.
-    // In MODE_POST buf[cur] holds C(X_k) and buf[1-cur] holds C(X_{k-1}), so
-    // X_k = S(buf[1-cur]).  Moments are identical before and after collision.
+    // State buffers: buf[cur] holds the pre-collision state X_k; the other
+    // buffer receives C(X_k) during a step.
     void *buf[2] = {nullptr, nullptr};
     int cur = 0;
-    int mode = MODE_PRE;
     bool has_state = false;
     // device tables
     int32_t *d_off[2] = {nullptr, nullptr};
@@ -428,7 +424,6 @@ int sllbm_init_equilibrium(sllbm_ctx *ctx, const double *rho, const double *u, c
         : Launch<float>::init_equilibrium(ctx->geo, ctx->cp, rho, u, T, static_cast<float *>(ctx->buf[ctx->cur]),
                                           ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "init_equilibrium");
-    ctx->mode = MODE_PRE;
     ctx->has_state = true;
     return SLLBM_OK;
 }
@@ -441,7 +436,6 @@ int sllbm_set_state(sllbm_ctx *ctx, const void *state)
     hipError_t e = hipMemcpyAsync(ctx->buf[ctx->cur], state, sllbm_state_bytes(ctx), hipMemcpyDeviceToDevice,
                                   ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "set_state");
-    ctx->mode = MODE_PRE;
     ctx->has_state = true;
     return SLLBM_OK;
 }
@@ -452,15 +446,31 @@ int sllbm_get_state(sllbm_ctx *ctx, void *state)
     if (!state) return fail(ctx, SLLBM_EINVAL, "NULL state");
     if (!ctx->has_state) return fail(ctx, SLLBM_ESTATE, "no state set");
     DeviceGuard guard(ctx->cfg.device);
-    hipError_t e;
-    if (ctx->mode == MODE_PRE) {
-        e = hipMemcpyAsync(state, ctx->buf[ctx->cur], sllbm_state_bytes(ctx), hipMemcpyDeviceToDevice, ctx->stream);
-    } else {
-        e = run_fused(ctx, other(ctx), state, nullptr, false);
-    }
+    hipError_t e =
+        hipMemcpyAsync(state, ctx->buf[ctx->cur], sllbm_state_bytes(ctx), hipMemcpyDeviceToDevice, ctx->stream);
     return check_launch(ctx, e, "get_state");
 }
 
+static hipError_t collide_into(sllbm_ctx *c, const void *in, void *out)
+{
+    if (is_fp64(c))
+        return Launch<double>::collide_into(c->geo, c->cp, static_cast<const double *>(in), static_cast<double *>(out),
+                                            c->stream);
+    return Launch<float>::collide_into(c->geo, c->cp, static_cast<const float *>(in), static_cast<float *>(out),
+                                       c->stream);
+}
+
+static hipError_t stream_into(sllbm_ctx *c, const void *in, void *out)
+{
+    if (is_fp64(c))
+        return launch_stream_z<double>(c->geo, fused_tables<double>(c), static_cast<const double *>(in),
+                                       static_cast<double *>(out), c->stream);
+    return launch_stream_z<float>(c->geo, fused_tables<float>(c), static_cast<const float *>(in),
+                                  static_cast<float *>(out), c->stream);
+}
+
+// n steps X <- S(C(X)): collision into the spare buffer, streaming back into
+// the state buffer (or into record slot s, from which the next step collides).
 static int step_impl(sllbm_ctx *ctx, int32_t n, char *record, int64_t stride)
 {
     if (!ctx) return SLLBM_EINVAL;
@@ -468,21 +478,18 @@ static int step_impl(sllbm_ctx *ctx, int32_t n, char *record, int64_t stride)
     if (!ctx->has_state) return fail(ctx, SLLBM_ESTATE, "no state set");
     if (n == 0) return SLLBM_OK;
     DeviceGuard guard(ctx->cfg.device);
-    hipError_t e = hipSuccess;
-    if (ctx->mode == MODE_PRE) {
-        // C(X_k) in place; afterwards buf[cur] = C(X_k)
-        e = is_fp64(ctx) ? Launch<double>::collide_only(ctx->geo, ctx->cp, static_cast<double *>(ctx->buf[ctx->cur]),
-                                                        ctx->stream)
-                         : Launch<float>::collide_only(ctx->geo, ctx->cp, static_cast<float *>(ctx->buf[ctx->cur]),
-                                                       ctx->stream);
-        if (e != hipSuccess) return hip_fail(ctx, e, "collide");
-        ctx->mode = MODE_POST;
-    }
+    void *state = ctx->buf[ctx->cur], *post = other(ctx);
     for (int32_t s = 0; s < n; ++s) {
-        void *pre = record ? record + static_cast<int64_t>(s) * stride : nullptr;
-        e = run_fused(ctx, ctx->buf[ctx->cur], other(ctx), pre, true);
-        if (e != hipSuccess) return hip_fail(ctx, e, "stream_collide");
-        ctx->cur = 1 - ctx->cur;
+        const void *src = (record && s > 0) ? record + static_cast<int64_t>(s - 1) * stride : state;
+        void *dst = record ? record + static_cast<int64_t>(s) * stride : state;
+        hipError_t e = collide_into(ctx, src, post);
+        if (e != hipSuccess) return hip_fail(ctx, e, "collide");
+        if ((e = stream_into(ctx, post, dst)) != hipSuccess) return hip_fail(ctx, e, "stream");
+    }
+    if (record) {
+        hipError_t e = hipMemcpyAsync(state, record + static_cast<int64_t>(n - 1) * stride, sllbm_state_bytes(ctx),
+                                      hipMemcpyDeviceToDevice, ctx->stream);
+        if (e != hipSuccess) return hip_fail(ctx, e, "record copy");
     }
     return SLLBM_OK;
 }
@@ -536,7 +543,7 @@ int sllbm_stream(sllbm_ctx *ctx, const void *in, void *out, int32_t transpose)
     if (!ctx) return SLLBM_EINVAL;
     if (!in || !out || in == out) return fail(ctx, SLLBM_EINVAL, "bad stream buffers");
     DeviceGuard guard(ctx->cfg.device);
-    if (!transpose) return check_launch(ctx, run_fused(ctx, in, out, nullptr, false), "stream");
+    if (!transpose) return check_launch(ctx, stream_into(ctx, in, out), "stream");
     const StreamTables &t = ctx->dtab[1];
     hipError_t e = is_fp64(ctx)
         ? Launch<double>::stream_only(ctx->geo, t, static_cast<const double *>(in), static_cast<double *>(out),
@@ -620,8 +627,6 @@ int sllbm_moments_vjp(sllbm_ctx *ctx, const double *drho, const double *du, cons
     if (!lam) return fail(ctx, SLLBM_EINVAL, "NULL lam");
     if (!ctx->has_state) return fail(ctx, SLLBM_ESTATE, "no state set");
     DeviceGuard guard(ctx->cfg.device);
-    // the Jacobian of (rho, u, T) depends on the moments only, which collision conserves,
-    // so the held buffer serves in either bookkeeping mode
     hipError_t e = is_fp64(ctx)
         ? Launch<double>::moments_vjp(ctx->geo, ctx->cp, static_cast<const double *>(ctx->buf[ctx->cur]), drho, du,
                                       dT, static_cast<double *>(lam), ctx->stream)

@@ -224,20 +224,26 @@ __global__ void __launch_bounds__(256) k_stream_tab(Geometry geo, StreamTables t
 
 // Collision of a whole state, two lanes per node (f on the even lane, g on
 // the odd one), with the same code as the fused step.
+// in and out may be the same buffer (each lane reads its 45 values first).
 template <typename S>
-__global__ void __launch_bounds__(256) k_collide(int64_t N, CollisionParams cp, S *__restrict__ state)
+__global__ void __launch_bounds__(256) k_collide(int64_t N, CollisionParams cp, const S *in, S *out)
 {
     const int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
     const int64_t n = t >> 1;
     const int pop = static_cast<int>(t & 1);
     if (n >= N) return;                    // both lanes of a pair leave together
-    S *p = state + static_cast<int64_t>(pop) * Q * N + n;
+    const int64_t o = static_cast<int64_t>(pop) * Q * N + n;
+    const S *p = in + o;
     S v[Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i) v[i] = p[static_cast<int64_t>(i) * N];
     collide_half<S>(v, pop != 0, cp);
+    // derive the store addresses afresh: otherwise the 45 load addresses stay
+    // live through the collision (90 registers)
+    S *d = out + o;
+    asm volatile("" : "+v"(d));
 #pragma unroll
-    for (int i = 0; i < Q; ++i) p[static_cast<int64_t>(i) * N] = v[i];
+    for (int i = 0; i < Q; ++i) d[static_cast<int64_t>(i) * N] = v[i];
 }
 
 template <typename S>
@@ -414,8 +420,14 @@ hipError_t Launch<S>::stream_only(const Geometry &g, const StreamTables &t, cons
 template <typename S>
 hipError_t Launch<S>::collide_only(const Geometry &g, const CollisionParams &cp, S *state, hipStream_t st)
 {
+    return collide_into(g, cp, state, state, st);
+}
+
+template <typename S>
+hipError_t Launch<S>::collide_into(const Geometry &g, const CollisionParams &cp, const S *in, S *out, hipStream_t st)
+{
     const int64_t blocks = (2 * g.nodes + 255) / 256;
-    hipLaunchKernelGGL((k_collide<S>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, g.nodes, cp, state);
+    hipLaunchKernelGGL((k_collide<S>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, g.nodes, cp, in, out);
     return hipGetLastError();
 }
 

@@ -100,6 +100,8 @@ struct Launch {
     static hipError_t stream_only(const Geometry &g, const StreamTables &t, const S *in, S *out,
                                   hipStream_t st);
     static hipError_t collide_only(const Geometry &g, const CollisionParams &cp, S *state, hipStream_t st);
+    static hipError_t collide_into(const Geometry &g, const CollisionParams &cp, const S *in, S *out,
+                                   hipStream_t st);
     static hipError_t init_equilibrium(const Geometry &g, const CollisionParams &cp, const double *rho,
                                        const double *u, const double *T, S *state, hipStream_t st);
     static hipError_t moments(const Geometry &g, const CollisionParams &cp, const S *state, double *rho,
@@ -127,6 +129,9 @@ struct Launch {
 template <typename S>
 hipError_t launch_fused(const Geometry &g, const FusedTables<S> &t, const CollisionParams &cp, const S *in, S *out,
                         S *pre, bool collide, hipStream_t st);
+// streaming only, z-march per (velocity, population) plane and x-y tile (stream.hip)
+template <typename S>
+hipError_t launch_stream_z(const Geometry &g, const FusedTables<S> &t, const S *in, S *out, hipStream_t st);
 void fused_tile(int p, int te[3]);
 void fused_bricks(Geometry &g, int concurrent);
 void build_fused_tables(const AxisTables &fwd, std::vector<int32_t> &omin, std::vector<int32_t> &lstar,
