@@ -1,10 +1,11 @@
 #!/usr/bin/env python3
 """Benchmark of the SLLBM hot path on one MI355X.
 
-One "step" is one fused pass of the whole per-time-step update (streaming of
-all 90 populations by the order-p semi-Lagrangian interpolation, moments,
-transport coefficients, equilibria, quasi-equilibrium term, relaxation) over
-the whole grid.  The headline workload is the FP64 compressible Taylor-Green
+One "step" is the whole per-time-step update of the state over the grid: the
+collision kernel (moments, transport coefficients, equilibria,
+quasi-equilibrium term, relaxation of all 90 populations of every node) and
+the streaming kernel (the order-p semi-Lagrangian interpolation of all 90
+populations).  The headline workload is the FP64 compressible Taylor-Green
 vortex on 16^3 cells of order 4 (64^3 nodes), Ma 1.25, Re 1600.
 
 Prints ONE JSON line (see the ``--help`` of the options).
@@ -23,27 +24,33 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, vendor figure
 Q = 45
 
+# sources that determine each timed kernel (a change voids committed counters)
+KERNEL_SOURCES = {
+    "k_stream_z": ("stream.hip", "tables.cpp", "sllbm_internal.h"),
+    "k_collide": ("kernels.hip", "collision.h", "velset.h", "sllbm_internal.h"),
+}
 
-def kernel_source_hash():
+
+def kernel_source_hash(kernel):
     h = hashlib.sha256()
-    for f in ("fused.hip", "collision.h", "velset.h", "sllbm_internal.h"):
+    for f in KERNEL_SOURCES[kernel]:
         with open(os.path.join(ROOT, "paper_2012_05537_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload, dtype):
-    """HBM bytes per launch of the fused kernel from the committed rocprofv3
-    counter summary, if it was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", "k_fused_traffic.json")
+def measured_traffic(kernel, workload, dtype):
+    """HBM bytes per launch of a kernel from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
     if not os.path.exists(path):
         return None
     try:
         data = json.load(open(path))
     except ValueError:
         return None
-    rec = data.get(f"{workload}:{dtype}")
-    if not rec or rec.get("kernel_source") != kernel_source_hash():
+    rec = data.get(f"{kernel}:{workload}:{dtype}")
+    if not rec or rec.get("kernel_source") != kernel_source_hash(kernel):
         return None
     return rec.get("bytes_per_launch")
 
@@ -62,28 +69,25 @@ def run_gpu(args, wl, precision):
     if args.copy_calibration:
         # a plain copy kernel of one state's size (reads B, writes B; an elementwise
         # kernel, not a DMA copy), so that a counter run sees the HBM counters of a
-        # kernel with known traffic beside k_fused
+        # kernel with known traffic beside the step's kernels
         src = torch.ones(ctx.state_bytes // 8, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)
         for _ in range(3):
             torch.mul(src, 1.0, out=dst)
         torch.cuda.synchronize()
         del src, dst
-    ctx.step(1)                       # leaves the pre-collision bookkeeping; from here one launch per step
     for _ in range(args.warmup):
         ctx.step(1)
     torch.cuda.synchronize()
-    stream = torch.cuda.current_stream()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
+    # HIP events around every kernel launch of the timed steps, on the library's stream
+    ctx.set_kernel_timing(True)
     t0 = time.perf_counter()
-    ev0.record(stream)
     for _ in range(args.steps):
         ctx.step(1)
-    ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    kernel_ms = ev0.elapsed_time(ev1) / args.steps
+    kt = ctx.kernel_times()
+    ctx.set_kernel_timing(False)
     try:
         tot = ctx.totals()
         ok = all(math.isfinite(v) for v in tot)
@@ -91,9 +95,11 @@ def run_gpu(args, wl, precision):
         tot, ok = None, False
     nodes = ctx.nodes
     elem = 8 if precision == 0 else 4
-    bytes_per_launch = 2 * 2 * Q * nodes * elem          # read 90 + write 90 values per node
+    bytes_per_launch = 2 * 2 * Q * nodes * elem          # each kernel reads 90 and writes 90 values per node
     ctx.close()
-    return dict(nodes=nodes, wall=wall, kernel_ms=kernel_ms, bytes=bytes_per_launch, finite=ok, totals=tot)
+    kernels = {name: {"ms": ms / max(n, 1), "launches": n} for name, (ms, n) in
+               (("k_collide", kt["collide"]), ("k_stream_z", kt["stream"]))}
+    return dict(nodes=nodes, wall=wall, kernels=kernels, bytes=bytes_per_launch, finite=ok, totals=tot)
 
 
 def run_adjoint(wl, precision):
@@ -187,8 +193,14 @@ def main():
     precision = 0 if prec_name == "fp64" else 1
     r = run_gpu(args, wl, precision)
     value = r["nodes"] * args.steps / r["wall"]
-    achieved = r["bytes"] / (r["kernel_ms"] * 1e-3) / 1e9
-    traffic = measured_traffic(args.workload, prec_name)
+    dom = max(r["kernels"], key=lambda k: r["kernels"][k]["ms"])
+    kms = r["kernels"][dom]["ms"]
+    achieved = r["bytes"] / (kms * 1e-3) / 1e9
+    kernels = {}
+    for k, v in r["kernels"].items():
+        gbs = r["bytes"] / (v["ms"] * 1e-3) / 1e9 if v["ms"] > 0 else None
+        kernels[k] = {"ms_per_launch": v["ms"], "launches": v["launches"], "algorithmic_GBps": gbs,
+                      "traffic": measured_traffic(k, args.workload, prec_name)}
     out = {
         "metric": "node-updates/s (D3V45 f+g)",
         "value": value,
@@ -208,9 +220,10 @@ def main():
                    "nodes": r["nodes"], "order": wl["p"], "cfl": wl["cfl"], "dt": wl["dt"],
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_fused", "kernel_ms": r["kernel_ms"],
-                     "algorithmic_bytes_per_launch": r["bytes"]},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": kernels[dom]["traffic"],
+                     "kernel": dom, "kernel_ms": kms, "algorithmic_bytes_per_launch": r["bytes"],
+                     "step_frac": r["bytes"] / (r["wall"] / args.steps) / 1e9 / HBM_PEAK_GBS},
+        "kernels": kernels,
         "finite": r["finite"],
     }
     if args.adjoint_workload != "none":

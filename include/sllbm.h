@@ -118,15 +118,24 @@ int sllbm_set_state(sllbm_ctx *ctx, const void *state);
 int sllbm_get_state(sllbm_ctx *ctx, void *state);
 
 /* Advance n >= 0 time steps of Eq. (5) with the quasi-equilibrium collision
- * of App. D: each step collides every node, then streams every population
- * by the semi-Lagrangian interpolation of Eqs. (8)-(9).  Internally the
- * collision of step k+1 is fused with the streaming of step k, so the hot
- * loop is one pass per step over the state. */
+ * of App. D: each step collides every node (one kernel, into a second
+ * buffer), then streams every population by the semi-Lagrangian
+ * interpolation of Eqs. (8)-(9) back into the state (a second kernel). */
 int sllbm_step(sllbm_ctx *ctx, int32_t n);
 
 /* As sllbm_step, and also writes the pre-collision state after each of the
  * n steps to states + k*stride_bytes (device), k = 0..n-1. */
 int sllbm_step_record(sllbm_ctx *ctx, int32_t n, void *states, int64_t stride_bytes);
+
+/* Kernel timing of the step loop.  With on != 0, every collision and
+ * streaming launch of sllbm_step / sllbm_step_record is bracketed by HIP
+ * events on the context's stream (up to 4096 launches of each kind are
+ * recorded; later ones are not).  sllbm_kernel_times synchronises the
+ * stream and writes to host out[4]: total milliseconds of the collision
+ * launches, their count, total milliseconds of the streaming launches, their
+ * count; it then clears the record.  on == 0 stops recording. */
+int sllbm_set_kernel_timing(sllbm_ctx *ctx, int32_t on);
+int sllbm_kernel_times(sllbm_ctx *ctx, double *out);
 
 /* rho, u, T of the current state at every node, Eq. (7) (device, double).
  * T from 2 rho E = rho |u|^2 + 2 C_v rho T.  Any pointer may be NULL. */

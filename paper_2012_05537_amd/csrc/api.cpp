@@ -1,6 +1,6 @@
 // C ABI of the SLLBM library (declared in include/sllbm.h): argument
-// validation, device memory, the pre/post-collision bookkeeping of the fused
-// step, and dispatch to the storage-type-specific launchers.
+// validation, device memory, the step loop (collision, then streaming) and
+// dispatch to the storage-type-specific launchers.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "sllbm_internal.h"
 
@@ -16,8 +17,7 @@ using namespace sllbm;
 namespace {
 
 constexpr int RED_BLOCKS = 1024;   // blocks of the deterministic reductions
-constexpr int ADJ_BLOCKS = 4096;
-constexpr int FUSED_CONCURRENT = 32;  // fused blocks one XCD holds at once (32 CUs, one block each)   // largest grid of the collision VJP (grid-stride beyond)
+constexpr int ADJ_BLOCKS = 4096;   // largest grid of the collision VJP (grid-stride beyond)
 
 std::string g_create_error;
 
@@ -30,9 +30,8 @@ struct sllbm_ctx {
     AxisTables htab[2];           // 0: forward streaming, 1: transposed
     StreamTables dtab[2]{};
     CollisionParams cp{};
-    Geometry fgeo{};              // tiling of the fused kernel (compile-time tiles per order)
     int32_t *d_omin = nullptr, *d_lstar = nullptr;
-    void *d_fw = nullptr;         // fused-table weights, storage type
+    void *d_cw = nullptr;         // cell-table weights, storage type
     hipStream_t stream = nullptr;
     size_t elem = 8;
     // State buffers: buf[cur] holds the pre-collision state X_k; the other
@@ -54,6 +53,10 @@ struct sllbm_ctx {
     double *d_scr_u = nullptr;     // [3N]
     double *d_scr_div = nullptr;   // [cells * (p+1)^3]
     double *d_adj_part = nullptr;  // [ADJ_BLOCKS] dmu_inf partials of the collision VJP
+    // kernel timing: event pairs per launch kind (0 collision, 1 streaming)
+    bool timing = false;
+    std::vector<hipEvent_t> ev[2];
+    int nev[2] = {0, 0};
     double h[3] = {0, 0, 0};       // cell widths (host)
     std::string err;
 };
@@ -93,6 +96,8 @@ hipError_t dalloc(T **p, size_t bytes)
 
 void free_ctx(sllbm_ctx *c)
 {
+    for (int k = 0; k < 2; ++k)
+        for (hipEvent_t e : c->ev[k]) (void)hipEventDestroy(e);
     for (int k = 0; k < 2; ++k) {
         (void)hipFree(c->buf[k]);
         (void)hipFree(c->d_off[k]);
@@ -102,7 +107,7 @@ void free_ctx(sllbm_ctx *c)
     }
     (void)hipFree(c->d_omin);
     (void)hipFree(c->d_lstar);
-    (void)hipFree(c->d_fw);
+    (void)hipFree(c->d_cw);
     (void)hipFree(c->d_nodew);
     (void)hipFree(c->d_ccw);
     (void)hipFree(c->d_dmat);
@@ -173,36 +178,26 @@ int upload_tables(sllbm_ctx *c)
     }
     std::vector<int32_t> omin, lstar;
     std::vector<double> fw;
-    build_fused_tables(c->htab[0], omin, lstar, fw);
+    build_cell_tables(c->htab[0], omin, lstar, fw);
     std::vector<S> fws(fw.begin(), fw.end());
     hipError_t e;
     if ((e = dalloc(&c->d_omin, omin.size() * sizeof(int32_t))) != hipSuccess ||
         (e = dalloc(&c->d_lstar, lstar.size() * sizeof(int32_t))) != hipSuccess ||
-        (e = dalloc(reinterpret_cast<S **>(&c->d_fw), fws.size() * sizeof(S))) != hipSuccess)
+        (e = dalloc(reinterpret_cast<S **>(&c->d_cw), fws.size() * sizeof(S))) != hipSuccess)
         return fail(c, SLLBM_ENOMEM, std::string("table allocation: ") + hipGetErrorString(e));
     if ((e = hipMemcpy(c->d_omin, omin.data(), omin.size() * sizeof(int32_t), hipMemcpyHostToDevice)) !=
             hipSuccess ||
         (e = hipMemcpy(c->d_lstar, lstar.data(), lstar.size() * sizeof(int32_t), hipMemcpyHostToDevice)) !=
             hipSuccess ||
-        (e = hipMemcpy(c->d_fw, fws.data(), fws.size() * sizeof(S), hipMemcpyHostToDevice)) != hipSuccess)
+        (e = hipMemcpy(c->d_cw, fws.data(), fws.size() * sizeof(S), hipMemcpyHostToDevice)) != hipSuccess)
         return hip_fail(c, e, "table upload");
     return SLLBM_OK;
 }
 
 template <typename S>
-FusedTables<S> fused_tables(const sllbm_ctx *c)
+CellTables<S> cell_tables(const sllbm_ctx *c)
 {
-    return FusedTables<S>{c->d_omin, c->d_lstar, static_cast<const S *>(c->d_fw)};
-}
-
-// forward streaming of in into out, with collision (and pre-collision copy) if asked
-hipError_t run_fused(sllbm_ctx *c, const void *in, void *out, void *pre, bool collide)
-{
-    if (is_fp64_cfg(c))
-        return launch_fused<double>(c->fgeo, fused_tables<double>(c), c->cp, static_cast<const double *>(in),
-                                    static_cast<double *>(out), static_cast<double *>(pre), collide, c->stream);
-    return launch_fused<float>(c->fgeo, fused_tables<float>(c), c->cp, static_cast<const float *>(in),
-                               static_cast<float *>(out), static_cast<float *>(pre), collide, c->stream);
+    return CellTables<S>{c->d_omin, c->d_lstar, static_cast<const S *>(c->d_cw)};
 }
 
 bool is_fp64(const sllbm_ctx *c) { return c->cfg.precision == SLLBM_FP64; }
@@ -299,10 +294,6 @@ int sllbm_create(const sllbm_config *cfg, sllbm_ctx **out)
     }
     g.nodes = nodes;
     choose_tile(g);
-    c->fgeo = g;
-    fused_tile(g.p, c->fgeo.TE);
-    for (int a = 0; a < 3; ++a) c->fgeo.ntile[a] = (g.nel[a] + c->fgeo.TE[a] - 1) / c->fgeo.TE[a];
-    fused_bricks(c->fgeo, FUSED_CONCURRENT);
     c->cp.dt = cfg->dt;
     c->cp.Cv = 1.0 / (cfg->gamma - 1.0);
     c->cp.beta = 2.0 * c->cp.Cv - 3.0;
@@ -463,9 +454,9 @@ static hipError_t collide_into(sllbm_ctx *c, const void *in, void *out)
 static hipError_t stream_into(sllbm_ctx *c, const void *in, void *out)
 {
     if (is_fp64(c))
-        return launch_stream_z<double>(c->geo, fused_tables<double>(c), static_cast<const double *>(in),
+        return launch_stream_z<double>(c->geo, cell_tables<double>(c), static_cast<const double *>(in),
                                        static_cast<double *>(out), c->stream);
-    return launch_stream_z<float>(c->geo, fused_tables<float>(c), static_cast<const float *>(in),
+    return launch_stream_z<float>(c->geo, cell_tables<float>(c), static_cast<const float *>(in),
                                   static_cast<float *>(out), c->stream);
 }
 
@@ -479,12 +470,23 @@ static int step_impl(sllbm_ctx *ctx, int32_t n, char *record, int64_t stride)
     if (n == 0) return SLLBM_OK;
     DeviceGuard guard(ctx->cfg.device);
     void *state = ctx->buf[ctx->cur], *post = other(ctx);
+    // event pair around a launch of kind k, if timing is on and events remain
+    auto mark = [&](int k, int half) {
+        if (ctx->timing && ctx->nev[k] < static_cast<int>(ctx->ev[k].size()) / 2) {
+            (void)hipEventRecord(ctx->ev[k][2 * ctx->nev[k] + half], ctx->stream);
+            if (half) ++ctx->nev[k];
+        }
+    };
     for (int32_t s = 0; s < n; ++s) {
         const void *src = (record && s > 0) ? record + static_cast<int64_t>(s - 1) * stride : state;
         void *dst = record ? record + static_cast<int64_t>(s) * stride : state;
+        mark(0, 0);
         hipError_t e = collide_into(ctx, src, post);
         if (e != hipSuccess) return hip_fail(ctx, e, "collide");
+        mark(0, 1);
+        mark(1, 0);
         if ((e = stream_into(ctx, post, dst)) != hipSuccess) return hip_fail(ctx, e, "stream");
+        mark(1, 1);
     }
     if (record) {
         hipError_t e = hipMemcpyAsync(state, record + static_cast<int64_t>(n - 1) * stride, sllbm_state_bytes(ctx),
@@ -495,6 +497,49 @@ static int step_impl(sllbm_ctx *ctx, int32_t n, char *record, int64_t stride)
 }
 
 int sllbm_step(sllbm_ctx *ctx, int32_t n) { return step_impl(ctx, n, nullptr, 0); }
+
+int sllbm_set_kernel_timing(sllbm_ctx *ctx, int32_t on)
+{
+    if (!ctx) return SLLBM_EINVAL;
+    DeviceGuard guard(ctx->cfg.device);
+    if (on && ctx->ev[0].empty()) {
+        for (int k = 0; k < 2; ++k) {
+            ctx->ev[k].resize(2 * 4096);
+            for (auto &e : ctx->ev[k]) {
+                hipError_t r = hipEventCreate(&e);
+                if (r != hipSuccess) {
+                    e = nullptr;
+                    return hip_fail(ctx, r, "hipEventCreate");
+                }
+            }
+        }
+    }
+    ctx->timing = on != 0;
+    ctx->nev[0] = ctx->nev[1] = 0;
+    return SLLBM_OK;
+}
+
+int sllbm_kernel_times(sllbm_ctx *ctx, double *out)
+{
+    if (!ctx) return SLLBM_EINVAL;
+    if (!out) return fail(ctx, SLLBM_EINVAL, "NULL out");
+    DeviceGuard guard(ctx->cfg.device);
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "synchronize");
+    for (int k = 0; k < 2; ++k) {
+        double total = 0.0;
+        for (int j = 0; j < ctx->nev[k]; ++j) {
+            float ms = 0.0f;
+            if ((e = hipEventElapsedTime(&ms, ctx->ev[k][2 * j], ctx->ev[k][2 * j + 1])) != hipSuccess)
+                return hip_fail(ctx, e, "hipEventElapsedTime");
+            total += ms;
+        }
+        out[2 * k] = total;
+        out[2 * k + 1] = ctx->nev[k];
+        ctx->nev[k] = 0;
+    }
+    return SLLBM_OK;
+}
 
 int sllbm_step_record(sllbm_ctx *ctx, int32_t n, void *states, int64_t stride_bytes)
 {

@@ -1,7 +1,8 @@
-// HIP kernels (gfx950) of the SLLBM library besides the fused forward step
-// (fused.hip): the table-driven streaming used for the transposed operator
-// S^T (any tap count), collision of a whole state, equilibrium
-// initialisation, FP64 moments and deterministic totals.
+// HIP kernels (gfx950) of the SLLBM library besides the forward streaming
+// (stream.hip) and the reverse mode (adjoint.hip): the table-driven streaming
+// used for the transposed operator S^T (any tap count), the collision of a
+// whole state, equilibrium initialisation, FP64 moments and deterministic
+// totals.
 //
 // Table-driven streaming.  Psi_i = Iz (x) Iy (x) Ix is applied by sum
 // factorisation: a thread block owns a tile of whole cells, stages the
@@ -222,9 +223,9 @@ __global__ void __launch_bounds__(256) k_stream_tab(Geometry geo, StreamTables t
     }
 }
 
-// Collision of a whole state, two lanes per node (f on the even lane, g on
-// the odd one), with the same code as the fused step.
-// in and out may be the same buffer (each lane reads its 45 values first).
+// Collision of a whole state (Eq. (5) right-hand side with App. D), two
+// lanes per node (f on the even lane, g on the odd one).  in and out may be
+// the same buffer (each lane reads its 45 values first).
 template <typename S>
 __global__ void __launch_bounds__(256) k_collide(int64_t N, CollisionParams cp, const S *in, S *out)
 {

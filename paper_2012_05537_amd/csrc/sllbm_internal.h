@@ -58,7 +58,6 @@ struct Geometry {
     int p;           // order
     int TE[3];       // cells per tile and axis
     int ntile[3];    // tiles per axis
-    int brick[3];    // tiles per brick and axis (tile walk order of the fused kernel)
     int64_t nodes;   // N[0]*N[1]*N[2]
 };
 
@@ -71,11 +70,11 @@ struct StreamTables {
     int wmax[3];           // largest window extent per axis for a full tile
 };
 
-// Tables of the fused forward kernel, for each velocity i and axis a:
-// omin = smallest departure-cell offset of the p rows, lstar = first row that
-// uses cell omin + 1 (p if none), w = the p x (p+1) Lagrange weights.
+// Per-cell departure tables of the forward streaming, for each velocity i and
+// axis a: omin = smallest departure-cell offset of the p rows, lstar = first
+// row that uses cell omin + 1 (p if none), w = the p x (p+1) Lagrange weights.
 template <typename S>
-struct FusedTables {
+struct CellTables {
     const int32_t *omin;    // [Q][3]
     const int32_t *lstar;   // [Q][3]
     const S *w;             // [Q][3][p][p+1]
@@ -126,16 +125,12 @@ struct Launch {
                                            double *du, double *dT, hipStream_t st);
 };
 
+void build_cell_tables(const AxisTables &fwd, std::vector<int32_t> &omin, std::vector<int32_t> &lstar,
+                       std::vector<double> &w);
+
+// forward streaming, z-march per (velocity, population) plane and x-y tile (stream.hip)
 template <typename S>
-hipError_t launch_fused(const Geometry &g, const FusedTables<S> &t, const CollisionParams &cp, const S *in, S *out,
-                        S *pre, bool collide, hipStream_t st);
-// streaming only, z-march per (velocity, population) plane and x-y tile (stream.hip)
-template <typename S>
-hipError_t launch_stream_z(const Geometry &g, const FusedTables<S> &t, const S *in, S *out, hipStream_t st);
-void fused_tile(int p, int te[3]);
-void fused_bricks(Geometry &g, int concurrent);
-void build_fused_tables(const AxisTables &fwd, std::vector<int32_t> &omin, std::vector<int32_t> &lstar,
-                        std::vector<double> &w);
+hipError_t launch_stream_z(const Geometry &g, const CellTables<S> &t, const S *in, S *out, hipStream_t st);
 
 size_t stream_smem_bytes(const Geometry &g, const StreamTables &t, size_t elem);
 int tile_nodes(const Geometry &g);

@@ -56,7 +56,7 @@ struct ZTile {
 }  // namespace
 
 template <typename S, int P>
-__global__ void __launch_bounds__(ZTile<P>::NT) k_stream_z(Geometry g, FusedTables<S> tab, const S *__restrict__ in,
+__global__ void __launch_bounds__(ZTile<P>::NT) k_stream_z(Geometry g, CellTables<S> tab, const S *__restrict__ in,
                                                   S *__restrict__ out, int ntile_x, int ntiles, int zcells,
                                                   int nchunk)
 {
@@ -193,7 +193,7 @@ __global__ void __launch_bounds__(ZTile<P>::NT) k_stream_z(Geometry g, FusedTabl
 }
 
 template <typename S, int P>
-static hipError_t launch_z(const Geometry &g, const FusedTables<S> &t, const S *in, S *out, hipStream_t st)
+static hipError_t launch_z(const Geometry &g, const CellTables<S> &t, const S *in, S *out, hipStream_t st)
 {
     using Z = ZTile<P>;
     const int ntx = (g.N[0] + Z::TX - 1) / Z::TX, nty = (g.N[1] + Z::TY - 1) / Z::TY;
@@ -214,7 +214,7 @@ static hipError_t launch_z(const Geometry &g, const FusedTables<S> &t, const S *
 }
 
 template <typename S>
-hipError_t launch_stream_z(const Geometry &g, const FusedTables<S> &t, const S *in, S *out, hipStream_t st)
+hipError_t launch_stream_z(const Geometry &g, const CellTables<S> &t, const S *in, S *out, hipStream_t st)
 {
     switch (g.p) {
     case 1: return launch_z<S, 1>(g, t, in, out, st);
@@ -227,9 +227,9 @@ hipError_t launch_stream_z(const Geometry &g, const FusedTables<S> &t, const S *
     }
 }
 
-template hipError_t launch_stream_z<double>(const Geometry &, const FusedTables<double> &, const double *, double *,
+template hipError_t launch_stream_z<double>(const Geometry &, const CellTables<double> &, const double *, double *,
                                             hipStream_t);
-template hipError_t launch_stream_z<float>(const Geometry &, const FusedTables<float> &, const float *, float *,
+template hipError_t launch_stream_z<float>(const Geometry &, const CellTables<float> &, const float *, float *,
                                            hipStream_t);
 
 }  // namespace sllbm

@@ -163,7 +163,7 @@ void build_axis_tables(const VelocitySet &vs, int p, const double h[3], double d
 
 namespace sllbm {
 
-void build_fused_tables(const AxisTables &fwd, std::vector<int32_t> &omin, std::vector<int32_t> &lstar,
+void build_cell_tables(const AxisTables &fwd, std::vector<int32_t> &omin, std::vector<int32_t> &lstar,
                         std::vector<double> &w)
 {
     const int p = fwd.p, K = fwd.K;

@@ -66,6 +66,8 @@ _SIGS = {
     "sllbm_loss": (ctypes.c_int, [_VP, _VP, _VP]),
     "sllbm_loss_grad": (ctypes.c_int, [_VP, _VP, _VP]),
     "sllbm_adjoint_step": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP]),
+    "sllbm_set_kernel_timing": (ctypes.c_int, [_VP, ctypes.c_int32]),
+    "sllbm_kernel_times": (ctypes.c_int, [_VP, _VP]),
     "sllbm_moments_vjp": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP]),
     "sllbm_init_equilibrium_vjp": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
     "sllbm_stream": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int32]),
@@ -211,6 +213,17 @@ class SLLBM:
         if states.shape[0] < n or not states.is_contiguous() or states.dtype != self.dtype:
             raise ValueError("record buffer too small or wrong dtype")
         self._check(self._lib.sllbm_step_record(self._h, int(n), _ptr(states), int(self.state_bytes)))
+
+    def set_kernel_timing(self, on=True):
+        self._sync_stream()
+        self._check(self._lib.sllbm_set_kernel_timing(self._h, int(bool(on))))
+
+    def kernel_times(self):
+        """{'collide': (total_ms, launches), 'stream': (total_ms, launches)}; clears the record."""
+        self._sync_stream()
+        out = (ctypes.c_double * 4)()
+        self._check(self._lib.sllbm_kernel_times(self._h, ctypes.addressof(out)))
+        return {"collide": (out[0], int(out[1])), "stream": (out[2], int(out[3]))}
 
     def moments(self):
         self._sync_stream()
