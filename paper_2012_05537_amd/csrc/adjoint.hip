@@ -112,15 +112,24 @@ __global__ void __launch_bounds__(256) k_collide_vjp(int64_t N, CollisionParams 
     const int64_t nn = active ? n : 0;
     const int64_t off = static_cast<int64_t>(pop) * vs::Q * N + nn;
 
-    double h[vs::Q], al[vs::Q];
+    // X enters only through its raw moments and sum alpha h, so it is dead
+    // before the sweep; alpha stays in registers
+    double al[vs::Q];
+    RawMoments rm;
+    double dot_ah = 0.0;
+    {
+        double h[vs::Q];
 #pragma unroll
-    for (int i = 0; i < vs::Q; ++i) {
-        h[i] = static_cast<double>(X[off + static_cast<int64_t>(i) * N]);
-        al[i] = static_cast<double>(mu[off + static_cast<int64_t>(i) * N]);
+        for (int i = 0; i < vs::Q; ++i) {
+            h[i] = static_cast<double>(X[off + static_cast<int64_t>(i) * N]);
+            al[i] = static_cast<double>(mu[off + static_cast<int64_t>(i) * N]);
+        }
+        rm = raw_moments(h);
+#pragma unroll
+        for (int i = 0; i < vs::Q; ++i) dot_ah = fma(al[i], h[i], dot_ah);
     }
 
     // ---- forward quantities (as in collide_half) ----
-    const RawMoments rm = raw_moments(h);
     const double ktr = rm.m2[0] + rm.m2[3] + rm.m2[5];
     const double p_m0 = __shfl_xor(rm.m0, 1);
     const double p_j0 = __shfl_xor(rm.m1[0], 1), p_j1 = __shfl_xor(rm.m1[1], 1), p_j2 = __shfl_xor(rm.m1[2], 1);
@@ -151,7 +160,7 @@ __global__ void __launch_bounds__(256) k_collide_vjp(int64_t N, CollisionParams 
     for (int s = 0; s < 4; ++s) br[s] = bracket(u2, th, SHELL_X2[s]);
 
     // ---- reverse sweep over the velocities (own population) ----
-    double s_om = 0, s_ka = 0, s_heq = 0, s_eqT = 0, s_u2 = 0, s_th = 0;
+    double s_ka = 0, s_heq = 0, s_eqT = 0, s_u2 = 0, s_th = 0;
     double ubar[3] = {0, 0, 0};
     double abar[10];
 #pragma unroll
@@ -160,7 +169,6 @@ __global__ void __launch_bounds__(256) k_collide_vjp(int64_t N, CollisionParams 
         const double w = vs::T.w[0];
         const double feq = w * rho * br[0].a0;
         const double heq = eqs * feq;
-        s_om = fma(al[0], heq - h[0], s_om);
         s_heq = fma(al[0], heq, s_heq);
         s_eqT = fma(al[0], feq, s_eqT);
         s_u2 = fma(al[0] * w * rho * eqs, br[0].d0u, s_u2);
@@ -178,7 +186,6 @@ __global__ void __launch_bounds__(256) k_collide_vjp(int64_t N, CollisionParams 
 #pragma unroll
         for (int m = 0; m < 10; ++m) hs = fma(vs::H3.c[i][m], qb[m], hs);
         const double ai = al[i], aj = al[j];
-        s_om += ai * (heq_i - h[i]) + aj * (heq_j - h[j]);
         s_ka += (ai - aj) * hs;
         s_heq += ai * heq_i + aj * heq_j;
         s_eqT += ai * feq_i + aj * feq_j;
@@ -212,8 +219,8 @@ __global__ void __launch_bounds__(256) k_collide_vjp(int64_t N, CollisionParams 
         uq[c] -= abar[m] * C2[sym2(a, b)];
     }
 
-    // ---- pair totals ----
-    const double S_om = pair_sum(s_om), S_ka = pair_sum(s_ka);
+    // ---- pair totals (sum alpha (s h^eq - h) = s_heq - dot_ah) ----
+    const double S_om = pair_sum(s_heq - dot_ah), S_ka = pair_sum(s_ka);
     const double S_heq = pair_sum(om * s_heq);
     const double S_eqT = pair_sum(is_g ? om * cp.beta * s_eqT : 0.0);
     const double S_u2 = pair_sum(om * s_u2), S_th = pair_sum(om * s_th);
@@ -244,22 +251,47 @@ __global__ void __launch_bounds__(256) k_collide_vjp(int64_t N, CollisionParams 
     rho_bar -= (ub[0] * u[0] + ub[1] * u[1] + ub[2] * u[2]) * ir;
 
     // ---- per-velocity outputs ----
+    // Abar : (xi - u)^3 = T3 - T2 + T1 - T0 and Abar : (-xi - u)^3 = -(T3 + T2 + T1 + T0)
+    // with T3 = Abar : xi xi xi, T2 = Bs : xi xi, T1 = Cv . xi, T0 = Abar : u u u,
+    // where Bs and Cv collect Abar with one and two of its indices contracted with u
     if (active) {
+        double Bs[6] = {0, 0, 0, 0, 0, 0}, Cu[3] = {0, 0, 0}, T0 = 0.0;
+#pragma unroll
+        for (int m = 0; m < 10; ++m) {
+            const int a = vs::IDX3[m][0], b = vs::IDX3[m][1], c = vs::IDX3[m][2];
+            Bs[sym2(b, c)] = fma(abar[m], u[a], Bs[sym2(b, c)]);
+            Bs[sym2(a, c)] = fma(abar[m], u[b], Bs[sym2(a, c)]);
+            Bs[sym2(a, b)] = fma(abar[m], u[c], Bs[sym2(a, b)]);
+            Cu[a] = fma(abar[m], u[b] * u[c], Cu[a]);
+            Cu[b] = fma(abar[m], u[a] * u[c], Cu[b]);
+            Cu[c] = fma(abar[m], u[a] * u[b], Cu[c]);
+            T0 = fma(abar[m], u[a] * u[b] * u[c], T0);
+        }
         S *lp = lam + off;
         asm volatile("" : "+v"(lp));      // fresh store addresses (the load addresses are not kept live)
         const double one_m = 1.0 - om;
+        const double base_f = rho_bar, x2g = is_g ? 0.0 : 1.0, kg = is_g ? K_bar : 0.0;
+        {   // rest velocity: xi = 0
+            double r = one_m * al[0] - T0 + kg;
+            if (!is_g) r += base_f;
+            lp[0] = static_cast<S>(r);
+        }
 #pragma unroll
-        for (int k = 0; k < vs::Q; ++k) {
-            const double d0 = vs::T.xi[k][0] - u[0], d1 = vs::T.xi[k][1] - u[1], d2 = vs::T.xi[k][2] - u[2];
-            const double dd[3] = {d0, d1, d2};
-            double qterm = 0.0;
+        for (int q = 0; q < 22; ++q) {
+            const int i = vs::PAIRS.a[q], j = vs::PAIRS.b[q];
+            const double x = vs::T.xi[i][0], y = vs::T.xi[i][1], z = vs::T.xi[i][2];
+            double T3 = 0.0;
 #pragma unroll
-            for (int m = 0; m < 10; ++m)
-                qterm = fma(abar[m], dd[vs::IDX3[m][0]] * dd[vs::IDX3[m][1]] * dd[vs::IDX3[m][2]], qterm);
-            double r = one_m * al[k] + K_bar * (is_g ? 1.0 : vs::T.x2[k]) + qterm;
-            if (!is_g)
-                r += rho_bar + J_bar[0] * vs::T.xi[k][0] + J_bar[1] * vs::T.xi[k][1] + J_bar[2] * vs::T.xi[k][2];
-            lp[static_cast<int64_t>(k) * N] = static_cast<S>(r);
+            for (int m = 0; m < 10; ++m) T3 = fma(abar[m], vs::H3.mono[i][m], T3);
+            const double T2 = Bs[0] * (x * x) + Bs[1] * (x * y) + Bs[2] * (x * z) + Bs[3] * (y * y) +
+                              Bs[4] * (y * z) + Bs[5] * (z * z);
+            const double T1 = Cu[0] * x + Cu[1] * y + Cu[2] * z;
+            const double jx = is_g ? 0.0 : J_bar[0] * x + J_bar[1] * y + J_bar[2] * z;
+            const double common = kg + x2g * (base_f + K_bar * vs::T.x2[i]);
+            const double ri = one_m * al[i] + common + jx + (T3 - T2 + T1 - T0);
+            const double rj = one_m * al[j] + common - jx - (T3 + T2 + T1 + T0);
+            lp[static_cast<int64_t>(i) * N] = static_cast<S>(ri);
+            lp[static_cast<int64_t>(j) * N] = static_cast<S>(rj);
         }
     }
 
@@ -572,17 +604,15 @@ hipError_t Launch<S>::loss_grad(const Geometry &g, const S *state, const double 
 }
 
 template <typename S>
-hipError_t Launch<S>::adjoint_step(const Geometry &g, const StreamTables &t, const CollisionParams &cp,
-                                   const S *state_n, const S *lam_next, S *lam_out, double *dmu_partials, int nblocks,
-                                   double *dmu, hipStream_t st)
+hipError_t Launch<S>::collide_vjp(const Geometry &g, const CollisionParams &cp, const S *state_n, S *lam,
+                                  double *dmu_partials, int nblocks, double *dmu, hipStream_t st)
 {
-    // lam_out <- S^T lam_next, then lam_out <- J_C(X_n)^T lam_out in place
-    hipError_t e = stream_only(g, t, lam_next, lam_out, st);
-    if (e != hipSuccess) return e;
+    // lam <- J_C(X_n)^T lam in place
     const int blocks = static_cast<int>(std::min<int64_t>((2 * g.nodes + 255) / 256, nblocks));
     hipLaunchKernelGGL((k_collide_vjp<S>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, g.nodes, cp,
-                       state_n, lam_out, lam_out, dmu_partials);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+                       state_n, lam, lam, dmu_partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
     if (dmu) {
         hipLaunchKernelGGL(k_accumulate, dim3(1), dim3(256), 0, st, dmu_partials, blocks, dmu, 1);
         e = hipGetLastError();

@@ -54,6 +54,7 @@ struct sllbm_ctx {
     double *d_scr_div = nullptr;   // [cells * (p+1)^3]
     double *d_adj_part = nullptr;  // [ADJ_BLOCKS] dmu_inf partials of the collision VJP
     // kernel timing: event pairs per launch kind (0 collision, 1 streaming)
+    bool zt_ok = false;           // transposed streaming may use the z-march (nel_z >= 3, spans <= 3p + 1)
     bool timing = false;
     std::vector<hipEvent_t> ev[2];
     int nev[2] = {0, 0};
@@ -305,6 +306,9 @@ int sllbm_create(const sllbm_config *cfg, sllbm_ctx **out)
     double h[3];
     for (int a = 0; a < 3; ++a) c->h[a] = h[a] = cfg->length[a] / cfg->n_el[a];
     build_axis_tables(c->vs, g.p, h, cfg->dt, c->htab[0], c->htab[1]);
+    c->zt_ok = g.nel[2] >= 3;
+    for (int i = 0; i < Q * 3; ++i)
+        if (c->htab[1].span[i] > 3 * g.p + 1) c->zt_ok = false;
 
     auto bail = [&](int rc) {
         g_create_error = c->err;
@@ -460,6 +464,23 @@ static hipError_t stream_into(sllbm_ctx *c, const void *in, void *out)
                                   static_cast<float *>(out), c->stream);
 }
 
+// S^T: the transposed z-march where it applies, else the table-driven gather
+static hipError_t stream_t_into(sllbm_ctx *c, const void *in, void *out)
+{
+    if (c->zt_ok) {
+        if (is_fp64(c))
+            return launch_stream_zt<double>(c->geo, cell_tables<double>(c), c->dtab[1], static_cast<const double *>(in),
+                                            static_cast<double *>(out), c->stream);
+        return launch_stream_zt<float>(c->geo, cell_tables<float>(c), c->dtab[1], static_cast<const float *>(in),
+                                       static_cast<float *>(out), c->stream);
+    }
+    if (is_fp64(c))
+        return Launch<double>::stream_only(c->geo, c->dtab[1], static_cast<const double *>(in),
+                                           static_cast<double *>(out), c->stream);
+    return Launch<float>::stream_only(c->geo, c->dtab[1], static_cast<const float *>(in), static_cast<float *>(out),
+                                      c->stream);
+}
+
 // n steps X <- S(C(X)): collision into the spare buffer, streaming back into
 // the state buffer (or into record slot s, from which the next step collides).
 static int step_impl(sllbm_ctx *ctx, int32_t n, char *record, int64_t stride)
@@ -589,13 +610,7 @@ int sllbm_stream(sllbm_ctx *ctx, const void *in, void *out, int32_t transpose)
     if (!in || !out || in == out) return fail(ctx, SLLBM_EINVAL, "bad stream buffers");
     DeviceGuard guard(ctx->cfg.device);
     if (!transpose) return check_launch(ctx, stream_into(ctx, in, out), "stream");
-    const StreamTables &t = ctx->dtab[1];
-    hipError_t e = is_fp64(ctx)
-        ? Launch<double>::stream_only(ctx->geo, t, static_cast<const double *>(in), static_cast<double *>(out),
-                                      ctx->stream)
-        : Launch<float>::stream_only(ctx->geo, t, static_cast<const float *>(in), static_cast<float *>(out),
-                                     ctx->stream);
-    return check_launch(ctx, e, "stream");
+    return check_launch(ctx, stream_t_into(ctx, in, out), "stream");
 }
 
 int sllbm_collide(sllbm_ctx *ctx, void *state)
@@ -655,15 +670,14 @@ int sllbm_adjoint_step(sllbm_ctx *ctx, const void *state_n, const void *lam_next
     if (!state_n || !lam_next || !lam_out) return fail(ctx, SLLBM_EINVAL, "NULL argument");
     if (lam_out == lam_next || lam_out == state_n) return fail(ctx, SLLBM_EINVAL, "lam_out aliases an input");
     DeviceGuard guard(ctx->cfg.device);
-    const StreamTables &t = ctx->dtab[1];
-    hipError_t e = is_fp64(ctx)
-        ? Launch<double>::adjoint_step(ctx->geo, t, ctx->cp, static_cast<const double *>(state_n),
-                                       static_cast<const double *>(lam_next), static_cast<double *>(lam_out),
-                                       ctx->d_adj_part, ADJ_BLOCKS, dmu, ctx->stream)
-        : Launch<float>::adjoint_step(ctx->geo, t, ctx->cp, static_cast<const float *>(state_n),
-                                      static_cast<const float *>(lam_next), static_cast<float *>(lam_out),
-                                      ctx->d_adj_part, ADJ_BLOCKS, dmu, ctx->stream);
-    return check_launch(ctx, e, "adjoint_step");
+    hipError_t e = stream_t_into(ctx, lam_next, lam_out);
+    if (e != hipSuccess) return hip_fail(ctx, e, "adjoint_step (transposed streaming)");
+    e = is_fp64(ctx)
+        ? Launch<double>::collide_vjp(ctx->geo, ctx->cp, static_cast<const double *>(state_n),
+                                      static_cast<double *>(lam_out), ctx->d_adj_part, ADJ_BLOCKS, dmu, ctx->stream)
+        : Launch<float>::collide_vjp(ctx->geo, ctx->cp, static_cast<const float *>(state_n),
+                                     static_cast<float *>(lam_out), ctx->d_adj_part, ADJ_BLOCKS, dmu, ctx->stream);
+    return check_launch(ctx, e, "adjoint_step (collision VJP)");
 }
 
 int sllbm_moments_vjp(sllbm_ctx *ctx, const double *drho, const double *du, const double *dT, void *lam)

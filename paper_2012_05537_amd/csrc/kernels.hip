@@ -359,15 +359,23 @@ __global__ void __launch_bounds__(256) k_totals_partial(Geometry geo, const S *_
     }
 }
 
-// Stage 2: one block adds the per-block partials in block order.
+// Stage 2: one block of 256 threads adds the per-block partials: thread t
+// sums blocks t, t + 256, ... in order, then a fixed tree (deterministic).
 template <int NV>
-__global__ void k_reduce_partials(const double *__restrict__ partials, int nblocks, double *__restrict__ out,
-                                  int accumulate)
+__global__ void __launch_bounds__(256) k_reduce_partials(const double *__restrict__ partials, int nblocks,
+                                                         double *__restrict__ out, int accumulate)
 {
-    if (threadIdx.x < NV) {
-        double s = 0.0;
-        for (int b = 0; b < nblocks; ++b) s += partials[b * NV + threadIdx.x];
-        out[threadIdx.x] = accumulate ? out[threadIdx.x] + s : s;
+    __shared__ double red[NV * 256];
+    double acc[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) acc[k] = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += 256)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) acc[k] += partials[b * NV + k];
+    block_sum<NV>(acc, red);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) out[k] = accumulate ? out[k] + acc[k] : acc[k];
     }
 }
 
@@ -457,7 +465,7 @@ hipError_t Launch<S>::totals(const Geometry &g, const CollisionParams &, const S
     hipLaunchKernelGGL((k_totals_partial<S>), dim3(nblocks), dim3(256), 0, st, g, state, nodew, partials);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_reduce_partials<5>), dim3(1), dim3(64), 0, st, partials, nblocks, out5, 0);
+    hipLaunchKernelGGL((k_reduce_partials<5>), dim3(1), dim3(256), 0, st, partials, nblocks, out5, 0);
     return hipGetLastError();
 }
 

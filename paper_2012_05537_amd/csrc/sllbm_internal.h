@@ -115,9 +115,9 @@ struct Launch {
                                 const double *nodew, const double *h, double *scratch_rho,
                                 double *scratch_u, double *scratch_div, double *partials, int nblocks, S *lam,
                                 hipStream_t st);
-    static hipError_t adjoint_step(const Geometry &g, const StreamTables &t, const CollisionParams &cp,
-                                   const S *state_n, const S *lam_next, S *lam_out, double *dmu_partials,
-                                   int nblocks, double *dmu, hipStream_t st);
+    // lam <- J_C(X_n)^T lam in place; dL/dmu_inf added to *dmu if not NULL
+    static hipError_t collide_vjp(const Geometry &g, const CollisionParams &cp, const S *state_n, S *lam,
+                                  double *dmu_partials, int nblocks, double *dmu, hipStream_t st);
     static hipError_t moments_vjp(const Geometry &g, const CollisionParams &cp, const S *state, const double *drho,
                                   const double *du, const double *dT, S *lam, hipStream_t st);
     static hipError_t init_equilibrium_vjp(const Geometry &g, const CollisionParams &cp, const double *rho,
@@ -131,6 +131,11 @@ void build_cell_tables(const AxisTables &fwd, std::vector<int32_t> &omin, std::v
 // forward streaming, z-march per (velocity, population) plane and x-y tile (stream.hip)
 template <typename S>
 hipError_t launch_stream_z(const Geometry &g, const CellTables<S> &t, const S *in, S *out, hipStream_t st);
+// transposed streaming, same march (stream.hip); needs nel[2] >= 3 and transposed
+// row spans <= 3p + 1
+template <typename S>
+hipError_t launch_stream_zt(const Geometry &g, const CellTables<S> &t, const StreamTables &adj, const S *in, S *out,
+                            hipStream_t st);
 
 size_t stream_smem_bytes(const Geometry &g, const StreamTables &t, size_t elem);
 int tile_nodes(const Geometry &g);

@@ -213,6 +213,208 @@ static hipError_t launch_z(const Geometry &g, const CellTables<S> &t, const S *i
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Transposed streaming S^T (the adjoint of Eqs. (8)-(9)), same z-march.
+//
+// Along x and y the transposed 1-D operator is a gather over the transposed
+// tables (node m of a cell reads at most 2P nodes at offsets relative to its
+// cell start).  Along z it is applied as the scatter of the forward operator:
+// input row e*P + l, which the forward step gathers into source rows
+// (e + o_l)*P + k, adds W[l][k] times its value to those rows.  A thread
+// keeps the 2P + 1 rows of source cells e + omin and e + omin + 1 in
+// registers; after input cell e the rows of cell e + omin are complete (the
+// next input cell only reaches cells e + omin + 1 and up) and are written.
+// Row 0 of source cell c also receives, as row P of cell c - 1, from input
+// cells c - omin - 1 and c - omin - 2, so a chunk of input cells [e0, e1)
+// first scatters cells e0 - 2 and e0 - 1 without writing; then every written
+// row has all its contributions.  Requires at least three cells along z
+// (with two, one input cell would reach the same row twice by wrapping).
+// ---------------------------------------------------------------------------
+template <int P>
+struct ZTileT {
+    static constexpr int XN = 16, YN = 16;
+    static constexpr int TXC = XN / P > 0 ? XN / P : 1, TYC = YN / P > 0 ? YN / P : 1;
+    static constexpr int TX = TXC * P, TY = TYC * P;
+    static constexpr int K = 2 * P;                           // taps of a transposed row
+    static constexpr int SPMAX = 3 * P + 1;                   // largest offset span of a transposed row set
+    static constexpr int WX = TX + SPMAX - 1, WY = TY + SPMAX - 1;
+    static constexpr int NT = (TX * TY + 63) / 64 * 64;
+    static constexpr int LK = (WX * WY + NT - 1) / NT;
+    static constexpr int XT = WY * TX, XK = (XT + NT - 1) / NT;
+};
+
+template <typename S, int P>
+__global__ void __launch_bounds__(ZTileT<P>::NT) k_stream_zt(Geometry g, CellTables<S> fwd, const int32_t *__restrict__ toff,
+                                                             const S *__restrict__ twt, const int32_t *__restrict__ tlo,
+                                                             const int32_t *__restrict__ tspan, const S *__restrict__ in,
+                                                             S *__restrict__ out, int ntile_x, int ntiles, int zcells,
+                                                             int nchunk)
+{
+    using Z = ZTileT<P>;
+    constexpr int TX = Z::TX, TY = Z::TY, NT = Z::NT, LK = Z::LK, XK = Z::XK, K = Z::K;
+    __shared__ S pl[P][Z::WX * Z::WY];
+    __shared__ S bx[P][Z::WY * TX];
+
+    const int tid = threadIdx.x;
+    const int L = __builtin_amdgcn_readfirstlane(xcd_linear(blockIdx.x, gridDim.x));
+    const int q = L / (ntiles * nchunk);
+    const int rem = L - q * ntiles * nchunk;
+    const int chunk = rem / ntiles, tile = rem - chunk * ntiles;
+    const int i = q >> 1, pop = q & 1;
+    const int X0 = (tile % ntile_x) * TX, Y0 = (tile / ntile_x) * TY;
+    const int Nx = g.N[0], Ny = g.N[1], Nz = g.N[2];
+    const int64_t N = g.nodes, NP = static_cast<int64_t>(Nx) * Ny;
+    const int lox = tlo[i * 3 + 0], loy = tlo[i * 3 + 1];
+    const int wxs = TX + tspan[i * 3 + 0] - 1, wys = TY + tspan[i * 3 + 1] - 1;   // window of this velocity
+    const int wp = wxs * wys;
+    const int omz = fwd.omin[i * 3 + 2], lsz = fwd.lstar[i * 3 + 2];
+    const S *Wz = fwd.w + (i * 3 + 2) * P * (P + 1);
+    const int32_t *ox = toff + (i * 3 + 0) * P * K, *oy = toff + (i * 3 + 1) * P * K;
+    const S *wxt = twt + (i * 3 + 0) * P * K, *wyt = twt + (i * 3 + 1) * P * K;
+    const S *__restrict__ src = in + static_cast<int64_t>(pop * 45 + i) * N;
+    S *__restrict__ dst = out + static_cast<int64_t>(pop * 45 + i) * N;
+
+    int loff[LK];
+#pragma unroll
+    for (int k = 0; k < LK; ++k) {
+        int e = tid + k * NT;
+        e = e < wp ? e : wp - 1;
+        const int wx = e % wxs, wy = e / wxs;
+        loff[k] = wrapi(Y0 + loy + wy, Ny) * Nx + wrapi(X0 + lox + wx, Nx);
+    }
+    // x-gather tasks: output (wy, tx) from window row wy
+    int xs[XK][K], xd[XK];
+    S xw[XK][K];
+#pragma unroll
+    for (int k = 0; k < XK; ++k) {
+        int e = tid + k * NT;
+        e = e < wys * TX ? e : wys * TX - 1;
+        const int tx = e % TX, wy = e / TX, m = tx % P;
+        xd[k] = wy * TX + tx;
+#pragma unroll
+        for (int t = 0; t < K; ++t) {
+            xs[k][t] = wy * wxs + tx - m + ox[m * K + t] - lox;
+            xw[k][t] = wxt[m * K + t];
+        }
+    }
+    const int tx = tid % TX, ty = tid / TX;
+    const bool own = tid < TX * TY && X0 + tx < Nx && Y0 + ty < Ny;
+    const int my = ty % P;
+    int ys[K];
+    S yw[K];
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+        ys[t] = (ty - my + oy[my * K + t] - loy) * TX + (tid < TX * TY ? tx : 0);
+        yw[t] = wyt[my * K + t];
+    }
+    const int64_t oxy = static_cast<int64_t>(Y0 + ty) * Nx + (X0 + tx);
+    S wz[P][P + 1];
+#pragma unroll
+    for (int l = 0; l < P; ++l)
+#pragma unroll
+        for (int r = 0; r <= P; ++r) wz[l][r] = Wz[l * (P + 1) + r];
+
+    // input cells e0 - 2 .. e1 - 1; row l of cell e is z = e*P + l
+    const int e0 = chunk * zcells, e1 = min(g.nel[2], e0 + zcells);
+    S raw[P][LK];
+    auto load_cell = [&](int e) {
+#pragma unroll
+        for (int r = 0; r < P; ++r) {
+            const int64_t zo = static_cast<int64_t>(wrapi(e * P + r, Nz)) * NP;
+#pragma unroll
+            for (int j = 0; j < LK; ++j) raw[r][j] = src[zo + loff[j]];
+        }
+    };
+    S acc[2 * P + 1];
+#pragma unroll
+    for (int r = 0; r <= 2 * P; ++r) acc[r] = 0;
+    load_cell(e0 - 2);
+    for (int e = e0 - 2; e < e1; ++e) {
+#pragma unroll
+        for (int r = 0; r < P; ++r)
+#pragma unroll
+            for (int j = 0; j < LK; ++j)
+                if (tid + j * NT < wp) pl[r][tid + j * NT] = raw[r][j];
+        if (e + 1 < e1) load_cell(e + 1);
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < P; ++r)
+#pragma unroll
+            for (int k = 0; k < XK; ++k) {
+                if (tid + k * NT < wys * TX) {
+                    S v = 0;
+#pragma unroll
+                    for (int t = 0; t < K; ++t) v = fma(xw[k][t], pl[r][xs[k][t]], v);
+                    bx[r][xd[k]] = v;
+                }
+            }
+        __syncthreads();
+#pragma unroll
+        for (int l = 0; l < P; ++l) {
+            S a = 0;
+#pragma unroll
+            for (int t = 0; t < K; ++t) a = fma(yw[t], bx[l][ys[t]], a);
+            const bool hi = l >= lsz;
+#pragma unroll
+            for (int r = 0; r <= P; ++r) {
+                const S c = wz[l][r] * a;
+                acc[P + r] += hi ? c : S(0);
+                acc[r] += hi ? S(0) : c;
+            }
+        }
+        if (e >= e0 && own) {
+#pragma unroll
+            for (int r = 0; r < P; ++r)
+                dst[static_cast<int64_t>(wrapi((e + omz) * P + r, Nz)) * NP + oxy] = acc[r];
+        }
+#pragma unroll
+        for (int r = 0; r <= P; ++r) acc[r] = acc[r + P];
+#pragma unroll
+        for (int r = P + 1; r <= 2 * P; ++r) acc[r] = 0;
+    }
+}
+
+template <typename S, int P>
+static hipError_t launch_zt(const Geometry &g, const CellTables<S> &t, const int32_t *toff, const S *twt,
+                            const int32_t *tlo, const int32_t *tspan, const S *in, S *out, hipStream_t st)
+{
+    using Z = ZTileT<P>;
+    const int ntx = (g.N[0] + Z::TX - 1) / Z::TX, nty = (g.N[1] + Z::TY - 1) / Z::TY;
+    const int ntiles = ntx * nty;
+    int nchunk = 1;
+    while (nchunk < g.nel[2] && static_cast<int64_t>(ntiles) * 90 * nchunk < ZCHUNK_TARGET_BLOCKS &&
+           g.nel[2] / (2 * nchunk) >= ZCHUNK_MIN_CELLS)
+        nchunk *= 2;
+    const int zcells = (g.nel[2] + nchunk - 1) / nchunk;
+    nchunk = (g.nel[2] + zcells - 1) / zcells;
+    const int64_t nb = static_cast<int64_t>(ntiles) * 90 * nchunk;
+    if (nb > (int64_t(1) << 31) - 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_stream_zt<S, P>), dim3(static_cast<unsigned>(nb)), dim3(Z::NT), 0, st, g, t, toff, twt, tlo,
+                       tspan, in, out, ntx, ntiles, zcells, nchunk);
+    return hipGetLastError();
+}
+
+template <typename S>
+hipError_t launch_stream_zt(const Geometry &g, const CellTables<S> &t, const StreamTables &adj, const S *in, S *out,
+                            hipStream_t st)
+{
+    const S *wt = static_cast<const S *>(adj.wt);
+    switch (g.p) {
+    case 1: return launch_zt<S, 1>(g, t, adj.off, wt, adj.lo, adj.span, in, out, st);
+    case 2: return launch_zt<S, 2>(g, t, adj.off, wt, adj.lo, adj.span, in, out, st);
+    case 3: return launch_zt<S, 3>(g, t, adj.off, wt, adj.lo, adj.span, in, out, st);
+    case 4: return launch_zt<S, 4>(g, t, adj.off, wt, adj.lo, adj.span, in, out, st);
+    case 5: return launch_zt<S, 5>(g, t, adj.off, wt, adj.lo, adj.span, in, out, st);
+    case 6: return launch_zt<S, 6>(g, t, adj.off, wt, adj.lo, adj.span, in, out, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template hipError_t launch_stream_zt<double>(const Geometry &, const CellTables<double> &, const StreamTables &,
+                                             const double *, double *, hipStream_t);
+template hipError_t launch_stream_zt<float>(const Geometry &, const CellTables<float> &, const StreamTables &,
+                                            const float *, float *, hipStream_t);
+
 template <typename S>
 hipError_t launch_stream_z(const Geometry &g, const CellTables<S> &t, const S *in, S *out, hipStream_t st)
 {

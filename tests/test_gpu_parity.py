@@ -61,19 +61,31 @@ def test_stream_matches_oracle(oracle, n_el, p, dt, length):
     assert rel_err(F, fo) < TOL64 and rel_err(G, go) < TOL64
 
 
-@pytest.mark.parametrize("n_el,p,dt,length", STREAM_CASES[:4])
+# the transposed streaming marches along z for three or more cells (in chunks
+# when there are few tiles: (2, 2, 8) at p = 4) and gathers otherwise
+TRANSPOSE_CASES = STREAM_CASES + [
+    ((2, 2, 8), 4, 0.31, 2 * math.pi),
+    ((3, 2, 3), 2, 1.3, 2 * math.pi),        # shifts of several cells, three cells along z
+    ((2, 3, 12), 3, 0.2, (1.0, 2.0, 6.0)),
+]
+
+
+@pytest.mark.parametrize("n_el,p,dt,length", TRANSPOSE_CASES)
 def test_transposed_stream_is_adjoint(oracle, n_el, p, dt, length):
-    """<S x, y> = <x, S^T y> with the library's transposed gather."""
+    """<S x, y> = <x, S^T y> per population and velocity, with S x from the
+    oracle's direct gather and S^T y from the library."""
+    _say(f"transposed stream n_el={n_el} p={p} dt={dt}")
     ctx, cfg = make_pair(oracle, n_el, p, dt, 0.01, length=length)
     rng = np.random.default_rng(7)
     N = oracle.num_nodes(cfg)
     x = rng.normal(size=(2, Q, N))
     y = rng.normal(size=(2, Q, N))
-    Sx = ctx.stream(to_dev(ctx, x[0], x[1])).cpu().numpy()
+    Sx = np.stack(oracle.stream(cfg, x[0], x[1]))
     STy = ctx.stream(to_dev(ctx, y[0], y[1]), transpose=True).cpu().numpy()
     lhs = np.einsum("pin,pin->pi", Sx, y)
     rhs = np.einsum("pin,pin->pi", x, STy)
-    assert np.allclose(lhs, rhs, rtol=1e-12, atol=1e-9)
+    scale = np.einsum("pin,pin->pi", np.abs(Sx), np.abs(y))
+    assert np.all(np.abs(lhs - rhs) <= 1e-13 * scale), np.max(np.abs(lhs - rhs) / scale)
 
 
 @pytest.mark.parametrize("law,pr", [(0, 0.71), (1, 1.0), (0, 2.0)])
