@@ -54,11 +54,13 @@ __device__ __forceinline__ double viscosity_factor(const CollisionParams &cp, do
     return fac;
 }
 
-// bracket b(c) = a0 + a1 c + a2 c^2 + c^3/6 + c^4/24 and its derivatives
+// bracket b(c) = a0 + a1 c + a2 c^2 + c^3/6 + c^4/24 and its derivatives in
+// |u|^2 and theta; d a1/d|u|^2 = -1/2, d a2/d|u|^2 = -1/4, d a1/d theta =
+// (x2 - 5)/2 and d a2/d theta = (x2 - 7)/4 are constants of the shell
 struct Bracket {
     double a0, a1, a2;           // value coefficients
-    double d0u, d1u, d2u;        // d a_k / d |u|^2
-    double d0t, d1t, d2t;        // d a_k / d theta
+    double d0u;                  // d a0 / d |u|^2
+    double d0t;                  // d a0 / d theta
 };
 
 __device__ __forceinline__ Bracket bracket(double u2, double th, double x2)
@@ -69,13 +71,13 @@ __device__ __forceinline__ Bracket bracket(double u2, double th, double x2)
     b.a1 = e.a1;
     b.a2 = e.a2;
     b.d0u = -0.5 + 0.25 * u2 - 0.25 * th * (x2 - 5.0);
-    b.d1u = -0.5;
-    b.d2u = -0.25;
     b.d0t = 0.5 * (x2 - 3.0) - 0.25 * u2 * (x2 - 5.0) + 0.25 * th * (x2 * x2 - 10.0 * x2 + 15.0);
-    b.d1t = 0.5 * (x2 - 5.0);
-    b.d2t = 0.25 * (x2 - 7.0);
     return b;
 }
+
+constexpr double D1U = -0.5, D2U = -0.25;
+__host__ __device__ constexpr double d1t_of(double x2) { return 0.5 * (x2 - 5.0); }
+__host__ __device__ constexpr double d2t_of(double x2) { return 0.25 * (x2 - 7.0); }
 
 __device__ __forceinline__ double bval(const Bracket &b, double c)
 {
@@ -155,6 +157,15 @@ __global__ void __launch_bounds__(256) k_collide_vjp(int64_t N, CollisionParams 
     const double th = T - 1.0;
     const double eqs = is_g ? cp.beta * T : 1.0;
 
+    // centred second moment of the own population (for the Qbar -> u term);
+    // the raw moments are dead after this
+    double C2[6];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = a; b < 3; ++b)
+            C2[sym2(a, b)] = rm.m2[sym2(a, b)] - u[a] * rm.m1[b] - u[b] * rm.m1[a] + rm.m0 * u[a] * u[b];
+
     Bracket br[4];
 #pragma unroll
     for (int s = 0; s < 4; ++s) br[s] = bracket(u2, th, SHELL_X2[s]);
@@ -195,21 +206,16 @@ __global__ void __launch_bounds__(256) k_collide_vjp(int64_t N, CollisionParams 
         ubar[1] = fma(gu, vs::T.xi[i][1], ubar[1]);
         ubar[2] = fma(gu, vs::T.xi[i][2], ubar[2]);
         const double sp = ai + aj, sm = ai - aj;
-        s_u2 += wre * (sp * (b.d0u + c * c * b.d2u) + sm * c * b.d1u);
-        s_th += wre * (sp * (b.d0t + c * c * b.d2t) + sm * c * b.d1t);
+        const double x2 = SHELL_X2[vs::T.shell[i]];
+        s_u2 += wre * (sp * (b.d0u + c * c * D2U) + sm * c * D1U);
+        s_th += wre * (sp * (b.d0t + c * c * d2t_of(x2)) + sm * c * d1t_of(x2));
 #pragma unroll
         for (int m = 0; m < 10; ++m) abar[m] = fma(sm, vs::H3.c[i][m], abar[m]);
     }
 #pragma unroll
     for (int m = 0; m < 10; ++m) abar[m] *= kap;
 
-    // Qbar -> u: -sum_m abar_m (delta_ad C2_bc + delta_bd C2_ac + delta_cd C2_ab), C2 centred second moment
-    double C2[6];
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int b = a; b < 3; ++b)
-            C2[sym2(a, b)] = rm.m2[sym2(a, b)] - u[a] * rm.m1[b] - u[b] * rm.m1[a] + rm.m0 * u[a] * u[b];
+    // Qbar -> u: -sum_m abar_m (delta_ad C2_bc + delta_bd C2_ac + delta_cd C2_ab)
     double uq[3] = {0, 0, 0};
 #pragma unroll
     for (int m = 0; m < 10; ++m) {
@@ -354,8 +360,9 @@ __global__ void __launch_bounds__(256) k_init_vjp(int64_t N, CollisionParams cp,
         gu[0] = fma(gc, vs::T.xi[i][0], gu[0]);
         gu[1] = fma(gc, vs::T.xi[i][1], gu[1]);
         gu[2] = fma(gc, vs::T.xi[i][2], gu[2]);
-        gu2 += e * w * r * (br.d0u + c * br.d1u + c * c * br.d2u);
-        gt += e * w * r * (br.d0t + c * br.d1t + c * c * br.d2t) + b * cp.beta * w * r * bv;
+        const double x2 = vs::T.x2[i];
+        gu2 += e * w * r * (br.d0u + c * D1U + c * c * D2U);
+        gt += e * w * r * (br.d0t + c * d1t_of(x2) + c * c * d2t_of(x2)) + b * cp.beta * w * r * bv;
     }
     if (drho) drho[n] = gr;
     if (du) {
