@@ -50,7 +50,7 @@ struct ZTile {
     static constexpr int WX = TX + P + 1, WY = TY + P + 1;    // source window
     static constexpr int NT = (TX * TY + 63) / 64 * 64;       // one thread per output column
     static constexpr int LK = (WX * WY + NT - 1) / NT;        // window loads per thread and row
-    static constexpr int XT = WY * TX, XK = (XT + NT - 1) / NT;   // x-pass outputs per thread and row
+    static constexpr int NG = TXC + 1;                        // source cells of an x window row
 };
 
 }  // namespace
@@ -61,7 +61,7 @@ __global__ void __launch_bounds__(ZTile<P>::NT) k_stream_z(Geometry g, CellTable
                                                   int nchunk)
 {
     using Z = ZTile<P>;
-    constexpr int TX = Z::TX, TY = Z::TY, WX = Z::WX, WY = Z::WY, NT = Z::NT, LK = Z::LK, XK = Z::XK;
+    constexpr int TX = Z::TX, TY = Z::TY, WX = Z::WX, WY = Z::WY, NT = Z::NT, LK = Z::LK;
     constexpr int WP = WX * WY;
     // one batch of source rows (P + 1 for the first cell, P afterwards); single
     // buffers suffice with two barriers per batch: a thread stores the next
@@ -96,19 +96,14 @@ __global__ void __launch_bounds__(ZTile<P>::NT) k_stream_z(Geometry g, CellTable
         const int wx = e % WX, wy = e / WX;
         loff[k] = wrapi(Y0 + omy * P + wy, Ny) * Nx + wrapi(X0 + omx * P + wx, Nx);
     }
-    // x-pass tasks: output (wy, tx) from window row wy, columns cx .. cx + P
-    int xsrc[XK], xdst[XK];
-    S xw[XK][P + 1];
+    // x-pass by source cell: window cell c = g + 1 (g = -1 .. TXC - 1) feeds the
+    // outputs g*P + lsx + j, j = 0 .. P-1 (those inside the tile), output j
+    // with weight row (lsx + j) mod P, the same for every thread
+    S xw[P][P + 1];
 #pragma unroll
-    for (int k = 0; k < XK; ++k) {
-        int e = tid + k * NT;
-        e = e < Z::XT ? e : Z::XT - 1;
-        const int tx = e % TX, wy = e / TX, l = tx % P;
-        xsrc[k] = wy * WX + (tx / P + (l >= lsx ? 1 : 0)) * P;
-        xdst[k] = wy * TX + tx;
+    for (int j = 0; j < P; ++j)
 #pragma unroll
-        for (int r = 0; r <= P; ++r) xw[k][r] = Wx[l * (P + 1) + r];
-    }
+        for (int r = 0; r <= P; ++r) xw[j][r] = Wx[((lsx + j) % P) * (P + 1) + r];
     // y-pass task and output of this thread: node (X0 + tx, Y0 + ty)
     const int tx = tid % TX, ty = tid / TX;
     const bool own = tid < TX * TY && X0 + tx < Nx && Y0 + ty < Ny;
@@ -149,17 +144,30 @@ __global__ void __launch_bounds__(ZTile<P>::NT) k_stream_z(Geometry g, CellTable
                 if (tid + j * NT < WP) pl[r][tid + j * NT] = raw[r][j];
         if (next_nr > 0) load_rows(next_k0, next_nr);
         __syncthreads();
+        constexpr int XT = NR * WY * Z::NG;                   // (row, window row, source cell) tasks
 #pragma unroll
-        for (int r = 0; r < NR; ++r)
+        for (int k = 0; k < (XT + NT - 1) / NT; ++k) {
+            const int e = tid + k * NT;
+            if (e < XT) {
+                const int r = e / (WY * Z::NG), rem = e - r * (WY * Z::NG);
+                const int wy = rem / Z::NG, g = rem - wy * Z::NG - 1;
+                const S *c = &pl[r][wy * WX + (g + 1) * P];
+                S v[P + 1];
 #pragma unroll
-            for (int k = 0; k < XK; ++k) {
-                if (tid + k * NT < Z::XT) {
-                    S acc = 0;
+                for (int m = 0; m <= P; ++m) v[m] = c[m];
+                S *o = &bx[r][wy * TX];
 #pragma unroll
-                    for (int m = 0; m <= P; ++m) acc = fma(xw[k][m], pl[r][xsrc[k] + m], acc);
-                    bx[r][xdst[k]] = acc;
+                for (int j = 0; j < P; ++j) {
+                    const int pos = g * P + lsx + j;
+                    if (pos >= 0 && pos < TX) {
+                        S acc = 0;
+#pragma unroll
+                        for (int m = 0; m <= P; ++m) acc = fma(xw[j][m], v[m], acc);
+                        o[pos] = acc;
+                    }
                 }
             }
+        }
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
