@@ -43,7 +43,7 @@ constexpr int ZCHUNK_MIN_CELLS = 4;
 
 template <int P>
 struct ZTile {
-    static constexpr int XN = 16, YN = 16;                    // target tile extent in nodes
+    static constexpr int XN = 32, YN = 8;                     // target tile extent in nodes (long x rows)
     static constexpr int TXC = XN / P > 0 ? XN / P : 1;       // cells per tile along x and y
     static constexpr int TYC = YN / P > 0 ? YN / P : 1;
     static constexpr int TX = TXC * P, TY = TYC * P;          // nodes per tile
@@ -51,6 +51,7 @@ struct ZTile {
     static constexpr int NT = (TX * TY + 63) / 64 * 64;       // one thread per output column
     static constexpr int LK = (WX * WY + NT - 1) / NT;        // window loads per thread and row
     static constexpr int NG = TXC + 1;                        // source cells of an x window row
+    static constexpr int BS = TX % 2 ? TX : TX + 1;           // odd row stride of the x-pass output (LDS banks)
 };
 
 }  // namespace
@@ -68,7 +69,8 @@ __global__ void __launch_bounds__(ZTile<P>::NT) k_stream_z(Geometry g, CellTable
     // batch only after the barrier that follows every thread's x-pass, and
     // overwrites bx only after the barrier that follows every thread's y-pass
     __shared__ S pl[P + 1][WP];
-    __shared__ S bx[P + 1][WY * TX];
+    constexpr int BS = Z::BS;
+    __shared__ S bx[P + 1][WY * BS];
 
     const int tid = threadIdx.x;
     const int L = __builtin_amdgcn_readfirstlane(xcd_linear(blockIdx.x, gridDim.x));
@@ -108,7 +110,7 @@ __global__ void __launch_bounds__(ZTile<P>::NT) k_stream_z(Geometry g, CellTable
     const int tx = tid % TX, ty = tid / TX;
     const bool own = tid < TX * TY && X0 + tx < Nx && Y0 + ty < Ny;
     const int ly = ty % P;
-    const int ysrc = (ty / P + (ly >= lsy ? 1 : 0)) * P * TX + (tid < TX * TY ? tx : 0);
+    const int ysrc = (ty / P + (ly >= lsy ? 1 : 0)) * P * Z::BS + (tid < TX * TY ? tx : 0);
     S yw[P + 1];
 #pragma unroll
     for (int r = 0; r <= P; ++r) yw[r] = Wy[ly * (P + 1) + r];
@@ -123,26 +125,29 @@ __global__ void __launch_bounds__(ZTile<P>::NT) k_stream_z(Geometry g, CellTable
     // order: z = (ez0 + omz) * P + k (mod Nz), k = 0 .. P + (ez1 - ez0) * P
     const int ez0 = chunk * zcells, ez1 = min(g.nel[2], ez0 + zcells);
     const int zb = (ez0 + omz) * P;
-    S raw[P + 1][LK];
-    auto load_rows = [&](int k0, int nr) {
+    // two register buffers of source rows: the rows of the cell after next are
+    // in flight while a cell is processed
+    S rawA[P + 1][LK], rawB[P][LK];
+    auto load_rows = [&](auto &raw, int k0, int nr) {
 #pragma unroll
         for (int r = 0; r <= P; ++r) {
-            if (r < nr) {
+            if (r < nr && r < static_cast<int>(sizeof(raw) / sizeof(raw[0]))) {
                 const int64_t zo = static_cast<int64_t>(wrapi(zb + k0 + r, Nz)) * NP;
 #pragma unroll
                 for (int j = 0; j < LK; ++j) raw[r][j] = src[zo + loff[j]];
             }
         }
     };
-    // a batch of NR rows: registers -> LDS, loads of the next batch, x-pass, y-pass
-    auto batch = [&](auto nr_c, int next_k0, int next_nr, S *res) {
+    // a batch of NR rows: registers -> LDS, the same registers reloaded with
+    // the rows two batches ahead, x-pass, y-pass
+    auto batch = [&](auto nr_c, auto &raw, int next_k0, int next_nr, S *res) {
         constexpr int NR = decltype(nr_c)::value;
 #pragma unroll
         for (int r = 0; r < NR; ++r)
 #pragma unroll
             for (int j = 0; j < LK; ++j)
                 if (tid + j * NT < WP) pl[r][tid + j * NT] = raw[r][j];
-        if (next_nr > 0) load_rows(next_k0, next_nr);
+        if (next_nr > 0) load_rows(raw, next_k0, next_nr);
         __syncthreads();
         constexpr int XT = NR * WY * Z::NG;                   // (row, window row, source cell) tasks
 #pragma unroll
@@ -150,12 +155,12 @@ __global__ void __launch_bounds__(ZTile<P>::NT) k_stream_z(Geometry g, CellTable
             const int e = tid + k * NT;
             if (e < XT) {
                 const int r = e / (WY * Z::NG), rem = e - r * (WY * Z::NG);
-                const int wy = rem / Z::NG, g = rem - wy * Z::NG - 1;
+                const int g = rem / WY - 1, wy = rem - (g + 1) * WY;   // neighbouring lanes: neighbouring rows
                 const S *c = &pl[r][wy * WX + (g + 1) * P];
                 S v[P + 1];
 #pragma unroll
                 for (int m = 0; m <= P; ++m) v[m] = c[m];
-                S *o = &bx[r][wy * TX];
+                S *o = &bx[r][wy * BS];
 #pragma unroll
                 for (int j = 0; j < P; ++j) {
                     const int pos = g * P + lsx + j;
@@ -173,18 +178,13 @@ __global__ void __launch_bounds__(ZTile<P>::NT) k_stream_z(Geometry g, CellTable
         for (int r = 0; r < NR; ++r) {
             S acc = 0;
 #pragma unroll
-            for (int m = 0; m <= P; ++m) acc = fma(yw[m], bx[r][ysrc + m * TX], acc);
+            for (int m = 0; m <= P; ++m) acc = fma(yw[m], bx[r][ysrc + m * BS], acc);
             res[r] = acc;
         }
     };
-
-    const int nel = ez1 - ez0;
+    // P outputs of cell ez along z from the rows in a, then slide by one cell
     S a[2 * P + 1];
-    load_rows(0, P + 1);
-    batch(std::integral_constant<int, P + 1>(), P + 1, nel > 0 ? P : 0, a);
-    for (int e = 0; e < nel; ++e) {
-        const int ez = ez0 + e;
-        batch(std::integral_constant<int, P>(), 2 * P + 1 + e * P, e + 1 < nel ? P : 0, a + P + 1);
+    auto emit = [&](int ez) {
         if (own) {
 #pragma unroll
             for (int l = 0; l < P; ++l) {
@@ -197,6 +197,22 @@ __global__ void __launch_bounds__(ZTile<P>::NT) k_stream_z(Geometry g, CellTable
         }
 #pragma unroll
         for (int r = 0; r <= P; ++r) a[r] = a[r + P];
+    };
+
+    // rows 0 .. P (first source cell) in rawA, then the rows of cell e
+    // (P + 1 + e*P .. 2P + e*P) alternate between rawB (even e) and rawA (odd e)
+    const int nel = ez1 - ez0;
+    auto rows_of = [&](int e) { return e < nel ? P : 0; };
+    load_rows(rawA, 0, P + 1);
+    load_rows(rawB, P + 1, rows_of(0));
+    batch(std::integral_constant<int, P + 1>(), rawA, 2 * P + 1, rows_of(1), a);
+    for (int e = 0; e < nel; e += 2) {
+        batch(std::integral_constant<int, P>(), rawB, P + 1 + (e + 2) * P, rows_of(e + 2), a + P + 1);
+        emit(ez0 + e);
+        if (e + 1 < nel) {
+            batch(std::integral_constant<int, P>(), rawA, P + 1 + (e + 3) * P, rows_of(e + 3), a + P + 1);
+            emit(ez0 + e + 1);
+        }
     }
 }
 
