@@ -26,8 +26,8 @@ Q = 45
 
 # sources that determine each timed kernel (a change voids committed counters)
 KERNEL_SOURCES = {
-    "k_stream_z": ("stream.hip", "tables.cpp", "sllbm_internal.h"),
-    "k_collide": ("kernels.hip", "collision.h", "velset.h", "sllbm_internal.h"),
+    "k_stream_z": ("stream.hip", "tables.cpp"),
+    "k_collide": ("kernels.hip", "collision.h", "velset.h"),
 }
 
 
@@ -78,25 +78,28 @@ def run_gpu(args, wl, precision):
         del src, dst
     for _ in range(args.warmup):
         ctx.step(1)
+    start = ctx.get_state()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         ctx.step(1)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    # the same K steps again with HIP events around every kernel launch, on the
-    # library's stream (kept out of the wall-clock region: each event record
-    # adds a few microseconds between the launches)
-    ctx.set_kernel_timing(True)
-    for _ in range(args.steps):
-        ctx.step(1)
-    kt = ctx.kernel_times()
-    ctx.set_kernel_timing(False)
     try:
         tot = ctx.totals()
         ok = all(math.isfinite(v) for v in tot)
     except RuntimeError:                 # non-finite totals: the flow itself blew up
         tot, ok = None, False
+    # the same K steps again from the same state with HIP events around every
+    # kernel launch, on the library's stream (kept out of the wall-clock region:
+    # each event record adds a few microseconds between the launches)
+    ctx.set_state(start)
+    ctx.set_kernel_timing(True)
+    for _ in range(args.steps):
+        ctx.step(1)
+    kt = ctx.kernel_times()
+    ctx.set_kernel_timing(False)
+    del start
     nodes = ctx.nodes
     elem = 8 if precision == 0 else 4
     bytes_per_launch = 2 * 2 * Q * nodes * elem          # each kernel reads 90 and writes 90 values per node

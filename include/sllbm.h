@@ -147,6 +147,17 @@ int sllbm_moments(sllbm_ctx *ctx, double *rho, double *u, double *T);
  * Returns ENONFINITE (and still fills out) if any value is not finite. */
 int sllbm_totals(sllbm_ctx *ctx, double *out);
 
+/* Taylor-Green diagnostics of Sec. III C as domain integrals, on a caller
+ * state (device) or, if state is NULL, on the current state:
+ *   out[0] = kinetic energy           int (1/2) rho |u|^2
+ *   out[1] = solenoidal dissipation   int mu(T) |curl u|^2
+ *   out[2] = dilatational dissipation (4/3) int mu(T) (div u)^2
+ * mu(T) is the context's viscosity law (mu_inf plays the paper's 1/(rho_ref
+ * Re)); derivatives are those of each cell's own interpolation polynomial,
+ * integrals the tensor Clenshaw-Curtis rule of each cell (host out[3]).
+ * Deterministic; synchronises the stream; ENONFINITE if a value is not finite. */
+int sllbm_diagnostics(sllbm_ctx *ctx, const void *state, double *out);
+
 /* ---- adjoint (reverse mode of the step map) ----------------------------- */
 
 /* Flow functional on a caller state (device):

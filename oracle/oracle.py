@@ -272,3 +272,13 @@ def loss(cfg, f, g):
     fn = _lib(False).oracle_loss
     fn.restype = ctypes.c_double
     return fn(ctypes.byref(cfg), _ptr(f), _ptr(g))
+
+def diagnostics(cfg, f, g):
+    """(kinetic energy, solenoidal dissipation, dilatational dissipation) as domain integrals."""
+    cplx = _is_cplx(f, g) or cfg.mu_inf_im != 0.0
+    dt = _dt(cplx)
+    f = np.ascontiguousarray(f, dtype=dt)
+    g = np.ascontiguousarray(g, dtype=dt)
+    out = np.zeros(3, dt)
+    getattr(_lib(cplx), _prefix(cplx) + "diagnostics")(ctypes.byref(cfg), _ptr(f), _ptr(g), _ptr(out))
+    return out

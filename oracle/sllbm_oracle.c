@@ -27,7 +27,7 @@
  * every state-dependent operation below is analytic, and the only floor() is
  * applied to the state-independent departure position.
  *
- * Readings of the paper taken here (see the design notes of the repository):
+ * Readings of the paper taken here:
  *   c_s = 1, T0 = 1, theta = T (lattice units); D = 3; C_v = 1/(gamma-1).
  *   T from 2 rho E = rho |u|^2 + 2 C_v rho T (the energy of the equilibria).
  *   Sutherland numerator 1 + S with S = 0.40417, so that mu(T=1) = mu_inf.
@@ -647,6 +647,67 @@ R FN(loss)(const oracle_cfg *c, const R *f, const R *g)
                         }
     free(rho); free(u); free(T);
     return L;
+}
+
+/* TGV diagnostics of Sec. III C, as domain integrals over the cells with the
+ * tensor Clenshaw-Curtis rule of each cell's support points and derivatives
+ * of each cell's own interpolation polynomial:
+ *   out[0] = kinetic energy        int (1/2) rho |u|^2
+ *   out[1] = solenoidal dissipation int mu(T) |curl u|^2
+ *   out[2] = dilatational dissipation (4/3) int mu(T) (div u)^2
+ * (the paper's 1/(rho_ref Re) prefactor is the mu_inf inside mu(T)). */
+void FN(diagnostics)(const oracle_cfg *c, const R *f, const R *g, R *out)
+{
+    int p = c->p;
+    int N[3] = {c->n_el[0] * p, c->n_el[1] * p, c->n_el[2] * p};
+    long Nl = (long)N[0] * N[1] * N[2];
+    R *rho = (R *)malloc(sizeof(R) * Nl), *u = (R *)malloc(sizeof(R) * 3 * Nl), *T = (R *)malloc(sizeof(R) * Nl);
+    FN(moments)(c, f, g, rho, u, T);
+    double t[16], wcc[16], Dm[16][16];
+    oracle_glc_nodes(p, t);
+    oracle_cc_weights(p, wcc);
+    for (int k = 0; k <= p; ++k) {
+        double dl[16];
+        oracle_lagrange_deriv(p, t[k], dl);
+        for (int m = 0; m <= p; ++m) Dm[k][m] = dl[m];
+    }
+    double h[3] = {c->length[0] / c->n_el[0], c->length[1] / c->n_el[1], c->length[2] / c->n_el[2]};
+    R ek = 0, es = 0, ec = 0;
+    for (int ez = 0; ez < c->n_el[2]; ++ez)
+        for (int ey = 0; ey < c->n_el[1]; ++ey)
+            for (int ex = 0; ex < c->n_el[0]; ++ex)
+                for (int kz = 0; kz <= p; ++kz)
+                    for (int ky = 0; ky <= p; ++ky)
+                        for (int kx = 0; kx <= p; ++kx) {
+                            int k3[3] = {kx, ky, kz}, e3[3] = {ex, ey, ez};
+                            long n = ((long)((ez * p + kz) % N[2]) * N[1] + (ey * p + ky) % N[1]) * N[0]
+                                   + (ex * p + kx) % N[0];
+                            R grad[3][3];             /* grad[a][b] = d u_a / d x_b inside this cell */
+                            for (int a = 0; a < 3; ++a)
+                                for (int b = 0; b < 3; ++b) {
+                                    R d = 0;
+                                    for (int m = 0; m <= p; ++m) {
+                                        int gg[3] = {e3[0] * p + k3[0], e3[1] * p + k3[1], e3[2] * p + k3[2]};
+                                        gg[b] = e3[b] * p + m;
+                                        long nm = ((long)(gg[2] % N[2]) * N[1] + gg[1] % N[1]) * N[0] + gg[0] % N[0];
+                                        d += Dm[k3[b]][m] * u[(long)a * Nl + nm];
+                                    }
+                                    grad[a][b] = d / h[b];
+                                }
+                            R w0 = grad[2][1] - grad[1][2], w1 = grad[0][2] - grad[2][0], w2 = grad[1][0] - grad[0][1];
+                            R div = grad[0][0] + grad[1][1] + grad[2][2];
+                            R ke = 0;
+                            for (int a = 0; a < 3; ++a) ke += u[(long)a * Nl + n] * u[(long)a * Nl + n];
+                            R mu = mu_of_T(c, T[n]);
+                            double W = (0.5 * h[0] * wcc[kx]) * (0.5 * h[1] * wcc[ky]) * (0.5 * h[2] * wcc[kz]);
+                            ek += W * 0.5 * rho[n] * ke;
+                            es += W * mu * (w0 * w0 + w1 * w1 + w2 * w2);
+                            ec += W * (4.0 / 3.0) * mu * div * div;
+                        }
+    out[0] = ek;
+    out[1] = es;
+    out[2] = ec;
+    free(rho); free(u); free(T);
 }
 
 #ifdef ORACLE_COMPLEX

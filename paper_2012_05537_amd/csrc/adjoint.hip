@@ -496,6 +496,83 @@ __global__ void __launch_bounds__(256) k_loss_cells(CellGeo g, const double *__r
     if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
+// TGV diagnostics (Sec. III C) per cell point: (1/2) rho |u|^2, mu(T) |curl u|^2
+// and (4/3) mu(T) (div u)^2, derivatives from the cell's own polynomial,
+// weighted by the tensor Clenshaw-Curtis rule; per-block partial sums.
+__global__ void __launch_bounds__(256) k_diag_cells(CellGeo g, CollisionParams cp, const double *__restrict__ dmat,
+                                                    const double *__restrict__ ccw, const double *__restrict__ rho,
+                                                    const double *__restrict__ u, const double *__restrict__ T,
+                                                    double *__restrict__ part)
+{
+    __shared__ double red[3][256];
+    const int p = g.p, p1 = p + 1;
+    const int64_t ncp = static_cast<int64_t>(g.nel[0]) * g.nel[1] * g.nel[2] * p1 * p1 * p1;
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int64_t c = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; c < ncp;
+         c += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        int64_t r = c;
+        int k[3], e[3];
+        k[0] = static_cast<int>(r % p1); r /= p1;
+        k[1] = static_cast<int>(r % p1); r /= p1;
+        k[2] = static_cast<int>(r % p1); r /= p1;
+        e[0] = static_cast<int>(r % g.nel[0]); r /= g.nel[0];
+        e[1] = static_cast<int>(r % g.nel[1]);
+        e[2] = static_cast<int>(r / g.nel[1]);
+        const int gx = e[0] * p + k[0], gy = e[1] * p + k[1], gz = e[2] * p + k[2];
+        double grad[3][3];                       // grad[a][b] = d u_a / d x_b
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) grad[a][b] = 0.0;
+        for (int m = 0; m <= p; ++m) {
+            const int64_t nx = node_of(g, e[0] * p + m, gy, gz);
+            const int64_t ny = node_of(g, gx, e[1] * p + m, gz);
+            const int64_t nz = node_of(g, gx, gy, e[2] * p + m);
+            const double dx = dmat[k[0] * p1 + m] / g.h[0], dy = dmat[k[1] * p1 + m] / g.h[1],
+                         dz = dmat[k[2] * p1 + m] / g.h[2];
+            for (int a = 0; a < 3; ++a) {
+                grad[a][0] = fma(dx, u[a * g.nodes + nx], grad[a][0]);
+                grad[a][1] = fma(dy, u[a * g.nodes + ny], grad[a][1]);
+                grad[a][2] = fma(dz, u[a * g.nodes + nz], grad[a][2]);
+            }
+        }
+        const int64_t n = node_of(g, gx, gy, gz);
+        const double w0 = grad[2][1] - grad[1][2], w1 = grad[0][2] - grad[2][0], w2 = grad[1][0] - grad[0][1];
+        const double div = grad[0][0] + grad[1][1] + grad[2][2];
+        const double ux = u[n], uy = u[g.nodes + n], uz = u[2 * g.nodes + n];
+        const double mu = viscosity_of(cp, T[n]);
+        const double W = (0.5 * g.h[0] * ccw[k[0]]) * (0.5 * g.h[1] * ccw[k[1]]) * (0.5 * g.h[2] * ccw[k[2]]);
+        acc[0] = fma(W, 0.5 * rho[n] * (ux * ux + uy * uy + uz * uz), acc[0]);
+        acc[1] = fma(W, mu * (w0 * w0 + w1 * w1 + w2 * w2), acc[1]);
+        acc[2] = fma(W, (4.0 / 3.0) * mu * div * div, acc[2]);
+    }
+    for (int q = 0; q < 3; ++q) red[q][threadIdx.x] = acc[q];
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s)
+            for (int q = 0; q < 3; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int q = 0; q < 3; ++q) part[blockIdx.x * 3 + q] = red[q][0];
+}
+
+// Fixed-order sum of n partial triples by one block (deterministic).
+__global__ void __launch_bounds__(256) k_sum3(const double *__restrict__ part, int n, double *__restrict__ out)
+{
+    __shared__ double red[3][256];
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < n; b += 256)
+        for (int q = 0; q < 3; ++q) acc[q] += part[b * 3 + q];
+    for (int q = 0; q < 3; ++q) red[q][threadIdx.x] = acc[q];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s)
+            for (int q = 0; q < 3; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int q = 0; q < 3; ++q) out[q] = red[q][0];
+}
+
 // dL/d(state) at every node: dL/drho and dL/du gathered from the cell points
 // whose value or derivative stencil contains the node, then chained through
 // rho = sum f and u = sum f xi / rho (g does not enter L).
@@ -607,6 +684,20 @@ hipError_t Launch<S>::loss_grad(const Geometry &g, const S *state, const double 
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL((k_loss_grad<S>), dim3(nb), dim3(256), 0, st, cell_geo(g, h), dmat, nodew, scratch_rho,
                        scratch_u, scratch_div, lam);
+    return hipGetLastError();
+}
+
+template <typename S>
+hipError_t Launch<S>::diagnostics(const Geometry &g, const CollisionParams &cp, const S *state, const double *dmat,
+                                  const double *ccw, const double *h, double *scratch_rho, double *scratch_u,
+                                  double *scratch_T, double *partials, int nblocks, double *out3, hipStream_t st)
+{
+    hipError_t e = moments(g, cp, state, scratch_rho, scratch_u, scratch_T, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_diag_cells, dim3(nblocks), dim3(256), 0, st, cell_geo(g, h), cp, dmat, ccw, scratch_rho,
+                       scratch_u, scratch_T, partials);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sum3, dim3(1), dim3(256), 0, st, partials, nblocks, out3);
     return hipGetLastError();
 }
 

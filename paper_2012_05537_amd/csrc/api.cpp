@@ -52,6 +52,7 @@ struct sllbm_ctx {
     double *d_scr_rho = nullptr;   // [N]   loss scratch
     double *d_scr_u = nullptr;     // [3N]
     double *d_scr_div = nullptr;   // [cells * (p+1)^3]
+    double *d_scr_T = nullptr;     // [N]   diagnostics scratch
     double *d_adj_part = nullptr;  // [ADJ_BLOCKS] dmu_inf partials of the collision VJP
     // kernel timing: event pairs per launch kind (0 collision, 1 streaming)
     bool zt_ok = false;           // transposed streaming may use the z-march (nel_z >= 3, spans <= 3p + 1)
@@ -117,6 +118,7 @@ void free_ctx(sllbm_ctx *c)
     (void)hipFree(c->d_scr_rho);
     (void)hipFree(c->d_scr_u);
     (void)hipFree(c->d_scr_div);
+    (void)hipFree(c->d_scr_T);
     (void)hipFree(c->d_adj_part);
 }
 
@@ -352,6 +354,7 @@ int sllbm_create(const sllbm_config *cfg, sllbm_ctx **out)
         (e = dalloc(&c->d_scr_rho, nodes * sizeof(double))) != hipSuccess ||
         (e = dalloc(&c->d_scr_u, 3 * nodes * sizeof(double))) != hipSuccess ||
         (e = dalloc(&c->d_scr_div, cpts * sizeof(double))) != hipSuccess ||
+        (e = dalloc(&c->d_scr_T, nodes * sizeof(double))) != hipSuccess ||
         (e = dalloc(&c->d_adj_part, ADJ_BLOCKS * sizeof(double))) != hipSuccess)
         return bail(fail(c, SLLBM_ENOMEM, std::string("allocation failed: ") + hipGetErrorString(e)));
     if ((e = hipMemcpy(c->d_nodew, nodew.data(), nodew.size() * sizeof(double), hipMemcpyHostToDevice)) !=
@@ -481,8 +484,9 @@ static hipError_t stream_t_into(sllbm_ctx *c, const void *in, void *out)
                                       c->stream);
 }
 
-// n steps X <- S(C(X)): collision into the spare buffer, streaming back into
-// the state buffer (or into record slot s, from which the next step collides).
+// n steps X <- S(C(X)): collision in place and streaming into the other
+// buffer, which becomes the state; with a record, collision into the spare
+// buffer and streaming into record slot s, from which the next step collides.
 static int step_impl(sllbm_ctx *ctx, int32_t n, char *record, int64_t stride)
 {
     if (!ctx) return SLLBM_EINVAL;
@@ -499,11 +503,25 @@ static int step_impl(sllbm_ctx *ctx, int32_t n, char *record, int64_t stride)
         }
     };
     for (int32_t s = 0; s < n; ++s) {
-        const void *src = (record && s > 0) ? record + static_cast<int64_t>(s - 1) * stride : state;
-        void *dst = record ? record + static_cast<int64_t>(s) * stride : state;
+        hipError_t e;
+        if (!record) {
+            // collide the state in place, stream it into the other buffer, swap:
+            // each kernel then reads and writes one buffer's worth of lines
+            mark(0, 0);
+            if ((e = collide_into(ctx, state, state)) != hipSuccess) return hip_fail(ctx, e, "collide");
+            mark(0, 1);
+            mark(1, 0);
+            if ((e = stream_into(ctx, state, post)) != hipSuccess) return hip_fail(ctx, e, "stream");
+            mark(1, 1);
+            ctx->cur = 1 - ctx->cur;
+            state = ctx->buf[ctx->cur];
+            post = other(ctx);
+            continue;
+        }
+        const void *src = s > 0 ? record + static_cast<int64_t>(s - 1) * stride : state;
+        void *dst = record + static_cast<int64_t>(s) * stride;
         mark(0, 0);
-        hipError_t e = collide_into(ctx, src, post);
-        if (e != hipSuccess) return hip_fail(ctx, e, "collide");
+        if ((e = collide_into(ctx, src, post)) != hipSuccess) return hip_fail(ctx, e, "collide");
         mark(0, 1);
         mark(1, 0);
         if ((e = stream_into(ctx, post, dst)) != hipSuccess) return hip_fail(ctx, e, "stream");
@@ -646,6 +664,30 @@ int sllbm_loss(sllbm_ctx *ctx, const void *state, double *out)
         (e = hipStreamSynchronize(ctx->stream)) != hipSuccess)
         return hip_fail(ctx, e, "loss copy");
     if (!std::isfinite(*out)) return fail(ctx, SLLBM_ENONFINITE, "non-finite loss");
+    return SLLBM_OK;
+}
+
+int sllbm_diagnostics(sllbm_ctx *ctx, const void *state, double *out)
+{
+    if (!ctx) return SLLBM_EINVAL;
+    if (!out) return fail(ctx, SLLBM_EINVAL, "NULL out");
+    if (!state && !ctx->has_state) return fail(ctx, SLLBM_ESTATE, "no state set");
+    DeviceGuard guard(ctx->cfg.device);
+    const void *st = state ? state : ctx->buf[ctx->cur];
+    hipError_t e = is_fp64(ctx)
+        ? Launch<double>::diagnostics(ctx->geo, ctx->cp, static_cast<const double *>(st), ctx->d_dmat, ctx->d_ccw,
+                                      ctx->h, ctx->d_scr_rho, ctx->d_scr_u, ctx->d_scr_T, ctx->d_partials, RED_BLOCKS,
+                                      ctx->d_small, ctx->stream)
+        : Launch<float>::diagnostics(ctx->geo, ctx->cp, static_cast<const float *>(st), ctx->d_dmat, ctx->d_ccw,
+                                     ctx->h, ctx->d_scr_rho, ctx->d_scr_u, ctx->d_scr_T, ctx->d_partials, RED_BLOCKS,
+                                     ctx->d_small, ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "diagnostics");
+    if ((e = hipMemcpyAsync(out, ctx->d_small, 3 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream)) !=
+            hipSuccess ||
+        (e = hipStreamSynchronize(ctx->stream)) != hipSuccess)
+        return hip_fail(ctx, e, "diagnostics copy");
+    for (int k = 0; k < 3; ++k)
+        if (!std::isfinite(out[k])) return fail(ctx, SLLBM_ENONFINITE, "non-finite diagnostics");
     return SLLBM_OK;
 }
 

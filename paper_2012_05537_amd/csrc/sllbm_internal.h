@@ -115,6 +115,10 @@ struct Launch {
                                 const double *nodew, const double *h, double *scratch_rho,
                                 double *scratch_u, double *scratch_div, double *partials, int nblocks, S *lam,
                                 hipStream_t st);
+    // kinetic energy, solenoidal and dilatational dissipation (device out3)
+    static hipError_t diagnostics(const Geometry &g, const CollisionParams &cp, const S *state, const double *dmat,
+                                  const double *ccw, const double *h, double *scratch_rho, double *scratch_u,
+                                  double *scratch_T, double *partials, int nblocks, double *out3, hipStream_t st);
     // lam <- J_C(X_n)^T lam in place; dL/dmu_inf added to *dmu if not NULL
     static hipError_t collide_vjp(const Geometry &g, const CollisionParams &cp, const S *state_n, S *lam,
                                   double *dmu_partials, int nblocks, double *dmu, hipStream_t st);

@@ -41,34 +41,48 @@ __device__ __forceinline__ int xcd_linear(int b, int nb)
 constexpr int64_t ZCHUNK_TARGET_BLOCKS = 2048;
 constexpr int ZCHUNK_MIN_CELLS = 4;
 
-template <int P>
+// V = values per window load (1, or 16 bytes when every window row starts
+// on a 16-byte boundary: p * sizeof(S) and N_x * sizeof(S) multiples of 16)
+template <int P, int V = 1>
 struct ZTile {
     static constexpr int XN = 32, YN = 8;                     // target tile extent in nodes (long x rows)
     static constexpr int TXC = XN / P > 0 ? XN / P : 1;       // cells per tile along x and y
     static constexpr int TYC = YN / P > 0 ? YN / P : 1;
     static constexpr int TX = TXC * P, TY = TYC * P;          // nodes per tile
     static constexpr int WX = TX + P + 1, WY = TY + P + 1;    // source window
+    static constexpr int WXC = (WX + V - 1) / V, WXP = WXC * V;   // loads per window row, padded row
     static constexpr int NT = (TX * TY + 63) / 64 * 64;       // one thread per output column
-    static constexpr int LK = (WX * WY + NT - 1) / NT;        // window loads per thread and row
+    static constexpr int LK = (WXC * WY + NT - 1) / NT;       // window loads per thread and row
     static constexpr int NG = TXC + 1;                        // source cells of an x window row
     static constexpr int BS = TX % 2 ? TX : TX + 1;           // odd row stride of the x-pass output (LDS banks)
 };
 
+template <typename S, int V>
+struct VecOf {
+    typedef S T __attribute__((ext_vector_type(V)));
+};
+template <typename S>
+struct VecOf<S, 1> {
+    typedef S T;
+};
+
 }  // namespace
 
-template <typename S, int P>
-__global__ void __launch_bounds__(ZTile<P>::NT) k_stream_z(Geometry g, CellTables<S> tab, const S *__restrict__ in,
-                                                  S *__restrict__ out, int ntile_x, int ntiles, int zcells,
-                                                  int nchunk)
+template <typename S, int P, int V>
+__global__ void __launch_bounds__((ZTile<P, V>::NT)) k_stream_z(Geometry g, CellTables<S> tab, const S *__restrict__ in,
+                                                     S *__restrict__ out, int ntile_x, int ntiles, int zcells,
+                                                     int nchunk)
 {
-    using Z = ZTile<P>;
-    constexpr int TX = Z::TX, TY = Z::TY, WX = Z::WX, WY = Z::WY, NT = Z::NT, LK = Z::LK;
+    using Z = ZTile<P, V>;
+    using VT = typename VecOf<S, V>::T;
+    constexpr int TX = Z::TX, TY = Z::TY, WX = Z::WXP, WY = Z::WY, NT = Z::NT, LK = Z::LK;
     constexpr int WP = WX * WY;
+    constexpr int NLD = Z::WXC * WY;                       // window loads per row
     // one batch of source rows (P + 1 for the first cell, P afterwards); single
     // buffers suffice with two barriers per batch: a thread stores the next
     // batch only after the barrier that follows every thread's x-pass, and
     // overwrites bx only after the barrier that follows every thread's y-pass
-    __shared__ S pl[P + 1][WP];
+    __shared__ __align__(16) S pl[P + 1][WP];
     constexpr int BS = Z::BS;
     __shared__ S bx[P + 1][WY * BS];
 
@@ -89,13 +103,14 @@ __global__ void __launch_bounds__(ZTile<P>::NT) k_stream_z(Geometry g, CellTable
     const S *__restrict__ src = in + static_cast<int64_t>(pop * 45 + i) * N;
     S *__restrict__ dst = out + static_cast<int64_t>(pop * 45 + i) * N;
 
-    // window loads of this thread: x-y offsets inside a z-plane
+    // window loads of this thread (V values each): x-y offsets inside a z-plane;
+    // load e covers window row e / WXC, columns V * (e % WXC) ...
     int loff[LK];
 #pragma unroll
     for (int k = 0; k < LK; ++k) {
         int e = tid + k * NT;
-        e = e < WP ? e : WP - 1;                           // surplus lanes repeat the last element
-        const int wx = e % WX, wy = e / WX;
+        e = e < NLD ? e : NLD - 1;                         // surplus lanes repeat the last load
+        const int wx = (e % Z::WXC) * V, wy = e / Z::WXC;
         loff[k] = wrapi(Y0 + omy * P + wy, Ny) * Nx + wrapi(X0 + omx * P + wx, Nx);
     }
     // x-pass by source cell: window cell c = g + 1 (g = -1 .. TXC - 1) feeds the
@@ -127,14 +142,14 @@ __global__ void __launch_bounds__(ZTile<P>::NT) k_stream_z(Geometry g, CellTable
     const int zb = (ez0 + omz) * P;
     // two register buffers of source rows: the rows of the cell after next are
     // in flight while a cell is processed
-    S rawA[P + 1][LK], rawB[P][LK];
+    VT rawA[P + 1][LK], rawB[P][LK];
     auto load_rows = [&](auto &raw, int k0, int nr) {
 #pragma unroll
         for (int r = 0; r <= P; ++r) {
             if (r < nr && r < static_cast<int>(sizeof(raw) / sizeof(raw[0]))) {
                 const int64_t zo = static_cast<int64_t>(wrapi(zb + k0 + r, Nz)) * NP;
 #pragma unroll
-                for (int j = 0; j < LK; ++j) raw[r][j] = src[zo + loff[j]];
+                for (int j = 0; j < LK; ++j) raw[r][j] = *reinterpret_cast<const VT *>(src + zo + loff[j]);
             }
         }
     };
@@ -146,7 +161,7 @@ __global__ void __launch_bounds__(ZTile<P>::NT) k_stream_z(Geometry g, CellTable
         for (int r = 0; r < NR; ++r)
 #pragma unroll
             for (int j = 0; j < LK; ++j)
-                if (tid + j * NT < WP) pl[r][tid + j * NT] = raw[r][j];
+                if (tid + j * NT < NLD) *reinterpret_cast<VT *>(&pl[r][V * (tid + j * NT)]) = raw[r][j];
         if (next_nr > 0) load_rows(raw, next_k0, next_nr);
         __syncthreads();
         constexpr int XT = NR * WY * Z::NG;                   // (row, window row, source cell) tasks
@@ -216,10 +231,10 @@ __global__ void __launch_bounds__(ZTile<P>::NT) k_stream_z(Geometry g, CellTable
     }
 }
 
-template <typename S, int P>
-static hipError_t launch_z(const Geometry &g, const CellTables<S> &t, const S *in, S *out, hipStream_t st)
+template <typename S, int P, int V>
+static hipError_t launch_zv(const Geometry &g, const CellTables<S> &t, const S *in, S *out, hipStream_t st)
 {
-    using Z = ZTile<P>;
+    using Z = ZTile<P, V>;
     const int ntx = (g.N[0] + Z::TX - 1) / Z::TX, nty = (g.N[1] + Z::TY - 1) / Z::TY;
     const int ntiles = ntx * nty;
     // split the z-march into chunks until the grid has a few blocks per CU
@@ -232,9 +247,22 @@ static hipError_t launch_z(const Geometry &g, const CellTables<S> &t, const S *i
     nchunk = (g.nel[2] + zcells - 1) / zcells;
     const int64_t nb = static_cast<int64_t>(ntiles) * 90 * nchunk;
     if (nb > (int64_t(1) << 31) - 1) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_stream_z<S, P>), dim3(static_cast<unsigned>(nb)), dim3(Z::NT), 0, st, g, t, in, out, ntx,
+    hipLaunchKernelGGL((k_stream_z<S, P, V>), dim3(static_cast<unsigned>(nb)), dim3(Z::NT), 0, st, g, t, in, out, ntx,
                        ntiles, zcells, nchunk);
     return hipGetLastError();
+}
+
+// 16-byte window loads when every window row starts on a 16-byte boundary
+template <typename S, int P>
+static hipError_t launch_z(const Geometry &g, const CellTables<S> &t, const S *in, S *out, hipStream_t st)
+{
+    constexpr int V = 16 / sizeof(S);
+    const bool aligned = (P * sizeof(S)) % 16 == 0 && (g.N[0] * sizeof(S)) % 16 == 0 &&
+                         reinterpret_cast<uintptr_t>(in) % 16 == 0;
+    if constexpr ((P * sizeof(S)) % 16 == 0 && ZTile<P, V>::TX % V == 0) {
+        if (aligned) return launch_zv<S, P, V>(g, t, in, out, st);
+    }
+    return launch_zv<S, P, 1>(g, t, in, out, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -254,30 +282,33 @@ static hipError_t launch_z(const Geometry &g, const CellTables<S> &t, const S *i
 // row has all its contributions.  Requires at least three cells along z
 // (with two, one input cell would reach the same row twice by wrapping).
 // ---------------------------------------------------------------------------
-template <int P>
+template <int P, int V = 1>
 struct ZTileT {
-    static constexpr int XN = 16, YN = 16;
+    static constexpr int XN = 32, YN = 8;
     static constexpr int TXC = XN / P > 0 ? XN / P : 1, TYC = YN / P > 0 ? YN / P : 1;
     static constexpr int TX = TXC * P, TY = TYC * P;
     static constexpr int K = 2 * P;                           // taps of a transposed row
     static constexpr int SPMAX = 3 * P + 1;                   // largest offset span of a transposed row set
-    static constexpr int WX = TX + SPMAX - 1, WY = TY + SPMAX - 1;
+    static constexpr int WXC = (TX + SPMAX - 1 + V - 1 + V - 1) / V;   // loads per window row (V-aligned start)
+    static constexpr int WX = WXC * V, WY = TY + SPMAX - 1;
     static constexpr int NT = (TX * TY + 63) / 64 * 64;
-    static constexpr int LK = (WX * WY + NT - 1) / NT;
-    static constexpr int XT = WY * TX, XK = (XT + NT - 1) / NT;
+    static constexpr int LK = (WXC * WY + NT - 1) / NT;
+    static constexpr int XR = NT / TX;                        // window rows per x-gather pass
+    static constexpr int XK = (WY + XR - 1) / XR;
+    static constexpr int BS = TX % 2 ? TX : TX + 1;
 };
 
-template <typename S, int P>
-__global__ void __launch_bounds__(ZTileT<P>::NT) k_stream_zt(Geometry g, CellTables<S> fwd, const int32_t *__restrict__ toff,
-                                                             const S *__restrict__ twt, const int32_t *__restrict__ tlo,
-                                                             const int32_t *__restrict__ tspan, const S *__restrict__ in,
-                                                             S *__restrict__ out, int ntile_x, int ntiles, int zcells,
-                                                             int nchunk)
+template <typename S, int P, int V>
+__global__ void __launch_bounds__((ZTileT<P, V>::NT))
+    k_stream_zt(Geometry g, CellTables<S> fwd, const int32_t *__restrict__ toff, const S *__restrict__ twt,
+                const int32_t *__restrict__ tlo, const int32_t *__restrict__ tspan, const S *__restrict__ in,
+                S *__restrict__ out, int ntile_x, int ntiles, int zcells, int nchunk)
 {
-    using Z = ZTileT<P>;
-    constexpr int TX = Z::TX, TY = Z::TY, NT = Z::NT, LK = Z::LK, XK = Z::XK, K = Z::K;
-    __shared__ S pl[P][Z::WX * Z::WY];
-    __shared__ S bx[P][Z::WY * TX];
+    using Z = ZTileT<P, V>;
+    using VT = typename VecOf<S, V>::T;
+    constexpr int TX = Z::TX, TY = Z::TY, NT = Z::NT, LK = Z::LK, XK = Z::XK, K = Z::K, BS = Z::BS;
+    __shared__ __align__(16) S pl[P][Z::WX * Z::WY];
+    __shared__ S bx[P][Z::WY * BS];
 
     const int tid = threadIdx.x;
     const int L = __builtin_amdgcn_readfirstlane(xcd_linear(blockIdx.x, gridDim.x));
@@ -289,8 +320,10 @@ __global__ void __launch_bounds__(ZTileT<P>::NT) k_stream_zt(Geometry g, CellTab
     const int Nx = g.N[0], Ny = g.N[1], Nz = g.N[2];
     const int64_t N = g.nodes, NP = static_cast<int64_t>(Nx) * Ny;
     const int lox = tlo[i * 3 + 0], loy = tlo[i * 3 + 1];
-    const int wxs = TX + tspan[i * 3 + 0] - 1, wys = TY + tspan[i * 3 + 1] - 1;   // window of this velocity
-    const int wp = wxs * wys;
+    const int lxa = lox - ((lox % V) + V) % V;            // window start, rounded down to V
+    const int wxc = (TX + tspan[i * 3 + 0] - 1 + (lox - lxa) + V - 1) / V;
+    const int wxs = wxc * V, wys = TY + tspan[i * 3 + 1] - 1;   // window of this velocity
+    const int nld = wxc * wys;
     const int omz = fwd.omin[i * 3 + 2], lsz = fwd.lstar[i * 3 + 2];
     const S *Wz = fwd.w + (i * 3 + 2) * P * (P + 1);
     const int32_t *ox = toff + (i * 3 + 0) * P * K, *oy = toff + (i * 3 + 1) * P * K;
@@ -302,24 +335,20 @@ __global__ void __launch_bounds__(ZTileT<P>::NT) k_stream_zt(Geometry g, CellTab
 #pragma unroll
     for (int k = 0; k < LK; ++k) {
         int e = tid + k * NT;
-        e = e < wp ? e : wp - 1;
-        const int wx = e % wxs, wy = e / wxs;
-        loff[k] = wrapi(Y0 + loy + wy, Ny) * Nx + wrapi(X0 + lox + wx, Nx);
+        e = e < nld ? e : nld - 1;
+        const int wx = (e % wxc) * V, wy = e / wxc;
+        loff[k] = wrapi(Y0 + loy + wy, Ny) * Nx + wrapi(X0 + lxa + wx, Nx);
     }
-    // x-gather tasks: output (wy, tx) from window row wy
-    int xs[XK][K], xd[XK];
-    S xw[XK][K];
+    // x-gather: thread (xrow, xt) handles column xt of window rows xrow, xrow + XR, ...;
+    // its taps (offsets within the row and weights) are fixed
+    const int xt = tid % TX, xrow = tid / TX, mx = xt % P;
+    const bool xact = xrow < Z::XR;
+    int xs[K];
+    S xw[K];
 #pragma unroll
-    for (int k = 0; k < XK; ++k) {
-        int e = tid + k * NT;
-        e = e < wys * TX ? e : wys * TX - 1;
-        const int tx = e % TX, wy = e / TX, m = tx % P;
-        xd[k] = wy * TX + tx;
-#pragma unroll
-        for (int t = 0; t < K; ++t) {
-            xs[k][t] = wy * wxs + tx - m + ox[m * K + t] - lox;
-            xw[k][t] = wxt[m * K + t];
-        }
+    for (int t = 0; t < K; ++t) {
+        xs[t] = xt - mx + ox[mx * K + t] - lxa;
+        xw[t] = wxt[mx * K + t];
     }
     const int tx = tid % TX, ty = tid / TX;
     const bool own = tid < TX * TY && X0 + tx < Nx && Y0 + ty < Ny;
@@ -328,7 +357,7 @@ __global__ void __launch_bounds__(ZTileT<P>::NT) k_stream_zt(Geometry g, CellTab
     S yw[K];
 #pragma unroll
     for (int t = 0; t < K; ++t) {
-        ys[t] = (ty - my + oy[my * K + t] - loy) * TX + (tid < TX * TY ? tx : 0);
+        ys[t] = (ty - my + oy[my * K + t] - loy) * BS + (tid < TX * TY ? tx : 0);
         yw[t] = wyt[my * K + t];
     }
     const int64_t oxy = static_cast<int64_t>(Y0 + ty) * Nx + (X0 + tx);
@@ -340,13 +369,13 @@ __global__ void __launch_bounds__(ZTileT<P>::NT) k_stream_zt(Geometry g, CellTab
 
     // input cells e0 - 2 .. e1 - 1; row l of cell e is z = e*P + l
     const int e0 = chunk * zcells, e1 = min(g.nel[2], e0 + zcells);
-    S raw[P][LK];
+    VT raw[P][LK];
     auto load_cell = [&](int e) {
 #pragma unroll
         for (int r = 0; r < P; ++r) {
             const int64_t zo = static_cast<int64_t>(wrapi(e * P + r, Nz)) * NP;
 #pragma unroll
-            for (int j = 0; j < LK; ++j) raw[r][j] = src[zo + loff[j]];
+            for (int j = 0; j < LK; ++j) raw[r][j] = *reinterpret_cast<const VT *>(src + zo + loff[j]);
         }
     };
     S acc[2 * P + 1];
@@ -358,20 +387,24 @@ __global__ void __launch_bounds__(ZTileT<P>::NT) k_stream_zt(Geometry g, CellTab
         for (int r = 0; r < P; ++r)
 #pragma unroll
             for (int j = 0; j < LK; ++j)
-                if (tid + j * NT < wp) pl[r][tid + j * NT] = raw[r][j];
+                if (tid + j * NT < nld) *reinterpret_cast<VT *>(&pl[r][V * (tid + j * NT)]) = raw[r][j];
         if (e + 1 < e1) load_cell(e + 1);
         __syncthreads();
+        if (xact) {
 #pragma unroll
-        for (int r = 0; r < P; ++r)
+            for (int r = 0; r < P; ++r)
 #pragma unroll
-            for (int k = 0; k < XK; ++k) {
-                if (tid + k * NT < wys * TX) {
-                    S v = 0;
+                for (int k = 0; k < XK; ++k) {
+                    const int wy = xrow + k * Z::XR;
+                    if (wy < wys) {
+                        const S *rowp = &pl[r][wy * wxs];
+                        S v = 0;
 #pragma unroll
-                    for (int t = 0; t < K; ++t) v = fma(xw[k][t], pl[r][xs[k][t]], v);
-                    bx[r][xd[k]] = v;
+                        for (int t = 0; t < K; ++t) v = fma(xw[t], rowp[xs[t]], v);
+                        bx[r][wy * BS + xt] = v;
+                    }
                 }
-            }
+        }
         __syncthreads();
 #pragma unroll
         for (int l = 0; l < P; ++l) {
@@ -398,11 +431,11 @@ __global__ void __launch_bounds__(ZTileT<P>::NT) k_stream_zt(Geometry g, CellTab
     }
 }
 
-template <typename S, int P>
-static hipError_t launch_zt(const Geometry &g, const CellTables<S> &t, const int32_t *toff, const S *twt,
-                            const int32_t *tlo, const int32_t *tspan, const S *in, S *out, hipStream_t st)
+template <typename S, int P, int V>
+static hipError_t launch_ztv(const Geometry &g, const CellTables<S> &t, const int32_t *toff, const S *twt,
+                             const int32_t *tlo, const int32_t *tspan, const S *in, S *out, hipStream_t st)
 {
-    using Z = ZTileT<P>;
+    using Z = ZTileT<P, V>;
     const int ntx = (g.N[0] + Z::TX - 1) / Z::TX, nty = (g.N[1] + Z::TY - 1) / Z::TY;
     const int ntiles = ntx * nty;
     int nchunk = 1;
@@ -413,9 +446,23 @@ static hipError_t launch_zt(const Geometry &g, const CellTables<S> &t, const int
     nchunk = (g.nel[2] + zcells - 1) / zcells;
     const int64_t nb = static_cast<int64_t>(ntiles) * 90 * nchunk;
     if (nb > (int64_t(1) << 31) - 1) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_stream_zt<S, P>), dim3(static_cast<unsigned>(nb)), dim3(Z::NT), 0, st, g, t, toff, twt, tlo,
-                       tspan, in, out, ntx, ntiles, zcells, nchunk);
+    hipLaunchKernelGGL((k_stream_zt<S, P, V>), dim3(static_cast<unsigned>(nb)), dim3(Z::NT), 0, st, g, t, toff, twt,
+                       tlo, tspan, in, out, ntx, ntiles, zcells, nchunk);
     return hipGetLastError();
+}
+
+template <typename S, int P>
+static hipError_t launch_zt(const Geometry &g, const CellTables<S> &t, const int32_t *toff, const S *twt,
+                            const int32_t *tlo, const int32_t *tspan, const S *in, S *out, hipStream_t st)
+{
+    // 16-byte loads need V-aligned window starts: tiles of a multiple of V
+    // nodes, rows of a multiple of V nodes, a 16-byte aligned buffer
+    constexpr int V = 16 / sizeof(S);
+    if constexpr (ZTileT<P, V>::TX % V == 0) {
+        if ((g.N[0] * sizeof(S)) % 16 == 0 && reinterpret_cast<uintptr_t>(in) % 16 == 0)
+            return launch_ztv<S, P, V>(g, t, toff, twt, tlo, tspan, in, out, st);
+    }
+    return launch_ztv<S, P, 1>(g, t, toff, twt, tlo, tspan, in, out, st);
 }
 
 template <typename S>

@@ -66,6 +66,7 @@ _SIGS = {
     "sllbm_loss": (ctypes.c_int, [_VP, _VP, _VP]),
     "sllbm_loss_grad": (ctypes.c_int, [_VP, _VP, _VP]),
     "sllbm_adjoint_step": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP]),
+    "sllbm_diagnostics": (ctypes.c_int, [_VP, _VP, _VP]),
     "sllbm_set_kernel_timing": (ctypes.c_int, [_VP, ctypes.c_int32]),
     "sllbm_kernel_times": (ctypes.c_int, [_VP, _VP]),
     "sllbm_moments_vjp": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP]),
@@ -239,6 +240,14 @@ class SLLBM:
         out = (ctypes.c_double * 5)()
         self._check(self._lib.sllbm_totals(self._h, ctypes.addressof(out)))
         return list(out)
+
+    def diagnostics(self, state=None):
+        """(kinetic energy, solenoidal dissipation, dilatational dissipation) of the state (default: current)."""
+        self._sync_stream()
+        out = (ctypes.c_double * 3)()
+        arg = None if state is None else self._state_arg(state)
+        self._check(self._lib.sllbm_diagnostics(self._h, arg, ctypes.addressof(out)))
+        return tuple(out)
 
     def loss(self, state):
         self._sync_stream()
