@@ -80,3 +80,28 @@ def test_null_arguments(lib):
     assert lib.sllbm_num_nodes(None) == -1
     assert lib.sllbm_step(None, 1) == 1
     assert lib.sllbm_velocity_set(None, None) == 1
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    """The binding has no fallback: a missing libsllbm.so is an error."""
+    import importlib
+    import paper_2012_05537_amd.sllbm as S
+    saved = S._lib
+    try:
+        S._lib = None
+        with pytest.raises(RuntimeError):
+            S.load_library(str(tmp_path / "libsllbm.so"))
+    finally:
+        S._lib = saved
+
+
+def test_bench_refuses_several_gpus():
+    """bench.py measures one GPU; asking for more exits with a message."""
+    import subprocess
+    import sys
+    import os
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
