@@ -1,0 +1,127 @@
+"""Parity at the full sizes of the FP32-mixed workloads (128^3 and 256^3
+nodes, order 4), in the launch configuration of the benchmark, on outputs the
+oracle evaluates one by one.
+
+* Forward: the GPU's initial state (FP32 storage) is given to the oracle,
+  which computes one step at sampled nodes (each sample collides its whole
+  (p+1)^3 departure stencil and interpolates); the GPU steps the same state.
+  Bar: the FP32-mixed tolerance 1e-5 relative to the largest population.
+* Adjoint: lambda_n = J_C(X)^T S^T lambda_{n+1} at sampled nodes, with S^T of
+  the library (its transpose identity is pinned on smaller grids) and J_C^T
+  from complex-step collisions of the sampled nodes in the oracle (collision
+  is node-local).  Bar: 1e-4 relative (FP32 storage of X and lambda).
+* Transposed streaming at 256^3: <S x, y> = <x, S^T y> for random x, y,
+  both sides from the library, per population and velocity.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import Q, workload_pair, to_np, require_gpu
+from paper_2012_05537_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+H = 1e-30
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def _init_gpu(ctx, w):
+    xs, ys, zs = (t.numpy() for t in ctx.node_coords())
+    rho, u, T = inputs.tgv_fields(xs, ys, zs, w["Ma"], w["gamma"])
+    dev = ctx.device
+    ctx.init_equilibrium(*(torch.from_numpy(x).to(dev) for x in (rho, u, T)))
+
+
+@pytest.mark.parametrize("name", ["c3", "c5"])
+def test_one_step_sampled_full_size(oracle, name):
+    _say(f"{name}: one FP32-mixed step at full size, sampled")
+    w, ctx, cfg = workload_pair(oracle, name)
+    _init_gpu(ctx, w)
+    X0 = ctx.get_state()
+    f0, g0 = to_np(X0)                         # the exact FP32 values, as float64
+    ctx.step(1)
+    X1 = ctx.get_state()
+    rng = np.random.default_rng(2021 if name == "c5" else 2012)
+    nodes = np.concatenate([[0, ctx.nodes - 1], rng.integers(0, ctx.nodes, 30)])
+    fs, gs = oracle.step_at_nodes(cfg, f0, g0, nodes)
+    idx = torch.from_numpy(nodes).to(ctx.device)
+    F = X1[0][:, idx].double().cpu().numpy().T
+    G = X1[1][:, idx].double().cpu().numpy().T
+    del f0, g0
+    ef = np.max(np.abs(F - fs)) / np.abs(fs).max()
+    eg = np.max(np.abs(G - gs)) / np.abs(gs).max()
+    _say(f"{name}: max rel error f {ef:.2e} g {eg:.2e}")
+    assert ef < 1e-5 and eg < 1e-5
+    ctx.close()
+
+
+def _collide_vjp_at(oracle, cfg_small, f, g, yf, yg):
+    """J_C^T y for a set of nodes held as a small grid (collision is node-local)."""
+    n = f.shape[1]
+    lf = np.zeros((Q, n))
+    lg = np.zeros((Q, n))
+    for pop in range(2):
+        for k in range(Q):
+            fc = f.astype(np.complex128)
+            gc = g.astype(np.complex128)
+            (gc if pop else fc)[k] += 1j * H
+            cf, cg = oracle.collide(cfg_small, fc, gc)
+            col = (np.sum(yf * cf.imag, axis=0) + np.sum(yg * cg.imag, axis=0)) / H
+            (lg if pop else lf)[k] = col
+    return lf, lg
+
+
+def test_adjoint_step_sampled_256cubed(oracle):
+    """c5 size (64^3 cells, p = 4, FP32 storage, CFL 10)."""
+    _say("c5: adjoint step at full size, sampled")
+    w, ctx, cfg = workload_pair(oracle, "c5")
+    _init_gpu(ctx, w)
+    ctx.step(2)
+    X = ctx.get_state()
+    gen = torch.Generator(device=ctx.device).manual_seed(5)
+    lam_next = torch.randn(X.shape, generator=gen, device=ctx.device, dtype=torch.float32)
+    y = ctx.stream(lam_next, transpose=True)
+    lam = ctx.adjoint_step(X, lam_next)
+    torch.cuda.synchronize()
+    nodes = np.random.default_rng(3).integers(0, ctx.nodes, 64)
+    idx = torch.from_numpy(nodes).to(ctx.device)
+    pick = lambda t: (t[0][:, idx].double().cpu().numpy(), t[1][:, idx].double().cpu().numpy())
+    f, g = pick(X)
+    yf, yg = pick(y)
+    LF, LG = pick(lam)
+    # the 64 sampled nodes as a 4^3-node grid of the same parameters (collision ignores geometry)
+    small = oracle.make_cfg((1, 1, 1), 4, w["dt"], w["mu_inf"], gamma=w["gamma"], prandtl=w["Pr"])
+    ef, eg = _collide_vjp_at(oracle, small, f, g, yf, yg)
+    err = max(np.max(np.abs(LF - ef)) / np.abs(ef).max(), np.max(np.abs(LG - eg)) / np.abs(eg).max())
+    _say(f"c5 adjoint sampled max rel error {err:.2e}")
+    assert err < 1e-4
+    ctx.close()
+
+
+def test_transposed_stream_identity_256cubed(oracle):
+    w, ctx, cfg = workload_pair(oracle, "c5")
+    gen = torch.Generator(device=ctx.device).manual_seed(11)
+    shape = (2, Q, ctx.nodes)
+    x = torch.randn(shape, generator=gen, device=ctx.device, dtype=torch.float32)
+    yv = torch.randn(shape, generator=gen, device=ctx.device, dtype=torch.float32)
+    Sx = ctx.stream(x)
+    STy = ctx.stream(yv, transpose=True)
+    lhs = (Sx.double() * yv.double()).sum(dim=2)
+    rhs = (x.double() * STy.double()).sum(dim=2)
+    scale = (Sx.double().abs() * yv.double().abs()).sum(dim=2)
+    rel = float(((lhs - rhs).abs() / scale).max())
+    _say(f"c5 transposed identity: max rel {rel:.2e}")
+    assert rel < 1e-5
+    ctx.close()
