@@ -135,6 +135,7 @@ def run_adjoint(wl, precision):
     amps.grad = None
     mu.grad = None
     torch.cuda.synchronize()
+    torch.cuda.reset_peak_memory_stats()
     t0 = time.perf_counter()
     L = roll(amps, mu)
     torch.cuda.synchronize()
@@ -142,11 +143,14 @@ def run_adjoint(wl, precision):
     L.backward()
     torch.cuda.synchronize()
     t2 = time.perf_counter()
+    # checkpoints, segment record and adjoint buffers (torch) plus the library's two state buffers
+    peak_gb = (torch.cuda.max_memory_allocated() + 2 * ctx.state_bytes) / 1e9
     ctx.close()
     return {"workload": f"{wl['name']}: {wl['n_el']}^3 cells p={wl['p']} ({ctx.nodes} nodes), {steps} steps, "
                         f"{len(modes)} modes + mu_inf, checkpoint {wl.get('checkpoint', 10)}",
             "forward_s": t1 - t0, "backward_s": t2 - t1, "backward_over_forward": (t2 - t1) / (t1 - t0),
-            "loss": L.item(), "grad_finite": bool(torch.isfinite(amps.grad).all() and math.isfinite(mu.grad.item()))}
+            "loss": L.item(), "grad_finite": bool(torch.isfinite(amps.grad).all() and math.isfinite(mu.grad.item())),
+            "device_memory_GB": peak_gb}
 
 
 def cpu_baseline(wl, budget_s):

@@ -27,8 +27,6 @@ struct sllbm_ctx {
     sllbm_config cfg{};
     Geometry geo{};
     VelocitySet vs{};
-    AxisTables htab[2];           // 0: forward streaming, 1: transposed
-    StreamTables dtab[2]{};
     CollisionParams cp{};
     int32_t *d_omin = nullptr, *d_lstar = nullptr;
     void *d_cw = nullptr;         // cell-table weights, storage type
@@ -39,11 +37,6 @@ struct sllbm_ctx {
     void *buf[2] = {nullptr, nullptr};
     int cur = 0;
     bool has_state = false;
-    // device tables
-    int32_t *d_off[2] = {nullptr, nullptr};
-    void *d_wt[2] = {nullptr, nullptr};
-    int32_t *d_lo[2] = {nullptr, nullptr};
-    int32_t *d_span[2] = {nullptr, nullptr};
     double *d_nodew = nullptr;     // [Nx + Ny + Nz] 1-D node quadrature weights
     double *d_ccw = nullptr;       // [p+1] Clenshaw-Curtis weights of a cell, mapped to [0, 1] per unit h
     double *d_dmat = nullptr;      // [(p+1)^2] d ell_m / ds at t_k
@@ -55,7 +48,6 @@ struct sllbm_ctx {
     double *d_scr_T = nullptr;     // [N]   diagnostics scratch
     double *d_adj_part = nullptr;  // [ADJ_BLOCKS] dmu_inf partials of the collision VJP
     // kernel timing: event pairs per launch kind (0 collision, 1 streaming)
-    bool zt_ok = false;           // transposed streaming may use the z-march (nel_z >= 3, spans <= 3p + 1)
     bool timing = false;
     std::vector<hipEvent_t> ev[2];
     int nev[2] = {0, 0};
@@ -100,13 +92,7 @@ void free_ctx(sllbm_ctx *c)
 {
     for (int k = 0; k < 2; ++k)
         for (hipEvent_t e : c->ev[k]) (void)hipEventDestroy(e);
-    for (int k = 0; k < 2; ++k) {
-        (void)hipFree(c->buf[k]);
-        (void)hipFree(c->d_off[k]);
-        (void)hipFree(c->d_wt[k]);
-        (void)hipFree(c->d_lo[k]);
-        (void)hipFree(c->d_span[k]);
-    }
+    for (int k = 0; k < 2; ++k) (void)hipFree(c->buf[k]);
     (void)hipFree(c->d_omin);
     (void)hipFree(c->d_lstar);
     (void)hipFree(c->d_cw);
@@ -122,66 +108,14 @@ void free_ctx(sllbm_ctx *c)
     (void)hipFree(c->d_adj_part);
 }
 
-// Cells per tile: about 8 x 8 x 4 nodes (at most 256, one node per thread).
-void choose_tile(Geometry &g)
-{
-    const int p = g.p;
-    int target[3] = {8, 8, 4};
-    for (int a = 0; a < 3; ++a) g.TE[a] = std::min(std::max(1, target[a] / p), g.nel[a]);
-    bool grown = true;
-    while (grown) {
-        grown = false;
-        for (int a = 2; a >= 0; --a) {
-            int TE[3] = {g.TE[0], g.TE[1], g.TE[2]};
-            TE[a] += 1;
-            if (TE[a] <= g.nel[a] && TE[0] * TE[1] * TE[2] * p * p * p <= 256) {
-                g.TE[a] = TE[a];
-                grown = true;
-                break;
-            }
-        }
-    }
-    for (int a = 0; a < 3; ++a) g.ntile[a] = (g.nel[a] + g.TE[a] - 1) / g.TE[a];
-}
-
-bool is_fp64_cfg(const sllbm_ctx *c) { return c->cfg.precision == SLLBM_FP64; }
-
+// departure tables of the forward streaming, in the storage type; the
+// transposed streaming uses the same tables
 template <typename S>
-int upload_tables(sllbm_ctx *c)
+int upload_tables(sllbm_ctx *c, const double h[3])
 {
-    const int p = c->geo.p;
-    for (int d = 0; d < 2; ++d) {
-        const AxisTables &h = c->htab[d];
-        const size_t n = h.off.size();
-        std::vector<S> wt(n);
-        for (size_t k = 0; k < n; ++k) wt[k] = static_cast<S>(h.wt[k]);
-        hipError_t e;
-        if ((e = dalloc(&c->d_off[d], n * sizeof(int32_t))) != hipSuccess ||
-            (e = dalloc(reinterpret_cast<S **>(&c->d_wt[d]), n * sizeof(S))) != hipSuccess ||
-            (e = dalloc(&c->d_lo[d], Q * 3 * sizeof(int32_t))) != hipSuccess ||
-            (e = dalloc(&c->d_span[d], Q * 3 * sizeof(int32_t))) != hipSuccess)
-            return fail(c, SLLBM_ENOMEM, std::string("table allocation: ") + hipGetErrorString(e));
-        if ((e = hipMemcpy(c->d_off[d], h.off.data(), n * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess ||
-            (e = hipMemcpy(c->d_wt[d], wt.data(), n * sizeof(S), hipMemcpyHostToDevice)) != hipSuccess ||
-            (e = hipMemcpy(c->d_lo[d], h.lo.data(), Q * 3 * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess ||
-            (e = hipMemcpy(c->d_span[d], h.span.data(), Q * 3 * sizeof(int32_t), hipMemcpyHostToDevice)) !=
-                hipSuccess)
-            return hip_fail(c, e, "table upload");
-        StreamTables &t = c->dtab[d];
-        t.off = c->d_off[d];
-        t.wt = c->d_wt[d];
-        t.lo = c->d_lo[d];
-        t.span = c->d_span[d];
-        t.K = h.K;
-        for (int a = 0; a < 3; ++a) {
-            int smax = 0;
-            for (int i = 0; i < Q; ++i) smax = std::max(smax, h.span[i * 3 + a]);
-            t.wmax[a] = (c->geo.TE[a] - 1) * p + smax;
-        }
-    }
     std::vector<int32_t> omin, lstar;
     std::vector<double> fw;
-    build_cell_tables(c->htab[0], omin, lstar, fw);
+    build_cell_tables(c->vs, c->geo.p, h, c->cfg.dt, omin, lstar, fw);
     std::vector<S> fws(fw.begin(), fw.end());
     hipError_t e;
     if ((e = dalloc(&c->d_omin, omin.size() * sizeof(int32_t))) != hipSuccess ||
@@ -210,14 +144,6 @@ void *other(sllbm_ctx *c) { return c->buf[1 - c->cur]; }
 int check_launch(sllbm_ctx *c, hipError_t e, const char *what)
 {
     return e == hipSuccess ? SLLBM_OK : hip_fail(c, e, what);
-}
-
-int check_smem(sllbm_ctx *c, int dir)
-{
-    const size_t need = stream_smem_bytes(c->geo, c->dtab[dir], c->elem);
-    if (need > 160 * 1024)
-        return fail(c, SLLBM_EINVAL, "streaming window does not fit in LDS (" + std::to_string(need) + " bytes)");
-    return SLLBM_OK;
 }
 
 }  // namespace
@@ -296,7 +222,6 @@ int sllbm_create(const sllbm_config *cfg, sllbm_ctx **out)
         g.N[a] = cfg->n_el[a] * cfg->order;
     }
     g.nodes = nodes;
-    choose_tile(g);
     c->cp.dt = cfg->dt;
     c->cp.Cv = 1.0 / (cfg->gamma - 1.0);
     c->cp.beta = 2.0 * c->cp.Cv - 3.0;
@@ -307,10 +232,6 @@ int sllbm_create(const sllbm_config *cfg, sllbm_ctx **out)
     build_velocity_set(c->vs);
     double h[3];
     for (int a = 0; a < 3; ++a) c->h[a] = h[a] = cfg->length[a] / cfg->n_el[a];
-    build_axis_tables(c->vs, g.p, h, cfg->dt, c->htab[0], c->htab[1]);
-    c->zt_ok = g.nel[2] >= 3;
-    for (int i = 0; i < Q * 3; ++i)
-        if (c->htab[1].span[i] > 3 * g.p + 1) c->zt_ok = false;
 
     auto bail = [&](int rc) {
         g_create_error = c->err;
@@ -318,9 +239,8 @@ int sllbm_create(const sllbm_config *cfg, sllbm_ctx **out)
         delete c;
         return rc;
     };
-    int rc = is_fp64(c) ? upload_tables<double>(c) : upload_tables<float>(c);
+    int rc = is_fp64(c) ? upload_tables<double>(c, h) : upload_tables<float>(c, h);
     if (rc != SLLBM_OK) return bail(rc);
-    if ((rc = check_smem(c, 0)) != SLLBM_OK || (rc = check_smem(c, 1)) != SLLBM_OK) return bail(rc);
 
     const size_t sb = static_cast<size_t>(sllbm_state_bytes(c));
     hipError_t e;
@@ -467,21 +387,14 @@ static hipError_t stream_into(sllbm_ctx *c, const void *in, void *out)
                                   static_cast<float *>(out), c->stream);
 }
 
-// S^T: the transposed z-march where it applies, else the table-driven gather
+// S^T: the transposed z-march
 static hipError_t stream_t_into(sllbm_ctx *c, const void *in, void *out)
 {
-    if (c->zt_ok) {
-        if (is_fp64(c))
-            return launch_stream_zt<double>(c->geo, cell_tables<double>(c), c->dtab[1], static_cast<const double *>(in),
-                                            static_cast<double *>(out), c->stream);
-        return launch_stream_zt<float>(c->geo, cell_tables<float>(c), c->dtab[1], static_cast<const float *>(in),
-                                       static_cast<float *>(out), c->stream);
-    }
     if (is_fp64(c))
-        return Launch<double>::stream_only(c->geo, c->dtab[1], static_cast<const double *>(in),
-                                           static_cast<double *>(out), c->stream);
-    return Launch<float>::stream_only(c->geo, c->dtab[1], static_cast<const float *>(in), static_cast<float *>(out),
-                                      c->stream);
+        return launch_stream_zt<double>(c->geo, cell_tables<double>(c), static_cast<const double *>(in),
+                                        static_cast<double *>(out), c->stream);
+    return launch_stream_zt<float>(c->geo, cell_tables<float>(c), static_cast<const float *>(in),
+                                   static_cast<float *>(out), c->stream);
 }
 
 // n steps X <- S(C(X)): collision in place and streaming into the other

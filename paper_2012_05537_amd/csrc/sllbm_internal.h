@@ -27,26 +27,17 @@ struct VelocitySet {
     int opposite[Q];          // index of -xi_i
 };
 
-// Per-axis 1-D interpolation tables for one direction (forward streaming or
-// its transpose).  Output node g = e*p + l along an axis receives
-//   sum_k wt[i][a][l][k] * in[(e*p + off[i][a][l][k]) mod N_a].
-struct AxisTables {
-    int p = 0;
-    int K = 0;                          // taps per output node (padded)
-    std::vector<int32_t> off;           // [Q][3][p][K]
-    std::vector<double> wt;             // [Q][3][p][K]
-    std::vector<int32_t> lo;            // [Q][3]: min offset
-    std::vector<int32_t> span;          // [Q][3]: max - min offset + 1
-};
-
 void build_velocity_set(VelocitySet &vs);
 void glc_points(int p, double *t);                       // t_k = (1 - cos(pi k/p))/2
 void lagrange_basis(int p, double s, double *ell);       // ell_k(s) on the GLC points
 void lagrange_basis_deriv(int p, double s, double *dl);  // d ell_k / ds
 void clenshaw_curtis(int p, double *w);                  // weights on [-1,1]
-// forward tables for displacement -xi*dt, and their exact transposes
-void build_axis_tables(const VelocitySet &vs, int p, const double h[3], double dt,
-                       AxisTables &fwd, AxisTables &adj);
+// Per velocity i and axis a, the departure cells of the p nodes of a cell
+// (displacement -xi_ia dt) are omin and omin + 1, the latter from node lstar
+// on (lstar = p if none), and node l interpolates its cell with the weights
+// w[i][a][l][0..p] (layout [Q][3][p][p+1]).
+void build_cell_tables(const VelocitySet &vs, int p, const double h[3], double dt, std::vector<int32_t> &omin,
+                       std::vector<int32_t> &lstar, std::vector<double> &w);
 
 // ---------------------------------------------------------------------------
 // Device-side parameter blocks (passed by value to kernels)
@@ -56,18 +47,7 @@ struct Geometry {
     int N[3];        // nodes per axis
     int nel[3];      // cells per axis
     int p;           // order
-    int TE[3];       // cells per tile and axis
-    int ntile[3];    // tiles per axis
     int64_t nodes;   // N[0]*N[1]*N[2]
-};
-
-struct StreamTables {
-    const int32_t *off;    // [Q][3][p][K]
-    const void *wt;        // [Q][3][p][K], storage type
-    const int32_t *lo;     // [Q][3]
-    const int32_t *span;   // [Q][3]
-    int K;
-    int wmax[3];           // largest window extent per axis for a full tile
 };
 
 // Per-cell departure tables of the forward streaming, for each velocity i and
@@ -95,9 +75,6 @@ struct CollisionParams {
 
 template <typename S>
 struct Launch {
-    // table-driven streaming (any tap count; used for the transpose)
-    static hipError_t stream_only(const Geometry &g, const StreamTables &t, const S *in, S *out,
-                                  hipStream_t st);
     static hipError_t collide_only(const Geometry &g, const CollisionParams &cp, S *state, hipStream_t st);
     static hipError_t collide_into(const Geometry &g, const CollisionParams &cp, const S *in, S *out,
                                    hipStream_t st);
@@ -129,20 +106,12 @@ struct Launch {
                                            double *du, double *dT, hipStream_t st);
 };
 
-void build_cell_tables(const AxisTables &fwd, std::vector<int32_t> &omin, std::vector<int32_t> &lstar,
-                       std::vector<double> &w);
-
 // forward streaming, z-march per (velocity, population) plane and x-y tile (stream.hip)
 template <typename S>
 hipError_t launch_stream_z(const Geometry &g, const CellTables<S> &t, const S *in, S *out, hipStream_t st);
-// transposed streaming, same march (stream.hip); needs nel[2] >= 3 and transposed
-// row spans <= 3p + 1
+// transposed streaming S^T, the same march gathering over source-cell groups
+// with the forward cell tables (stream.hip); any number of cells per axis
 template <typename S>
-hipError_t launch_stream_zt(const Geometry &g, const CellTables<S> &t, const StreamTables &adj, const S *in, S *out,
-                            hipStream_t st);
-
-size_t stream_smem_bytes(const Geometry &g, const StreamTables &t, size_t elem);
-int tile_nodes(const Geometry &g);
-int blocks_for(const Geometry &g);
+hipError_t launch_stream_zt(const Geometry &g, const CellTables<S> &t, const S *in, S *out, hipStream_t st);
 
 }  // namespace sllbm

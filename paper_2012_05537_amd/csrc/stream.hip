@@ -268,47 +268,41 @@ static hipError_t launch_z(const Geometry &g, const CellTables<S> &t, const S *i
 // ---------------------------------------------------------------------------
 // Transposed streaming S^T (the adjoint of Eqs. (8)-(9)), same z-march.
 //
-// Along x and y the transposed 1-D operator is a gather over the transposed
-// tables (node m of a cell reads at most 2P nodes at offsets relative to its
-// cell start).  Along z it is applied as the scatter of the forward operator:
-// input row e*P + l, which the forward step gathers into source rows
-// (e + o_l)*P + k, adds W[l][k] times its value to those rows.  A thread
-// keeps the 2P + 1 rows of source cells e + omin and e + omin + 1 in
-// registers; after input cell e the rows of cell e + omin are complete (the
-// next input cell only reaches cells e + omin + 1 and up) and are written.
-// Row 0 of source cell c also receives, as row P of cell c - 1, from input
-// cells c - omin - 1 and c - omin - 2, so a chunk of input cells [e0, e1)
-// first scatters cells e0 - 2 and e0 - 1 without writing; then every written
-// row has all its contributions.  Requires at least three cells along z
-// (with two, one input cell would reach the same row twice by wrapping).
+// Along an axis the forward nodes that read source cell c form a group: the
+// nodes (c - omin - 1)*P + lstar + j, j = 0 .. P-1, read it with weight row
+// (lstar + j) mod P.  Transposing, node k of cell c receives
+//   T[c*P + k] = sum_j W[(lstar + j) mod P][k] lam[group(c)_j]
+// and node 0 also, as point P of cell c - 1,
+//   + sum_j W[(lstar + j) mod P][P] lam[group(c - 1)_j].
+// So each output cell gathers two consecutive groups (2P inputs, starting at
+// (c - omin - 2)*P + lstar) with the forward weights; this holds for any
+// number of cells, wrap-around included.  The kernel is the forward one with
+// that gather along x, y (LDS) and z (a register window of 2P rows sliding by
+// one cell).
 // ---------------------------------------------------------------------------
 template <int P, int V = 1>
 struct ZTileT {
     static constexpr int XN = 32, YN = 8;
     static constexpr int TXC = XN / P > 0 ? XN / P : 1, TYC = YN / P > 0 ? YN / P : 1;
     static constexpr int TX = TXC * P, TY = TYC * P;
-    static constexpr int K = 2 * P;                           // taps of a transposed row
-    static constexpr int SPMAX = 3 * P + 1;                   // largest offset span of a transposed row set
-    static constexpr int WXC = (TX + SPMAX - 1 + V - 1 + V - 1) / V;   // loads per window row (V-aligned start)
-    static constexpr int WX = WXC * V, WY = TY + SPMAX - 1;
+    static constexpr int WXC = (TX + P + V - 1 + V - 1) / V;  // loads per window row (V-aligned start)
+    static constexpr int WX = WXC * V, WY = TY + P;
     static constexpr int NT = (TX * TY + 63) / 64 * 64;
     static constexpr int LK = (WXC * WY + NT - 1) / NT;
-    static constexpr int XR = NT / TX;                        // window rows per x-gather pass
-    static constexpr int XK = (WY + XR - 1) / XR;
     static constexpr int BS = TX % 2 ? TX : TX + 1;
 };
 
 template <typename S, int P, int V>
 __global__ void __launch_bounds__((ZTileT<P, V>::NT))
-    k_stream_zt(Geometry g, CellTables<S> fwd, const int32_t *__restrict__ toff, const S *__restrict__ twt,
-                const int32_t *__restrict__ tlo, const int32_t *__restrict__ tspan, const S *__restrict__ in,
-                S *__restrict__ out, int ntile_x, int ntiles, int zcells, int nchunk)
+    k_stream_zt(Geometry g, CellTables<S> tab, const S *__restrict__ in, S *__restrict__ out, int ntile_x,
+                int ntiles, int zcells, int nchunk)
 {
     using Z = ZTileT<P, V>;
     using VT = typename VecOf<S, V>::T;
-    constexpr int TX = Z::TX, TY = Z::TY, NT = Z::NT, LK = Z::LK, XK = Z::XK, K = Z::K, BS = Z::BS;
-    __shared__ __align__(16) S pl[P][Z::WX * Z::WY];
-    __shared__ S bx[P][Z::WY * BS];
+    constexpr int TX = Z::TX, TY = Z::TY, WX = Z::WX, WY = Z::WY, NT = Z::NT, LK = Z::LK, BS = Z::BS;
+    constexpr int NLD = Z::WXC * WY;
+    __shared__ __align__(16) S pl[P][WX * WY];
+    __shared__ S bx[P][WY * BS];
 
     const int tid = threadIdx.x;
     const int L = __builtin_amdgcn_readfirstlane(xcd_linear(blockIdx.x, gridDim.x));
@@ -319,126 +313,153 @@ __global__ void __launch_bounds__((ZTileT<P, V>::NT))
     const int X0 = (tile % ntile_x) * TX, Y0 = (tile / ntile_x) * TY;
     const int Nx = g.N[0], Ny = g.N[1], Nz = g.N[2];
     const int64_t N = g.nodes, NP = static_cast<int64_t>(Nx) * Ny;
-    const int lox = tlo[i * 3 + 0], loy = tlo[i * 3 + 1];
-    const int lxa = lox - ((lox % V) + V) % V;            // window start, rounded down to V
-    const int wxc = (TX + tspan[i * 3 + 0] - 1 + (lox - lxa) + V - 1) / V;
-    const int wxs = wxc * V, wys = TY + tspan[i * 3 + 1] - 1;   // window of this velocity
-    const int nld = wxc * wys;
-    const int omz = fwd.omin[i * 3 + 2], lsz = fwd.lstar[i * 3 + 2];
-    const S *Wz = fwd.w + (i * 3 + 2) * P * (P + 1);
-    const int32_t *ox = toff + (i * 3 + 0) * P * K, *oy = toff + (i * 3 + 1) * P * K;
-    const S *wxt = twt + (i * 3 + 0) * P * K, *wyt = twt + (i * 3 + 1) * P * K;
+    const int omx = tab.omin[i * 3 + 0], omy = tab.omin[i * 3 + 1], omz = tab.omin[i * 3 + 2];
+    const int lsx = tab.lstar[i * 3 + 0], lsy = tab.lstar[i * 3 + 1], lsz = tab.lstar[i * 3 + 2];
+    const S *Wx = tab.w + (i * 3 + 0) * P * (P + 1);
+    const S *Wy = tab.w + (i * 3 + 1) * P * (P + 1);
+    const S *Wz = tab.w + (i * 3 + 2) * P * (P + 1);
     const S *__restrict__ src = in + static_cast<int64_t>(pop * 45 + i) * N;
     S *__restrict__ dst = out + static_cast<int64_t>(pop * 45 + i) * N;
 
+    // input window: x from X0 + (-2 - omx)*P + lsx (rounded down to V: shift sx), y from Y0 + (-2 - omy)*P + lsy
+    const int offx = (-2 - omx) * P + lsx;
+    const int offxa = offx - ((offx % V) + V) % V, sx = offx - offxa;
+    const int offy = (-2 - omy) * P + lsy;
     int loff[LK];
 #pragma unroll
     for (int k = 0; k < LK; ++k) {
         int e = tid + k * NT;
-        e = e < nld ? e : nld - 1;
-        const int wx = (e % wxc) * V, wy = e / wxc;
-        loff[k] = wrapi(Y0 + loy + wy, Ny) * Nx + wrapi(X0 + lxa + wx, Nx);
+        e = e < NLD ? e : NLD - 1;
+        const int wx = (e % Z::WXC) * V, wy = e / Z::WXC;
+        loff[k] = wrapi(Y0 + offy + wy, Ny) * Nx + wrapi(X0 + offxa + wx, Nx);
     }
-    // x-gather: thread (xrow, xt) handles column xt of window rows xrow, xrow + XR, ...;
-    // its taps (offsets within the row and weights) are fixed
-    const int xt = tid % TX, xrow = tid / TX, mx = xt % P;
-    const bool xact = xrow < Z::XR;
-    int xs[K];
-    S xw[K];
+    // x and z weights, the same for every thread: w*[j][k] = W[(ls + j) mod P][k]
+    S wxu[P][P + 1], wzu[P][P + 1];
 #pragma unroll
-    for (int t = 0; t < K; ++t) {
-        xs[t] = xt - mx + ox[mx * K + t] - lxa;
-        xw[t] = wxt[mx * K + t];
-    }
+    for (int j = 0; j < P; ++j)
+#pragma unroll
+        for (int k = 0; k <= P; ++k) {
+            wxu[j][k] = Wx[((lsx + j) % P) * (P + 1) + k];
+            wzu[j][k] = Wz[((lsz + j) % P) * (P + 1) + k];
+        }
+    // output node (X0 + tx, Y0 + ty): point ky of tile cell cy along y gathers
+    // window rows (cy + 1)*P + j with yw[j], and for ky = 0 rows cy*P + j with yp[j]
     const int tx = tid % TX, ty = tid / TX;
     const bool own = tid < TX * TY && X0 + tx < Nx && Y0 + ty < Ny;
-    const int my = ty % P;
-    int ys[K];
-    S yw[K];
+    const int cy = ty / P, ky = ty % P;
+    const int ybase = cy * P * BS + (tid < TX * TY ? tx : 0);
+    S yw[P], yp[P];
 #pragma unroll
-    for (int t = 0; t < K; ++t) {
-        ys[t] = (ty - my + oy[my * K + t] - loy) * BS + (tid < TX * TY ? tx : 0);
-        yw[t] = wyt[my * K + t];
+    for (int j = 0; j < P; ++j) {
+        yw[j] = Wy[((lsy + j) % P) * (P + 1) + ky];
+        yp[j] = ky == 0 ? Wy[((lsy + j) % P) * (P + 1) + P] : S(0);
     }
     const int64_t oxy = static_cast<int64_t>(Y0 + ty) * Nx + (X0 + tx);
-    S wz[P][P + 1];
-#pragma unroll
-    for (int l = 0; l < P; ++l)
-#pragma unroll
-        for (int r = 0; r <= P; ++r) wz[l][r] = Wz[l * (P + 1) + r];
 
-    // input cells e0 - 2 .. e1 - 1; row l of cell e is z = e*P + l
-    const int e0 = chunk * zcells, e1 = min(g.nel[2], e0 + zcells);
-    VT raw[P][LK];
-    auto load_cell = [&](int e) {
+    // input rows in march order: z = (ez0 - omz - 2)*P + lsz + k (mod Nz), k = 0 .. P + nel*P - 1
+    const int ez0 = chunk * zcells, ez1 = min(g.nel[2], ez0 + zcells);
+    const int zb = (ez0 - omz - 2) * P + lsz;
+    VT rawA[P][LK], rawB[P][LK];
+    auto load_rows = [&](auto &raw, int k0, int nr) {
 #pragma unroll
         for (int r = 0; r < P; ++r) {
-            const int64_t zo = static_cast<int64_t>(wrapi(e * P + r, Nz)) * NP;
+            if (r < nr) {
+                const int64_t zo = static_cast<int64_t>(wrapi(zb + k0 + r, Nz)) * NP;
 #pragma unroll
-            for (int j = 0; j < LK; ++j) raw[r][j] = *reinterpret_cast<const VT *>(src + zo + loff[j]);
+                for (int j = 0; j < LK; ++j) raw[r][j] = *reinterpret_cast<const VT *>(src + zo + loff[j]);
+            }
         }
     };
-    S acc[2 * P + 1];
-#pragma unroll
-    for (int r = 0; r <= 2 * P; ++r) acc[r] = 0;
-    load_cell(e0 - 2);
-    for (int e = e0 - 2; e < e1; ++e) {
+    // P rows: registers -> LDS, reload with the rows two batches ahead, x-gather, y-gather
+    auto batch = [&](auto &raw, int next_k0, int next_nr, S *res) {
 #pragma unroll
         for (int r = 0; r < P; ++r)
 #pragma unroll
             for (int j = 0; j < LK; ++j)
-                if (tid + j * NT < nld) *reinterpret_cast<VT *>(&pl[r][V * (tid + j * NT)]) = raw[r][j];
-        if (e + 1 < e1) load_cell(e + 1);
+                if (tid + j * NT < NLD) *reinterpret_cast<VT *>(&pl[r][V * (tid + j * NT)]) = raw[r][j];
+        if (next_nr > 0) load_rows(raw, next_k0, next_nr);
         __syncthreads();
-        if (xact) {
+        // x: task (row, window row, output cell cl) reads groups cl and cl + 1 of the row
+        constexpr int XT = P * WY * Z::TXC;
 #pragma unroll
-            for (int r = 0; r < P; ++r)
+        for (int k = 0; k < (XT + NT - 1) / NT; ++k) {
+            const int e = tid + k * NT;
+            if (e < XT) {
+                const int r = e / (WY * Z::TXC), rem2 = e - r * (WY * Z::TXC);
+                const int cl = rem2 / WY, wy = rem2 - cl * WY;
+                const S *c = &pl[r][wy * WX + sx + cl * P];
+                S prev[P], cur[P];
 #pragma unroll
-                for (int k = 0; k < XK; ++k) {
-                    const int wy = xrow + k * Z::XR;
-                    if (wy < wys) {
-                        const S *rowp = &pl[r][wy * wxs];
-                        S v = 0;
-#pragma unroll
-                        for (int t = 0; t < K; ++t) v = fma(xw[t], rowp[xs[t]], v);
-                        bx[r][wy * BS + xt] = v;
-                    }
+                for (int j = 0; j < P; ++j) {
+                    prev[j] = c[j];
+                    cur[j] = c[P + j];
                 }
-        }
-        __syncthreads();
+                S *o = &bx[r][wy * BS + cl * P];
 #pragma unroll
-        for (int l = 0; l < P; ++l) {
-            S a = 0;
+                for (int kk = 0; kk < P; ++kk) {
+                    S acc = 0;
 #pragma unroll
-            for (int t = 0; t < K; ++t) a = fma(yw[t], bx[l][ys[t]], a);
-            const bool hi = l >= lsz;
+                    for (int j = 0; j < P; ++j) acc = fma(wxu[j][kk], cur[j], acc);
+                    if (kk == 0) {
 #pragma unroll
-            for (int r = 0; r <= P; ++r) {
-                const S c = wz[l][r] * a;
-                acc[P + r] += hi ? c : S(0);
-                acc[r] += hi ? S(0) : c;
+                        for (int j = 0; j < P; ++j) acc = fma(wxu[j][P], prev[j], acc);
+                    }
+                    o[kk] = acc;
+                }
             }
         }
-        if (e >= e0 && own) {
+        __syncthreads();
 #pragma unroll
-            for (int r = 0; r < P; ++r)
-                dst[static_cast<int64_t>(wrapi((e + omz) * P + r, Nz)) * NP + oxy] = acc[r];
+        for (int r = 0; r < P; ++r) {
+            S acc = 0;
+#pragma unroll
+            for (int j = 0; j < P; ++j) acc = fma(yw[j], bx[r][ybase + (P + j) * BS], acc);
+#pragma unroll
+            for (int j = 0; j < P; ++j) acc = fma(yp[j], bx[r][ybase + j * BS], acc);
+            res[r] = acc;
+        }
+    };
+    S a[2 * P];
+    auto emit = [&](int ez) {
+        if (own) {
+#pragma unroll
+            for (int k = 0; k < P; ++k) {
+                S acc = 0;
+#pragma unroll
+                for (int j = 0; j < P; ++j) acc = fma(wzu[j][k], a[P + j], acc);
+                if (k == 0) {
+#pragma unroll
+                    for (int j = 0; j < P; ++j) acc = fma(wzu[j][P], a[j], acc);
+                }
+                dst[static_cast<int64_t>(ez * P + k) * NP + oxy] = acc;
+            }
         }
 #pragma unroll
-        for (int r = 0; r <= P; ++r) acc[r] = acc[r + P];
-#pragma unroll
-        for (int r = P + 1; r <= 2 * P; ++r) acc[r] = 0;
+        for (int j = 0; j < P; ++j) a[j] = a[P + j];
+    };
+
+    const int nel = ez1 - ez0;
+    auto rows_of = [&](int e) { return e < nel ? P : 0; };
+    load_rows(rawA, 0, P);
+    load_rows(rawB, P, rows_of(0));
+    batch(rawA, 2 * P, rows_of(1), a);
+    for (int e = 0; e < nel; e += 2) {
+        batch(rawB, P + (e + 2) * P, rows_of(e + 2), a + P);
+        emit(ez0 + e);
+        if (e + 1 < nel) {
+            batch(rawA, P + (e + 3) * P, rows_of(e + 3), a + P);
+            emit(ez0 + e + 1);
+        }
     }
 }
 
 template <typename S, int P, int V>
-static hipError_t launch_ztv(const Geometry &g, const CellTables<S> &t, const int32_t *toff, const S *twt,
-                             const int32_t *tlo, const int32_t *tspan, const S *in, S *out, hipStream_t st)
+static hipError_t launch_ztv(const Geometry &g, const CellTables<S> &t, const S *in, S *out, hipStream_t st)
 {
     using Z = ZTileT<P, V>;
     const int ntx = (g.N[0] + Z::TX - 1) / Z::TX, nty = (g.N[1] + Z::TY - 1) / Z::TY;
     const int ntiles = ntx * nty;
-    int nchunk = 1;
+    int nchunk = 1;                                        // each chunk re-reads P source rows
     while (nchunk < g.nel[2] && static_cast<int64_t>(ntiles) * 90 * nchunk < ZCHUNK_TARGET_BLOCKS &&
            g.nel[2] / (2 * nchunk) >= ZCHUNK_MIN_CELLS)
         nchunk *= 2;
@@ -446,45 +467,42 @@ static hipError_t launch_ztv(const Geometry &g, const CellTables<S> &t, const in
     nchunk = (g.nel[2] + zcells - 1) / zcells;
     const int64_t nb = static_cast<int64_t>(ntiles) * 90 * nchunk;
     if (nb > (int64_t(1) << 31) - 1) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_stream_zt<S, P, V>), dim3(static_cast<unsigned>(nb)), dim3(Z::NT), 0, st, g, t, toff, twt,
-                       tlo, tspan, in, out, ntx, ntiles, zcells, nchunk);
+    hipLaunchKernelGGL((k_stream_zt<S, P, V>), dim3(static_cast<unsigned>(nb)), dim3(Z::NT), 0, st, g, t, in, out,
+                       ntx, ntiles, zcells, nchunk);
     return hipGetLastError();
 }
 
+// 16-byte window loads need V-aligned window starts: tiles and rows of a
+// multiple of V nodes and a 16-byte aligned buffer (the start is rounded down)
 template <typename S, int P>
-static hipError_t launch_zt(const Geometry &g, const CellTables<S> &t, const int32_t *toff, const S *twt,
-                            const int32_t *tlo, const int32_t *tspan, const S *in, S *out, hipStream_t st)
+static hipError_t launch_zt(const Geometry &g, const CellTables<S> &t, const S *in, S *out, hipStream_t st)
 {
-    // 16-byte loads need V-aligned window starts: tiles of a multiple of V
-    // nodes, rows of a multiple of V nodes, a 16-byte aligned buffer
     constexpr int V = 16 / sizeof(S);
     if constexpr (ZTileT<P, V>::TX % V == 0) {
         if ((g.N[0] * sizeof(S)) % 16 == 0 && reinterpret_cast<uintptr_t>(in) % 16 == 0)
-            return launch_ztv<S, P, V>(g, t, toff, twt, tlo, tspan, in, out, st);
+            return launch_ztv<S, P, V>(g, t, in, out, st);
     }
-    return launch_ztv<S, P, 1>(g, t, toff, twt, tlo, tspan, in, out, st);
+    return launch_ztv<S, P, 1>(g, t, in, out, st);
 }
 
 template <typename S>
-hipError_t launch_stream_zt(const Geometry &g, const CellTables<S> &t, const StreamTables &adj, const S *in, S *out,
-                            hipStream_t st)
+hipError_t launch_stream_zt(const Geometry &g, const CellTables<S> &t, const S *in, S *out, hipStream_t st)
 {
-    const S *wt = static_cast<const S *>(adj.wt);
     switch (g.p) {
-    case 1: return launch_zt<S, 1>(g, t, adj.off, wt, adj.lo, adj.span, in, out, st);
-    case 2: return launch_zt<S, 2>(g, t, adj.off, wt, adj.lo, adj.span, in, out, st);
-    case 3: return launch_zt<S, 3>(g, t, adj.off, wt, adj.lo, adj.span, in, out, st);
-    case 4: return launch_zt<S, 4>(g, t, adj.off, wt, adj.lo, adj.span, in, out, st);
-    case 5: return launch_zt<S, 5>(g, t, adj.off, wt, adj.lo, adj.span, in, out, st);
-    case 6: return launch_zt<S, 6>(g, t, adj.off, wt, adj.lo, adj.span, in, out, st);
+    case 1: return launch_zt<S, 1>(g, t, in, out, st);
+    case 2: return launch_zt<S, 2>(g, t, in, out, st);
+    case 3: return launch_zt<S, 3>(g, t, in, out, st);
+    case 4: return launch_zt<S, 4>(g, t, in, out, st);
+    case 5: return launch_zt<S, 5>(g, t, in, out, st);
+    case 6: return launch_zt<S, 6>(g, t, in, out, st);
     default: return hipErrorInvalidValue;
     }
 }
 
-template hipError_t launch_stream_zt<double>(const Geometry &, const CellTables<double> &, const StreamTables &,
-                                             const double *, double *, hipStream_t);
-template hipError_t launch_stream_zt<float>(const Geometry &, const CellTables<float> &, const StreamTables &,
-                                            const float *, float *, hipStream_t);
+template hipError_t launch_stream_zt<double>(const Geometry &, const CellTables<double> &, const double *, double *,
+                                             hipStream_t);
+template hipError_t launch_stream_zt<float>(const Geometry &, const CellTables<float> &, const float *, float *,
+                                            hipStream_t);
 
 template <typename S>
 hipError_t launch_stream_z(const Geometry &g, const CellTables<S> &t, const S *in, S *out, hipStream_t st)

@@ -83,105 +83,33 @@ void clenshaw_curtis(int p, double *w)
     }
 }
 
-void build_axis_tables(const VelocitySet &vs, int p, const double h[3], double dt, AxisTables &fwd,
-                       AxisTables &adj)
+void build_cell_tables(const VelocitySet &vs, int p, const double h[3], double dt, std::vector<int32_t> &omin,
+                       std::vector<int32_t> &lstar, std::vector<double> &w)
 {
     double t[MAXP + 1];
     glc_points(p, t);
-    fwd.p = adj.p = p;
-    fwd.K = p + 1;
-    adj.K = 2 * p;
-    fwd.off.assign(Q * 3 * p * fwd.K, 0);
-    fwd.wt.assign(Q * 3 * p * fwd.K, 0.0);
-    adj.off.assign(Q * 3 * p * adj.K, 0);
-    adj.wt.assign(Q * 3 * p * adj.K, 0.0);
-    fwd.lo.assign(Q * 3, 0);
-    fwd.span.assign(Q * 3, 0);
-    adj.lo.assign(Q * 3, 0);
-    adj.span.assign(Q * 3, 0);
-
-    for (int i = 0; i < Q; ++i) {
-        for (int a = 0; a < 3; ++a) {
-            const double shift = vs.xi[i][a] * dt / h[a];   // displacement in cell widths
-            int cell[MAXP];
-            double W[MAXP][MAXP + 1];
-            for (int l = 0; l < p; ++l) {
-                double s = t[l] - shift;                      // departure point, cell units
-                double o = std::floor(s);
-                cell[l] = static_cast<int>(o);
-                lagrange_basis(p, s - o, W[l]);
-            }
-            // forward rows: node l of cell e reads cell e + cell[l]
-            const int base = (i * 3 + a) * p;
-            int lo = 1 << 30, hi = -(1 << 30);
-            for (int l = 0; l < p; ++l) {
-                for (int k = 0; k <= p; ++k) {
-                    int off = cell[l] * p + k;
-                    fwd.off[(base + l) * fwd.K + k] = off;
-                    fwd.wt[(base + l) * fwd.K + k] = W[l][k];
-                    lo = std::min(lo, off);
-                    hi = std::max(hi, off);
-                }
-            }
-            fwd.lo[i * 3 + a] = lo;
-            fwd.span[i * 3 + a] = hi - lo + 1;
-            // transposed rows: source point m of cell E is read, with weight
-            // W[l][m], by node l of cell E - cell[l]; the shared point m = 0 is
-            // also point p of cell E-1, read by node l of cell E-1-cell[l].
-            lo = 1 << 30;
-            hi = -(1 << 30);
-            for (int m = 0; m < p; ++m) {
-                int n = 0;
-                int *orow = &adj.off[(base + m) * adj.K];
-                double *wrow = &adj.wt[(base + m) * adj.K];
-                for (int l = 0; l < p; ++l, ++n) {
-                    orow[n] = -cell[l] * p + l;
-                    wrow[n] = W[l][m];
-                }
-                if (m == 0) {
-                    for (int l = 0; l < p; ++l, ++n) {
-                        orow[n] = -(1 + cell[l]) * p + l;
-                        wrow[n] = W[l][p];
-                    }
-                }
-                for (; n < adj.K; ++n) {          // padding taps: weight 0, in-window offset
-                    orow[n] = orow[0];
-                    wrow[n] = 0.0;
-                }
-                for (int k = 0; k < adj.K; ++k) {
-                    lo = std::min(lo, orow[k]);
-                    hi = std::max(hi, orow[k]);
-                }
-            }
-            adj.lo[i * 3 + a] = lo;
-            adj.span[i * 3 + a] = hi - lo + 1;
-        }
-    }
-}
-
-}  // namespace sllbm
-
-namespace sllbm {
-
-void build_cell_tables(const AxisTables &fwd, std::vector<int32_t> &omin, std::vector<int32_t> &lstar,
-                        std::vector<double> &w)
-{
-    const int p = fwd.p, K = fwd.K;
     omin.assign(Q * 3, 0);
     lstar.assign(Q * 3, p);
     w.assign(Q * 3 * p * (p + 1), 0.0);
-    for (int i = 0; i < Q; ++i)
+    for (int i = 0; i < Q; ++i) {
         for (int a = 0; a < 3; ++a) {
-            const int base = (i * 3 + a) * p;
-            // departure cell of row l is off[l][0] / p; non-decreasing in l
-            const int o0 = fwd.off[base * K] / p;
-            omin[i * 3 + a] = o0;
+            // node l of a cell departs to t_l - xi dt / h (cell units): cell
+            // floor of that, local coordinate its fractional part (Eq. (9))
+            const double shift = vs.xi[i][a] * dt / h[a];
+            int cell[MAXP];
             for (int l = 0; l < p; ++l) {
-                const int o = fwd.off[(base + l) * K] / p - o0;
-                if (o == 1 && lstar[i * 3 + a] == p) lstar[i * 3 + a] = l;
-                for (int k = 0; k <= p; ++k) w[(base + l) * (p + 1) + k] = fwd.wt[(base + l) * K + k];
+                const double s = t[l] - shift;
+                const double o = std::floor(s);
+                cell[l] = static_cast<int>(o);
+                lagrange_basis(p, s - o, &w[((i * 3 + a) * p + l) * (p + 1)]);
             }
+            // t_l rises from 0 towards 1, so the departure cells are
+            // non-decreasing and span at most two neighbours
+            omin[i * 3 + a] = cell[0];
+            for (int l = 0; l < p; ++l)
+                if (cell[l] != cell[0] && lstar[i * 3 + a] == p) lstar[i * 3 + a] = l;
         }
+    }
 }
 
 }  // namespace sllbm

@@ -368,3 +368,48 @@ def test_adjoint_rejects_aliasing(oracle):
         ctx.adjoint_step(X, lam, lam)
     with pytest.raises(SllbmError):
         ctx.adjoint_step(X, lam, X)
+
+
+def test_rollout_gradient_c4_vs_central_differences(oracle):
+    """c4 workload: grad . v against central differences of the GPU forward
+    rollout, h = 1e-5 (relative to |a| and mu_inf) along a random direction v
+    in (a, mu_inf); bar 1e-5 relative (truncation O(h^2), rounding of the two
+    rollouts ~1e-15 |L| / h)."""
+    w, ctx, cfg, Rollout, fields = _rollout_setup(oracle, "c4")
+    rho, u, T, B, amps = fields
+    n = w["steps"]
+    roll = Rollout(ctx, rho, u, T, B, n, checkpoint=w["checkpoint"])
+    a = torch.tensor(amps, dtype=torch.float64, requires_grad=True)
+    mu = torch.tensor(w["mu_inf"], dtype=torch.float64, requires_grad=True)
+    roll(a, mu).backward()
+    rng = np.random.default_rng(7)
+    da = rng.normal(size=amps.size) * np.abs(amps).max()
+    dmu = float(rng.normal()) * w["mu_inf"]
+    h = 1e-5
+    f64 = dict(dtype=torch.float64)
+    with torch.no_grad():
+        lp = roll(torch.tensor(amps + h * da, **f64), torch.tensor(w["mu_inf"] + h * dmu, **f64)).item()
+        lm = roll(torch.tensor(amps - h * da, **f64), torch.tensor(w["mu_inf"] - h * dmu, **f64)).item()
+    fd = (lp - lm) / (2 * h)
+    got = float(a.grad.numpy() @ da + mu.grad.item() * dmu)
+    _say(f"c4 directional derivative: adjoint {got:.10e}, central difference {fd:.10e} (L {lp:.6e})")
+    assert got == pytest.approx(fd, rel=1e-5)
+
+
+def test_fp32_adjoint_vs_fp64_subcase(oracle):
+    """The 256^3-node FP32 workload's parameters (Ma 1.25, Re 1600, CFL 10,
+    16 modes seed 2021, sqrt(n) checkpoints) on its 16^3-cell subcase (64^3
+    nodes) for 6 steps: the FP32-mixed gradient against the FP64 gradient."""
+    grads = {}
+    for prec in (0, 1):
+        w, ctx, cfg, Rollout, fields = _rollout_setup(oracle, "c5", precision=prec, n_el=16)
+        rho, u, T, B, amps = fields
+        roll = Rollout(ctx, rho, u, T, B, 6, checkpoint="sqrt")
+        a = torch.tensor(amps, dtype=torch.float64, requires_grad=True)
+        mu = torch.tensor(w["mu_inf"], dtype=torch.float64, requires_grad=True)
+        roll(a, mu).backward()
+        grads[prec] = np.concatenate([a.grad.numpy(), [mu.grad.item()]])
+        ctx.close()
+    err = np.max(np.abs(grads[1] - grads[0])) / np.max(np.abs(grads[0]))
+    _say(f"c5 subcase: FP32-mixed vs FP64 gradient, max rel error {err:.2e}")
+    assert err < 1e-3

@@ -61,12 +61,15 @@ def test_stream_matches_oracle(oracle, n_el, p, dt, length):
     assert rel_err(F, fo) < TOL64 and rel_err(G, go) < TOL64
 
 
-# the transposed streaming marches along z for three or more cells (in chunks
-# when there are few tiles: (2, 2, 8) at p = 4) and gathers otherwise
+# the transposed streaming marches along z in chunks when there are few tiles
+# ((2, 2, 8) at p = 4); one- and two-cell axes wrap inside a source-cell group
 TRANSPOSE_CASES = STREAM_CASES + [
     ((2, 2, 8), 4, 0.31, 2 * math.pi),
     ((3, 2, 3), 2, 1.3, 2 * math.pi),        # shifts of several cells, three cells along z
     ((2, 3, 12), 3, 0.2, (1.0, 2.0, 6.0)),
+    ((3, 2, 1), 3, 0.6, 2 * math.pi),        # one cell along z
+    ((1, 1, 1), 4, 0.7, 2 * math.pi),        # a single cell
+    ((9, 2, 2), 2, 2.1, 2 * math.pi),        # shifts beyond one tile along x
 ]
 
 
@@ -86,6 +89,20 @@ def test_transposed_stream_is_adjoint(oracle, n_el, p, dt, length):
     rhs = np.einsum("pin,pin->pi", x, STy)
     scale = np.einsum("pin,pin->pi", np.abs(Sx), np.abs(y))
     assert np.all(np.abs(lhs - rhs) <= 1e-13 * scale), np.max(np.abs(lhs - rhs) / scale)
+
+
+@pytest.mark.parametrize("n_el,p,dt", [((4, 4, 4), 2, 0.41), ((5, 2, 3), 4, 0.37), ((3, 2, 1), 3, 0.6)])
+def test_transposed_stream_fp32(oracle, n_el, p, dt):
+    """FP32 storage (16-byte window loads where rows allow): S^T y against the
+    FP64 library result on the same FP32 input, within FP32 rounding."""
+    _say(f"transposed stream fp32 n_el={n_el} p={p} dt={dt}")
+    c64, cfg = make_pair(oracle, n_el, p, dt, 0.01)
+    c32, _ = make_pair(oracle, n_el, p, dt, 0.01, precision=1)
+    gen = torch.Generator(device=c64.device).manual_seed(3)
+    y = torch.randn((2, Q, c64.nodes), generator=gen, device=c64.device, dtype=torch.float32)
+    t32 = c32.stream(y, transpose=True).double()
+    t64 = c64.stream(y.double(), transpose=True)
+    assert float((t32 - t64).abs().max() / t64.abs().max()) < 1e-6
 
 
 @pytest.mark.parametrize("law,pr", [(0, 0.71), (1, 1.0), (0, 2.0)])
