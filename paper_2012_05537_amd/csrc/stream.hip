@@ -66,6 +66,13 @@ struct VecOf<S, 1> {
     typedef S T;
 };
 
+template <typename VT>
+__device__ __forceinline__ auto vcomp(const VT &v, int c)
+{
+    if constexpr (std::is_arithmetic_v<VT>) return v;
+    else return v[c];
+}
+
 }  // namespace
 
 template <typename S, int P, int V>
@@ -299,7 +306,8 @@ __global__ void __launch_bounds__((ZTileT<P, V>::NT))
 {
     using Z = ZTileT<P, V>;
     using VT = typename VecOf<S, V>::T;
-    constexpr int TX = Z::TX, TY = Z::TY, WX = Z::WX, WY = Z::WY, NT = Z::NT, LK = Z::LK, BS = Z::BS;
+    constexpr int TX = Z::TX, TY = Z::TY, WY = Z::WY, NT = Z::NT, LK = Z::LK, BS = Z::BS;
+    constexpr int WX = Z::WX % 2 ? Z::WX : Z::WX + 1;      // odd LDS row stride
     constexpr int NLD = Z::WXC * WY;
     __shared__ __align__(16) S pl[P][WX * WY];
     __shared__ S bx[P][WY * BS];
@@ -325,13 +333,14 @@ __global__ void __launch_bounds__((ZTileT<P, V>::NT))
     const int offx = (-2 - omx) * P + lsx;
     const int offxa = offx - ((offx % V) + V) % V, sx = offx - offxa;
     const int offy = (-2 - omy) * P + lsy;
-    int loff[LK];
+    int loff[LK], soff[LK];                                // HBM and LDS offsets of this thread's loads
 #pragma unroll
     for (int k = 0; k < LK; ++k) {
         int e = tid + k * NT;
         e = e < NLD ? e : NLD - 1;
         const int wx = (e % Z::WXC) * V, wy = e / Z::WXC;
         loff[k] = wrapi(Y0 + offy + wy, Ny) * Nx + wrapi(X0 + offxa + wx, Nx);
+        soff[k] = wy * WX + wx;
     }
     // x and z weights, the same for every thread: w*[j][k] = W[(ls + j) mod P][k]
     S wxu[P][P + 1], wzu[P][P + 1];
@@ -376,7 +385,10 @@ __global__ void __launch_bounds__((ZTileT<P, V>::NT))
         for (int r = 0; r < P; ++r)
 #pragma unroll
             for (int j = 0; j < LK; ++j)
-                if (tid + j * NT < NLD) *reinterpret_cast<VT *>(&pl[r][V * (tid + j * NT)]) = raw[r][j];
+                if (tid + j * NT < NLD) {
+#pragma unroll
+                    for (int c = 0; c < V; ++c) pl[r][soff[j] + c] = vcomp(raw[r][j], c);
+                }
         if (next_nr > 0) load_rows(raw, next_k0, next_nr);
         __syncthreads();
         // x: task (row, window row, output cell cl) reads groups cl and cl + 1 of the row
