@@ -190,6 +190,7 @@ def main():
     ap.add_argument("--adjoint-workload", default="c4",
                     help="workload whose rollout gradient is timed for the adjoint/forward ratio ('none' to skip)")
     ap.add_argument("--adjoint-cfl", type=float, default=None, help="CFL override of the adjoint workload")
+    ap.add_argument("--adjoint-steps", type=int, default=None, help="rollout length override of the adjoint workload")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run three plain copies of one state's size first (HBM counter calibration)")
     args = ap.parse_args()
@@ -239,6 +240,8 @@ def main():
     }
     if args.adjoint_workload != "none":
         over = {} if args.adjoint_cfl is None else {"cfl": args.adjoint_cfl}
+        if args.adjoint_steps is not None:
+            over["steps"] = args.adjoint_steps
         wa = inputs.workload(args.adjoint_workload, **over)
         out["adjoint"] = run_adjoint(wa, 0 if wa["precision"] == "fp64" else 1)
     if not args.no_cpu_baseline:
