@@ -94,19 +94,18 @@ __device__ __forceinline__ double bder(const Bracket &b, double c)    // d b / d
 // Collision VJP: lam = J_C(X)^T mu, two lanes per node.  dmu_part[block]
 // receives the block's sum of dL/dmu_inf.
 // ---------------------------------------------------------------------------
-// One lane per thread (no loop: a loop would hoist the several hundred FP64
-// constants of the sweep into scalar registers and spill them); lanes past
-// the last node work on node 0 and store nothing, so every shuffle partner is
-// live.  mu and lam may be the same buffer: each lane reads its 45 values
-// before writing them.
+// Grid-stride over lane pairs; the whole block runs the same number of
+// iterations, so every shuffle partner is live.  mu and lam may be the same
+// buffer: each lane reads its 45 values before writing them.
 template <typename S>
 __global__ void __launch_bounds__(256) k_collide_vjp(int64_t N, CollisionParams cp, const S *__restrict__ X,
                                                      const S *mu, S *lam, double *__restrict__ dmu_part)
 {
-    __shared__ double red[4];
+    __shared__ double red[256];
     double dmu_acc = 0.0;
-    {
-    const int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    for (int64_t t0 = blockIdx.x * static_cast<int64_t>(blockDim.x); t0 < 2 * N; t0 += stride) {
+    const int64_t t = t0 + threadIdx.x;
     const int64_t n = t >> 1;
     const int pop = static_cast<int>(t & 1);
     const bool is_g = pop != 0;
@@ -304,12 +303,13 @@ __global__ void __launch_bounds__(256) k_collide_vjp(int64_t N, CollisionParams 
     // ---- dL/dmu_inf: mu = mu_inf * fac, counted once per node (f lane) ----
     if (active && !is_g) dmu_acc += mu_bar * fac;
     }
-    // block sum in a fixed order: butterfly within each wave, then the 4 waves
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) dmu_acc += __shfl_xor(dmu_acc, o);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = dmu_acc;
+    red[threadIdx.x] = dmu_acc;
     __syncthreads();
-    if (threadIdx.x == 0) dmu_part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) dmu_part[blockIdx.x] = red[0];
 }
 
 // Fixed-order sum of n block partials by one block of 256 threads; the
@@ -318,8 +318,17 @@ __global__ void __launch_bounds__(256) k_accumulate(const double *__restrict__ p
                                                     int add)
 {
     __shared__ double red[256];
-    double s = 0.0;
-    for (int b = threadIdx.x; b < n; b += 256) s += part[b];
+    // eight interleaved running sums per thread (eight loads in flight), combined in a fixed order
+    double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int b = threadIdx.x;
+    for (; b + 7 * 256 < n; b += 8 * 256) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) a[k] += part[b + k * 256];
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        if (b + k * 256 < n) a[k] += part[b + k * 256];
+    const double s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
     red[threadIdx.x] = s;
     __syncthreads();
     for (int k = 128; k > 0; k >>= 1) {
@@ -704,11 +713,8 @@ template <typename S>
 hipError_t Launch<S>::collide_vjp(const Geometry &g, const CollisionParams &cp, const S *state_n, S *lam,
                                   double *dmu_partials, int nblocks, double *dmu, hipStream_t st)
 {
-    // lam <- J_C(X_n)^T lam in place; one block per 128 nodes, each leaving
-    // one dmu partial (dmu_partials holds nblocks of them)
-    const int64_t need = (2 * g.nodes + 255) / 256;
-    if (need > nblocks) return hipErrorInvalidValue;
-    const int blocks = static_cast<int>(need);
+    // lam <- J_C(X_n)^T lam in place
+    const int blocks = static_cast<int>(std::min<int64_t>((2 * g.nodes + 255) / 256, nblocks));
     hipLaunchKernelGGL((k_collide_vjp<S>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, g.nodes, cp,
                        state_n, lam, lam, dmu_partials);
     hipError_t e = hipGetLastError();

@@ -17,6 +17,7 @@ using namespace sllbm;
 namespace {
 
 constexpr int RED_BLOCKS = 1024;   // blocks of the deterministic reductions
+constexpr int ADJ_BLOCKS = 4096;   // largest grid of the collision VJP (grid-stride beyond)
 
 std::string g_create_error;
 
@@ -45,8 +46,7 @@ struct sllbm_ctx {
     double *d_scr_u = nullptr;     // [3N]
     double *d_scr_div = nullptr;   // [cells * (p+1)^3]
     double *d_scr_T = nullptr;     // [N]   diagnostics scratch
-    double *d_adj_part = nullptr;  // [adj_blocks] dmu_inf partials of the collision VJP (one per block)
-    int adj_blocks = 0;            // blocks of the collision VJP: 256 lanes, two per node
+    double *d_adj_part = nullptr;  // [ADJ_BLOCKS] dmu_inf partials of the collision VJP
     // kernel timing: event pairs per launch kind (0 collision, 1 streaming)
     bool timing = false;
     std::vector<hipEvent_t> ev[2];
@@ -222,7 +222,6 @@ int sllbm_create(const sllbm_config *cfg, sllbm_ctx **out)
         g.N[a] = cfg->n_el[a] * cfg->order;
     }
     g.nodes = nodes;
-    c->adj_blocks = static_cast<int>((2 * nodes + 255) / 256);   // nodes < 2^31
     c->cp.dt = cfg->dt;
     c->cp.Cv = 1.0 / (cfg->gamma - 1.0);
     c->cp.beta = 2.0 * c->cp.Cv - 3.0;
@@ -276,7 +275,7 @@ int sllbm_create(const sllbm_config *cfg, sllbm_ctx **out)
         (e = dalloc(&c->d_scr_u, 3 * nodes * sizeof(double))) != hipSuccess ||
         (e = dalloc(&c->d_scr_div, cpts * sizeof(double))) != hipSuccess ||
         (e = dalloc(&c->d_scr_T, nodes * sizeof(double))) != hipSuccess ||
-        (e = dalloc(&c->d_adj_part, c->adj_blocks * sizeof(double))) != hipSuccess)
+        (e = dalloc(&c->d_adj_part, ADJ_BLOCKS * sizeof(double))) != hipSuccess)
         return bail(fail(c, SLLBM_ENOMEM, std::string("allocation failed: ") + hipGetErrorString(e)));
     if ((e = hipMemcpy(c->d_nodew, nodew.data(), nodew.size() * sizeof(double), hipMemcpyHostToDevice)) !=
             hipSuccess ||
@@ -628,12 +627,11 @@ int sllbm_adjoint_step(sllbm_ctx *ctx, const void *state_n, const void *lam_next
     DeviceGuard guard(ctx->cfg.device);
     hipError_t e = stream_t_into(ctx, lam_next, lam_out);
     if (e != hipSuccess) return hip_fail(ctx, e, "adjoint_step (transposed streaming)");
-    e = is_fp64(ctx) ? Launch<double>::collide_vjp(ctx->geo, ctx->cp, static_cast<const double *>(state_n),
-                                                   static_cast<double *>(lam_out), ctx->d_adj_part, ctx->adj_blocks,
-                                                   dmu, ctx->stream)
-                     : Launch<float>::collide_vjp(ctx->geo, ctx->cp, static_cast<const float *>(state_n),
-                                                  static_cast<float *>(lam_out), ctx->d_adj_part, ctx->adj_blocks,
-                                                  dmu, ctx->stream);
+    e = is_fp64(ctx)
+        ? Launch<double>::collide_vjp(ctx->geo, ctx->cp, static_cast<const double *>(state_n),
+                                      static_cast<double *>(lam_out), ctx->d_adj_part, ADJ_BLOCKS, dmu, ctx->stream)
+        : Launch<float>::collide_vjp(ctx->geo, ctx->cp, static_cast<const float *>(state_n),
+                                     static_cast<float *>(lam_out), ctx->d_adj_part, ADJ_BLOCKS, dmu, ctx->stream);
     return check_launch(ctx, e, "adjoint_step (collision VJP)");
 }
 
