@@ -43,6 +43,7 @@ class Cfg(ctypes.Structure):
         ("mu_inf", ctypes.c_double),
         ("mu_inf_im", ctypes.c_double),
         ("viscosity_law", ctypes.c_int),
+        ("faces", ctypes.POINTER(ctypes.c_double) * 3),
     ]
 
 
@@ -64,12 +65,27 @@ def _ptr(a):
 
 
 def make_cfg(n_el, p, dt, mu_inf, gamma=1.4, prandtl=0.71, length=2 * np.pi,
-             viscosity_law=SUTHERLAND, mu_inf_im=0.0):
+             viscosity_law=SUTHERLAND, mu_inf_im=0.0, widths=None):
+    """widths: None (equal cells) or, per axis, None or the n_el[a] cell widths
+    of a graded axis (their sum replaces length[a])."""
     if np.isscalar(n_el):
         n_el = (n_el, n_el, n_el)
     if np.isscalar(length):
         length = (length, length, length)
+    length = list(length)
     c = Cfg()
+    c._faces = [None, None, None]            # keeps the face arrays alive with the cfg
+    for a in range(3):
+        w = None if widths is None else widths[a]
+        if w is None:
+            continue
+        w = np.asarray(w, dtype=np.float64)
+        if w.shape != (int(n_el[a]),) or not np.all(w > 0):
+            raise ValueError("widths[%d] must hold n_el[%d] positive cell widths" % (a, a))
+        faces = np.concatenate([[0.0], np.cumsum(w)])
+        length[a] = float(faces[-1])
+        c._faces[a] = faces
+        c.faces[a] = faces.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     c.n_el[:] = [int(v) for v in n_el]
     c.p = int(p)
     c.length[:] = [float(v) for v in length]
@@ -261,7 +277,17 @@ def totals(cfg, f, g):
     return out
 
 
+def is_graded(cfg):
+    return any(getattr(cfg, "_faces", [None] * 3)[a] is not None for a in range(3))
+
+
+def _equal_cells_only(cfg, what):
+    if is_graded(cfg):
+        raise NotImplementedError(what + ": equal cells only")
+
+
 def loss(cfg, f, g):
+    _equal_cells_only(cfg, "loss")
     cplx = _is_cplx(f, g)
     f = np.ascontiguousarray(f, dtype=_dt(cplx))
     g = np.ascontiguousarray(g, dtype=_dt(cplx))
@@ -274,6 +300,7 @@ def loss(cfg, f, g):
     return fn(ctypes.byref(cfg), _ptr(f), _ptr(g))
 
 def diagnostics(cfg, f, g):
+    _equal_cells_only(cfg, "diagnostics")
     """(kinetic energy, solenoidal dissipation, dilatational dissipation) as domain integrals."""
     cplx = _is_cplx(f, g) or cfg.mu_inf_im != 0.0
     dt = _dt(cplx)

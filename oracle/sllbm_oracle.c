@@ -17,7 +17,8 @@
  *     h^eq and contracts their difference with all 27 components of H^(3)
  *     (App. D);
  *   - streaming traces every (node, velocity) pair back to x - xi*dt, finds
- *     the enclosing cell with floor(), and sums the (p+1)^3 tensor-product
+ *     the enclosing cell (floor() on equal cells, bisection over the cell
+ *     faces on a graded mesh), and sums the (p+1)^3 tensor-product
  *     Lagrange basis values over that cell's support points (Eqs. (8)-(9)).
  *     No per-axis factorisation and no precomputed tables are used.
  *
@@ -66,6 +67,8 @@ typedef struct {
     double mu_inf;         /* dynamic viscosity at T = 1 */
     double mu_inf_im;      /* imaginary part of mu_inf (complex build only) */
     int viscosity_law;     /* 0 = Sutherland, 1 = constant mu = mu_inf */
+    const double *faces[3];/* graded mesh: n_el[a] + 1 cell-face coordinates per axis,
+                              faces[a][0] = 0, faces[a][n_el] = length[a]; NULL = equal cells */
 } oracle_cfg;
 
 /* ------------------------------------------------------------------------- */
@@ -205,11 +208,59 @@ void oracle_cc_weights(int p, double *wcc)
     }
 }
 
-/* position of unique node g (= e*p + l) along an axis */
+/* position of unique node g (= e*p + l) along an axis of equal cells */
 static double node_pos(int g, int p, double h)
 {
     int e = g / p, l = g % p;
     return e * h + h * 0.5 * (1.0 - cos(M_PI * (double)l / (double)p));
+}
+
+/* Graded meshes (cells of unequal width along an axis, still periodic and
+ * axis-aligned): the GLC points of cell e are mapped onto [F_e, F_{e+1}]. */
+static double face_of(const oracle_cfg *c, int a, int e)
+{
+    return c->faces[a] ? c->faces[a][e] : e * (c->length[a] / c->n_el[a]);
+}
+
+static double axis_node_pos(const oracle_cfg *c, int a, int g)
+{
+    int p = c->p;
+    if (!c->faces[a]) return node_pos(g, p, c->length[a] / c->n_el[a]);
+    int e = g / p, l = g % p;
+    double F0 = face_of(c, a, e), F1 = face_of(c, a, e + 1);
+    return F0 + (F1 - F0) * 0.5 * (1.0 - cos(M_PI * (double)l / (double)p));
+}
+
+/* Departure cell of node g along axis a for the displacement -shift: first
+ * source node index base = E*p and local coordinate t in [0,1).  Equal
+ * cells: floor(X/h).  Graded cells: X wrapped into [0, L), then the cell
+ * whose faces enclose it (bisection over the faces). */
+static void departure_cell(const oracle_cfg *c, int a, int g, double shift, int *base, double *t)
+{
+    int p = c->p, ne = c->n_el[a];
+    if (!c->faces[a]) {
+        double h = c->length[a] / ne;
+        double X = node_pos(g, p, h) - shift;
+        double s = X / h;
+        double E = floor(s);
+        long Ei = (long)E % ne;
+        if (Ei < 0) Ei += ne;
+        *base = (int)(Ei * p);
+        *t = s - E;
+        return;
+    }
+    double L = c->length[a];
+    double X = axis_node_pos(c, a, g) - shift;
+    X -= L * floor(X / L);
+    if (X >= L) X = 0.0;                      /* rounding of the wrap */
+    int lo = 0, hi = ne;                       /* faces[lo] <= X < faces[hi] */
+    while (hi - lo > 1) {
+        int mid = (lo + hi) / 2;
+        if (c->faces[a][mid] <= X) lo = mid; else hi = mid;
+    }
+    double F0 = c->faces[a][lo], F1 = c->faces[a][lo + 1];
+    *base = lo * p;
+    *t = (X - F0) / (F1 - F0);
 }
 
 void oracle_node_coords(const oracle_cfg *c, double *x, double *y, double *z)
@@ -217,8 +268,7 @@ void oracle_node_coords(const oracle_cfg *c, double *x, double *y, double *z)
     double *out[3] = {x, y, z};
     for (int a = 0; a < 3; ++a) {
         int n = c->n_el[a] * c->p;
-        double h = c->length[a] / c->n_el[a];
-        for (int g = 0; g < n; ++g) out[a][g] = node_pos(g, c->p, h);
+        for (int g = 0; g < n; ++g) out[a][g] = axis_node_pos(c, a, g);
     }
 }
 
@@ -418,7 +468,7 @@ void FN(collide)(const oracle_cfg *c, R *f, R *g)
 }
 
 /* Value of population i at the departure point of node (gx, gy, gz):
- * cell found by floor(), then the (p+1)^3 tensor Lagrange sum over it. */
+ * enclosing cell per axis, then the (p+1)^3 tensor Lagrange sum over it. */
 static void departure_value(const oracle_cfg *c, const double *xi, int i, int gx, int gy, int gz,
                             const R *f, const R *g, R *fv, R *gv)
 {
@@ -428,14 +478,8 @@ static void departure_value(const oracle_cfg *c, const double *xi, int i, int gx
     int gidx[3] = {gx, gy, gz};
     for (int a = 0; a < 3; ++a) {
         N[a] = c->n_el[a] * p;
-        double h = c->length[a] / c->n_el[a];
-        double X = node_pos(gidx[a], p, h) - xi[3 * i + a] * c->dt;   /* departure point */
-        double s = X / h;
-        double E = floor(s);
-        double t = s - E;                                            /* local coordinate in [0,1) */
-        long Ei = (long)E % c->n_el[a];
-        if (Ei < 0) Ei += c->n_el[a];
-        base[a] = (int)(Ei * p);
+        double t;                                                    /* local coordinate in [0,1) */
+        departure_cell(c, a, gidx[a], xi[3 * i + a] * c->dt, &base[a], &t);
         oracle_lagrange(p, t, ell[a]);
     }
     long Nl = (long)N[0] * N[1] * N[2];
@@ -513,14 +557,9 @@ void FN(step_at_nodes)(const oracle_cfg *c, const R *f, const R *g, int nsamp, c
             int base[3];
             double ell[3][16];
             for (int a = 0; a < 3; ++a) {
-                double h = c->length[a] / c->n_el[a];
-                double X = node_pos(gidx[a], p, h) - xi[3 * i + a] * c->dt;
-                double sx = X / h;
-                double E = floor(sx);
-                long Ei = (long)E % c->n_el[a];
-                if (Ei < 0) Ei += c->n_el[a];
-                base[a] = (int)(Ei * p);
-                oracle_lagrange(p, sx - E, ell[a]);
+                double t;
+                departure_cell(c, a, gidx[a], xi[3 * i + a] * c->dt, &base[a], &t);
+                oracle_lagrange(p, t, ell[a]);
             }
             R sf = 0, sg = 0;
             for (int kz = 0; kz <= p; ++kz)
@@ -556,16 +595,20 @@ void FN(moments)(const oracle_cfg *c, const R *f, const R *g, R *rho, R *u, R *T
     }
 }
 
-/* Quadrature weight of unique node g along one axis: Clenshaw-Curtis weight of
- * its local point, mapped to a cell of width h; cell end points are shared by
- * two cells, so their weights add. */
-static double node_weight(int g, int p, double h)
+/* Quadrature weight of unique node g along axis a: Clenshaw-Curtis weight of
+ * its local point, mapped to its cell; cell end points are shared by two
+ * cells (the previous one, periodically), so their weights add. */
+static double node_weight(const oracle_cfg *c, int a, int g)
 {
     double wcc[16];
+    int p = c->p, ne = c->n_el[a];
     oracle_cc_weights(p, wcc);
-    int l = g % p;
-    double wl = (l == 0) ? wcc[0] + wcc[p] : wcc[l];
-    return 0.5 * h * wl;
+    int e = g / p, l = g % p;
+    double h = face_of(c, a, e + 1) - face_of(c, a, e);
+    if (l != 0) return 0.5 * h * wcc[l];
+    int ep = (e + ne - 1) % ne;
+    double hp = face_of(c, a, ep + 1) - face_of(c, a, ep);
+    return 0.5 * (h * wcc[0] + hp * wcc[p]);
 }
 
 /* Domain integrals of rho, rho u (3) and rho E (Eq. (7)), summed in node order. */
@@ -576,13 +619,12 @@ void FN(totals)(const oracle_cfg *c, const R *f, const R *g, R *out)
     int p = c->p;
     int Nx = c->n_el[0] * p, Ny = c->n_el[1] * p, Nz = c->n_el[2] * p;
     long N = n_nodes(c);
-    double h[3] = {c->length[0] / c->n_el[0], c->length[1] / c->n_el[1], c->length[2] / c->n_el[2]};
     for (int k = 0; k < 5; ++k) out[k] = 0;
     for (int gz = 0; gz < Nz; ++gz)
         for (int gy = 0; gy < Ny; ++gy)
             for (int gx = 0; gx < Nx; ++gx) {
                 long n = ((long)gz * Ny + gy) * Nx + gx;
-                double W = node_weight(gx, p, h[0]) * node_weight(gy, p, h[1]) * node_weight(gz, p, h[2]);
+                double W = node_weight(c, 0, gx) * node_weight(c, 1, gy) * node_weight(c, 2, gz);
                 R r = 0, j[3] = {0, 0, 0}, twoE = 0;
                 for (int i = 0; i < Q; ++i) {
                     R fi = f[(long)i * N + n];
@@ -601,7 +643,8 @@ void FN(totals)(const oracle_cfg *c, const R *f, const R *g, R *out)
  *   L = sum over cells of the tensor Clenshaw-Curtis quadrature of
  *       (1/2) rho |u|^2 + (div u)^2,
  * with div u from the derivative of each cell's own interpolation polynomial
- * (so it is discontinuous across cell faces, as in Sec. III C). */
+ * (so it is discontinuous across cell faces, as in Sec. III C).  Equal cells
+ * only (the wrapper refuses a graded mesh). */
 R FN(loss)(const oracle_cfg *c, const R *f, const R *g)
 {
     int p = c->p;
@@ -655,7 +698,8 @@ R FN(loss)(const oracle_cfg *c, const R *f, const R *g)
  *   out[0] = kinetic energy        int (1/2) rho |u|^2
  *   out[1] = solenoidal dissipation int mu(T) |curl u|^2
  *   out[2] = dilatational dissipation (4/3) int mu(T) (div u)^2
- * (the paper's 1/(rho_ref Re) prefactor is the mu_inf inside mu(T)). */
+ * (the paper's 1/(rho_ref Re) prefactor is the mu_inf inside mu(T)).
+ * Equal cells only (the wrapper refuses a graded mesh). */
 void FN(diagnostics)(const oracle_cfg *c, const R *f, const R *g, R *out)
 {
     int p = c->p;
