@@ -27,6 +27,7 @@ Q = 45
 # sources that determine each timed kernel (a change voids committed counters)
 KERNEL_SOURCES = {
     "k_stream_z": ("stream.hip", "tables.cpp"),
+    "k_stream_graded": ("stream_graded.hip", "tables.cpp"),
     "k_collide": ("kernels.hip", "collision.h", "velset.h"),
 }
 
@@ -62,6 +63,9 @@ def run_gpu(args, wl, precision):
 
     ctx = SLLBM(wl["n_el"], wl["p"], wl["dt"], wl["mu_inf"], gamma=wl["gamma"], prandtl=wl["Pr"],
                 precision=precision)
+    if args.mesh == "graded":
+        w = inputs.graded_widths(wl["n_el"], amplitude=inputs.GRADED["amplitude"])
+        ctx.set_mesh(w, w, w)
     xs, ys, zs = (t.numpy() for t in ctx.node_coords())
     rho, u, T = inputs.tgv_fields(xs, ys, zs, wl["Ma"], wl["gamma"])
     dev = ctx.device
@@ -105,7 +109,8 @@ def run_gpu(args, wl, precision):
     bytes_per_launch = 2 * 2 * Q * nodes * elem          # each kernel reads 90 and writes 90 values per node
     ctx.close()
     kernels = {name: {"ms": ms / max(n, 1), "launches": n} for name, (ms, n) in
-               (("k_collide", kt["collide"]), ("k_stream_z", kt["stream"]))}
+               (("k_collide", kt["collide"]),
+                ("k_stream_graded" if args.mesh == "graded" else "k_stream_z", kt["stream"]))}
     return dict(nodes=nodes, wall=wall, kernels=kernels, bytes=bytes_per_launch, finite=ok, totals=tot)
 
 
@@ -153,14 +158,19 @@ def run_adjoint(wl, precision):
             "device_memory_GB": peak_gb}
 
 
-def cpu_baseline(wl, budget_s):
+def cpu_baseline(wl, budget_s, graded=False):
     """The FP64 oracle on the host cores: whole-grid steps of the same workload
-    (same grid, same parameters) until about budget_s seconds have run."""
+    (same grid, same mesh, same parameters) until about budget_s seconds have run."""
     import numpy as np
     from oracle import oracle as O
     from paper_2012_05537_amd import inputs
 
-    cfg = O.make_cfg(wl["n_el"], wl["p"], wl["dt"], wl["mu_inf"], gamma=wl["gamma"], prandtl=wl["Pr"])
+    widths = None
+    if graded:
+        w = inputs.graded_widths(wl["n_el"], amplitude=inputs.GRADED["amplitude"])
+        widths = [w, w, w]
+    cfg = O.make_cfg(wl["n_el"], wl["p"], wl["dt"], wl["mu_inf"], gamma=wl["gamma"], prandtl=wl["Pr"],
+                     widths=widths)
     rho, u, T = inputs.tgv_fields(*O.node_coords(cfg), wl["Ma"], wl["gamma"])
     f, g = O.init_equilibrium(cfg, rho, u, T)
     steps = 0
@@ -184,6 +194,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="c2", help="workload key (c1..c5)")
     ap.add_argument("--cfl", type=float, default=1.0)
+    ap.add_argument("--mesh", choices=["equal", "graded"], default="equal",
+                    help="equal cells, or the cosine-graded cells of every axis (streaming on per-node tables)")
     ap.add_argument("--precision", choices=["fp64", "fp32"], default=None)
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -201,6 +213,7 @@ def main():
 
     from paper_2012_05537_amd import inputs
     wl = inputs.workload(args.workload, cfl=args.cfl)
+    wkey = args.workload if args.mesh == "equal" else args.workload + "-graded"
     prec_name = args.precision or wl["precision"]
     precision = 0 if prec_name == "fp64" else 1
     r = run_gpu(args, wl, precision)
@@ -212,7 +225,7 @@ def main():
     for k, v in r["kernels"].items():
         gbs = r["bytes"] / (v["ms"] * 1e-3) / 1e9 if v["ms"] > 0 else None
         kernels[k] = {"ms_per_launch": v["ms"], "launches": v["launches"], "algorithmic_GBps": gbs,
-                      "traffic": measured_traffic(k, args.workload, prec_name)}
+                      "traffic": measured_traffic(k, wkey, prec_name)}
     out = {
         "metric": "node-updates/s (D3V45 f+g)",
         "value": value,
@@ -226,7 +239,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if precision == 0 else "f32 (f64 moments)",
         "data": "synthetic: closed-form compressible Taylor-Green vortex",
-        "config": {"workload": f"{args.workload}: TGV {wl['n_el']}^3 cells p={wl['p']} "
+        "config": {"workload": f"{wkey}: TGV {wl['n_el']}^3 "
+                               f"{'cells' if args.mesh == 'equal' else 'cosine-graded cells (a = 0.3)'} p={wl['p']} "
                                f"({r['nodes']} nodes), Ma {wl['Ma']}, Re {wl['Re']}, CFL {wl['cfl']}, "
                                f"{prec_name}",
                    "nodes": r["nodes"], "order": wl["p"], "cfl": wl["cfl"], "dt": wl["dt"],
@@ -245,7 +259,7 @@ def main():
         wa = inputs.workload(args.adjoint_workload, **over)
         out["adjoint"] = run_adjoint(wa, 0 if wa["precision"] == "fp64" else 1)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_budget, graded=args.mesh == "graded")
     print(json.dumps(out), flush=True)
     return 0
 

@@ -2,8 +2,8 @@
  * sllbm.h -- C ABI of the MI355X (gfx950) semi-Lagrangian lattice Boltzmann
  * library: the per-time-step update of the 45-velocity f and g populations
  * of the compressible SLLBM (Wilde, Kraemer, Reith, Foysi, arXiv:2012.05537)
- * on a periodic hexahedral mesh of equal cells with Gauss-Lobatto-Chebyshev
- * support points.
+ * on a periodic hexahedral mesh of equal cells (or of axis-aligned cells of
+ * unequal width, sllbm_set_mesh) with Gauss-Lobatto-Chebyshev support points.
  *
  * Conventions shared by every call
  * --------------------------------
@@ -106,6 +106,22 @@ int sllbm_node_coords(const sllbm_ctx *ctx, double *x, double *y, double *z);
 
 /* Change mu_inf (the "relaxation time" parameter; tau - 1/2 = mu/(P dt)). */
 int sllbm_set_viscosity(sllbm_ctx *ctx, double mu_inf);
+
+/* Graded mesh (Sec. II A: departure points are traced through the
+ * neighbouring cells; with unequal cells the per-cell interpolation matrices
+ * are no longer shared, subsection "Numerical efficiency").  widths_a: host
+ * array of n_el[a] positive cell widths along axis a, or NULL to keep equal
+ * cells on that axis (at least one must be given); a given axis gets length
+ * sum(widths_a), node g = e*order + l of it sits at F_e + w_e t_l (F_e =
+ * w_0 + ... + w_{e-1}).  The departure cell of every (node, velocity, axis)
+ * is located once here and per-node tables are uploaded; the state is kept.
+ * Afterwards sllbm_stream, _step, _step_record, _collide, _moments,
+ * _totals and _node_coords use the graded mesh; transposed streaming,
+ * sllbm_adjoint_step, _loss, _loss_grad and _diagnostics return EINVAL.
+ * Synchronises the context's stream.  On failure the previous mesh stays.
+ * Errors: EINVAL (NULL widths, non-positive width, or a source window of a
+ * 32 x 8 tile larger than the 160 KB of LDS), ENOMEM, EDEVICE. */
+int sllbm_set_mesh(sllbm_ctx *ctx, const double *widths_x, const double *widths_y, const double *widths_z);
 
 /* State := equilibrium of the given fields (Eq. (6); g^eq = (2C_v - D) T f^eq).
  * rho, u, T: device.  Errors: EINVAL on NULL. */

@@ -52,6 +52,13 @@ struct sllbm_ctx {
     std::vector<hipEvent_t> ev[2];
     int nev[2] = {0, 0};
     double h[3] = {0, 0, 0};       // cell widths (host)
+    // graded mesh (sllbm_set_mesh): cell faces per graded axis (empty: equal
+    // cells), per-node departure tables on the device
+    bool graded = false;
+    std::vector<double> faces[3];
+    int32_t *d_gsrc[3] = {nullptr, nullptr, nullptr};
+    void *d_gw[3] = {nullptr, nullptr, nullptr};
+    int gwxm = 0, gwym = 0;
     std::string err;
 };
 
@@ -93,6 +100,10 @@ void free_ctx(sllbm_ctx *c)
     for (int k = 0; k < 2; ++k)
         for (hipEvent_t e : c->ev[k]) (void)hipEventDestroy(e);
     for (int k = 0; k < 2; ++k) (void)hipFree(c->buf[k]);
+    for (int a = 0; a < 3; ++a) {
+        (void)hipFree(c->d_gsrc[a]);
+        (void)hipFree(c->d_gw[a]);
+    }
     (void)hipFree(c->d_omin);
     (void)hipFree(c->d_lstar);
     (void)hipFree(c->d_cw);
@@ -137,6 +148,19 @@ CellTables<S> cell_tables(const sllbm_ctx *c)
     return CellTables<S>{c->d_omin, c->d_lstar, static_cast<const S *>(c->d_cw)};
 }
 
+template <typename S>
+NodeTables<S> node_tables(const sllbm_ctx *c)
+{
+    NodeTables<S> t{};
+    for (int a = 0; a < 3; ++a) {
+        t.src[a] = c->d_gsrc[a];
+        t.w[a] = static_cast<const S *>(c->d_gw[a]);
+    }
+    t.wxm = c->gwxm;
+    t.wym = c->gwym;
+    return t;
+}
+
 bool is_fp64(const sllbm_ctx *c) { return c->cfg.precision == SLLBM_FP64; }
 
 void *other(sllbm_ctx *c) { return c->buf[1 - c->cur]; }
@@ -144,6 +168,66 @@ void *other(sllbm_ctx *c) { return c->buf[1 - c->cur]; }
 int check_launch(sllbm_ctx *c, hipError_t e, const char *what)
 {
     return e == hipSuccess ? SLLBM_OK : hip_fail(c, e, what);
+}
+
+// Per-node departure tables of the three axes (graded mesh) in the storage
+// type, their tile windows, and the quadrature weights of the nodes.
+template <typename S>
+int upload_graded(sllbm_ctx *c)
+{
+    const Geometry &g = c->geo;
+    const int p = g.p;
+    int wmax[2] = {0, 0};
+    hipError_t e;
+    for (int a = 0; a < 3; ++a) {
+        std::vector<int32_t> src;
+        std::vector<double> w;
+        build_node_tables(c->vs, p, g.nel[a], c->cfg.length[a], c->faces[a], a, c->cfg.dt, src, w);
+        if (a < 2) {
+            const int T = a == 0 ? graded_tile_x() : graded_tile_y();
+            for (int i = 0; i < Q; ++i)
+                wmax[a] = std::max(wmax[a], graded_window(&src[static_cast<size_t>(i) * g.N[a]], g.N[a], p, T));
+        }
+        std::vector<S> ws(w.begin(), w.end());
+        (void)hipFree(c->d_gsrc[a]);
+        (void)hipFree(c->d_gw[a]);
+        c->d_gsrc[a] = nullptr;
+        c->d_gw[a] = nullptr;
+        if ((e = dalloc(&c->d_gsrc[a], src.size() * sizeof(int32_t))) != hipSuccess ||
+            (e = dalloc(reinterpret_cast<S **>(&c->d_gw[a]), ws.size() * sizeof(S))) != hipSuccess)
+            return fail(c, SLLBM_ENOMEM, std::string("graded table allocation: ") + hipGetErrorString(e));
+        if ((e = hipMemcpy(c->d_gsrc[a], src.data(), src.size() * sizeof(int32_t), hipMemcpyHostToDevice)) !=
+                hipSuccess ||
+            (e = hipMemcpy(c->d_gw[a], ws.data(), ws.size() * sizeof(S), hipMemcpyHostToDevice)) != hipSuccess)
+            return hip_fail(c, e, "graded table upload");
+    }
+    c->gwxm = wmax[0];
+    c->gwym = wmax[1];
+    const size_t smem = graded_smem_bytes(p, c->gwxm, c->gwym, sizeof(S));
+    if (smem > 160 * 1024)
+        return fail(c, SLLBM_EINVAL, "graded mesh: the source window of a tile needs " + std::to_string(smem) +
+                                         " bytes of LDS (more than 160 KB); the grading is too strong");
+    // node quadrature weights: Clenshaw-Curtis weight of the local point
+    // times half the cell width; a cell's first point also carries the last
+    // weight of the previous cell (periodic)
+    double cc[MAXP + 1];
+    clenshaw_curtis(p, cc);
+    std::vector<double> nodew;
+    for (int a = 0; a < 3; ++a) {
+        const int ne = g.nel[a];
+        auto width = [&](int el) {
+            return c->faces[a].empty() ? c->cfg.length[a] / ne : c->faces[a][el + 1] - c->faces[a][el];
+        };
+        for (int n = 0; n < g.N[a]; ++n) {
+            const int el = n / p, l = n % p;
+            nodew.push_back(l == 0 ? 0.5 * (width(el) * cc[0] + width((el + ne - 1) % ne) * cc[p])
+                                   : 0.5 * width(el) * cc[l]);
+        }
+    }
+    if ((e = hipMemcpy(c->d_nodew, nodew.data(), nodew.size() * sizeof(double), hipMemcpyHostToDevice)) !=
+        hipSuccess)
+        return hip_fail(c, e, "node weight upload");
+    return SLLBM_OK;
 }
 
 }  // namespace
@@ -312,14 +396,55 @@ int sllbm_node_coords(const sllbm_ctx *ctx, double *x, double *y, double *z)
     if (!ctx || !x || !y || !z) return SLLBM_EINVAL;
     double *out[3] = {x, y, z};
     const int p = ctx->geo.p;
+    for (int a = 0; a < 3; ++a)
+        for (int n = 0; n < ctx->geo.N[a]; ++n)
+            out[a][n] = axis_node_position(p, ctx->cfg.n_el[a], ctx->cfg.length[a], ctx->faces[a], n);
+    return SLLBM_OK;
+}
+
+int sllbm_set_mesh(sllbm_ctx *ctx, const double *widths_x, const double *widths_y, const double *widths_z)
+{
+    if (!ctx) return SLLBM_EINVAL;
+    const double *wd[3] = {widths_x, widths_y, widths_z};
+    if (!wd[0] && !wd[1] && !wd[2]) return fail(ctx, SLLBM_EINVAL, "set_mesh: no graded axis given");
+    std::vector<double> faces[3];
     for (int a = 0; a < 3; ++a) {
-        const double h = ctx->cfg.length[a] / ctx->cfg.n_el[a];
-        for (int n = 0; n < ctx->geo.N[a]; ++n) {
-            const int e = n / p, l = n % p;
-            out[a][n] = e * h + h * 0.5 * (1.0 - std::cos(M_PI * l / p));
+        if (!wd[a]) continue;
+        faces[a].assign(1, 0.0);
+        for (int e = 0; e < ctx->cfg.n_el[a]; ++e) {
+            if (!(wd[a][e] > 0.0) || !std::isfinite(wd[a][e]))
+                return fail(ctx, SLLBM_EINVAL, "set_mesh: cell widths must be positive and finite");
+            faces[a].push_back(faces[a].back() + wd[a][e]);
         }
     }
-    return SLLBM_OK;
+    DeviceGuard guard(ctx->cfg.device);
+    hipError_t e = ctx->stream ? hipStreamSynchronize(ctx->stream) : hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(ctx, e, "set_mesh");
+    std::vector<double> old_faces[3];
+    double old_length[3];
+    const bool was_graded = ctx->graded;
+    for (int a = 0; a < 3; ++a) {
+        old_faces[a] = ctx->faces[a];
+        old_length[a] = ctx->cfg.length[a];
+        if (faces[a].empty()) continue;
+        ctx->cfg.length[a] = faces[a].back();
+        ctx->faces[a] = faces[a];
+    }
+    auto upload = [&]() { return is_fp64(ctx) ? upload_graded<double>(ctx) : upload_graded<float>(ctx); };
+    const int rc = upload();
+    if (rc == SLLBM_OK) {
+        ctx->graded = true;
+        return SLLBM_OK;
+    }
+    // keep the previous mesh (its tables are rebuilt if it was graded)
+    const std::string msg = ctx->err;
+    for (int a = 0; a < 3; ++a) {
+        ctx->faces[a] = old_faces[a];
+        ctx->cfg.length[a] = old_length[a];
+    }
+    ctx->graded = was_graded && upload() == SLLBM_OK;
+    ctx->err = msg;
+    return rc;
 }
 
 int sllbm_set_viscosity(sllbm_ctx *ctx, double mu_inf)
@@ -380,6 +505,13 @@ static hipError_t collide_into(sllbm_ctx *c, const void *in, void *out)
 
 static hipError_t stream_into(sllbm_ctx *c, const void *in, void *out)
 {
+    if (c->graded) {
+        if (is_fp64(c))
+            return launch_stream_graded<double>(c->geo, node_tables<double>(c), static_cast<const double *>(in),
+                                                static_cast<double *>(out), c->stream);
+        return launch_stream_graded<float>(c->geo, node_tables<float>(c), static_cast<const float *>(in),
+                                           static_cast<float *>(out), c->stream);
+    }
     if (is_fp64(c))
         return launch_stream_z<double>(c->geo, cell_tables<double>(c), static_cast<const double *>(in),
                                        static_cast<double *>(out), c->stream);
@@ -541,6 +673,7 @@ int sllbm_stream(sllbm_ctx *ctx, const void *in, void *out, int32_t transpose)
     if (!in || !out || in == out) return fail(ctx, SLLBM_EINVAL, "bad stream buffers");
     DeviceGuard guard(ctx->cfg.device);
     if (!transpose) return check_launch(ctx, stream_into(ctx, in, out), "stream");
+    if (ctx->graded) return fail(ctx, SLLBM_EINVAL, "transposed streaming needs equal cells");
     return check_launch(ctx, stream_t_into(ctx, in, out), "stream");
 }
 
@@ -566,6 +699,7 @@ int sllbm_loss(sllbm_ctx *ctx, const void *state, double *out)
 {
     if (!ctx) return SLLBM_EINVAL;
     if (!state || !out) return fail(ctx, SLLBM_EINVAL, "NULL argument");
+    if (ctx->graded) return fail(ctx, SLLBM_EINVAL, "loss needs equal cells");
     DeviceGuard guard(ctx->cfg.device);
     hipError_t e = is_fp64(ctx)
         ? Launch<double>::loss(ctx->geo, static_cast<const double *>(state), ctx->d_dmat, ctx->d_ccw, ctx->h,
@@ -585,6 +719,7 @@ int sllbm_diagnostics(sllbm_ctx *ctx, const void *state, double *out)
     if (!ctx) return SLLBM_EINVAL;
     if (!out) return fail(ctx, SLLBM_EINVAL, "NULL out");
     if (!state && !ctx->has_state) return fail(ctx, SLLBM_ESTATE, "no state set");
+    if (ctx->graded) return fail(ctx, SLLBM_EINVAL, "diagnostics need equal cells");
     DeviceGuard guard(ctx->cfg.device);
     const void *st = state ? state : ctx->buf[ctx->cur];
     hipError_t e = is_fp64(ctx)
@@ -608,6 +743,7 @@ int sllbm_loss_grad(sllbm_ctx *ctx, const void *state, void *lam)
 {
     if (!ctx) return SLLBM_EINVAL;
     if (!state || !lam || state == lam) return fail(ctx, SLLBM_EINVAL, "bad loss_grad buffers");
+    if (ctx->graded) return fail(ctx, SLLBM_EINVAL, "loss_grad needs equal cells");
     DeviceGuard guard(ctx->cfg.device);
     hipError_t e = is_fp64(ctx)
         ? Launch<double>::loss_grad(ctx->geo, static_cast<const double *>(state), ctx->d_dmat, ctx->d_ccw,
@@ -624,6 +760,7 @@ int sllbm_adjoint_step(sllbm_ctx *ctx, const void *state_n, const void *lam_next
     if (!ctx) return SLLBM_EINVAL;
     if (!state_n || !lam_next || !lam_out) return fail(ctx, SLLBM_EINVAL, "NULL argument");
     if (lam_out == lam_next || lam_out == state_n) return fail(ctx, SLLBM_EINVAL, "lam_out aliases an input");
+    if (ctx->graded) return fail(ctx, SLLBM_EINVAL, "adjoint_step needs equal cells");
     DeviceGuard guard(ctx->cfg.device);
     hipError_t e = stream_t_into(ctx, lam_next, lam_out);
     if (e != hipSuccess) return hip_fail(ctx, e, "adjoint_step (transposed streaming)");

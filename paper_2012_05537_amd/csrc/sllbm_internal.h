@@ -39,6 +39,17 @@ void clenshaw_curtis(int p, double *w);                  // weights on [-1,1]
 void build_cell_tables(const VelocitySet &vs, int p, const double h[3], double dt, std::vector<int32_t> &omin,
                        std::vector<int32_t> &lstar, std::vector<double> &w);
 
+// Graded meshes (periodic, axis-aligned cells of unequal width): faces holds
+// the n_el + 1 cell-face coordinates of the axis (empty: equal cells of
+// length / n_el).  Node g = e*p + l sits at faces[e] + width_e t_l.
+double axis_node_position(int p, int ne, double length, const std::vector<double> &faces, int g);
+// Per-node departure tables of one axis: node g of velocity i interpolates
+// the p + 1 source nodes src[i][g] + k (not wrapped: src is non-decreasing
+// in g; reduce modulo n_el * p to address memory) with the weights
+// w[i][g][k] (layout [Q][N][p+1]).
+void build_node_tables(const VelocitySet &vs, int p, int ne, double length, const std::vector<double> &faces,
+                       int axis, double dt, std::vector<int32_t> &src, std::vector<double> &w);
+
 // ---------------------------------------------------------------------------
 // Device-side parameter blocks (passed by value to kernels)
 // ---------------------------------------------------------------------------
@@ -58,6 +69,16 @@ struct CellTables {
     const int32_t *omin;    // [Q][3]
     const int32_t *lstar;   // [Q][3]
     const S *w;             // [Q][3][p][p+1]
+};
+
+// Per-node departure tables of a graded mesh (build_node_tables), one set
+// per axis, in the storage type; wxm / wym bound the source window of an x-y
+// tile of the graded streaming kernel over all velocities and tiles.
+template <typename S>
+struct NodeTables {
+    const int32_t *src[3];  // [Q][N_a]
+    const S *w[3];          // [Q][N_a][p+1]
+    int wxm, wym;
 };
 
 struct CollisionParams {
@@ -113,5 +134,12 @@ hipError_t launch_stream_z(const Geometry &g, const CellTables<S> &t, const S *i
 // with the forward cell tables (stream.hip); any number of cells per axis
 template <typename S>
 hipError_t launch_stream_zt(const Geometry &g, const CellTables<S> &t, const S *in, S *out, hipStream_t st);
+// streaming on a graded mesh (stream_graded.hip)
+template <typename S>
+hipError_t launch_stream_graded(const Geometry &g, const NodeTables<S> &t, const S *in, S *out, hipStream_t st);
+size_t graded_smem_bytes(int p, int wxm, int wym, size_t elem);
+int graded_window(const int32_t *src, int N, int p, int T);
+int graded_tile_x();
+int graded_tile_y();
 
 }  // namespace sllbm

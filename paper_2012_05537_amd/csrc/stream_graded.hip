@@ -1,0 +1,190 @@
+// Semi-Lagrangian streaming (Sec. II A, Eqs. (8)-(9)) on a graded mesh:
+// periodic, axis-aligned cells of unequal width.
+//
+// The departure point of every node still factorises per axis, but the
+// departure cell and the 1-D Lagrange weights now depend on the node, not
+// only on its local point: each axis carries per-node tables (first source
+// node, p + 1 weights), built once per mesh.  Along an axis the first source
+// node is non-decreasing in the output node, so the source window of an x-y
+// tile is one contiguous (wrapped) range per axis.
+//
+// A block owns one (velocity, population) plane over a 32 x 8 x-y tile and a
+// range of output z-rows.  It walks the source z-rows in order; for each it
+// loads the tile's window into LDS, interpolates along x (per-thread taps)
+// and then along y, and keeps the result in a per-thread ring of the last
+// p + 1 source rows, from which each output z-row takes its p + 1 taps.
+// Every source row is read once per plane and tile column of the chunk.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "sllbm_internal.h"
+
+namespace sllbm {
+
+namespace {
+
+__device__ __forceinline__ int wrapg(int x, int n)
+{
+    int r = x % n;
+    return r < 0 ? r + n : r;
+}
+
+__device__ __forceinline__ int xcd_order(int b, int nb)
+{
+    const int xcd = b & 7, slot = b >> 3;
+    const int per = nb >> 3, rem = nb & 7;
+    return xcd < rem ? xcd * (per + 1) + slot : rem * (per + 1) + (xcd - rem) * per + slot;
+}
+
+constexpr int GTX = 32, GTY = 8, GNT = GTX * GTY;
+constexpr int64_t GRADED_TARGET_BLOCKS = 2048;
+
+}  // namespace
+
+template <typename S, int P>
+__global__ void __launch_bounds__(GNT) k_stream_graded(Geometry g, NodeTables<S> tab, const S *__restrict__ in,
+                                                        S *__restrict__ out, int ntile_x, int ntiles, int zrows,
+                                                        int nchunk)
+{
+    constexpr int RZ = P + 1;                              // ring of source rows per thread
+    constexpr int AS = GTX + 1;                            // odd row stride of the x-pass result
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int wxm = tab.wxm, wym = tab.wym;
+    S *pl = reinterpret_cast<S *>(smem_raw);               // [wym][wxm] source window of one z-row
+    S *A = pl + wym * wxm;                                 // [wym][AS]  x-interpolated rows
+    S *ring = A + wym * AS;                                // [RZ][GNT]  x-y interpolated source rows
+
+    const int tid = threadIdx.x;
+    const int L = __builtin_amdgcn_readfirstlane(xcd_order(blockIdx.x, gridDim.x));
+    const int q = L / (ntiles * nchunk);
+    const int rem = L - q * ntiles * nchunk;
+    const int chunk = rem / ntiles, tile = rem - chunk * ntiles;
+    const int i = q >> 1, pop = q & 1;
+    const int X0 = (tile % ntile_x) * GTX, Y0 = (tile / ntile_x) * GTY;
+    const int Nx = g.N[0], Ny = g.N[1], Nz = g.N[2];
+    const int64_t N = g.nodes, NP = static_cast<int64_t>(Nx) * Ny;
+    const int32_t *sx = tab.src[0] + static_cast<int64_t>(i) * Nx;
+    const int32_t *sy = tab.src[1] + static_cast<int64_t>(i) * Ny;
+    const int32_t *sz = tab.src[2] + static_cast<int64_t>(i) * Nz;
+    const S *wxt = tab.w[0] + static_cast<int64_t>(i) * Nx * (P + 1);
+    const S *wyt = tab.w[1] + static_cast<int64_t>(i) * Ny * (P + 1);
+    const S *wzt = tab.w[2] + static_cast<int64_t>(i) * Nz * (P + 1);
+    const S *__restrict__ src = in + static_cast<int64_t>(pop * 45 + i) * N;
+    S *__restrict__ dst = out + static_cast<int64_t>(pop * 45 + i) * N;
+
+    // source window of the tile (first source nodes are non-decreasing)
+    const int xs0 = sx[X0], wxb = sx[min(X0 + GTX, Nx) - 1] - xs0 + P + 1;
+    const int ys0 = sy[Y0], wyb = sy[min(Y0 + GTY, Ny) - 1] - ys0 + P + 1;
+    const int nwin = wxb * wyb;
+
+    // taps of this thread's output column (clamped on ragged tiles, not stored)
+    const int tx = tid % GTX, ty = tid / GTX;
+    const bool own = X0 + tx < Nx && Y0 + ty < Ny;
+    const int gx = min(X0 + tx, Nx - 1), gy = min(Y0 + ty, Ny - 1);
+    const int ox = sx[gx] - xs0, oy = sy[gy] - ys0;
+    S wx[P + 1], wy[P + 1];
+#pragma unroll
+    for (int k = 0; k <= P; ++k) {
+        wx[k] = wxt[gx * (P + 1) + k];
+        wy[k] = wyt[gy * (P + 1) + k];
+    }
+    const int64_t oxy = static_cast<int64_t>(gy) * Nx + gx;
+
+    const int zo0 = chunk * zrows, zo1 = min(Nz, zo0 + zrows);
+    const int r0 = sz[zo0];                                // first source row of the chunk (not wrapped)
+    int rnext = r0;
+    for (int zo = zo0; zo < zo1; ++zo) {
+        const int s = sz[zo];
+        // bring in source rows up to s + P (rows below s are no longer needed)
+        for (; rnext <= s + P; ++rnext) {
+            const int64_t zoff = static_cast<int64_t>(wrapg(rnext, Nz)) * NP;
+            for (int e = tid; e < nwin; e += GNT) {
+                const int wy_ = e / wxb, wx_ = e - wy_ * wxb;
+                pl[wy_ * wxm + wx_] =
+                    src[zoff + static_cast<int64_t>(wrapg(ys0 + wy_, Ny)) * Nx + wrapg(xs0 + wx_, Nx)];
+            }
+            __syncthreads();
+            for (int wy_ = ty; wy_ < wyb; wy_ += GTY) {
+                S acc = 0;
+#pragma unroll
+                for (int k = 0; k <= P; ++k) acc = fma(wx[k], pl[wy_ * wxm + ox + k], acc);
+                A[wy_ * AS + tx] = acc;
+            }
+            __syncthreads();
+            S acc = 0;
+#pragma unroll
+            for (int k = 0; k <= P; ++k) acc = fma(wy[k], A[(oy + k) * AS + tx], acc);
+            ring[((rnext - r0) % RZ) * GNT + tid] = acc;
+        }
+        S acc = 0;
+#pragma unroll
+        for (int k = 0; k <= P; ++k)
+            acc = fma(wzt[zo * (P + 1) + k], ring[((s + k - r0) % RZ) * GNT + tid], acc);
+        if (own) dst[static_cast<int64_t>(zo) * NP + oxy] = acc;
+    }
+}
+
+size_t graded_smem_bytes(int p, int wxm, int wym, size_t elem)
+{
+    return (static_cast<size_t>(wym) * wxm + static_cast<size_t>(wym) * (GTX + 1) +
+            static_cast<size_t>(p + 1) * GNT) * elem;
+}
+
+// largest source window of a 32 x 8 tile along an axis (tile extent T)
+int graded_window(const int32_t *src, int N, int p, int T)
+{
+    int w = 0;
+    for (int t0 = 0; t0 < N; t0 += T) w = std::max(w, src[std::min(t0 + T, N) - 1] - src[t0] + p + 1);
+    return w;
+}
+
+int graded_tile_x() { return GTX; }
+int graded_tile_y() { return GTY; }
+
+template <typename S, int P>
+static hipError_t launch_g(const Geometry &g, const NodeTables<S> &t, const S *in, S *out, hipStream_t st)
+{
+    const int ntx = (g.N[0] + GTX - 1) / GTX, nty = (g.N[1] + GTY - 1) / GTY;
+    const int ntiles = ntx * nty;
+    // split the z-march into chunks (each re-reads p source rows) until the
+    // grid has a few blocks per CU slot
+    int nchunk = 1;
+    while (static_cast<int64_t>(ntiles) * 90 * nchunk < GRADED_TARGET_BLOCKS && g.N[2] / (2 * nchunk) >= 4 * P)
+        nchunk *= 2;
+    const int zrows = (g.N[2] + nchunk - 1) / nchunk;
+    nchunk = (g.N[2] + zrows - 1) / zrows;
+    const int64_t nb = static_cast<int64_t>(ntiles) * 90 * nchunk;
+    if (nb > (int64_t(1) << 31) - 1) return hipErrorInvalidValue;
+    const size_t smem = graded_smem_bytes(P, t.wxm, t.wym, sizeof(S));
+    if (smem > 160 * 1024) return hipErrorInvalidValue;
+    if (smem > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_stream_graded<S, P>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(smem));
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((k_stream_graded<S, P>), dim3(static_cast<unsigned>(nb)), dim3(GNT), smem, st, g, t, in, out,
+                       ntx, ntiles, zrows, nchunk);
+    return hipGetLastError();
+}
+
+template <typename S>
+hipError_t launch_stream_graded(const Geometry &g, const NodeTables<S> &t, const S *in, S *out, hipStream_t st)
+{
+    switch (g.p) {
+    case 1: return launch_g<S, 1>(g, t, in, out, st);
+    case 2: return launch_g<S, 2>(g, t, in, out, st);
+    case 3: return launch_g<S, 3>(g, t, in, out, st);
+    case 4: return launch_g<S, 4>(g, t, in, out, st);
+    case 5: return launch_g<S, 5>(g, t, in, out, st);
+    case 6: return launch_g<S, 6>(g, t, in, out, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template hipError_t launch_stream_graded<double>(const Geometry &, const NodeTables<double> &, const double *,
+                                                 double *, hipStream_t);
+template hipError_t launch_stream_graded<float>(const Geometry &, const NodeTables<float> &, const float *, float *,
+                                                hipStream_t);
+
+}  // namespace sllbm

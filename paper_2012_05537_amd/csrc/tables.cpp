@@ -112,4 +112,53 @@ void build_cell_tables(const VelocitySet &vs, int p, const double h[3], double d
     }
 }
 
+double axis_node_position(int p, int ne, double length, const std::vector<double> &faces, int g)
+{
+    const int e = g / p, l = g % p;
+    if (faces.empty()) {
+        const double h = length / ne;
+        return e * h + h * 0.5 * (1.0 - std::cos(M_PI * l / p));
+    }
+    return faces[e] + (faces[e + 1] - faces[e]) * 0.5 * (1.0 - std::cos(M_PI * l / p));
+}
+
+void build_node_tables(const VelocitySet &vs, int p, int ne, double length, const std::vector<double> &faces,
+                       int axis, double dt, std::vector<int32_t> &src, std::vector<double> &w)
+{
+    const int N = ne * p;
+    src.assign(static_cast<size_t>(Q) * N, 0);
+    w.assign(static_cast<size_t>(Q) * N * (p + 1), 0.0);
+    for (int i = 0; i < Q; ++i) {
+        const double shift = vs.xi[i][axis] * dt;
+        for (int g = 0; g < N; ++g) {
+            const double X = axis_node_position(p, ne, length, faces, g) - shift;   // departure point
+            int64_t E;                                // departure cell, not wrapped (monotone in g)
+            double t;                                 // local coordinate in [0, 1)
+            if (faces.empty()) {
+                const double sc = X / (length / ne);
+                const double fl = std::floor(sc);
+                E = static_cast<int64_t>(fl);
+                t = sc - fl;
+            } else {
+                double k = std::floor(X / length);
+                double Xw = X - k * length;
+                if (Xw >= length) {                   // rounding of the wrap
+                    Xw = 0.0;
+                    k += 1.0;
+                }
+                int lo = 0, hi = ne;                  // faces[lo] <= Xw < faces[hi]
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) / 2;
+                    if (faces[mid] <= Xw) lo = mid;
+                    else hi = mid;
+                }
+                E = lo + static_cast<int64_t>(k) * ne;
+                t = (Xw - faces[lo]) / (faces[lo + 1] - faces[lo]);
+            }
+            src[static_cast<size_t>(i) * N + g] = static_cast<int32_t>(E * p);
+            lagrange_basis(p, t, &w[(static_cast<size_t>(i) * N + g) * (p + 1)]);
+        }
+    }
+}
+
 }  // namespace sllbm

@@ -40,6 +40,20 @@ WORKLOADS = {
 }
 
 
+# Graded-mesh variant of the 64^3-node workload: the cells of every axis are
+# stretched by a cosine profile (largest / smallest width close to
+# (1 + a)/(1 - a) = 1.86 at a = 0.3), finest near the domain faces,
+# coarsest in the middle.
+GRADED = dict(base="c2", amplitude=0.3)
+
+
+def graded_widths(n, length=2 * math.pi, amplitude=0.3):
+    """n cell widths w_e proportional to 1 - a cos(2 pi (e + 1/2) / n), summing to length."""
+    e = np.arange(n)
+    w = 1.0 - amplitude * np.cos(2 * math.pi * (e + 0.5) / n)
+    return w * (length / w.sum())
+
+
 def velocity_scale(Ma, gamma):
     """U = Ma * adiabatic sound speed sqrt(gamma T0)."""
     return Ma * math.sqrt(gamma * T0)

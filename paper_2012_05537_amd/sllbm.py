@@ -56,6 +56,7 @@ _SIGS = {
     "sllbm_velocity_set": (ctypes.c_int, [_VP, _VP]),
     "sllbm_node_coords": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
     "sllbm_set_viscosity": (ctypes.c_int, [_VP, ctypes.c_double]),
+    "sllbm_set_mesh": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
     "sllbm_init_equilibrium": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
     "sllbm_set_state": (ctypes.c_int, [_VP, _VP]),
     "sllbm_get_state": (ctypes.c_int, [_VP, _VP]),
@@ -187,6 +188,23 @@ class SLLBM:
     def set_viscosity(self, mu_inf):
         self._check(self._lib.sllbm_set_viscosity(self._h, float(mu_inf)))
         self.cfg.mu_inf = float(mu_inf)
+
+    def set_mesh(self, widths_x=None, widths_y=None, widths_z=None):
+        """Graded mesh: per axis None (equal cells) or the n_el[a] cell widths."""
+        arrs = []
+        for a, w in enumerate((widths_x, widths_y, widths_z)):
+            if w is None:
+                arrs.append(None)
+                continue
+            v = [float(x) for x in (w.tolist() if hasattr(w, "tolist") else w)]
+            if len(v) != self.cfg.n_el[a]:
+                raise ValueError("axis %d needs %d cell widths" % (a, self.cfg.n_el[a]))
+            arrs.append((ctypes.c_double * len(v))(*v))
+        self._sync_stream()
+        self._check(self._lib.sllbm_set_mesh(self._h, *[None if x is None else ctypes.addressof(x) for x in arrs]))
+        for a, x in enumerate(arrs):
+            if x is not None:
+                self.cfg.length[a] = float(sum(x))
 
     def init_equilibrium(self, rho, u, T):
         self._sync_stream()
