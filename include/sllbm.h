@@ -119,8 +119,9 @@ int sllbm_set_viscosity(sllbm_ctx *ctx, double mu_inf);
  * _totals and _node_coords use the graded mesh; transposed streaming,
  * sllbm_adjoint_step, _loss, _loss_grad and _diagnostics return EINVAL.
  * Synchronises the context's stream.  On failure the previous mesh stays.
- * Errors: EINVAL (NULL widths, non-positive width, or a source window of a
- * 32 x 8 tile larger than the 160 KB of LDS), ENOMEM, EDEVICE. */
+ * Errors: EINVAL (no widths, a non-positive width, or a grading so strong
+ * that the source window of a 32 x 8 tile exceeds 4096 nodes or the 160 KB
+ * of LDS), ENOMEM, EDEVICE. */
 int sllbm_set_mesh(sllbm_ctx *ctx, const double *widths_x, const double *widths_y, const double *widths_z);
 
 /* State := equilibrium of the given fields (Eq. (6); g^eq = (2C_v - D) T f^eq).

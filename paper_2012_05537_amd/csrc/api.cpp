@@ -204,6 +204,10 @@ int upload_graded(sllbm_ctx *c)
     c->gwxm = wmax[0];
     c->gwym = wmax[1];
     const size_t smem = graded_smem_bytes(p, c->gwxm, c->gwym, sizeof(S));
+    if (c->gwxm * c->gwym > graded_max_window())
+        return fail(c, SLLBM_EINVAL, "graded mesh: the source window of a tile has " +
+                                         std::to_string(c->gwxm * c->gwym) + " nodes (more than " +
+                                         std::to_string(graded_max_window()) + "); the grading is too strong");
     if (smem > 160 * 1024)
         return fail(c, SLLBM_EINVAL, "graded mesh: the source window of a tile needs " + std::to_string(smem) +
                                          " bytes of LDS (more than 160 KB); the grading is too strong");

@@ -140,6 +140,7 @@ hipError_t launch_stream_graded(const Geometry &g, const NodeTables<S> &t, const
 size_t graded_smem_bytes(int p, int wxm, int wym, size_t elem);
 int graded_window(const int32_t *src, int N, int p, int T);
 int graded_tile_x();
+int graded_max_window();                 // largest tile window (elements) the graded kernel takes
 int graded_tile_y();
 
 }  // namespace sllbm

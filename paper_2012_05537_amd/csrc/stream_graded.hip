@@ -10,9 +10,10 @@
 //
 // A block owns one (velocity, population) plane over a 32 x 8 x-y tile and a
 // range of output z-rows.  It walks the source z-rows in order; for each it
-// loads the tile's window into LDS, interpolates along x (per-thread taps)
-// and then along y, and keeps the result in a per-thread ring of the last
-// p + 1 source rows, from which each output z-row takes its p + 1 taps.
+// stores the tile's window (loaded into registers while the previous row was
+// processed) in LDS, interpolates along x (per-thread taps) and then along y,
+// and keeps the result in a per-thread ring of the last p + 1 source rows,
+// from which each output z-row takes its p + 1 taps.
 // Every source row is read once per plane and tile column of the chunk.
 #include <hip/hip_runtime.h>
 
@@ -42,7 +43,7 @@ constexpr int64_t GRADED_TARGET_BLOCKS = 2048;
 
 }  // namespace
 
-template <typename S, int P>
+template <typename S, int P, int LK>
 __global__ void __launch_bounds__(GNT) k_stream_graded(Geometry g, NodeTables<S> tab, const S *__restrict__ in,
                                                         S *__restrict__ out, int ntile_x, int ntiles, int zrows,
                                                         int nchunk)
@@ -76,7 +77,16 @@ __global__ void __launch_bounds__(GNT) k_stream_graded(Geometry g, NodeTables<S>
     // source window of the tile (first source nodes are non-decreasing)
     const int xs0 = sx[X0], wxb = sx[min(X0 + GTX, Nx) - 1] - xs0 + P + 1;
     const int ys0 = sy[Y0], wyb = sy[min(Y0 + GTY, Ny) - 1] - ys0 + P + 1;
-    const int nwin = wxb * wyb;
+    const int nwin = wxb * wyb;                            // <= LK * GNT (checked by the launcher)
+    // this thread's window elements: offset inside a z-plane and in LDS
+    int loff[LK], soff[LK];
+#pragma unroll
+    for (int k = 0; k < LK; ++k) {
+        const int e = min(tid + k * GNT, nwin - 1);
+        const int wy_ = e / wxb, wx_ = e - wy_ * wxb;
+        loff[k] = wrapg(ys0 + wy_, Ny) * Nx + wrapg(xs0 + wx_, Nx);
+        soff[k] = wy_ * wxm + wx_;
+    }
 
     // taps of this thread's output column (clamped on ragged tiles, not stored)
     const int tx = tid % GTX, ty = tid / GTX;
@@ -93,17 +103,23 @@ __global__ void __launch_bounds__(GNT) k_stream_graded(Geometry g, NodeTables<S>
 
     const int zo0 = chunk * zrows, zo1 = min(Nz, zo0 + zrows);
     const int r0 = sz[zo0];                                // first source row of the chunk (not wrapped)
+    // the window of source row r goes to registers one row ahead of its use
+    S raw[LK];
+    auto load_row = [&](int r) {
+        const S *base = src + static_cast<int64_t>(wrapg(r, Nz)) * NP;
+#pragma unroll
+        for (int k = 0; k < LK; ++k) raw[k] = base[loff[k]];
+    };
+    load_row(r0);
     int rnext = r0;
     for (int zo = zo0; zo < zo1; ++zo) {
         const int s = sz[zo];
         // bring in source rows up to s + P (rows below s are no longer needed)
         for (; rnext <= s + P; ++rnext) {
-            const int64_t zoff = static_cast<int64_t>(wrapg(rnext, Nz)) * NP;
-            for (int e = tid; e < nwin; e += GNT) {
-                const int wy_ = e / wxb, wx_ = e - wy_ * wxb;
-                pl[wy_ * wxm + wx_] =
-                    src[zoff + static_cast<int64_t>(wrapg(ys0 + wy_, Ny)) * Nx + wrapg(xs0 + wx_, Nx)];
-            }
+#pragma unroll
+            for (int k = 0; k < LK; ++k)
+                if (tid + k * GNT < nwin) pl[soff[k]] = raw[k];
+            load_row(rnext + 1);                           // in bounds (wrapped); unused past the chunk
             __syncthreads();
             for (int wy_ = ty; wy_ < wyb; wy_ += GTY) {
                 S acc = 0;
@@ -140,10 +156,11 @@ int graded_window(const int32_t *src, int N, int p, int T)
 }
 
 int graded_tile_x() { return GTX; }
+int graded_max_window() { return 16 * GNT; }
 int graded_tile_y() { return GTY; }
 
-template <typename S, int P>
-static hipError_t launch_g(const Geometry &g, const NodeTables<S> &t, const S *in, S *out, hipStream_t st)
+template <typename S, int P, int LK>
+static hipError_t launch_gk(const Geometry &g, const NodeTables<S> &t, const S *in, S *out, hipStream_t st)
 {
     const int ntx = (g.N[0] + GTX - 1) / GTX, nty = (g.N[1] + GTY - 1) / GTY;
     const int ntiles = ntx * nty;
@@ -159,13 +176,25 @@ static hipError_t launch_g(const Geometry &g, const NodeTables<S> &t, const S *i
     const size_t smem = graded_smem_bytes(P, t.wxm, t.wym, sizeof(S));
     if (smem > 160 * 1024) return hipErrorInvalidValue;
     if (smem > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_stream_graded<S, P>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_stream_graded<S, P, LK>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(smem));
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((k_stream_graded<S, P>), dim3(static_cast<unsigned>(nb)), dim3(GNT), smem, st, g, t, in, out,
-                       ntx, ntiles, zrows, nchunk);
+    hipLaunchKernelGGL((k_stream_graded<S, P, LK>), dim3(static_cast<unsigned>(nb)), dim3(GNT), smem, st, g, t, in,
+                       out, ntx, ntiles, zrows, nchunk);
     return hipGetLastError();
+}
+
+// window loads per thread: the smallest LK with LK * 256 >= the largest window
+template <typename S, int P>
+static hipError_t launch_g(const Geometry &g, const NodeTables<S> &t, const S *in, S *out, hipStream_t st)
+{
+    const int nw = t.wxm * t.wym;
+    if (nw <= 2 * GNT) return launch_gk<S, P, 2>(g, t, in, out, st);
+    if (nw <= 4 * GNT) return launch_gk<S, P, 4>(g, t, in, out, st);
+    if (nw <= 8 * GNT) return launch_gk<S, P, 8>(g, t, in, out, st);
+    if (nw <= 16 * GNT) return launch_gk<S, P, 16>(g, t, in, out, st);
+    return hipErrorInvalidValue;
 }
 
 template <typename S>
