@@ -9,11 +9,11 @@
 // tile is one contiguous (wrapped) range per axis.
 //
 // A block owns one (velocity, population) plane over a 32 x 8 x-y tile and a
-// range of output z-rows.  It walks the source z-rows in order; for each it
-// stores the tile's window (loaded into registers while the previous row was
-// processed) in LDS, interpolates along x (per-thread taps) and then along y,
-// and keeps the result in a per-thread ring of the last p + 1 source rows,
-// from which each output z-row takes its p + 1 taps.
+// range of output z-rows.  It walks the source z-rows in order, two at a
+// time: it stores their tile windows (loaded into registers while the
+// previous two rows were processed) in LDS, interpolates along x (per-thread
+// taps) and then along y, and keeps the results in a per-thread ring of
+// source rows, from which each output z-row takes its p + 1 taps.
 // Every source row is read once per plane and tile column of the chunk.
 #include <hip/hip_runtime.h>
 
@@ -39,6 +39,7 @@ __device__ __forceinline__ int xcd_order(int b, int nb)
 }
 
 constexpr int GTX = 32, GTY = 8, GNT = GTX * GTY;
+constexpr int GRB = 2;                         // source z-rows interpolated per batch
 constexpr int64_t GRADED_TARGET_BLOCKS = 2048;
 
 }  // namespace
@@ -48,13 +49,15 @@ __global__ void __launch_bounds__(GNT) k_stream_graded(Geometry g, NodeTables<S>
                                                         S *__restrict__ out, int ntile_x, int ntiles, int zrows,
                                                         int nchunk)
 {
-    constexpr int RZ = P + 1;                              // ring of source rows per thread
+    constexpr int RB = GRB;                                // source rows per batch (two barriers each)
+    constexpr int RZ = P + RB;                             // ring of source rows per thread
     constexpr int AS = GTX + 1;                            // odd row stride of the x-pass result
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int wxm = tab.wxm, wym = tab.wym;
-    S *pl = reinterpret_cast<S *>(smem_raw);               // [wym][wxm] source window of one z-row
-    S *A = pl + wym * wxm;                                 // [wym][AS]  x-interpolated rows
-    S *ring = A + wym * AS;                                // [RZ][GNT]  x-y interpolated source rows
+    const int WP = wym * wxm, AP = wym * AS;
+    S *pl = reinterpret_cast<S *>(smem_raw);               // [RB][wym][wxm] source windows of a batch
+    S *A = pl + RB * WP;                                   // [RB][wym][AS] x-interpolated rows
+    S *ring = A + RB * AP;                                 // [RZ][GNT]     x-y interpolated source rows
 
     const int tid = threadIdx.x;
     const int L = __builtin_amdgcn_readfirstlane(xcd_order(blockIdx.x, gridDim.x));
@@ -103,35 +106,47 @@ __global__ void __launch_bounds__(GNT) k_stream_graded(Geometry g, NodeTables<S>
 
     const int zo0 = chunk * zrows, zo1 = min(Nz, zo0 + zrows);
     const int r0 = sz[zo0];                                // first source row of the chunk (not wrapped)
-    // the window of source row r goes to registers one row ahead of its use
-    S raw[LK];
-    auto load_row = [&](int r) {
-        const S *base = src + static_cast<int64_t>(wrapg(r, Nz)) * NP;
+    // the windows of the next batch of source rows are loaded into registers
+    // while the current batch is interpolated
+    S raw[RB][LK];
+    auto load_batch = [&](int r) {
 #pragma unroll
-        for (int k = 0; k < LK; ++k) raw[k] = base[loff[k]];
+        for (int b = 0; b < RB; ++b) {
+            const S *base = src + static_cast<int64_t>(wrapg(r + b, Nz)) * NP;
+#pragma unroll
+            for (int k = 0; k < LK; ++k) raw[b][k] = base[loff[k]];
+        }
     };
-    load_row(r0);
-    int rnext = r0;
+    load_batch(r0);
+    int rnext = r0;                                        // first source row not yet in the ring
     for (int zo = zo0; zo < zo1; ++zo) {
         const int s = sz[zo];
-        // bring in source rows up to s + P (rows below s are no longer needed)
-        for (; rnext <= s + P; ++rnext) {
+        // bring in batches until row s + P is in the ring; the ring then holds
+        // rows s .. s + P (older rows are no longer needed)
+        for (; rnext <= s + P; rnext += RB) {
 #pragma unroll
-            for (int k = 0; k < LK; ++k)
-                if (tid + k * GNT < nwin) pl[soff[k]] = raw[k];
-            load_row(rnext + 1);                           // in bounds (wrapped); unused past the chunk
+            for (int b = 0; b < RB; ++b)
+#pragma unroll
+                for (int k = 0; k < LK; ++k)
+                    if (tid + k * GNT < nwin) pl[b * WP + soff[k]] = raw[b][k];
+            load_batch(rnext + RB);                        // in bounds (wrapped); unused past the chunk
             __syncthreads();
-            for (int wy_ = ty; wy_ < wyb; wy_ += GTY) {
+#pragma unroll
+            for (int b = 0; b < RB; ++b)
+                for (int wy_ = ty; wy_ < wyb; wy_ += GTY) {
+                    S acc = 0;
+#pragma unroll
+                    for (int k = 0; k <= P; ++k) acc = fma(wx[k], pl[b * WP + wy_ * wxm + ox + k], acc);
+                    A[b * AP + wy_ * AS + tx] = acc;
+                }
+            __syncthreads();
+#pragma unroll
+            for (int b = 0; b < RB; ++b) {
                 S acc = 0;
 #pragma unroll
-                for (int k = 0; k <= P; ++k) acc = fma(wx[k], pl[wy_ * wxm + ox + k], acc);
-                A[wy_ * AS + tx] = acc;
+                for (int k = 0; k <= P; ++k) acc = fma(wy[k], A[b * AP + (oy + k) * AS + tx], acc);
+                ring[((rnext + b - r0) % RZ) * GNT + tid] = acc;
             }
-            __syncthreads();
-            S acc = 0;
-#pragma unroll
-            for (int k = 0; k <= P; ++k) acc = fma(wy[k], A[(oy + k) * AS + tx], acc);
-            ring[((rnext - r0) % RZ) * GNT + tid] = acc;
         }
         S acc = 0;
 #pragma unroll
@@ -143,8 +158,8 @@ __global__ void __launch_bounds__(GNT) k_stream_graded(Geometry g, NodeTables<S>
 
 size_t graded_smem_bytes(int p, int wxm, int wym, size_t elem)
 {
-    return (static_cast<size_t>(wym) * wxm + static_cast<size_t>(wym) * (GTX + 1) +
-            static_cast<size_t>(p + 1) * GNT) * elem;
+    return (GRB * (static_cast<size_t>(wym) * wxm + static_cast<size_t>(wym) * (GTX + 1)) +
+            static_cast<size_t>(p + GRB) * GNT) * elem;
 }
 
 // largest source window of a 32 x 8 tile along an axis (tile extent T)
