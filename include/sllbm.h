@@ -114,14 +114,15 @@ int sllbm_set_viscosity(sllbm_ctx *ctx, double mu_inf);
  * cells on that axis (at least one must be given); a given axis gets length
  * sum(widths_a), node g = e*order + l of it sits at F_e + w_e t_l (F_e =
  * w_0 + ... + w_{e-1}).  The departure cell of every (node, velocity, axis)
- * is located once here and per-node tables are uploaded; the state is kept.
- * Afterwards sllbm_stream, _step, _step_record, _collide, _moments,
- * _totals and _node_coords use the graded mesh; transposed streaming,
- * sllbm_adjoint_step, _loss, _loss_grad and _diagnostics return EINVAL.
- * Synchronises the context's stream.  On failure the previous mesh stays.
+ * is located once here and per-node tables (and their transposes, for S^T)
+ * are uploaded; the state is kept.  Afterwards every call uses the graded
+ * mesh (streaming in both directions, steps, adjoint steps; totals, loss,
+ * loss gradient and diagnostics with each cell's own width).  Synchronises
+ * the context's stream.  On failure the previous mesh stays.
  * Errors: EINVAL (no widths, a non-positive width, or a grading so strong
  * that the source window of a 32 x 8 tile exceeds 4096 nodes or the 160 KB
- * of LDS), ENOMEM, EDEVICE. */
+ * of LDS, or that one node is read by more than 24 nodes of an axis),
+ * ENOMEM, EDEVICE. */
 int sllbm_set_mesh(sllbm_ctx *ctx, const double *widths_x, const double *widths_y, const double *widths_z);
 
 /* State := equilibrium of the given fields (Eq. (6); g^eq = (2C_v - D) T f^eq).

@@ -281,13 +281,7 @@ def is_graded(cfg):
     return any(getattr(cfg, "_faces", [None] * 3)[a] is not None for a in range(3))
 
 
-def _equal_cells_only(cfg, what):
-    if is_graded(cfg):
-        raise NotImplementedError(what + ": equal cells only")
-
-
 def loss(cfg, f, g):
-    _equal_cells_only(cfg, "loss")
     cplx = _is_cplx(f, g)
     f = np.ascontiguousarray(f, dtype=_dt(cplx))
     g = np.ascontiguousarray(g, dtype=_dt(cplx))
@@ -300,7 +294,6 @@ def loss(cfg, f, g):
     return fn(ctypes.byref(cfg), _ptr(f), _ptr(g))
 
 def diagnostics(cfg, f, g):
-    _equal_cells_only(cfg, "diagnostics")
     """(kinetic energy, solenoidal dissipation, dilatational dissipation) as domain integrals."""
     cplx = _is_cplx(f, g) or cfg.mu_inf_im != 0.0
     dt = _dt(cplx)

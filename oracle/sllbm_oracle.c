@@ -222,6 +222,12 @@ static double face_of(const oracle_cfg *c, int a, int e)
     return c->faces[a] ? c->faces[a][e] : e * (c->length[a] / c->n_el[a]);
 }
 
+/* width of cell e along axis a (L / n_el on equal cells) */
+static double cell_width(const oracle_cfg *c, int a, int e)
+{
+    return c->faces[a] ? c->faces[a][e + 1] - c->faces[a][e] : c->length[a] / c->n_el[a];
+}
+
 static double axis_node_pos(const oracle_cfg *c, int a, int g)
 {
     int p = c->p;
@@ -643,8 +649,8 @@ void FN(totals)(const oracle_cfg *c, const R *f, const R *g, R *out)
  *   L = sum over cells of the tensor Clenshaw-Curtis quadrature of
  *       (1/2) rho |u|^2 + (div u)^2,
  * with div u from the derivative of each cell's own interpolation polynomial
- * (so it is discontinuous across cell faces, as in Sec. III C).  Equal cells
- * only (the wrapper refuses a graded mesh). */
+ * (so it is discontinuous across cell faces, as in Sec. III C); on a graded
+ * mesh each cell uses its own width. */
 R FN(loss)(const oracle_cfg *c, const R *f, const R *g)
 {
     int p = c->p;
@@ -660,11 +666,11 @@ R FN(loss)(const oracle_cfg *c, const R *f, const R *g)
         oracle_lagrange_deriv(p, t[k], dl);
         for (int m = 0; m <= p; ++m) Dm[k][m] = dl[m];     /* d l_m / ds at s = t_k */
     }
-    double h[3] = {c->length[0] / c->n_el[0], c->length[1] / c->n_el[1], c->length[2] / c->n_el[2]};
     R L = 0;
     for (int ez = 0; ez < c->n_el[2]; ++ez)
         for (int ey = 0; ey < c->n_el[1]; ++ey)
-            for (int ex = 0; ex < c->n_el[0]; ++ex)
+            for (int ex = 0; ex < c->n_el[0]; ++ex) {
+                double h[3] = {cell_width(c, 0, ex), cell_width(c, 1, ey), cell_width(c, 2, ez)};
                 for (int kz = 0; kz <= p; ++kz)
                     for (int ky = 0; ky <= p; ++ky)
                         for (int kx = 0; kx <= p; ++kx) {
@@ -688,6 +694,7 @@ R FN(loss)(const oracle_cfg *c, const R *f, const R *g)
                             double W = (0.5 * h[0] * wcc[kx]) * (0.5 * h[1] * wcc[ky]) * (0.5 * h[2] * wcc[kz]);
                             L += W * (0.5 * rho[n] * ke + div * div);
                         }
+            }
     free(rho); free(u); free(T);
     return L;
 }
@@ -698,8 +705,8 @@ R FN(loss)(const oracle_cfg *c, const R *f, const R *g)
  *   out[0] = kinetic energy        int (1/2) rho |u|^2
  *   out[1] = solenoidal dissipation int mu(T) |curl u|^2
  *   out[2] = dilatational dissipation (4/3) int mu(T) (div u)^2
- * (the paper's 1/(rho_ref Re) prefactor is the mu_inf inside mu(T)).
- * Equal cells only (the wrapper refuses a graded mesh). */
+ * (the paper's 1/(rho_ref Re) prefactor is the mu_inf inside mu(T)); on a
+ * graded mesh each cell uses its own width. */
 void FN(diagnostics)(const oracle_cfg *c, const R *f, const R *g, R *out)
 {
     int p = c->p;
@@ -715,11 +722,11 @@ void FN(diagnostics)(const oracle_cfg *c, const R *f, const R *g, R *out)
         oracle_lagrange_deriv(p, t[k], dl);
         for (int m = 0; m <= p; ++m) Dm[k][m] = dl[m];
     }
-    double h[3] = {c->length[0] / c->n_el[0], c->length[1] / c->n_el[1], c->length[2] / c->n_el[2]};
     R ek = 0, es = 0, ec = 0;
     for (int ez = 0; ez < c->n_el[2]; ++ez)
         for (int ey = 0; ey < c->n_el[1]; ++ey)
-            for (int ex = 0; ex < c->n_el[0]; ++ex)
+            for (int ex = 0; ex < c->n_el[0]; ++ex) {
+                double h[3] = {cell_width(c, 0, ex), cell_width(c, 1, ey), cell_width(c, 2, ez)};
                 for (int kz = 0; kz <= p; ++kz)
                     for (int ky = 0; ky <= p; ++ky)
                         for (int kx = 0; kx <= p; ++kx) {
@@ -748,6 +755,7 @@ void FN(diagnostics)(const oracle_cfg *c, const R *f, const R *g, R *out)
                             es += W * mu * (w0 * w0 + w1 * w1 + w2 * w2);
                             ec += W * (4.0 / 3.0) * mu * div * div;
                         }
+            }
     out[0] = ek;
     out[1] = es;
     out[2] = ec;

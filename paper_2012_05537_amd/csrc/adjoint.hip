@@ -4,9 +4,9 @@
 // the node-local collision (Eq. (5) with App. D) and S the semi-Lagrangian
 // streaming (Eq. (9)), which is linear.  Its vector-Jacobian product is
 //   lambda_n = J_C(X_n)^T S^T lambda_{n+1}.
-// S^T is the transposed z-march of the streaming (stream.hip); this file holds the collision VJP, the VJP of the equilibrium
-// initialisation, and the flow functional used for gradients with its
-// derivative.  All reverse arithmetic is in double; states are stored in the
+// S^T is the transposed streaming (stream.hip, stream_graded.hip); this file
+// holds the collision VJP, the VJP of the equilibrium initialisation, and the
+// flow functional used for gradients with its derivative.  All reverse arithmetic is in double; states are stored in the
 // context's storage type.
 //
 // Collision VJP (per node, f on the even lane of a pair, g on the odd lane).
@@ -452,8 +452,17 @@ __global__ void __launch_bounds__(256) k_rho_u(int64_t N, const S *__restrict__ 
 struct CellGeo {
     int N[3], nel[3], p;
     int64_t nodes;
-    double h[3];
+    double h[3];                 // cell width per axis (equal cells)
+    const double *hw;            // graded mesh: widths of the x, then y, then z cells (NULL: equal cells)
 };
+
+// width of cell e along axis a
+__device__ __forceinline__ double cell_h(const CellGeo &g, int a, int e)
+{
+    if (!g.hw) return g.h[a];
+    const int off = a == 0 ? 0 : (a == 1 ? g.nel[0] : g.nel[0] + g.nel[1]);
+    return g.hw[off + e];
+}
 
 __device__ __forceinline__ int64_t node_of(const CellGeo &g, int gx, int gy, int gz)
 {
@@ -483,15 +492,16 @@ __global__ void __launch_bounds__(256) k_loss_cells(CellGeo g, const double *__r
         const int ey = static_cast<int>(r % g.nel[1]);
         const int ez = static_cast<int>(r / g.nel[1]);
         const int gx = ex * p + kx, gy = ey * p + ky, gz = ez * p + kz;
+        const double hx = cell_h(g, 0, ex), hy = cell_h(g, 1, ey), hz = cell_h(g, 2, ez);
         double div = 0.0;
         for (int m = 0; m <= p; ++m) {
-            div += dmat[kx * p1 + m] * u[node_of(g, ex * p + m, gy, gz)] / g.h[0];
-            div += dmat[ky * p1 + m] * u[g.nodes + node_of(g, gx, ey * p + m, gz)] / g.h[1];
-            div += dmat[kz * p1 + m] * u[2 * g.nodes + node_of(g, gx, gy, ez * p + m)] / g.h[2];
+            div += dmat[kx * p1 + m] * u[node_of(g, ex * p + m, gy, gz)] / hx;
+            div += dmat[ky * p1 + m] * u[g.nodes + node_of(g, gx, ey * p + m, gz)] / hy;
+            div += dmat[kz * p1 + m] * u[2 * g.nodes + node_of(g, gx, gy, ez * p + m)] / hz;
         }
         const int64_t n = node_of(g, gx, gy, gz);
         const double ux = u[n], uy = u[g.nodes + n], uz = u[2 * g.nodes + n];
-        const double W = (0.5 * g.h[0] * ccw[kx]) * (0.5 * g.h[1] * ccw[ky]) * (0.5 * g.h[2] * ccw[kz]);
+        const double W = (0.5 * hx * ccw[kx]) * (0.5 * hy * ccw[ky]) * (0.5 * hz * ccw[kz]);
         acc += W * (0.5 * rho[n] * (ux * ux + uy * uy + uz * uz) + div * div);
         if (sdiv) sdiv[c] = 2.0 * W * div;
     }
@@ -527,6 +537,7 @@ __global__ void __launch_bounds__(256) k_diag_cells(CellGeo g, CollisionParams c
         e[1] = static_cast<int>(r % g.nel[1]);
         e[2] = static_cast<int>(r / g.nel[1]);
         const int gx = e[0] * p + k[0], gy = e[1] * p + k[1], gz = e[2] * p + k[2];
+        const double hx = cell_h(g, 0, e[0]), hy = cell_h(g, 1, e[1]), hz = cell_h(g, 2, e[2]);
         double grad[3][3];                       // grad[a][b] = d u_a / d x_b
         for (int a = 0; a < 3; ++a)
             for (int b = 0; b < 3; ++b) grad[a][b] = 0.0;
@@ -534,8 +545,8 @@ __global__ void __launch_bounds__(256) k_diag_cells(CellGeo g, CollisionParams c
             const int64_t nx = node_of(g, e[0] * p + m, gy, gz);
             const int64_t ny = node_of(g, gx, e[1] * p + m, gz);
             const int64_t nz = node_of(g, gx, gy, e[2] * p + m);
-            const double dx = dmat[k[0] * p1 + m] / g.h[0], dy = dmat[k[1] * p1 + m] / g.h[1],
-                         dz = dmat[k[2] * p1 + m] / g.h[2];
+            const double dx = dmat[k[0] * p1 + m] / hx, dy = dmat[k[1] * p1 + m] / hy,
+                         dz = dmat[k[2] * p1 + m] / hz;
             for (int a = 0; a < 3; ++a) {
                 grad[a][0] = fma(dx, u[a * g.nodes + nx], grad[a][0]);
                 grad[a][1] = fma(dy, u[a * g.nodes + ny], grad[a][1]);
@@ -547,7 +558,7 @@ __global__ void __launch_bounds__(256) k_diag_cells(CellGeo g, CollisionParams c
         const double div = grad[0][0] + grad[1][1] + grad[2][2];
         const double ux = u[n], uy = u[g.nodes + n], uz = u[2 * g.nodes + n];
         const double mu = viscosity_of(cp, T[n]);
-        const double W = (0.5 * g.h[0] * ccw[k[0]]) * (0.5 * g.h[1] * ccw[k[1]]) * (0.5 * g.h[2] * ccw[k[2]]);
+        const double W = (0.5 * hx * ccw[k[0]]) * (0.5 * hy * ccw[k[1]]) * (0.5 * hz * ccw[k[2]]);
         acc[0] = fma(W, 0.5 * rho[n] * (ux * ux + uy * uy + uz * uz), acc[0]);
         acc[1] = fma(W, mu * (w0 * w0 + w1 * w1 + w2 * w2), acc[1]);
         acc[2] = fma(W, (4.0 / 3.0) * mu * div * div, acc[2]);
@@ -630,9 +641,9 @@ __global__ void __launch_bounds__(256) k_loss_grad(CellGeo g, const double *__re
                         const int64_t cp = ((static_cast<int64_t>(E[2]) * g.nel[1] + E[1]) * g.nel[0] + E[0]) *
                                                (p1 * p1 * p1) +
                                            (kk[2] * p1 + kk[1]) * p1 + kk[0];
-                        s += sdiv[cp] * dmat[ka * p1 + ck[a][oa]];
+                        s += sdiv[cp] * dmat[ka * p1 + ck[a][oa]] / cell_h(g, a, E[a]);
                     }
-        du[a] = r * uu[a] * W + s / g.h[a];
+        du[a] = r * uu[a] * W + s;
     }
     const double drho = 0.5 * (uu[0] * uu[0] + uu[1] * uu[1] + uu[2] * uu[2]) * W -
                         (du[0] * uu[0] + du[1] * uu[1] + du[2] * uu[2]) / r;
@@ -649,7 +660,7 @@ __global__ void __launch_bounds__(256) k_loss_grad(CellGeo g, const double *__re
 // Launchers
 // ---------------------------------------------------------------------------
 
-static CellGeo cell_geo(const Geometry &g, const double *hh)
+static CellGeo cell_geo(const Geometry &g, const double *hh, const double *hw)
 {
     CellGeo c;
     for (int a = 0; a < 3; ++a) {
@@ -657,6 +668,7 @@ static CellGeo cell_geo(const Geometry &g, const double *hh)
         c.nel[a] = g.nel[a];
         c.h[a] = hh[a];
     }
+    c.hw = hw;
     c.p = g.p;
     c.nodes = g.nodes;
     return c;
@@ -664,14 +676,15 @@ static CellGeo cell_geo(const Geometry &g, const double *hh)
 
 template <typename S>
 hipError_t Launch<S>::loss(const Geometry &g, const S *state, const double *dmat, const double *ccw, const double *h,
-                           double *scratch_rho, double *scratch_u, double *partials, int nblocks, double *out1,
+                           const double *hw, double *scratch_rho, double *scratch_u, double *partials, int nblocks,
+                           double *out1,
                            hipStream_t st)
 {
     const unsigned nb = static_cast<unsigned>((g.nodes + 255) / 256);
     hipLaunchKernelGGL((k_rho_u<S>), dim3(nb), dim3(256), 0, st, g.nodes, state, scratch_rho, scratch_u);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_loss_cells, dim3(nblocks), dim3(256), 0, st, cell_geo(g, h), dmat, ccw, scratch_rho,
+    hipLaunchKernelGGL(k_loss_cells, dim3(nblocks), dim3(256), 0, st, cell_geo(g, h, hw), dmat, ccw, scratch_rho,
                        scratch_u, static_cast<double *>(nullptr), partials);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_accumulate, dim3(1), dim3(256), 0, st, partials, nblocks, out1, 0);
@@ -680,29 +693,31 @@ hipError_t Launch<S>::loss(const Geometry &g, const S *state, const double *dmat
 
 template <typename S>
 hipError_t Launch<S>::loss_grad(const Geometry &g, const S *state, const double *dmat, const double *ccw,
-                                const double *nodew, const double *h, double *scratch_rho, double *scratch_u,
-                                double *scratch_div, double *partials, int nblocks, S *lam, hipStream_t st)
+                                const double *nodew, const double *h, const double *hw, double *scratch_rho,
+                                double *scratch_u, double *scratch_div, double *partials, int nblocks, S *lam,
+                                hipStream_t st)
 {
     const unsigned nb = static_cast<unsigned>((g.nodes + 255) / 256);
     hipLaunchKernelGGL((k_rho_u<S>), dim3(nb), dim3(256), 0, st, g.nodes, state, scratch_rho, scratch_u);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_loss_cells, dim3(nblocks), dim3(256), 0, st, cell_geo(g, h), dmat, ccw, scratch_rho,
+    hipLaunchKernelGGL(k_loss_cells, dim3(nblocks), dim3(256), 0, st, cell_geo(g, h, hw), dmat, ccw, scratch_rho,
                        scratch_u, scratch_div, partials);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL((k_loss_grad<S>), dim3(nb), dim3(256), 0, st, cell_geo(g, h), dmat, nodew, scratch_rho,
+    hipLaunchKernelGGL((k_loss_grad<S>), dim3(nb), dim3(256), 0, st, cell_geo(g, h, hw), dmat, nodew, scratch_rho,
                        scratch_u, scratch_div, lam);
     return hipGetLastError();
 }
 
 template <typename S>
 hipError_t Launch<S>::diagnostics(const Geometry &g, const CollisionParams &cp, const S *state, const double *dmat,
-                                  const double *ccw, const double *h, double *scratch_rho, double *scratch_u,
-                                  double *scratch_T, double *partials, int nblocks, double *out3, hipStream_t st)
+                                  const double *ccw, const double *h, const double *hw, double *scratch_rho,
+                                  double *scratch_u, double *scratch_T, double *partials, int nblocks, double *out3,
+                                  hipStream_t st)
 {
     hipError_t e = moments(g, cp, state, scratch_rho, scratch_u, scratch_T, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_diag_cells, dim3(nblocks), dim3(256), 0, st, cell_geo(g, h), cp, dmat, ccw, scratch_rho,
+    hipLaunchKernelGGL(k_diag_cells, dim3(nblocks), dim3(256), 0, st, cell_geo(g, h, hw), cp, dmat, ccw, scratch_rho,
                        scratch_u, scratch_T, partials);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_sum3, dim3(1), dim3(256), 0, st, partials, nblocks, out3);

@@ -56,9 +56,11 @@ struct sllbm_ctx {
     // cells), per-node departure tables on the device
     bool graded = false;
     std::vector<double> faces[3];
-    int32_t *d_gsrc[3] = {nullptr, nullptr, nullptr};
-    void *d_gw[3] = {nullptr, nullptr, nullptr};
-    int gwxm = 0, gwym = 0;
+    // per direction (0: S, 1: S^T) and axis
+    int32_t *d_gsrc[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
+    void *d_gw[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
+    int gk[2] = {0, 0}, gwxm[2] = {0, 0}, gwym[2] = {0, 0};
+    double *d_hw = nullptr;        // graded cell widths: x cells, then y, then z (loss, diagnostics)
     std::string err;
 };
 
@@ -100,10 +102,12 @@ void free_ctx(sllbm_ctx *c)
     for (int k = 0; k < 2; ++k)
         for (hipEvent_t e : c->ev[k]) (void)hipEventDestroy(e);
     for (int k = 0; k < 2; ++k) (void)hipFree(c->buf[k]);
-    for (int a = 0; a < 3; ++a) {
-        (void)hipFree(c->d_gsrc[a]);
-        (void)hipFree(c->d_gw[a]);
-    }
+    for (int d = 0; d < 2; ++d)
+        for (int a = 0; a < 3; ++a) {
+            (void)hipFree(c->d_gsrc[d][a]);
+            (void)hipFree(c->d_gw[d][a]);
+        }
+    (void)hipFree(c->d_hw);
     (void)hipFree(c->d_omin);
     (void)hipFree(c->d_lstar);
     (void)hipFree(c->d_cw);
@@ -149,19 +153,22 @@ CellTables<S> cell_tables(const sllbm_ctx *c)
 }
 
 template <typename S>
-NodeTables<S> node_tables(const sllbm_ctx *c)
+NodeTables<S> node_tables(const sllbm_ctx *c, int dir)
 {
     NodeTables<S> t{};
     for (int a = 0; a < 3; ++a) {
-        t.src[a] = c->d_gsrc[a];
-        t.w[a] = static_cast<const S *>(c->d_gw[a]);
+        t.src[a] = c->d_gsrc[dir][a];
+        t.w[a] = static_cast<const S *>(c->d_gw[dir][a]);
     }
-    t.wxm = c->gwxm;
-    t.wym = c->gwym;
+    t.k = c->gk[dir];
+    t.wxm = c->gwxm[dir];
+    t.wym = c->gwym[dir];
     return t;
 }
 
 bool is_fp64(const sllbm_ctx *c) { return c->cfg.precision == SLLBM_FP64; }
+
+const double *graded_hw(const sllbm_ctx *c) { return c->graded ? c->d_hw : nullptr; }
 
 void *other(sllbm_ctx *c) { return c->buf[1 - c->cur]; }
 
@@ -171,46 +178,67 @@ int check_launch(sllbm_ctx *c, hipError_t e, const char *what)
 }
 
 // Per-node departure tables of the three axes (graded mesh) in the storage
-// type, their tile windows, and the quadrature weights of the nodes.
+// type, for S and for S^T, their tile windows, and the quadrature weights of
+// the nodes.
 template <typename S>
 int upload_graded(sllbm_ctx *c)
 {
     const Geometry &g = c->geo;
     const int p = g.p;
-    int wmax[2] = {0, 0};
     hipError_t e;
+    std::vector<int32_t> src[2][3];
+    std::vector<double> w[2][3];
+    int band = 1;
     for (int a = 0; a < 3; ++a) {
-        std::vector<int32_t> src;
-        std::vector<double> w;
-        build_node_tables(c->vs, p, g.nel[a], c->cfg.length[a], c->faces[a], a, c->cfg.dt, src, w);
-        if (a < 2) {
-            const int T = a == 0 ? graded_tile_x() : graded_tile_y();
-            for (int i = 0; i < Q; ++i)
-                wmax[a] = std::max(wmax[a], graded_window(&src[static_cast<size_t>(i) * g.N[a]], g.N[a], p, T));
-        }
-        std::vector<S> ws(w.begin(), w.end());
-        (void)hipFree(c->d_gsrc[a]);
-        (void)hipFree(c->d_gw[a]);
-        c->d_gsrc[a] = nullptr;
-        c->d_gw[a] = nullptr;
-        if ((e = dalloc(&c->d_gsrc[a], src.size() * sizeof(int32_t))) != hipSuccess ||
-            (e = dalloc(reinterpret_cast<S **>(&c->d_gw[a]), ws.size() * sizeof(S))) != hipSuccess)
-            return fail(c, SLLBM_ENOMEM, std::string("graded table allocation: ") + hipGetErrorString(e));
-        if ((e = hipMemcpy(c->d_gsrc[a], src.data(), src.size() * sizeof(int32_t), hipMemcpyHostToDevice)) !=
-                hipSuccess ||
-            (e = hipMemcpy(c->d_gw[a], ws.data(), ws.size() * sizeof(S), hipMemcpyHostToDevice)) != hipSuccess)
-            return hip_fail(c, e, "graded table upload");
+        build_node_tables(c->vs, p, g.nel[a], c->cfg.length[a], c->faces[a], a, c->cfg.dt, src[0][a], w[0][a]);
+        int b = 1;
+        build_transposed_node_tables(g.N[a], p, src[0][a], w[0][a], 0, src[1][a], w[1][a], b);
+        band = std::max(band, b);
     }
-    c->gwxm = wmax[0];
-    c->gwym = wmax[1];
-    const size_t smem = graded_smem_bytes(p, c->gwxm, c->gwym, sizeof(S));
-    if (c->gwxm * c->gwym > graded_max_window())
-        return fail(c, SLLBM_EINVAL, "graded mesh: the source window of a tile has " +
-                                         std::to_string(c->gwxm * c->gwym) + " nodes (more than " +
-                                         std::to_string(graded_max_window()) + "); the grading is too strong");
-    if (smem > 160 * 1024)
-        return fail(c, SLLBM_EINVAL, "graded mesh: the source window of a tile needs " + std::to_string(smem) +
-                                         " bytes of LDS (more than 160 KB); the grading is too strong");
+    c->gk[0] = p + 1;
+    c->gk[1] = graded_taps_supported(band);
+    if (c->gk[1] == 0)
+        return fail(c, SLLBM_EINVAL, "graded mesh: an input node is read by " + std::to_string(band) +
+                                         " output nodes of one axis (at most 24 for the transposed streaming); "
+                                         "the grading is too strong");
+    for (int a = 0; a < 3; ++a) {
+        int b = 1;
+        build_transposed_node_tables(g.N[a], p, src[0][a], w[0][a], c->gk[1], src[1][a], w[1][a], b);
+    }
+    for (int d = 0; d < 2; ++d) {
+        int wmax[2] = {0, 0};
+        for (int a = 0; a < 3; ++a) {
+            if (a < 2) {
+                const int T = a == 0 ? graded_tile_x() : graded_tile_y();
+                for (int i = 0; i < Q; ++i)
+                    wmax[a] = std::max(wmax[a], graded_window(&src[d][a][static_cast<size_t>(i) * g.N[a]], g.N[a],
+                                                              c->gk[d], T));
+            }
+            std::vector<S> ws(w[d][a].begin(), w[d][a].end());
+            (void)hipFree(c->d_gsrc[d][a]);
+            (void)hipFree(c->d_gw[d][a]);
+            c->d_gsrc[d][a] = nullptr;
+            c->d_gw[d][a] = nullptr;
+            if ((e = dalloc(&c->d_gsrc[d][a], src[d][a].size() * sizeof(int32_t))) != hipSuccess ||
+                (e = dalloc(reinterpret_cast<S **>(&c->d_gw[d][a]), ws.size() * sizeof(S))) != hipSuccess)
+                return fail(c, SLLBM_ENOMEM, std::string("graded table allocation: ") + hipGetErrorString(e));
+            if ((e = hipMemcpy(c->d_gsrc[d][a], src[d][a].data(), src[d][a].size() * sizeof(int32_t),
+                               hipMemcpyHostToDevice)) != hipSuccess ||
+                (e = hipMemcpy(c->d_gw[d][a], ws.data(), ws.size() * sizeof(S), hipMemcpyHostToDevice)) !=
+                    hipSuccess)
+                return hip_fail(c, e, "graded table upload");
+        }
+        c->gwxm[d] = wmax[0];
+        c->gwym[d] = wmax[1];
+        const size_t smem = graded_smem_bytes(c->gk[d], c->gwxm[d], c->gwym[d], sizeof(S));
+        if (c->gwxm[d] * c->gwym[d] > graded_max_window())
+            return fail(c, SLLBM_EINVAL, "graded mesh: the source window of a tile has " +
+                                             std::to_string(c->gwxm[d] * c->gwym[d]) + " nodes (more than " +
+                                             std::to_string(graded_max_window()) + "); the grading is too strong");
+        if (smem > 160 * 1024)
+            return fail(c, SLLBM_EINVAL, "graded mesh: the source window of a tile needs " + std::to_string(smem) +
+                                             " bytes of LDS (more than 160 KB); the grading is too strong");
+    }
     // node quadrature weights: Clenshaw-Curtis weight of the local point
     // times half the cell width; a cell's first point also carries the last
     // weight of the previous cell (periodic)
@@ -231,6 +259,16 @@ int upload_graded(sllbm_ctx *c)
     if ((e = hipMemcpy(c->d_nodew, nodew.data(), nodew.size() * sizeof(double), hipMemcpyHostToDevice)) !=
         hipSuccess)
         return hip_fail(c, e, "node weight upload");
+    std::vector<double> hw;
+    for (int a = 0; a < 3; ++a)
+        for (int el = 0; el < g.nel[a]; ++el)
+            hw.push_back(c->faces[a].empty() ? c->cfg.length[a] / g.nel[a] : c->faces[a][el + 1] - c->faces[a][el]);
+    (void)hipFree(c->d_hw);
+    c->d_hw = nullptr;
+    if ((e = dalloc(&c->d_hw, hw.size() * sizeof(double))) != hipSuccess)
+        return fail(c, SLLBM_ENOMEM, std::string("cell width allocation: ") + hipGetErrorString(e));
+    if ((e = hipMemcpy(c->d_hw, hw.data(), hw.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_fail(c, e, "cell width upload");
     return SLLBM_OK;
 }
 
@@ -511,9 +549,9 @@ static hipError_t stream_into(sllbm_ctx *c, const void *in, void *out)
 {
     if (c->graded) {
         if (is_fp64(c))
-            return launch_stream_graded<double>(c->geo, node_tables<double>(c), static_cast<const double *>(in),
+            return launch_stream_graded<double>(c->geo, node_tables<double>(c, 0), static_cast<const double *>(in),
                                                 static_cast<double *>(out), c->stream);
-        return launch_stream_graded<float>(c->geo, node_tables<float>(c), static_cast<const float *>(in),
+        return launch_stream_graded<float>(c->geo, node_tables<float>(c, 0), static_cast<const float *>(in),
                                            static_cast<float *>(out), c->stream);
     }
     if (is_fp64(c))
@@ -523,9 +561,17 @@ static hipError_t stream_into(sllbm_ctx *c, const void *in, void *out)
                                   static_cast<float *>(out), c->stream);
 }
 
-// S^T: the transposed z-march
+// S^T: the transposed z-march (equal cells) or the graded march over the
+// transposed per-node tables
 static hipError_t stream_t_into(sllbm_ctx *c, const void *in, void *out)
 {
+    if (c->graded) {
+        if (is_fp64(c))
+            return launch_stream_graded<double>(c->geo, node_tables<double>(c, 1), static_cast<const double *>(in),
+                                                static_cast<double *>(out), c->stream);
+        return launch_stream_graded<float>(c->geo, node_tables<float>(c, 1), static_cast<const float *>(in),
+                                           static_cast<float *>(out), c->stream);
+    }
     if (is_fp64(c))
         return launch_stream_zt<double>(c->geo, cell_tables<double>(c), static_cast<const double *>(in),
                                         static_cast<double *>(out), c->stream);
@@ -677,7 +723,6 @@ int sllbm_stream(sllbm_ctx *ctx, const void *in, void *out, int32_t transpose)
     if (!in || !out || in == out) return fail(ctx, SLLBM_EINVAL, "bad stream buffers");
     DeviceGuard guard(ctx->cfg.device);
     if (!transpose) return check_launch(ctx, stream_into(ctx, in, out), "stream");
-    if (ctx->graded) return fail(ctx, SLLBM_EINVAL, "transposed streaming needs equal cells");
     return check_launch(ctx, stream_t_into(ctx, in, out), "stream");
 }
 
@@ -703,13 +748,14 @@ int sllbm_loss(sllbm_ctx *ctx, const void *state, double *out)
 {
     if (!ctx) return SLLBM_EINVAL;
     if (!state || !out) return fail(ctx, SLLBM_EINVAL, "NULL argument");
-    if (ctx->graded) return fail(ctx, SLLBM_EINVAL, "loss needs equal cells");
     DeviceGuard guard(ctx->cfg.device);
     hipError_t e = is_fp64(ctx)
         ? Launch<double>::loss(ctx->geo, static_cast<const double *>(state), ctx->d_dmat, ctx->d_ccw, ctx->h,
-                               ctx->d_scr_rho, ctx->d_scr_u, ctx->d_partials, RED_BLOCKS, ctx->d_small, ctx->stream)
+                               graded_hw(ctx), ctx->d_scr_rho, ctx->d_scr_u, ctx->d_partials, RED_BLOCKS, ctx->d_small,
+                               ctx->stream)
         : Launch<float>::loss(ctx->geo, static_cast<const float *>(state), ctx->d_dmat, ctx->d_ccw, ctx->h,
-                              ctx->d_scr_rho, ctx->d_scr_u, ctx->d_partials, RED_BLOCKS, ctx->d_small, ctx->stream);
+                              graded_hw(ctx), ctx->d_scr_rho, ctx->d_scr_u, ctx->d_partials, RED_BLOCKS, ctx->d_small,
+                              ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "loss");
     if ((e = hipMemcpyAsync(out, ctx->d_small, sizeof(double), hipMemcpyDeviceToHost, ctx->stream)) != hipSuccess ||
         (e = hipStreamSynchronize(ctx->stream)) != hipSuccess)
@@ -723,16 +769,15 @@ int sllbm_diagnostics(sllbm_ctx *ctx, const void *state, double *out)
     if (!ctx) return SLLBM_EINVAL;
     if (!out) return fail(ctx, SLLBM_EINVAL, "NULL out");
     if (!state && !ctx->has_state) return fail(ctx, SLLBM_ESTATE, "no state set");
-    if (ctx->graded) return fail(ctx, SLLBM_EINVAL, "diagnostics need equal cells");
     DeviceGuard guard(ctx->cfg.device);
     const void *st = state ? state : ctx->buf[ctx->cur];
     hipError_t e = is_fp64(ctx)
         ? Launch<double>::diagnostics(ctx->geo, ctx->cp, static_cast<const double *>(st), ctx->d_dmat, ctx->d_ccw,
-                                      ctx->h, ctx->d_scr_rho, ctx->d_scr_u, ctx->d_scr_T, ctx->d_partials, RED_BLOCKS,
-                                      ctx->d_small, ctx->stream)
+                                      ctx->h, graded_hw(ctx), ctx->d_scr_rho, ctx->d_scr_u, ctx->d_scr_T,
+                                      ctx->d_partials, RED_BLOCKS, ctx->d_small, ctx->stream)
         : Launch<float>::diagnostics(ctx->geo, ctx->cp, static_cast<const float *>(st), ctx->d_dmat, ctx->d_ccw,
-                                     ctx->h, ctx->d_scr_rho, ctx->d_scr_u, ctx->d_scr_T, ctx->d_partials, RED_BLOCKS,
-                                     ctx->d_small, ctx->stream);
+                                     ctx->h, graded_hw(ctx), ctx->d_scr_rho, ctx->d_scr_u, ctx->d_scr_T,
+                                     ctx->d_partials, RED_BLOCKS, ctx->d_small, ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "diagnostics");
     if ((e = hipMemcpyAsync(out, ctx->d_small, 3 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream)) !=
             hipSuccess ||
@@ -747,15 +792,16 @@ int sllbm_loss_grad(sllbm_ctx *ctx, const void *state, void *lam)
 {
     if (!ctx) return SLLBM_EINVAL;
     if (!state || !lam || state == lam) return fail(ctx, SLLBM_EINVAL, "bad loss_grad buffers");
-    if (ctx->graded) return fail(ctx, SLLBM_EINVAL, "loss_grad needs equal cells");
     DeviceGuard guard(ctx->cfg.device);
     hipError_t e = is_fp64(ctx)
         ? Launch<double>::loss_grad(ctx->geo, static_cast<const double *>(state), ctx->d_dmat, ctx->d_ccw,
-                                    ctx->d_nodew, ctx->h, ctx->d_scr_rho, ctx->d_scr_u, ctx->d_scr_div,
-                                    ctx->d_partials, RED_BLOCKS, static_cast<double *>(lam), ctx->stream)
+                                    ctx->d_nodew, ctx->h, graded_hw(ctx), ctx->d_scr_rho, ctx->d_scr_u,
+                                    ctx->d_scr_div, ctx->d_partials, RED_BLOCKS, static_cast<double *>(lam),
+                                    ctx->stream)
         : Launch<float>::loss_grad(ctx->geo, static_cast<const float *>(state), ctx->d_dmat, ctx->d_ccw,
-                                   ctx->d_nodew, ctx->h, ctx->d_scr_rho, ctx->d_scr_u, ctx->d_scr_div,
-                                   ctx->d_partials, RED_BLOCKS, static_cast<float *>(lam), ctx->stream);
+                                   ctx->d_nodew, ctx->h, graded_hw(ctx), ctx->d_scr_rho, ctx->d_scr_u,
+                                   ctx->d_scr_div, ctx->d_partials, RED_BLOCKS, static_cast<float *>(lam),
+                                   ctx->stream);
     return check_launch(ctx, e, "loss_grad");
 }
 
@@ -764,7 +810,6 @@ int sllbm_adjoint_step(sllbm_ctx *ctx, const void *state_n, const void *lam_next
     if (!ctx) return SLLBM_EINVAL;
     if (!state_n || !lam_next || !lam_out) return fail(ctx, SLLBM_EINVAL, "NULL argument");
     if (lam_out == lam_next || lam_out == state_n) return fail(ctx, SLLBM_EINVAL, "lam_out aliases an input");
-    if (ctx->graded) return fail(ctx, SLLBM_EINVAL, "adjoint_step needs equal cells");
     DeviceGuard guard(ctx->cfg.device);
     hipError_t e = stream_t_into(ctx, lam_next, lam_out);
     if (e != hipSuccess) return hip_fail(ctx, e, "adjoint_step (transposed streaming)");

@@ -49,6 +49,13 @@ double axis_node_position(int p, int ne, double length, const std::vector<double
 // w[i][g][k] (layout [Q][N][p+1]).
 void build_node_tables(const VelocitySet &vs, int p, int ne, double length, const std::vector<double> &faces,
                        int axis, double dt, std::vector<int32_t> &src, std::vector<double> &w);
+// The transpose of those per-node rows (for S^T): input node m of velocity i
+// collects w[i][g][k] from every output g with src[i][g] + k = m (mod N); its
+// readers are consecutive, g = srcT[i][m] + j, j < band, with weight
+// wT[i][m][j] (layout [Q][N][kt], zero-padded).  band (out) is the largest
+// count of readers; kt <= 0 only computes band.
+void build_transposed_node_tables(int N, int p, const std::vector<int32_t> &src, const std::vector<double> &w,
+                                  int kt, std::vector<int32_t> &srcT, std::vector<double> &wT, int &band);
 
 // ---------------------------------------------------------------------------
 // Device-side parameter blocks (passed by value to kernels)
@@ -76,8 +83,9 @@ struct CellTables {
 // tile of the graded streaming kernel over all velocities and tiles.
 template <typename S>
 struct NodeTables {
-    const int32_t *src[3];  // [Q][N_a]
-    const S *w[3];          // [Q][N_a][p+1]
+    const int32_t *src[3];  // [Q][N_a] first input node of each output node (not wrapped, non-decreasing)
+    const S *w[3];          // [Q][N_a][k] weights of the k consecutive input nodes
+    int k;                  // taps per output node (a value graded_taps_supported returns)
     int wxm, wym;
 };
 
@@ -106,17 +114,19 @@ struct Launch {
     static hipError_t totals(const Geometry &g, const CollisionParams &cp, const S *state,
                              const double *nodew, double *partials, int nblocks, double *out5,
                              hipStream_t st);
+    // h: cell width per axis; hw: graded cell widths (x, then y, then z cells) or NULL
     static hipError_t loss(const Geometry &g, const S *state, const double *dmat, const double *ccw,
-                           const double *h, double *scratch_rho, double *scratch_u, double *partials,
-                           int nblocks, double *out1, hipStream_t st);
+                           const double *h, const double *hw, double *scratch_rho, double *scratch_u,
+                           double *partials, int nblocks, double *out1, hipStream_t st);
     static hipError_t loss_grad(const Geometry &g, const S *state, const double *dmat, const double *ccw,
-                                const double *nodew, const double *h, double *scratch_rho,
+                                const double *nodew, const double *h, const double *hw, double *scratch_rho,
                                 double *scratch_u, double *scratch_div, double *partials, int nblocks, S *lam,
                                 hipStream_t st);
     // kinetic energy, solenoidal and dilatational dissipation (device out3)
     static hipError_t diagnostics(const Geometry &g, const CollisionParams &cp, const S *state, const double *dmat,
-                                  const double *ccw, const double *h, double *scratch_rho, double *scratch_u,
-                                  double *scratch_T, double *partials, int nblocks, double *out3, hipStream_t st);
+                                  const double *ccw, const double *h, const double *hw, double *scratch_rho,
+                                  double *scratch_u, double *scratch_T, double *partials, int nblocks, double *out3,
+                                  hipStream_t st);
     // lam <- J_C(X_n)^T lam in place; dL/dmu_inf added to *dmu if not NULL
     static hipError_t collide_vjp(const Geometry &g, const CollisionParams &cp, const S *state_n, S *lam,
                                   double *dmu_partials, int nblocks, double *dmu, hipStream_t st);
@@ -137,8 +147,9 @@ hipError_t launch_stream_zt(const Geometry &g, const CellTables<S> &t, const S *
 // streaming on a graded mesh (stream_graded.hip)
 template <typename S>
 hipError_t launch_stream_graded(const Geometry &g, const NodeTables<S> &t, const S *in, S *out, hipStream_t st);
-size_t graded_smem_bytes(int p, int wxm, int wym, size_t elem);
-int graded_window(const int32_t *src, int N, int p, int T);
+size_t graded_smem_bytes(int taps, int wxm, int wym, size_t elem);
+int graded_window(const int32_t *src, int N, int taps, int T);
+int graded_taps_supported(int taps);      // smallest supported tap count >= taps, 0 if none
 int graded_tile_x();
 int graded_max_window();                 // largest tile window (elements) the graded kernel takes
 int graded_tile_y();

@@ -44,13 +44,13 @@ constexpr int64_t GRADED_TARGET_BLOCKS = 2048;
 
 }  // namespace
 
-template <typename S, int P, int LK>
+template <typename S, int K, int LK>
 __global__ void __launch_bounds__(GNT) k_stream_graded(Geometry g, NodeTables<S> tab, const S *__restrict__ in,
                                                         S *__restrict__ out, int ntile_x, int ntiles, int zrows,
                                                         int nchunk)
 {
     constexpr int RB = GRB;                                // source rows per batch (two barriers each)
-    constexpr int RZ = P + RB;                             // ring of source rows per thread
+    constexpr int RZ = K - 1 + RB;                         // ring of source rows per thread
     constexpr int AS = GTX + 1;                            // odd row stride of the x-pass result
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int wxm = tab.wxm, wym = tab.wym;
@@ -71,15 +71,15 @@ __global__ void __launch_bounds__(GNT) k_stream_graded(Geometry g, NodeTables<S>
     const int32_t *sx = tab.src[0] + static_cast<int64_t>(i) * Nx;
     const int32_t *sy = tab.src[1] + static_cast<int64_t>(i) * Ny;
     const int32_t *sz = tab.src[2] + static_cast<int64_t>(i) * Nz;
-    const S *wxt = tab.w[0] + static_cast<int64_t>(i) * Nx * (P + 1);
-    const S *wyt = tab.w[1] + static_cast<int64_t>(i) * Ny * (P + 1);
-    const S *wzt = tab.w[2] + static_cast<int64_t>(i) * Nz * (P + 1);
+    const S *wxt = tab.w[0] + static_cast<int64_t>(i) * Nx * K;
+    const S *wyt = tab.w[1] + static_cast<int64_t>(i) * Ny * K;
+    const S *wzt = tab.w[2] + static_cast<int64_t>(i) * Nz * K;
     const S *__restrict__ src = in + static_cast<int64_t>(pop * 45 + i) * N;
     S *__restrict__ dst = out + static_cast<int64_t>(pop * 45 + i) * N;
 
     // source window of the tile (first source nodes are non-decreasing)
-    const int xs0 = sx[X0], wxb = sx[min(X0 + GTX, Nx) - 1] - xs0 + P + 1;
-    const int ys0 = sy[Y0], wyb = sy[min(Y0 + GTY, Ny) - 1] - ys0 + P + 1;
+    const int xs0 = sx[X0], wxb = sx[min(X0 + GTX, Nx) - 1] - xs0 + K;
+    const int ys0 = sy[Y0], wyb = sy[min(Y0 + GTY, Ny) - 1] - ys0 + K;
     const int nwin = wxb * wyb;                            // <= LK * GNT (checked by the launcher)
     // this thread's window elements: offset inside a z-plane and in LDS
     int loff[LK], soff[LK];
@@ -96,11 +96,11 @@ __global__ void __launch_bounds__(GNT) k_stream_graded(Geometry g, NodeTables<S>
     const bool own = X0 + tx < Nx && Y0 + ty < Ny;
     const int gx = min(X0 + tx, Nx - 1), gy = min(Y0 + ty, Ny - 1);
     const int ox = sx[gx] - xs0, oy = sy[gy] - ys0;
-    S wx[P + 1], wy[P + 1];
+    S wx[K], wy[K];
 #pragma unroll
-    for (int k = 0; k <= P; ++k) {
-        wx[k] = wxt[gx * (P + 1) + k];
-        wy[k] = wyt[gy * (P + 1) + k];
+    for (int k = 0; k < K; ++k) {
+        wx[k] = wxt[gx * K + k];
+        wy[k] = wyt[gy * K + k];
     }
     const int64_t oxy = static_cast<int64_t>(gy) * Nx + gx;
 
@@ -121,9 +121,9 @@ __global__ void __launch_bounds__(GNT) k_stream_graded(Geometry g, NodeTables<S>
     int rnext = r0;                                        // first source row not yet in the ring
     for (int zo = zo0; zo < zo1; ++zo) {
         const int s = sz[zo];
-        // bring in batches until row s + P is in the ring; the ring then holds
-        // rows s .. s + P (older rows are no longer needed)
-        for (; rnext <= s + P; rnext += RB) {
+        // bring in batches until row s + K - 1 is in the ring; the ring then
+        // holds rows s .. s + K - 1 (older rows are no longer needed)
+        for (; rnext <= s + K - 1; rnext += RB) {
 #pragma unroll
             for (int b = 0; b < RB; ++b)
 #pragma unroll
@@ -136,7 +136,7 @@ __global__ void __launch_bounds__(GNT) k_stream_graded(Geometry g, NodeTables<S>
                 for (int wy_ = ty; wy_ < wyb; wy_ += GTY) {
                     S acc = 0;
 #pragma unroll
-                    for (int k = 0; k <= P; ++k) acc = fma(wx[k], pl[b * WP + wy_ * wxm + ox + k], acc);
+                    for (int k = 0; k < K; ++k) acc = fma(wx[k], pl[b * WP + wy_ * wxm + ox + k], acc);
                     A[b * AP + wy_ * AS + tx] = acc;
                 }
             __syncthreads();
@@ -144,37 +144,45 @@ __global__ void __launch_bounds__(GNT) k_stream_graded(Geometry g, NodeTables<S>
             for (int b = 0; b < RB; ++b) {
                 S acc = 0;
 #pragma unroll
-                for (int k = 0; k <= P; ++k) acc = fma(wy[k], A[b * AP + (oy + k) * AS + tx], acc);
+                for (int k = 0; k < K; ++k) acc = fma(wy[k], A[b * AP + (oy + k) * AS + tx], acc);
                 ring[((rnext + b - r0) % RZ) * GNT + tid] = acc;
             }
         }
         S acc = 0;
 #pragma unroll
-        for (int k = 0; k <= P; ++k)
-            acc = fma(wzt[zo * (P + 1) + k], ring[((s + k - r0) % RZ) * GNT + tid], acc);
+        for (int k = 0; k < K; ++k)
+            acc = fma(wzt[zo * K + k], ring[((s + k - r0) % RZ) * GNT + tid], acc);
         if (own) dst[static_cast<int64_t>(zo) * NP + oxy] = acc;
     }
 }
 
-size_t graded_smem_bytes(int p, int wxm, int wym, size_t elem)
+size_t graded_smem_bytes(int taps, int wxm, int wym, size_t elem)
 {
     return (GRB * (static_cast<size_t>(wym) * wxm + static_cast<size_t>(wym) * (GTX + 1)) +
-            static_cast<size_t>(p + GRB) * GNT) * elem;
+            static_cast<size_t>(taps - 1 + GRB) * GNT) * elem;
 }
 
 // largest source window of a 32 x 8 tile along an axis (tile extent T)
-int graded_window(const int32_t *src, int N, int p, int T)
+int graded_window(const int32_t *src, int N, int taps, int T)
 {
     int w = 0;
-    for (int t0 = 0; t0 < N; t0 += T) w = std::max(w, src[std::min(t0 + T, N) - 1] - src[t0] + p + 1);
+    for (int t0 = 0; t0 < N; t0 += T) w = std::max(w, src[std::min(t0 + T, N) - 1] - src[t0] + taps);
     return w;
+}
+
+int graded_taps_supported(int taps)
+{
+    static const int ks[] = {2, 3, 4, 5, 6, 7, 8, 10, 12, 14, 16, 20, 24};
+    for (int k : ks)
+        if (k >= taps) return k;
+    return 0;
 }
 
 int graded_tile_x() { return GTX; }
 int graded_max_window() { return 16 * GNT; }
 int graded_tile_y() { return GTY; }
 
-template <typename S, int P, int LK>
+template <typename S, int K, int LK>
 static hipError_t launch_gk(const Geometry &g, const NodeTables<S> &t, const S *in, S *out, hipStream_t st)
 {
     const int ntx = (g.N[0] + GTX - 1) / GTX, nty = (g.N[1] + GTY - 1) / GTY;
@@ -182,46 +190,55 @@ static hipError_t launch_gk(const Geometry &g, const NodeTables<S> &t, const S *
     // split the z-march into chunks (each re-reads p source rows) until the
     // grid has a few blocks per CU slot
     int nchunk = 1;
-    while (static_cast<int64_t>(ntiles) * 90 * nchunk < GRADED_TARGET_BLOCKS && g.N[2] / (2 * nchunk) >= 4 * P)
+    while (static_cast<int64_t>(ntiles) * 90 * nchunk < GRADED_TARGET_BLOCKS && g.N[2] / (2 * nchunk) >= 4 * K)
         nchunk *= 2;
     const int zrows = (g.N[2] + nchunk - 1) / nchunk;
     nchunk = (g.N[2] + zrows - 1) / zrows;
     const int64_t nb = static_cast<int64_t>(ntiles) * 90 * nchunk;
     if (nb > (int64_t(1) << 31) - 1) return hipErrorInvalidValue;
-    const size_t smem = graded_smem_bytes(P, t.wxm, t.wym, sizeof(S));
+    const size_t smem = graded_smem_bytes(K, t.wxm, t.wym, sizeof(S));
     if (smem > 160 * 1024) return hipErrorInvalidValue;
     if (smem > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_stream_graded<S, P, LK>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_stream_graded<S, K, LK>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(smem));
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((k_stream_graded<S, P, LK>), dim3(static_cast<unsigned>(nb)), dim3(GNT), smem, st, g, t, in,
+    hipLaunchKernelGGL((k_stream_graded<S, K, LK>), dim3(static_cast<unsigned>(nb)), dim3(GNT), smem, st, g, t, in,
                        out, ntx, ntiles, zrows, nchunk);
     return hipGetLastError();
 }
 
 // window loads per thread: the smallest LK with LK * 256 >= the largest window
-template <typename S, int P>
+template <typename S, int K>
 static hipError_t launch_g(const Geometry &g, const NodeTables<S> &t, const S *in, S *out, hipStream_t st)
 {
     const int nw = t.wxm * t.wym;
-    if (nw <= 2 * GNT) return launch_gk<S, P, 2>(g, t, in, out, st);
-    if (nw <= 4 * GNT) return launch_gk<S, P, 4>(g, t, in, out, st);
-    if (nw <= 8 * GNT) return launch_gk<S, P, 8>(g, t, in, out, st);
-    if (nw <= 16 * GNT) return launch_gk<S, P, 16>(g, t, in, out, st);
+    if (nw <= 2 * GNT) return launch_gk<S, K, 2>(g, t, in, out, st);
+    if (nw <= 4 * GNT) return launch_gk<S, K, 4>(g, t, in, out, st);
+    if (nw <= 8 * GNT) return launch_gk<S, K, 8>(g, t, in, out, st);
+    if (nw <= 16 * GNT) return launch_gk<S, K, 16>(g, t, in, out, st);
     return hipErrorInvalidValue;
 }
 
+// taps per output: p + 1 for the forward tables, the padded band width of
+// the transposed ones (graded_taps_supported)
 template <typename S>
 hipError_t launch_stream_graded(const Geometry &g, const NodeTables<S> &t, const S *in, S *out, hipStream_t st)
 {
-    switch (g.p) {
-    case 1: return launch_g<S, 1>(g, t, in, out, st);
+    switch (t.k) {
     case 2: return launch_g<S, 2>(g, t, in, out, st);
     case 3: return launch_g<S, 3>(g, t, in, out, st);
     case 4: return launch_g<S, 4>(g, t, in, out, st);
     case 5: return launch_g<S, 5>(g, t, in, out, st);
     case 6: return launch_g<S, 6>(g, t, in, out, st);
+    case 7: return launch_g<S, 7>(g, t, in, out, st);
+    case 8: return launch_g<S, 8>(g, t, in, out, st);
+    case 10: return launch_g<S, 10>(g, t, in, out, st);
+    case 12: return launch_g<S, 12>(g, t, in, out, st);
+    case 14: return launch_g<S, 14>(g, t, in, out, st);
+    case 16: return launch_g<S, 16>(g, t, in, out, st);
+    case 20: return launch_g<S, 20>(g, t, in, out, st);
+    case 24: return launch_g<S, 24>(g, t, in, out, st);
     default: return hipErrorInvalidValue;
     }
 }

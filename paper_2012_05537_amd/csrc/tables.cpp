@@ -9,6 +9,7 @@
 // tensor product of three 1-D operators, each described by p rows of (p+1)
 // taps; these rows are all that is stored.
 #include <algorithm>
+#include <cstdint>
 #include <cmath>
 
 #include "sllbm_internal.h"
@@ -158,6 +159,57 @@ void build_node_tables(const VelocitySet &vs, int p, int ne, double length, cons
             src[static_cast<size_t>(i) * N + g] = static_cast<int32_t>(E * p);
             lagrange_basis(p, t, &w[(static_cast<size_t>(i) * N + g) * (p + 1)]);
         }
+    }
+}
+
+void build_transposed_node_tables(int N, int p, const std::vector<int32_t> &src, const std::vector<double> &w,
+                                  int kt, std::vector<int32_t> &srcT, std::vector<double> &wT, int &band)
+{
+    srcT.assign(static_cast<size_t>(Q) * N, 0);
+    wT.assign(static_cast<size_t>(Q) * N * std::max(kt, 1), 0.0);
+    band = 1;
+    std::vector<int64_t> lo(N), hi(N);
+    for (int i = 0; i < Q; ++i) {
+        const int32_t *s = &src[static_cast<size_t>(i) * N];
+        int32_t *st = &srcT[static_cast<size_t>(i) * N];
+        std::fill(lo.begin(), lo.end(), INT64_MAX);
+        std::fill(hi.begin(), hi.end(), INT64_MIN);
+        // forward output g reads input node s[g] + k; as an output of S^T,
+        // input node m = (s[g] + k) mod N collects it from output g - jN
+        // (the outputs repeat with period N, their inputs shifted by N)
+        auto visit = [&](auto &&fn) {
+            for (int g = 0; g < N; ++g)
+                for (int k = 0; k <= p; ++k) {
+                    const int64_t t = static_cast<int64_t>(s[g]) + k;
+                    const int64_t m = ((t % N) + N) % N;
+                    fn(static_cast<int>(m), g - (t - m), g, k);   // t - m = jN
+                }
+        };
+        visit([&](int m, int64_t gu, int, int) {
+            lo[m] = std::min(lo[m], gu);
+            hi[m] = std::max(hi[m], gu);
+        });
+        // band starts: a node some output reads starts at its first reader; a
+        // node none reads takes the start of the next read node (N later past
+        // the wrap), so the starts stay non-decreasing
+        int64_t next = 0;
+        for (int m = 2 * N - 1; m >= 0; --m) {
+            const int mm = m % N;
+            if (hi[mm] >= lo[mm]) {
+                next = lo[mm] + (m >= N ? N : 0);
+                if (m < N) st[mm] = static_cast<int32_t>(lo[mm]);
+            } else if (m < N) {
+                st[mm] = static_cast<int32_t>(next);
+            }
+        }
+        for (int m = 0; m < N; ++m)
+            if (hi[m] >= lo[m]) band = std::max(band, static_cast<int>(hi[m] - lo[m] + 1));
+        if (kt <= 0) continue;
+        visit([&](int m, int64_t gu, int g, int k) {
+            const int64_t slot = gu - st[m];
+            if (slot >= 0 && slot < kt)
+                wT[(static_cast<size_t>(i) * N + m) * kt + slot] = w[(static_cast<size_t>(i) * N + g) * (p + 1) + k];
+        });
     }
 }
 

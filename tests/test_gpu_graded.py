@@ -159,7 +159,133 @@ def test_graded_full_size_sampled(oracle):
     ctx.close()
 
 
-def test_graded_refusals_and_bad_widths(oracle):
+@pytest.mark.parametrize("n_el,p,dt,graded", [CASES[0], CASES[1], CASES[2], CASES[3], CASES[5]])
+def test_graded_transposed_stream_is_adjoint(oracle, n_el, p, dt, graded):
+    """<S x, y> = <x, S^T y> per population and velocity, S x from the oracle's
+    graded gather, S^T y from the library's transposed per-node tables."""
+    _say(f"graded transposed stream n_el={n_el} p={p} dt={dt}")
+    widths = _widths_for(n_el, graded, 2 * math.pi, 10 * p)
+    ctx, cfg = _graded_pair(oracle, n_el, p, dt, widths)
+    rng = np.random.default_rng(8)
+    N = oracle.num_nodes(cfg)
+    x = rng.normal(size=(2, Q, N))
+    y = rng.normal(size=(2, Q, N))
+    Sx = np.stack(oracle.stream(cfg, x[0], x[1]))
+    STy = ctx.stream(to_dev(ctx, y[0], y[1]), transpose=True).cpu().numpy()
+    lhs = np.einsum("pin,pin->pi", Sx, y)
+    rhs = np.einsum("pin,pin->pi", x, STy)
+    scale = np.einsum("pin,pin->pi", np.abs(Sx), np.abs(y))
+    assert np.all(np.abs(lhs - rhs) <= 1e-13 * scale), np.max(np.abs(lhs - rhs) / scale)
+    ctx.close()
+
+
+def test_graded_adjoint_step_dot_product(oracle):
+    """<adjoint_step(X, lam), v> = <lam, d step(X)[v]> on a graded mesh, with
+    d step[v] from a complex-step oracle step (collide, then graded stream)."""
+    n_el, p, dt, mu = (4, 3, 5), 3, 0.3, 0.0106
+    widths = _widths_for(n_el, (1, 1, 1), 2 * math.pi, 70)
+    ctx, cfg = _graded_pair(oracle, n_el, p, dt, widths, mu=mu)
+    xs, ys, zs = oracle.node_coords(cfg)
+    rho, u, T = inputs.tgv_fields(xs, ys, zs, 0.5, 1.4)
+    f, g = oracle.init_equilibrium(cfg, rho, u, T)
+    rng = np.random.default_rng(3)
+    f = f * (1.0 + 0.02 * rng.normal(size=f.shape))
+    g = g * (1.0 + 0.02 * rng.normal(size=g.shape))
+    N = f.shape[1]
+    lf, lg = rng.normal(size=(Q, N)), rng.normal(size=(Q, N))
+    LF, LG = to_np(ctx.adjoint_step(to_dev(ctx, f, g), to_dev(ctx, lf, lg)))
+    H = 1e-30
+    for trial in range(3):
+        vf, vg = rng.normal(size=(Q, N)), rng.normal(size=(Q, N))
+        sf, sg = oracle.step(cfg, f + 1j * H * vf, g + 1j * H * vg, 1)
+        ref = (np.sum(lf * sf.imag) + np.sum(lg * sg.imag)) / H
+        got = np.sum(LF * vf) + np.sum(LG * vg)
+        assert abs(got - ref) <= 1e-12 * np.sum(np.abs(LF * vf) + np.abs(LG * vg)), (trial, got, ref)
+    ctx.close()
+
+
+def _noisy_graded(oracle, n_el, p, widths, seed, mu=0.01, dt=0.1):
+    ctx, cfg = _graded_pair(oracle, n_el, p, dt, widths, mu=mu)
+    xs, ys, zs = oracle.node_coords(cfg)
+    rho, u, T = inputs.tgv_fields(xs, ys, zs, 0.5, 1.4)
+    f, g = oracle.init_equilibrium(cfg, rho, u, T)
+    rng = np.random.default_rng(seed)
+    f = f * (1.0 + 0.02 * rng.normal(size=f.shape))
+    g = g * (1.0 + 0.02 * rng.normal(size=g.shape))
+    return ctx, cfg, f, g
+
+
+@pytest.mark.parametrize("n_el,p", [((3, 4, 2), 2), ((2, 3, 3), 3)])
+def test_graded_loss_and_diagnostics_match_oracle(oracle, n_el, p):
+    widths = _widths_for(n_el, (1, 1, 1), 2 * math.pi, 40 + p)
+    ctx, cfg, f, g = _noisy_graded(oracle, n_el, p, widths, seed=p)
+    X = to_dev(ctx, f, g)
+    assert ctx.loss(X) == pytest.approx(oracle.loss(cfg, f, g), rel=1e-12)
+    got = np.array(ctx.diagnostics(X))
+    ref = np.array(oracle.diagnostics(cfg, f, g))
+    assert np.all(np.abs(got - ref) <= 1e-12 * np.abs(ref))
+    ctx.close()
+
+
+def test_graded_loss_grad_elementwise(oracle):
+    """dL/df_i(n) at every population and node from complex steps of the
+    oracle's loss on the graded mesh (each cell with its own width)."""
+    n_el, p = (3, 2, 2), 2
+    widths = _widths_for(n_el, (1, 1, 0), 2 * math.pi, 44)
+    ctx, cfg, f, g = _noisy_graded(oracle, n_el, p, widths, seed=12)
+    LF, LG = to_np(ctx.loss_grad(to_dev(ctx, f, g)))
+    N = f.shape[1]
+    H = 1e-30
+    ref = np.zeros((Q, N))
+    gc = g.astype(np.complex128)
+    for k in range(Q):
+        for n in range(N):
+            fc = f.astype(np.complex128)
+            fc[k, n] += 1j * H
+            ref[k, n] = oracle.loss(cfg, fc, gc).imag / H
+    assert rel_err(LF, ref) < 1e-12, rel_err(LF, ref)
+    assert np.all(LG == 0.0)
+    ctx.close()
+
+
+def test_graded_rollout_gradient(oracle):
+    """Gradient of an 8-step rollout on a graded mesh (4 modes and mu_inf)
+    against complex-step oracle rollouts on the same mesh."""
+    from paper_2012_05537_amd.adjoint import Rollout
+    n_el, p, dt, mu, Ma = (4, 3, 4), 2, 0.3, 0.0106, 0.5
+    widths = _widths_for(n_el, (1, 1, 1), 2 * math.pi, 60)
+    ctx, cfg = _graded_pair(oracle, n_el, p, dt, widths, mu=mu)
+    xs, ys, zs = oracle.node_coords(cfg)
+    rho, u, T = inputs.tgv_fields(xs, ys, zs, Ma, 1.4)
+    modes = inputs.fourier_modes(2012, 4, Ma, 1.4, 0.01)
+    B = inputs.mode_basis(xs, ys, zs, modes)
+    amps = np.array([m[3] for m in modes])
+    n = 8
+    roll = Rollout(ctx, rho, u, T, B, n, checkpoint=3)
+    a = torch.tensor(amps, dtype=torch.float64, requires_grad=True)
+    m_ = torch.tensor(mu, dtype=torch.float64, requires_grad=True)
+    L = roll(a, m_)
+    L.backward()
+    H = 1e-30
+
+    def directional(da, dmu):
+        c = oracle.make_cfg(n_el, p, dt, mu, widths=widths, mu_inf_im=H * dmu)
+        uc = u + np.tensordot(amps + 1j * H * da, B, axes=(0, 0))
+        fc, gc = oracle.init_equilibrium(c, rho.astype(np.complex128), uc, T.astype(np.complex128))
+        fc, gc = oracle.step(c, fc, gc, n)
+        Lc = oracle.loss(c, fc, gc)
+        return Lc.real, Lc.imag / H
+
+    L_ref, _ = directional(np.zeros_like(amps), 0.0)
+    assert L.item() == pytest.approx(L_ref, rel=1e-12)
+    rng = np.random.default_rng(5)
+    da, dmu = rng.normal(size=amps.size), float(rng.normal()) * mu
+    got = float(a.grad.numpy() @ da + m_.grad.item() * dmu)
+    assert got == pytest.approx(directional(da, dmu)[1], rel=1e-10)
+    ctx.close()
+
+
+def test_graded_bad_widths_keep_the_mesh(oracle):
     from paper_2012_05537_amd.sllbm import SLLBM, SllbmError
     n_el, p, dt = (3, 2, 2), 2, 0.2
     ctx = SLLBM(n_el, p, dt, 0.01)
@@ -171,14 +297,25 @@ def test_graded_refusals_and_bad_widths(oracle):
     with pytest.raises(ValueError):
         ctx.set_mesh(np.array([1.0, 2.0]))                # wrong count
     assert torch.equal(ctx.stream(x), ref)                # the equal-cell mesh stays
-    ctx.set_mesh(None, np.array([2.0, 1.0]))
-    ctx.set_state(x)
+    ctx.close()
+
+
+def test_graded_too_strong_grading_keeps_the_previous_mesh(oracle):
+    """15 cells of width 0.01 beside one of 2 pi - 0.15: the nodes of the wide
+    cell are read by 32 nodes of the axis (more than the 24 taps of the
+    transposed streaming), so set_mesh fails and the previous graded mesh stays."""
+    from paper_2012_05537_amd.sllbm import SLLBM, SllbmError
+    n_el, p, dt = (16, 3, 2), 2, 0.2
+    ctx = SLLBM(n_el, p, dt, 0.01)
+    ctx.set_mesh(None, _rand_widths(3, 2 * math.pi, 5))
+    gen = torch.Generator(device=ctx.device).manual_seed(2)
+    x = torch.randn((2, Q, ctx.nodes), generator=gen, device=ctx.device, dtype=torch.float64)
+    ref, ref_t = ctx.stream(x), ctx.stream(x, transpose=True)
+    coords = [c.clone() for c in ctx.node_coords()]
+    w = np.full(16, 0.01)
+    w[0] = 2 * math.pi - 0.15
     with pytest.raises(SllbmError):
-        ctx.stream(x, transpose=True)
-    with pytest.raises(SllbmError):
-        ctx.adjoint_step(x, x.clone())
-    with pytest.raises(SllbmError):
-        ctx.loss(x)
-    with pytest.raises(SllbmError):
-        ctx.diagnostics()
+        ctx.set_mesh(w)
+    assert torch.equal(ctx.stream(x), ref) and torch.equal(ctx.stream(x, transpose=True), ref_t)
+    assert all(torch.equal(a, b) for a, b in zip(ctx.node_coords(), coords))
     ctx.close()

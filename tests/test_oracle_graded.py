@@ -143,11 +143,64 @@ def test_smooth_field_error_order(oracle, p):
     assert 0.85 * 2 ** (p + 1) < ratio < 1.15 * 2 ** (p + 1), (errs, ratio)
 
 
-def test_loss_and_diagnostics_refuse_graded(oracle):
-    cfg = oracle.make_cfg((2, 1, 1), 2, 0.1, 0.01, widths=[np.array([1.0, 2.0]), None, None])
-    N = oracle.num_nodes(cfg)
-    f = np.ones((Q, N))
-    with pytest.raises(NotImplementedError):
-        oracle.loss(cfg, f, f)
-    with pytest.raises(NotImplementedError):
-        oracle.diagnostics(cfg, f, f)
+SUTH = 0.40417
+
+
+def _mu(mu_inf, T):
+    return mu_inf * (1 + SUTH) * T ** 1.5 / (T + SUTH)
+
+
+def _pw_closed_forms(vals, w):
+    """For a periodic piecewise-linear profile: integral of v^2 and of v'^2."""
+    v1 = np.roll(vals, -1)
+    sq = np.sum(w * (vals * vals + vals * v1 + v1 * v1) / 3.0)
+    slope2 = np.sum((v1 - vals) ** 2 / w)
+    return sq, slope2
+
+
+@pytest.mark.parametrize("p", [2, 3])
+def test_graded_shear_diagnostics(oracle, p):
+    """u_x(y) linear inside every graded y-cell: curl only, each cell with its
+    own slope; kinetic energy and solenoidal dissipation in closed form."""
+    n_el, L, mu_inf, T0 = (2, 5, 3), (2.0, 3.0, 1.5), 0.013, 1.4
+    wy = _graded_widths(5, L[1], 80)
+    cfg = oracle.make_cfg(n_el, p, 0.1, mu_inf, length=L, widths=[None, wy, None])
+    fy = np.concatenate([[0.0], np.cumsum(wy)])
+    vals = np.random.default_rng(81).uniform(-0.1, 0.1, 5)
+    xs, ys, zs = oracle.node_coords(cfg)
+    Y = np.meshgrid(zs, ys, xs, indexing="ij")[1].reshape(-1)
+    N = Y.size
+    u = np.zeros((3, N))
+    u[0] = _pw_linear(Y, fy, vals)
+    f, g = oracle.init_equilibrium(cfg, np.ones(N), u, np.full(N, T0))
+    ek, es, ec = oracle.diagnostics(cfg, f, g)
+    sq, slope2 = _pw_closed_forms(vals, wy)
+    area = L[0] * L[2]
+    assert ek == pytest.approx(0.5 * sq * area, rel=1e-12)
+    assert es == pytest.approx(_mu(mu_inf, T0) * slope2 * area, rel=1e-12)
+    assert abs(ec) < 1e-12 * es
+
+
+@pytest.mark.parametrize("p", [2, 4])
+def test_graded_compression_loss_and_diagnostics(oracle, p):
+    """u_x(x) linear inside every graded x-cell: divergence only; the flow
+    functional and the dilatational dissipation in closed form."""
+    n_el, L, mu_inf, rho0 = (6, 1, 2), (3.0, 1.0, 2.0), 0.011, 1.2
+    wx = _graded_widths(6, L[0], 90)
+    cfg = oracle.make_cfg(n_el, p, 0.1, mu_inf, length=L, widths=[wx, None, None],
+                          viscosity_law=oracle.CONSTANT)
+    fx = np.concatenate([[0.0], np.cumsum(wx)])
+    vals = np.random.default_rng(91).uniform(-0.1, 0.1, 6)
+    xs, ys, zs = oracle.node_coords(cfg)
+    X = np.meshgrid(zs, ys, xs, indexing="ij")[2].reshape(-1)
+    N = X.size
+    u = np.zeros((3, N))
+    u[0] = _pw_linear(X, fx, vals)
+    f, g = oracle.init_equilibrium(cfg, np.full(N, rho0), u, np.full(N, 0.9))
+    sq, slope2 = _pw_closed_forms(vals, wx)
+    area = L[1] * L[2]
+    ek, es, ec = oracle.diagnostics(cfg, f, g)
+    assert ec == pytest.approx(4.0 / 3.0 * mu_inf * slope2 * area, rel=1e-12)
+    assert abs(es) < 1e-12 * ec
+    assert ek == pytest.approx(0.5 * rho0 * sq * area, rel=1e-12)
+    assert oracle.loss(cfg, f, g) == pytest.approx((0.5 * rho0 * sq + slope2) * area, rel=1e-12)
