@@ -114,7 +114,7 @@ def run_gpu(args, wl, precision):
     return dict(nodes=nodes, wall=wall, kernels=kernels, bytes=bytes_per_launch, finite=ok, totals=tot)
 
 
-def run_adjoint(wl, precision):
+def run_adjoint(wl, precision, graded=False):
     """Wall time of a checkpointed rollout gradient of the workload (forward
     rollout with checkpoints, then the reverse sweep with segment replay), and
     the ratio backward / forward."""
@@ -126,6 +126,9 @@ def run_adjoint(wl, precision):
 
     ctx = SLLBM(wl["n_el"], wl["p"], wl["dt"], wl["mu_inf"], gamma=wl["gamma"], prandtl=wl["Pr"],
                 precision=precision)
+    if graded:
+        w = inputs.graded_widths(wl["n_el"], amplitude=inputs.GRADED["amplitude"])
+        ctx.set_mesh(w, w, w)
     xs, ys, zs = (t.numpy() for t in ctx.node_coords())
     md = wl.get("modes") or dict(seed=2012, count=16, scale=0.01)
     modes = inputs.fourier_modes(md["seed"], md["count"], wl["Ma"], wl["gamma"], md["scale"])
@@ -151,7 +154,9 @@ def run_adjoint(wl, precision):
     # checkpoints, segment record and adjoint buffers (torch) plus the library's two state buffers
     peak_gb = (torch.cuda.max_memory_allocated() + 2 * ctx.state_bytes) / 1e9
     ctx.close()
-    return {"workload": f"{wl['name']}: {wl['n_el']}^3 cells p={wl['p']} ({ctx.nodes} nodes), {steps} steps, "
+    cells = "cosine-graded cells" if graded else "cells"
+    return {"workload": f"{wl['name']}{'-graded' if graded else ''}: {wl['n_el']}^3 {cells} p={wl['p']} "
+                        f"({ctx.nodes} nodes), {steps} steps, "
                         f"{len(modes)} modes + mu_inf, checkpoint {wl.get('checkpoint', 10)}",
             "forward_s": t1 - t0, "backward_s": t2 - t1, "backward_over_forward": (t2 - t1) / (t1 - t0),
             "loss": L.item(), "grad_finite": bool(torch.isfinite(amps.grad).all() and math.isfinite(mu.grad.item())),
@@ -257,7 +262,7 @@ def main():
         if args.adjoint_steps is not None:
             over["steps"] = args.adjoint_steps
         wa = inputs.workload(args.adjoint_workload, **over)
-        out["adjoint"] = run_adjoint(wa, 0 if wa["precision"] == "fp64" else 1)
+        out["adjoint"] = run_adjoint(wa, 0 if wa["precision"] == "fp64" else 1, graded=args.mesh == "graded")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_budget, graded=args.mesh == "graded")
     print(json.dumps(out), flush=True)
