@@ -228,7 +228,10 @@ int upload_graded(sllbm_ctx *c)
                     hipSuccess)
                 return hip_fail(c, e, "graded table upload");
         }
-        c->gwxm[d] = wmax[0];
+        // room for the 16-byte-aligned start of a window row: up to V - 1
+        // more nodes, rows a multiple of V nodes long
+        const int V = graded_window_pad(sizeof(S));
+        c->gwxm[d] = (wmax[0] + V - 1 + V - 1) / V * V;
         c->gwym[d] = wmax[1];
         const size_t smem = graded_smem_bytes(c->gk[d], c->gwxm[d], c->gwym[d], sizeof(S));
         if (c->gwxm[d] * c->gwym[d] > graded_max_window())

@@ -151,6 +151,7 @@ size_t graded_smem_bytes(int taps, int wxm, int wym, size_t elem);
 int graded_window(const int32_t *src, int N, int taps, int T);
 int graded_taps_supported(int taps);      // smallest supported tap count >= taps, 0 if none
 int graded_tile_x();
+int graded_window_pad(size_t elem);      // window rows are padded to this many nodes (16-byte loads)
 int graded_max_window();                 // largest tile window (elements) the graded kernel takes
 int graded_tile_y();
 

@@ -44,7 +44,16 @@ constexpr int64_t GRADED_TARGET_BLOCKS = 2048;
 
 }  // namespace
 
-template <typename S, int K, int LK>
+template <typename S, int V>
+struct VecG {
+    typedef S T __attribute__((ext_vector_type(V)));
+};
+template <typename S>
+struct VecG<S, 1> {
+    typedef S T;
+};
+
+template <typename S, int K, int LK, int V>
 __global__ void __launch_bounds__(GNT) k_stream_graded(Geometry g, NodeTables<S> tab, const S *__restrict__ in,
                                                         S *__restrict__ out, int ntile_x, int ntiles, int zrows,
                                                         int nchunk)
@@ -77,16 +86,20 @@ __global__ void __launch_bounds__(GNT) k_stream_graded(Geometry g, NodeTables<S>
     const S *__restrict__ src = in + static_cast<int64_t>(pop * 45 + i) * N;
     S *__restrict__ dst = out + static_cast<int64_t>(pop * 45 + i) * N;
 
-    // source window of the tile (first source nodes are non-decreasing)
-    const int xs0 = sx[X0], wxb = sx[min(X0 + GTX, Nx) - 1] - xs0 + K;
+    // source window of the tile (first source nodes are non-decreasing); its
+    // x start is rounded down to V nodes (shift sh) for V-wide loads
+    using VT = typename VecG<S, V>::T;
+    const int xs = sx[X0], wxb = sx[min(X0 + GTX, Nx) - 1] - xs + K;
+    const int sh = ((xs % V) + V) % V, xs0 = xs - sh;
+    const int wxv = (wxb + sh + V - 1) / V;                // V-wide loads per window row
     const int ys0 = sy[Y0], wyb = sy[min(Y0 + GTY, Ny) - 1] - ys0 + K;
-    const int nwin = wxb * wyb;                            // <= LK * GNT (checked by the launcher)
-    // this thread's window elements: offset inside a z-plane and in LDS
+    const int nwin = wxv * wyb;                            // <= LK * GNT (checked by the launcher)
+    // this thread's window loads: offset inside a z-plane and in LDS
     int loff[LK], soff[LK];
 #pragma unroll
     for (int k = 0; k < LK; ++k) {
         const int e = min(tid + k * GNT, nwin - 1);
-        const int wy_ = e / wxb, wx_ = e - wy_ * wxb;
+        const int wy_ = e / wxv, wx_ = (e - wy_ * wxv) * V;
         loff[k] = wrapg(ys0 + wy_, Ny) * Nx + wrapg(xs0 + wx_, Nx);
         soff[k] = wy_ * wxm + wx_;
     }
@@ -95,7 +108,7 @@ __global__ void __launch_bounds__(GNT) k_stream_graded(Geometry g, NodeTables<S>
     const int tx = tid % GTX, ty = tid / GTX;
     const bool own = X0 + tx < Nx && Y0 + ty < Ny;
     const int gx = min(X0 + tx, Nx - 1), gy = min(Y0 + ty, Ny - 1);
-    const int ox = sx[gx] - xs0, oy = sy[gy] - ys0;
+    const int ox = sx[gx] - xs0, oy = sy[gy] - ys0;        // ox includes the shift sh
     S wx[K], wy[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -108,13 +121,13 @@ __global__ void __launch_bounds__(GNT) k_stream_graded(Geometry g, NodeTables<S>
     const int r0 = sz[zo0];                                // first source row of the chunk (not wrapped)
     // the windows of the next batch of source rows are loaded into registers
     // while the current batch is interpolated
-    S raw[RB][LK];
+    VT raw[RB][LK];
     auto load_batch = [&](int r) {
 #pragma unroll
         for (int b = 0; b < RB; ++b) {
             const S *base = src + static_cast<int64_t>(wrapg(r + b, Nz)) * NP;
 #pragma unroll
-            for (int k = 0; k < LK; ++k) raw[b][k] = base[loff[k]];
+            for (int k = 0; k < LK; ++k) raw[b][k] = *reinterpret_cast<const VT *>(base + loff[k]);
         }
     };
     load_batch(r0);
@@ -128,7 +141,7 @@ __global__ void __launch_bounds__(GNT) k_stream_graded(Geometry g, NodeTables<S>
             for (int b = 0; b < RB; ++b)
 #pragma unroll
                 for (int k = 0; k < LK; ++k)
-                    if (tid + k * GNT < nwin) pl[b * WP + soff[k]] = raw[b][k];
+                    if (tid + k * GNT < nwin) *reinterpret_cast<VT *>(&pl[b * WP + soff[k]]) = raw[b][k];
             load_batch(rnext + RB);                        // in bounds (wrapped); unused past the chunk
             __syncthreads();
 #pragma unroll
@@ -179,10 +192,11 @@ int graded_taps_supported(int taps)
 }
 
 int graded_tile_x() { return GTX; }
+int graded_window_pad(size_t elem) { return static_cast<int>(16 / elem); }
 int graded_max_window() { return 16 * GNT; }
 int graded_tile_y() { return GTY; }
 
-template <typename S, int K, int LK>
+template <typename S, int K, int LK, int V>
 static hipError_t launch_gk(const Geometry &g, const NodeTables<S> &t, const S *in, S *out, hipStream_t st)
 {
     const int ntx = (g.N[0] + GTX - 1) / GTX, nty = (g.N[1] + GTY - 1) / GTY;
@@ -199,25 +213,37 @@ static hipError_t launch_gk(const Geometry &g, const NodeTables<S> &t, const S *
     const size_t smem = graded_smem_bytes(K, t.wxm, t.wym, sizeof(S));
     if (smem > 160 * 1024) return hipErrorInvalidValue;
     if (smem > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_stream_graded<S, K, LK>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_stream_graded<S, K, LK, V>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(smem));
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((k_stream_graded<S, K, LK>), dim3(static_cast<unsigned>(nb)), dim3(GNT), smem, st, g, t, in,
+    hipLaunchKernelGGL((k_stream_graded<S, K, LK, V>), dim3(static_cast<unsigned>(nb)), dim3(GNT), smem, st, g, t, in,
                        out, ntx, ntiles, zrows, nchunk);
     return hipGetLastError();
 }
 
 // window loads per thread: the smallest LK with LK * 256 >= the largest window
+template <typename S, int K, int V>
+static hipError_t launch_gv(const Geometry &g, const NodeTables<S> &t, const S *in, S *out, hipStream_t st)
+{
+    const int nw = (t.wxm / V) * t.wym;                    // V-wide loads of the largest window
+    if (nw <= 1 * GNT) return launch_gk<S, K, 1, V>(g, t, in, out, st);
+    if (nw <= 2 * GNT) return launch_gk<S, K, 2, V>(g, t, in, out, st);
+    if (nw <= 4 * GNT) return launch_gk<S, K, 4, V>(g, t, in, out, st);
+    if (nw <= 8 * GNT) return launch_gk<S, K, 8, V>(g, t, in, out, st);
+    if (nw <= 16 * GNT) return launch_gk<S, K, 16, V>(g, t, in, out, st);
+    return hipErrorInvalidValue;
+}
+
+// 16-byte window loads when x rows hold a multiple of 16 bytes and the
+// buffer is 16-byte aligned (the window start is rounded down)
 template <typename S, int K>
 static hipError_t launch_g(const Geometry &g, const NodeTables<S> &t, const S *in, S *out, hipStream_t st)
 {
-    const int nw = t.wxm * t.wym;
-    if (nw <= 2 * GNT) return launch_gk<S, K, 2>(g, t, in, out, st);
-    if (nw <= 4 * GNT) return launch_gk<S, K, 4>(g, t, in, out, st);
-    if (nw <= 8 * GNT) return launch_gk<S, K, 8>(g, t, in, out, st);
-    if (nw <= 16 * GNT) return launch_gk<S, K, 16>(g, t, in, out, st);
-    return hipErrorInvalidValue;
+    constexpr int V = 16 / sizeof(S);
+    if ((g.N[0] * sizeof(S)) % 16 == 0 && reinterpret_cast<uintptr_t>(in) % 16 == 0 && t.wxm % V == 0)
+        return launch_gv<S, K, V>(g, t, in, out, st);
+    return launch_gv<S, K, 1>(g, t, in, out, st);
 }
 
 // taps per output: p + 1 for the forward tables, the padded band width of
