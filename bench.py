@@ -212,8 +212,9 @@ def main():
                     help="run three plain copies of one state's size first (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (see the design notes on "
-              "how the step would shard); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path (the step would shard "
+              "as a periodic block decomposition with one halo exchange per step); run with --gpus 1",
+              file=sys.stderr)
         return 2
 
     from paper_2012_05537_amd import inputs
