@@ -3,12 +3,20 @@
  * library: the per-time-step update of the 45-velocity f and g populations
  * of the compressible SLLBM (Wilde, Kraemer, Reith, Foysi, arXiv:2012.05537)
  * on a periodic hexahedral mesh of equal cells (or of axis-aligned cells of
- * unequal width, sllbm_set_mesh) with Gauss-Lobatto-Chebyshev support points.
+ * unequal width, sllbm_set_mesh) with Gauss-Lobatto-Chebyshev support points,
+ * and its two-dimensional form with the 19-velocity set (SLLBM_D2Q19, the
+ * lattice of the shock-tube and 2-D Riemann cases of Sec. III A-B).
+ *
+ * Two dimensions (velocity_set = SLLBM_D2Q19): D = 2, n_el[2] = 1 and
+ * N_z = 1 (length[2] is not used); Q = 19 replaces 45 below; velocity
+ * fields u are [2][N]; totals report zero z momentum.  The calls of the
+ * adjoint section, sllbm_loss, sllbm_diagnostics, sllbm_set_mesh and the
+ * transposed sllbm_stream return EINVAL on such a context.
  *
  * Conventions shared by every call
  * --------------------------------
- *  Units      lattice units: c_s = 1, T0 = 1, gas constant 1, D = 3,
- *             C_v = 1/(gamma - 1).
+ *  Units      lattice units: c_s = 1, T0 = 1, gas constant 1, D = 3 (2 for
+ *             SLLBM_D2Q19), C_v = 1/(gamma - 1).
  *  Nodes      the unique periodic support points: N_a = n_el[a] * order per
  *             axis, N = N_x N_y N_z.  Node (gx, gy, gz) has linear index
  *             (gz * N_y + gy) * N_x + gx; along an axis, node g = e*order + l
@@ -49,6 +57,7 @@ extern "C" {
 #define SLLBM_ENONFINITE 5  /* a non-finite value was found */
 
 #define SLLBM_D3Q45 45
+#define SLLBM_D2Q19 19
 
 #define SLLBM_SUTHERLAND 0  /* mu = mu_inf (1+S) T^1.5/(T+S), S = 0.40417 (Sec. III C) */
 #define SLLBM_CONSTANT 1    /* mu = mu_inf */
@@ -63,7 +72,7 @@ typedef struct sllbm_ctx sllbm_ctx;
 typedef struct {
     int32_t n_el[3];        /* cells per axis, >= 1 */
     int32_t order;          /* GLC interpolation order p, 1..6 (Eq. (8)) */
-    int32_t velocity_set;   /* SLLBM_D3Q45 */
+    int32_t velocity_set;   /* SLLBM_D3Q45 or SLLBM_D2Q19 */
     int32_t viscosity_law;  /* SLLBM_SUTHERLAND or SLLBM_CONSTANT */
     int32_t precision;      /* SLLBM_FP64 or SLLBM_FP32_MIXED */
     int32_t device;         /* HIP device ordinal */
@@ -101,6 +110,12 @@ int64_t sllbm_state_bytes(const sllbm_ctx *ctx);
  * w[45] (host).  Returns 45. */
 int sllbm_velocity_set(double *xi, double *w);
 
+/* The velocity set velocity_set (SLLBM_D3Q45 or SLLBM_D2Q19, both exact to
+ * degree nine for the weight exp(-|xi|^2/2), Sec. II B) in the order the
+ * state uses: xi[Q][3] (z = 0 for D2Q19) and w[Q] (host).  Returns Q, or
+ * -1 for an unknown set or a NULL pointer. */
+int sllbm_lattice(int32_t velocity_set, double *xi, double *w);
+
 /* 1-D node coordinates along each axis (host arrays of N_x, N_y, N_z). */
 int sllbm_node_coords(const sllbm_ctx *ctx, double *x, double *y, double *z);
 
@@ -126,7 +141,7 @@ int sllbm_set_viscosity(sllbm_ctx *ctx, double mu_inf);
 int sllbm_set_mesh(sllbm_ctx *ctx, const double *widths_x, const double *widths_y, const double *widths_z);
 
 /* State := equilibrium of the given fields (Eq. (6); g^eq = (2C_v - D) T f^eq).
- * rho, u, T: device.  Errors: EINVAL on NULL. */
+ * rho, u ([D][N]), T: device.  Errors: EINVAL on NULL. */
 int sllbm_init_equilibrium(sllbm_ctx *ctx, const double *rho, const double *u, const double *T);
 
 /* State := caller's pre-collision populations (device, storage type). */
@@ -155,8 +170,8 @@ int sllbm_step_record(sllbm_ctx *ctx, int32_t n, void *states, int64_t stride_by
 int sllbm_set_kernel_timing(sllbm_ctx *ctx, int32_t on);
 int sllbm_kernel_times(sllbm_ctx *ctx, double *out);
 
-/* rho, u, T of the current state at every node, Eq. (7) (device, double).
- * T from 2 rho E = rho |u|^2 + 2 C_v rho T.  Any pointer may be NULL. */
+/* rho, u ([D][N]), T of the current state at every node, Eq. (7) (device,
+ * double).  T from 2 rho E = rho |u|^2 + 2 C_v rho T.  Any pointer may be NULL. */
 int sllbm_moments(sllbm_ctx *ctx, double *rho, double *u, double *T);
 
 /* Domain integrals of rho, rho u_x, rho u_y, rho u_z and rho E with

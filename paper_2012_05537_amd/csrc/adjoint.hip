@@ -65,7 +65,7 @@ struct Bracket {
 __device__ __forceinline__ Bracket bracket(double u2, double th, double x2)
 {
     Bracket b;
-    const EqShell e = eq_shell(u2, th, x2);
+    const EqShell e = eq_shell<3>(u2, th, x2);
     b.a0 = e.a0;
     b.a1 = e.a1;
     b.a2 = e.a2;
@@ -116,7 +116,7 @@ __global__ void __launch_bounds__(256) k_collide_vjp(int64_t N, CollisionParams 
     // X enters only through its raw moments and sum alpha h, so it is dead
     // before the sweep; alpha stays in registers
     double al[vs::Q];
-    RawMoments rm;
+    RawMoments<D3Q45> rm;
     double dot_ah = 0.0;
     {
         double h[vs::Q];
@@ -125,7 +125,7 @@ __global__ void __launch_bounds__(256) k_collide_vjp(int64_t N, CollisionParams 
             h[i] = static_cast<double>(X[off + static_cast<int64_t>(i) * N]);
             al[i] = static_cast<double>(mu[off + static_cast<int64_t>(i) * N]);
         }
-        rm = raw_moments(h);
+        rm = raw_moments<D3Q45>(h);
 #pragma unroll
         for (int i = 0; i < vs::Q; ++i) dot_ah = fma(al[i], h[i], dot_ah);
     }
@@ -144,7 +144,7 @@ __global__ void __launch_bounds__(256) k_collide_vjp(int64_t N, CollisionParams 
     const double Cv = cp.Cv;
     const double T = (K * ir - u2) / (2.0 * Cv);
     double qb[10];
-    centred_third(rm, u, qb);
+    centred_third<D3Q45>(rm, u, qb);
     const double P = rho * T;
     double dfac;
     const double fac = viscosity_factor(cp, T, dfac);
@@ -167,7 +167,7 @@ __global__ void __launch_bounds__(256) k_collide_vjp(int64_t N, CollisionParams 
 
     Bracket br[4];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) br[s] = bracket(u2, th, SHELL_X2[s]);
+    for (int s = 0; s < 4; ++s) br[s] = bracket(u2, th, vs::SHELL_X2[s]);
 
     // ---- reverse sweep over the velocities (own population) ----
     double s_ka = 0, s_heq = 0, s_eqT = 0, s_u2 = 0, s_th = 0;
@@ -205,7 +205,7 @@ __global__ void __launch_bounds__(256) k_collide_vjp(int64_t N, CollisionParams 
         ubar[1] = fma(gu, vs::T.xi[i][1], ubar[1]);
         ubar[2] = fma(gu, vs::T.xi[i][2], ubar[2]);
         const double sp = ai + aj, sm = ai - aj;
-        const double x2 = SHELL_X2[vs::T.shell[i]];
+        const double x2 = vs::SHELL_X2[vs::T.shell[i]];
         s_u2 += wre * (sp * (b.d0u + c * c * D2U) + sm * c * D1U);
         s_th += wre * (sp * (b.d0t + c * c * d2t_of(x2)) + sm * c * d1t_of(x2));
 #pragma unroll

@@ -32,6 +32,7 @@ struct sllbm_ctx {
     void *d_cw = nullptr;         // cell-table weights, storage type
     hipStream_t stream = nullptr;
     size_t elem = 8;
+    bool d2 = false;              // two-dimensional lattice (D2Q19, N_z = 1)
     // State buffers: buf[cur] holds the pre-collision state X_k; the other
     // buffer receives C(X_k) during a step.
     void *buf[2] = {nullptr, nullptr};
@@ -168,6 +169,13 @@ NodeTables<S> node_tables(const sllbm_ctx *c, int dir)
 
 bool is_fp64(const sllbm_ctx *c) { return c->cfg.precision == SLLBM_FP64; }
 
+// calls that exist for the three-dimensional lattice only (adjoint, loss,
+// diagnostics, graded meshes)
+int refuse_2d(sllbm_ctx *c, const char *what)
+{
+    return fail(c, SLLBM_EINVAL, std::string(what) + " is not available on the two-dimensional lattice (D2Q19)");
+}
+
 const double *graded_hw(const sllbm_ctx *c) { return c->graded ? c->d_hw : nullptr; }
 
 void *other(sllbm_ctx *c) { return c->buf[1 - c->cur]; }
@@ -284,13 +292,19 @@ extern "C" {
 int sllbm_velocity_set(double *xi, double *w)
 {
     if (!xi || !w) return SLLBM_EINVAL;
+    return sllbm_lattice(SLLBM_D3Q45, xi, w);
+}
+
+int sllbm_lattice(int32_t velocity_set, double *xi, double *w)
+{
+    if (!xi || !w) return -1;
     VelocitySet vs;
-    build_velocity_set(vs);
-    for (int i = 0; i < Q; ++i) {
+    if (!build_velocity_set(vs, velocity_set)) return -1;
+    for (int i = 0; i < vs.q; ++i) {
         for (int k = 0; k < 3; ++k) xi[3 * i + k] = vs.xi[i][k];
         w[i] = vs.w[i];
     }
-    return Q;
+    return vs.q;
 }
 
 const char *sllbm_last_error(const sllbm_ctx *ctx) { return ctx ? ctx->err.c_str() : g_create_error.c_str(); }
@@ -299,7 +313,7 @@ int64_t sllbm_num_nodes(const sllbm_ctx *ctx) { return ctx ? ctx->geo.nodes : -1
 
 int64_t sllbm_state_bytes(const sllbm_ctx *ctx)
 {
-    return ctx ? static_cast<int64_t>(2 * Q) * ctx->geo.nodes * static_cast<int64_t>(ctx->elem) : -1;
+    return ctx ? static_cast<int64_t>(2 * ctx->vs.q) * ctx->geo.nodes * static_cast<int64_t>(ctx->elem) : -1;
 }
 
 int sllbm_create(const sllbm_config *cfg, sllbm_ctx **out)
@@ -307,15 +321,18 @@ int sllbm_create(const sllbm_config *cfg, sllbm_ctx **out)
     if (!out) return fail(nullptr, SLLBM_EINVAL, "out is NULL");
     *out = nullptr;
     if (!cfg) return fail(nullptr, SLLBM_EINVAL, "cfg is NULL");
-    if (cfg->velocity_set != SLLBM_D3Q45) return fail(nullptr, SLLBM_EINVAL, "velocity_set must be SLLBM_D3Q45");
+    if (cfg->velocity_set != SLLBM_D3Q45 && cfg->velocity_set != SLLBM_D2Q19)
+        return fail(nullptr, SLLBM_EINVAL, "velocity_set must be SLLBM_D3Q45 or SLLBM_D2Q19");
+    const bool d2 = cfg->velocity_set == SLLBM_D2Q19;
     if (cfg->order < 1 || cfg->order > MAXP) return fail(nullptr, SLLBM_EINVAL, "order must be in 1..6");
-    for (int a = 0; a < 3; ++a) {
+    for (int a = 0; a < (d2 ? 2 : 3); ++a) {
         if (cfg->n_el[a] < 1) return fail(nullptr, SLLBM_EINVAL, "n_el must be >= 1");
         if (!(cfg->length[a] > 0.0) || !std::isfinite(cfg->length[a]))
             return fail(nullptr, SLLBM_EINVAL, "length must be positive");
     }
-    const int64_t nodes = static_cast<int64_t>(cfg->n_el[0]) * cfg->order * cfg->n_el[1] * cfg->order *
-                          cfg->n_el[2] * cfg->order;
+    if (d2 && cfg->n_el[2] != 1) return fail(nullptr, SLLBM_EINVAL, "n_el[2] must be 1 for SLLBM_D2Q19");
+    const int64_t nz = d2 ? 1 : static_cast<int64_t>(cfg->n_el[2]) * cfg->order;
+    const int64_t nodes = static_cast<int64_t>(cfg->n_el[0]) * cfg->order * cfg->n_el[1] * cfg->order * nz;
     if (static_cast<int64_t>(cfg->n_el[0]) * cfg->order > (1 << 20) ||
         static_cast<int64_t>(cfg->n_el[1]) * cfg->order > (1 << 20) ||
         static_cast<int64_t>(cfg->n_el[2]) * cfg->order > (1 << 20) || nodes >= (int64_t(1) << 31))
@@ -344,23 +361,26 @@ int sllbm_create(const sllbm_config *cfg, sllbm_ctx **out)
     sllbm_ctx *c = new sllbm_ctx();
     c->cfg = *cfg;
     c->elem = cfg->precision == SLLBM_FP64 ? sizeof(double) : sizeof(float);
+    c->d2 = d2;
     Geometry &g = c->geo;
     g.p = cfg->order;
     for (int a = 0; a < 3; ++a) {
         g.nel[a] = cfg->n_el[a];
         g.N[a] = cfg->n_el[a] * cfg->order;
     }
+    if (d2) g.N[2] = 1;                       // one node across z
     g.nodes = nodes;
     c->cp.dt = cfg->dt;
     c->cp.Cv = 1.0 / (cfg->gamma - 1.0);
-    c->cp.beta = 2.0 * c->cp.Cv - 3.0;
+    c->cp.beta = 2.0 * c->cp.Cv - (d2 ? 2.0 : 3.0);   // g^eq = (2 C_v - D) T f^eq
     c->cp.inv_pr = 1.0 / cfg->prandtl;
     c->cp.mu_inf = cfg->mu_inf;
     c->cp.law = cfg->viscosity_law;
 
-    build_velocity_set(c->vs);
+    build_velocity_set(c->vs, cfg->velocity_set);
     double h[3];
     for (int a = 0; a < 3; ++a) c->h[a] = h[a] = cfg->length[a] / cfg->n_el[a];
+    if (d2) c->h[2] = h[2] = 1.0;             // no z axis: unit width (xi_z = 0)
 
     auto bail = [&](int rc) {
         g_create_error = c->err;
@@ -385,7 +405,7 @@ int sllbm_create(const sllbm_config *cfg, sllbm_ctx **out)
     for (int a = 0; a < 3; ++a)
         for (int n = 0; n < g.N[a]; ++n) {
             const int l = n % p;
-            nodew.push_back(0.5 * h[a] * (l == 0 ? cc[0] + cc[p] : cc[l]));
+            nodew.push_back(d2 && a == 2 ? 1.0 : 0.5 * h[a] * (l == 0 ? cc[0] + cc[p] : cc[l]));
         }
     std::vector<double> dmat((p + 1) * (p + 1));
     for (int k = 0; k <= p; ++k) {
@@ -451,6 +471,7 @@ int sllbm_set_mesh(sllbm_ctx *ctx, const double *widths_x, const double *widths_
 {
     if (!ctx) return SLLBM_EINVAL;
     const double *wd[3] = {widths_x, widths_y, widths_z};
+    if (ctx->d2) return refuse_2d(ctx, "sllbm_set_mesh");
     if (!wd[0] && !wd[1] && !wd[2]) return fail(ctx, SLLBM_EINVAL, "set_mesh: no graded axis given");
     std::vector<double> faces[3];
     for (int a = 0; a < 3; ++a) {
@@ -506,11 +527,18 @@ int sllbm_init_equilibrium(sllbm_ctx *ctx, const double *rho, const double *u, c
     if (!ctx) return SLLBM_EINVAL;
     if (!rho || !u || !T) return fail(ctx, SLLBM_EINVAL, "NULL field");
     DeviceGuard guard(ctx->cfg.device);
-    hipError_t e = is_fp64(ctx)
-        ? Launch<double>::init_equilibrium(ctx->geo, ctx->cp, rho, u, T, static_cast<double *>(ctx->buf[ctx->cur]),
-                                           ctx->stream)
-        : Launch<float>::init_equilibrium(ctx->geo, ctx->cp, rho, u, T, static_cast<float *>(ctx->buf[ctx->cur]),
-                                          ctx->stream);
+    void *st = ctx->buf[ctx->cur];
+    hipError_t e;
+    if (ctx->d2)
+        e = is_fp64(ctx) ? Launch2D<double>::init_equilibrium(ctx->geo, ctx->cp, rho, u, T, static_cast<double *>(st),
+                                                              ctx->stream)
+                         : Launch2D<float>::init_equilibrium(ctx->geo, ctx->cp, rho, u, T, static_cast<float *>(st),
+                                                             ctx->stream);
+    else
+        e = is_fp64(ctx) ? Launch<double>::init_equilibrium(ctx->geo, ctx->cp, rho, u, T, static_cast<double *>(st),
+                                                            ctx->stream)
+                         : Launch<float>::init_equilibrium(ctx->geo, ctx->cp, rho, u, T, static_cast<float *>(st),
+                                                           ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "init_equilibrium");
     ctx->has_state = true;
     return SLLBM_OK;
@@ -541,6 +569,13 @@ int sllbm_get_state(sllbm_ctx *ctx, void *state)
 
 static hipError_t collide_into(sllbm_ctx *c, const void *in, void *out)
 {
+    if (c->d2) {
+        if (is_fp64(c))
+            return Launch2D<double>::collide_into(c->geo, c->cp, static_cast<const double *>(in),
+                                                  static_cast<double *>(out), c->stream);
+        return Launch2D<float>::collide_into(c->geo, c->cp, static_cast<const float *>(in), static_cast<float *>(out),
+                                             c->stream);
+    }
     if (is_fp64(c))
         return Launch<double>::collide_into(c->geo, c->cp, static_cast<const double *>(in), static_cast<double *>(out),
                                             c->stream);
@@ -550,6 +585,13 @@ static hipError_t collide_into(sllbm_ctx *c, const void *in, void *out)
 
 static hipError_t stream_into(sllbm_ctx *c, const void *in, void *out)
 {
+    if (c->d2) {
+        if (is_fp64(c))
+            return launch_stream_2d<double>(c->geo, cell_tables<double>(c), static_cast<const double *>(in),
+                                            static_cast<double *>(out), c->stream);
+        return launch_stream_2d<float>(c->geo, cell_tables<float>(c), static_cast<const float *>(in),
+                                       static_cast<float *>(out), c->stream);
+    }
     if (c->graded) {
         if (is_fp64(c))
             return launch_stream_graded<double>(c->geo, node_tables<double>(c, 0), static_cast<const double *>(in),
@@ -691,11 +733,18 @@ int sllbm_moments(sllbm_ctx *ctx, double *rho, double *u, double *T)
     if (!ctx) return SLLBM_EINVAL;
     if (!ctx->has_state) return fail(ctx, SLLBM_ESTATE, "no state set");
     DeviceGuard guard(ctx->cfg.device);
-    hipError_t e = is_fp64(ctx)
-        ? Launch<double>::moments(ctx->geo, ctx->cp, static_cast<const double *>(ctx->buf[ctx->cur]), rho, u, T,
-                                  ctx->stream)
-        : Launch<float>::moments(ctx->geo, ctx->cp, static_cast<const float *>(ctx->buf[ctx->cur]), rho, u, T,
-                                 ctx->stream);
+    const void *st = ctx->buf[ctx->cur];
+    hipError_t e;
+    if (ctx->d2)
+        e = is_fp64(ctx) ? Launch2D<double>::moments(ctx->geo, ctx->cp, static_cast<const double *>(st), rho, u, T,
+                                                     ctx->stream)
+                         : Launch2D<float>::moments(ctx->geo, ctx->cp, static_cast<const float *>(st), rho, u, T,
+                                                    ctx->stream);
+    else
+        e = is_fp64(ctx) ? Launch<double>::moments(ctx->geo, ctx->cp, static_cast<const double *>(st), rho, u, T,
+                                                   ctx->stream)
+                         : Launch<float>::moments(ctx->geo, ctx->cp, static_cast<const float *>(st), rho, u, T,
+                                                  ctx->stream);
     return check_launch(ctx, e, "moments");
 }
 
@@ -705,11 +754,18 @@ int sllbm_totals(sllbm_ctx *ctx, double *out)
     if (!out) return fail(ctx, SLLBM_EINVAL, "NULL out");
     if (!ctx->has_state) return fail(ctx, SLLBM_ESTATE, "no state set");
     DeviceGuard guard(ctx->cfg.device);
-    hipError_t e = is_fp64(ctx)
-        ? Launch<double>::totals(ctx->geo, ctx->cp, static_cast<const double *>(ctx->buf[ctx->cur]), ctx->d_nodew,
-                                 ctx->d_partials, RED_BLOCKS, ctx->d_small, ctx->stream)
-        : Launch<float>::totals(ctx->geo, ctx->cp, static_cast<const float *>(ctx->buf[ctx->cur]), ctx->d_nodew,
-                                ctx->d_partials, RED_BLOCKS, ctx->d_small, ctx->stream);
+    const void *st = ctx->buf[ctx->cur];
+    hipError_t e;
+    if (ctx->d2)
+        e = is_fp64(ctx) ? Launch2D<double>::totals(ctx->geo, static_cast<const double *>(st), ctx->d_nodew,
+                                                    ctx->d_partials, RED_BLOCKS, ctx->d_small, ctx->stream)
+                         : Launch2D<float>::totals(ctx->geo, static_cast<const float *>(st), ctx->d_nodew,
+                                                   ctx->d_partials, RED_BLOCKS, ctx->d_small, ctx->stream);
+    else
+        e = is_fp64(ctx) ? Launch<double>::totals(ctx->geo, ctx->cp, static_cast<const double *>(st), ctx->d_nodew,
+                                                  ctx->d_partials, RED_BLOCKS, ctx->d_small, ctx->stream)
+                         : Launch<float>::totals(ctx->geo, ctx->cp, static_cast<const float *>(st), ctx->d_nodew,
+                                                 ctx->d_partials, RED_BLOCKS, ctx->d_small, ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "totals");
     if ((e = hipMemcpyAsync(out, ctx->d_small, 5 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream)) !=
             hipSuccess ||
@@ -724,6 +780,7 @@ int sllbm_stream(sllbm_ctx *ctx, const void *in, void *out, int32_t transpose)
 {
     if (!ctx) return SLLBM_EINVAL;
     if (!in || !out || in == out) return fail(ctx, SLLBM_EINVAL, "bad stream buffers");
+    if (transpose && ctx->d2) return refuse_2d(ctx, "transposed streaming");
     DeviceGuard guard(ctx->cfg.device);
     if (!transpose) return check_launch(ctx, stream_into(ctx, in, out), "stream");
     return check_launch(ctx, stream_t_into(ctx, in, out), "stream");
@@ -734,10 +791,7 @@ int sllbm_collide(sllbm_ctx *ctx, void *state)
     if (!ctx) return SLLBM_EINVAL;
     if (!state) return fail(ctx, SLLBM_EINVAL, "NULL state");
     DeviceGuard guard(ctx->cfg.device);
-    hipError_t e = is_fp64(ctx)
-        ? Launch<double>::collide_only(ctx->geo, ctx->cp, static_cast<double *>(state), ctx->stream)
-        : Launch<float>::collide_only(ctx->geo, ctx->cp, static_cast<float *>(state), ctx->stream);
-    return check_launch(ctx, e, "collide");
+    return check_launch(ctx, collide_into(ctx, state, state), "collide");
 }
 
 }  // extern "C"
@@ -751,6 +805,7 @@ int sllbm_loss(sllbm_ctx *ctx, const void *state, double *out)
 {
     if (!ctx) return SLLBM_EINVAL;
     if (!state || !out) return fail(ctx, SLLBM_EINVAL, "NULL argument");
+    if (ctx->d2) return refuse_2d(ctx, "sllbm_loss");
     DeviceGuard guard(ctx->cfg.device);
     hipError_t e = is_fp64(ctx)
         ? Launch<double>::loss(ctx->geo, static_cast<const double *>(state), ctx->d_dmat, ctx->d_ccw, ctx->h,
@@ -771,6 +826,7 @@ int sllbm_diagnostics(sllbm_ctx *ctx, const void *state, double *out)
 {
     if (!ctx) return SLLBM_EINVAL;
     if (!out) return fail(ctx, SLLBM_EINVAL, "NULL out");
+    if (ctx->d2) return refuse_2d(ctx, "sllbm_diagnostics");
     if (!state && !ctx->has_state) return fail(ctx, SLLBM_ESTATE, "no state set");
     DeviceGuard guard(ctx->cfg.device);
     const void *st = state ? state : ctx->buf[ctx->cur];
@@ -795,6 +851,7 @@ int sllbm_loss_grad(sllbm_ctx *ctx, const void *state, void *lam)
 {
     if (!ctx) return SLLBM_EINVAL;
     if (!state || !lam || state == lam) return fail(ctx, SLLBM_EINVAL, "bad loss_grad buffers");
+    if (ctx->d2) return refuse_2d(ctx, "sllbm_loss_grad");
     DeviceGuard guard(ctx->cfg.device);
     hipError_t e = is_fp64(ctx)
         ? Launch<double>::loss_grad(ctx->geo, static_cast<const double *>(state), ctx->d_dmat, ctx->d_ccw,
@@ -813,6 +870,7 @@ int sllbm_adjoint_step(sllbm_ctx *ctx, const void *state_n, const void *lam_next
     if (!ctx) return SLLBM_EINVAL;
     if (!state_n || !lam_next || !lam_out) return fail(ctx, SLLBM_EINVAL, "NULL argument");
     if (lam_out == lam_next || lam_out == state_n) return fail(ctx, SLLBM_EINVAL, "lam_out aliases an input");
+    if (ctx->d2) return refuse_2d(ctx, "sllbm_adjoint_step");
     DeviceGuard guard(ctx->cfg.device);
     hipError_t e = stream_t_into(ctx, lam_next, lam_out);
     if (e != hipSuccess) return hip_fail(ctx, e, "adjoint_step (transposed streaming)");
@@ -828,6 +886,7 @@ int sllbm_moments_vjp(sllbm_ctx *ctx, const double *drho, const double *du, cons
 {
     if (!ctx) return SLLBM_EINVAL;
     if (!lam) return fail(ctx, SLLBM_EINVAL, "NULL lam");
+    if (ctx->d2) return refuse_2d(ctx, "sllbm_moments_vjp");
     if (!ctx->has_state) return fail(ctx, SLLBM_ESTATE, "no state set");
     DeviceGuard guard(ctx->cfg.device);
     hipError_t e = is_fp64(ctx)
@@ -843,6 +902,7 @@ int sllbm_init_equilibrium_vjp(sllbm_ctx *ctx, const double *rho, const double *
 {
     if (!ctx) return SLLBM_EINVAL;
     if (!rho || !u || !T || !lam0) return fail(ctx, SLLBM_EINVAL, "NULL argument");
+    if (ctx->d2) return refuse_2d(ctx, "sllbm_init_equilibrium_vjp");
     DeviceGuard guard(ctx->cfg.device);
     hipError_t e = is_fp64(ctx)
         ? Launch<double>::init_equilibrium_vjp(ctx->geo, ctx->cp, rho, u, T, static_cast<const double *>(lam0),

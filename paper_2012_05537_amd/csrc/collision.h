@@ -11,8 +11,11 @@
 //    M0..M3 of h; Qbar[h^eq] = 0 identically, so Qbar^neq = Qbar[h].
 //  * Equilibrium (Eq. (6), App. A/B) in scalar form: with c = xi.u,
 //      f^eq = w rho (A0 + A1 c + A2 c^2 + c^3/6 + c^4/24),
-//    A0..A2 depending on |u|^2, T - 1 and the shell radius |xi|^2 only, and
+//    A0..A2 depending on |u|^2, T - 1, the shell radius |xi|^2 and the
+//    dimension D only (the traces of the Hermite tensors), and
 //    g^eq = (2 C_v - D) T f^eq.
+// Every function is generic over the lattice L (D3Q45 or D2Q19 traits of
+// velset.h); in two dimensions the z components are absent.
 //  * h* = (w/3!) Qbar : H^(3)(xi); odd in xi, so h*_-i = -h*_i.
 //  * Relaxation h' = h + (h^eq - h)/tau + (1/tau - 1/tau_Pr) h*.
 // In FP32-mixed storage (S = float) the moments, transport coefficients,
@@ -35,40 +38,42 @@ __device__ __forceinline__ double viscosity_of(const CollisionParams &cp, double
     return cp.mu_inf * (1.0 + SUTHERLAND_S) * T * sqrt(T) / (T + SUTHERLAND_S);
 }
 
-// Raw moments of one population array over the pairs (d = odd part, s = even part).
+// Raw moments of one population array over the pairs (d = odd part, s =
+// even part).  m2 in the 3-D component order xx xy xz yy yz zz (the z
+// entries stay zero in two dimensions); m3 over the lattice's unique
+// rank-3 components.
+template <class L>
 struct RawMoments {
-    double m0, m1[3], m2[6], m3[10];
+    double m0, m1[3], m2[6], m3[L::NM3];
 };
 
-template <typename S>
-__device__ __forceinline__ RawMoments raw_moments(const S (&h)[vs::Q])
+constexpr int IDX2[6][2] = {{0, 0}, {0, 1}, {0, 2}, {1, 1}, {1, 2}, {2, 2}};
+
+template <class L, typename S>
+__device__ __forceinline__ RawMoments<L> raw_moments(const S (&h)[L::Q])
 {
-    RawMoments r;
+    RawMoments<L> r;
     r.m0 = static_cast<double>(h[0]);
 #pragma unroll
     for (int k = 0; k < 3; ++k) r.m1[k] = 0.0;
 #pragma unroll
     for (int k = 0; k < 6; ++k) r.m2[k] = 0.0;
 #pragma unroll
-    for (int k = 0; k < 10; ++k) r.m3[k] = 0.0;
+    for (int k = 0; k < L::NM3; ++k) r.m3[k] = 0.0;
 #pragma unroll
-    for (int q = 0; q < 22; ++q) {
-        const int i = vs::PAIRS.a[q], j = vs::PAIRS.b[q];
+    for (int q = 0; q < L::NPAIR; ++q) {
+        const int i = L::PAIRS.a[q], j = L::PAIRS.b[q];
         const double hi = static_cast<double>(h[i]), hj = static_cast<double>(h[j]);
         const double s = hi + hj, d = hi - hj;
-        const double x = vs::T.xi[i][0], y = vs::T.xi[i][1], z = vs::T.xi[i][2];
+        const double *x = L::T.xi[i];
         r.m0 += s;
-        r.m1[0] = fma(d, x, r.m1[0]);
-        r.m1[1] = fma(d, y, r.m1[1]);
-        r.m1[2] = fma(d, z, r.m1[2]);
-        r.m2[0] = fma(s, x * x, r.m2[0]);
-        r.m2[1] = fma(s, x * y, r.m2[1]);
-        r.m2[2] = fma(s, x * z, r.m2[2]);
-        r.m2[3] = fma(s, y * y, r.m2[3]);
-        r.m2[4] = fma(s, y * z, r.m2[4]);
-        r.m2[5] = fma(s, z * z, r.m2[5]);
 #pragma unroll
-        for (int m = 0; m < 10; ++m) r.m3[m] = fma(d, vs::H3.mono[i][m], r.m3[m]);
+        for (int a = 0; a < L::D; ++a) r.m1[a] = fma(d, x[a], r.m1[a]);
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+            if (IDX2[k][1] < L::D) r.m2[k] = fma(s, x[IDX2[k][0]] * x[IDX2[k][1]], r.m2[k]);
+#pragma unroll
+        for (int m = 0; m < L::NM3; ++m) r.m3[m] = fma(d, L::H3.mono[i][m], r.m3[m]);
     }
     return r;
 }
@@ -80,11 +85,12 @@ __host__ __device__ constexpr int sym2(int a, int b)
 }
 
 // Qbar_abc = M3 - sym3(u M2) + sym3(u u M1) - M0 u u u
-__device__ __forceinline__ void centred_third(const RawMoments &r, const double (&u)[3], double (&qb)[10])
+template <class L>
+__device__ __forceinline__ void centred_third(const RawMoments<L> &r, const double (&u)[3], double (&qb)[L::NM3])
 {
 #pragma unroll
-    for (int m = 0; m < 10; ++m) {
-        const int a = vs::IDX3[m][0], b = vs::IDX3[m][1], c = vs::IDX3[m][2];
+    for (int m = 0; m < L::NM3; ++m) {
+        const int a = L::IDX3[m][0], b = L::IDX3[m][1], c = L::IDX3[m][2];
         qb[m] = r.m3[m] - (u[a] * r.m2[sym2(b, c)] + u[b] * r.m2[sym2(a, c)] + u[c] * r.m2[sym2(a, b)]) +
                 (u[a] * u[b] * r.m1[c] + u[a] * u[c] * r.m1[b] + u[b] * u[c] * r.m1[a]) - r.m0 * u[a] * u[b] * u[c];
     }
@@ -94,17 +100,20 @@ struct EqShell {
     double a0, a1, a2;
 };
 
-__device__ __forceinline__ EqShell eq_shell(double u2, double th, double x2)
+// Hermite series to fourth order contracted in the scalar invariants
+// c = xi.u, |u|^2, |xi|^2 and theta = T - 1; the traces of H^(n) bring in
+// D, D + 2 and D + 4 (for D = 3: x2 - 3, x2 - 5, x2 - 7, x2^2 - 10 x2 + 15).
+template <int D>
+__host__ __device__ __forceinline__ EqShell eq_shell(double u2, double th, double x2)
 {
+    constexpr double d0 = D, d2 = D + 2, d4 = D + 4;
     EqShell e;
-    e.a0 = 1.0 - 0.5 * u2 + 0.5 * th * (x2 - 3.0) + 0.125 * u2 * u2 - 0.25 * th * u2 * (x2 - 5.0) +
-           0.125 * th * th * (x2 * x2 - 10.0 * x2 + 15.0);
-    e.a1 = 1.0 - 0.5 * u2 + 0.5 * th * (x2 - 5.0);
-    e.a2 = 0.5 - 0.25 * u2 + 0.25 * th * (x2 - 7.0);
+    e.a0 = 1.0 - 0.5 * u2 + 0.5 * th * (x2 - d0) + 0.125 * u2 * u2 - 0.25 * th * u2 * (x2 - d2) +
+           0.125 * th * th * (x2 * x2 - 2.0 * d2 * x2 + d0 * d2);
+    e.a1 = 1.0 - 0.5 * u2 + 0.5 * th * (x2 - d2);
+    e.a2 = 0.5 - 0.25 * u2 + 0.25 * th * (x2 - d4);
     return e;
 }
-
-constexpr double SHELL_X2[4] = {0.0, 3.0, 15.0, 9.0};
 
 
 // Collision of one node whose two populations are held by a lane pair: the
@@ -113,26 +122,27 @@ constexpr double SHELL_X2[4] = {0.0, 3.0, 15.0, 9.0};
 // parts (tr M2[f] and M0[g]); each lane then builds Qbar of its own
 // population and relaxes it (g^eq = (2 C_v - D) T f^eq).  Both lanes of a
 // pair must be active.
-template <typename S>
-__device__ __forceinline__ void collide_half(S (&v)[vs::Q], bool is_g, const CollisionParams &cp)
+template <class L, typename S>
+__device__ __forceinline__ void collide_half(S (&v)[L::Q], bool is_g, const CollisionParams &cp)
 {
     using R = S;
-    const RawMoments rm = raw_moments(v);
-    const double ktr = rm.m2[0] + rm.m2[3] + rm.m2[5];
+    constexpr bool D3 = L::D == 3;
+    const RawMoments<L> rm = raw_moments<L>(v);
+    const double ktr = D3 ? rm.m2[0] + rm.m2[3] + rm.m2[5] : rm.m2[0] + rm.m2[3];
     const double p_m0 = __shfl_xor(rm.m0, 1);
     const double p_j0 = __shfl_xor(rm.m1[0], 1);
     const double p_j1 = __shfl_xor(rm.m1[1], 1);
-    const double p_j2 = __shfl_xor(rm.m1[2], 1);
+    const double p_j2 = D3 ? __shfl_xor(rm.m1[2], 1) : 0.0;
     const double p_tr = __shfl_xor(ktr, 1);
     const double rho = is_g ? p_m0 : rm.m0;
     const double ir = 1.0 / rho;
     const double u[3] = {(is_g ? p_j0 : rm.m1[0]) * ir, (is_g ? p_j1 : rm.m1[1]) * ir,
-                         (is_g ? p_j2 : rm.m1[2]) * ir};
+                         D3 ? (is_g ? p_j2 : rm.m1[2]) * ir : 0.0};
     const double K = is_g ? p_tr + rm.m0 : ktr + p_m0;          // 2 rho E
-    const double u2 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    const double u2 = D3 ? u[0] * u[0] + u[1] * u[1] + u[2] * u[2] : u[0] * u[0] + u[1] * u[1];
     const double T = (K * ir - u2) / (2.0 * cp.Cv);
-    double qb[10];
-    centred_third(rm, u, qb);
+    double qb[L::NM3];
+    centred_third<L>(rm, u, qb);
 
     const double P = rho * T;
     const double tau = viscosity_of(cp, T) / (P * cp.dt) + 0.5;
@@ -142,37 +152,37 @@ __device__ __forceinline__ void collide_half(S (&v)[vs::Q], bool is_g, const Col
     const double th = T - 1.0;
     const R eqs = static_cast<R>(is_g ? cp.beta * T : 1.0);
 
-    R A0[4], A1[4], A2[4];
+    R A0[L::NSHELL], A1[L::NSHELL], A2[L::NSHELL];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-        const EqShell e = eq_shell(u2, th, SHELL_X2[s]);
+    for (int s = 0; s < L::NSHELL; ++s) {
+        const EqShell e = eq_shell<L::D>(u2, th, L::SHELL_X2[s]);
         A0[s] = static_cast<R>(e.a0 * rho);
         A1[s] = static_cast<R>(e.a1 * rho);
         A2[s] = static_cast<R>(e.a2 * rho);
     }
     const R rho6 = static_cast<R>(rho / 6.0), rho24 = static_cast<R>(rho / 24.0);
-    R qr[10];
+    R qr[L::NM3];
 #pragma unroll
-    for (int m = 0; m < 10; ++m) qr[m] = static_cast<R>(qb[m]);
+    for (int m = 0; m < L::NM3; ++m) qr[m] = static_cast<R>(qb[m]);
     const R ux = static_cast<R>(u[0]), uy = static_cast<R>(u[1]), uz = static_cast<R>(u[2]);
     {
-        const R heq = eqs * static_cast<R>(vs::T.w[0]) * A0[0];
+        const R heq = eqs * static_cast<R>(L::T.w[0]) * A0[0];
         const R vi = v[0];
         v[0] = fma(om, heq - vi, vi);
     }
 #pragma unroll
-    for (int q = 0; q < 22; ++q) {
-        const int i = vs::PAIRS.a[q], j = vs::PAIRS.b[q];
-        const int s = vs::T.shell[i];
-        const R c = static_cast<R>(vs::T.xi[i][0]) * ux + static_cast<R>(vs::T.xi[i][1]) * uy +
-                    static_cast<R>(vs::T.xi[i][2]) * uz;
+    for (int q = 0; q < L::NPAIR; ++q) {
+        const int i = L::PAIRS.a[q], j = L::PAIRS.b[q];
+        const int s = L::T.shell[i];
+        R c = static_cast<R>(L::T.xi[i][0]) * ux + static_cast<R>(L::T.xi[i][1]) * uy;
+        if constexpr (D3) c += static_cast<R>(L::T.xi[i][2]) * uz;
         const R c2 = c * c;
         const R even = fma(c2, fma(c2, rho24, A2[s]), A0[s]);
         const R odd = c * fma(c2, rho6, A1[s]);
-        const R we = eqs * static_cast<R>(vs::T.w[i]);
+        const R we = eqs * static_cast<R>(L::T.w[i]);
         R hs = 0;
 #pragma unroll
-        for (int m = 0; m < 10; ++m) hs = fma(static_cast<R>(vs::H3.c[i][m]), qr[m], hs);
+        for (int m = 0; m < L::NM3; ++m) hs = fma(static_cast<R>(L::H3.c[i][m]), qr[m], hs);
         const R vi = v[i], vj = v[j];
         v[i] = fma(kap, hs, fma(om, fma(we, even, we * odd) - vi, vi));
         v[j] = fma(-kap, hs, fma(om, fma(we, even, -we * odd) - vj, vj));

@@ -14,28 +14,30 @@ namespace sllbm {
 // Collision of a whole state (Eq. (5) right-hand side with App. D), two
 // lanes per node (f on the even lane, g on the odd one).  in and out may be
 // the same buffer (each lane reads its 45 values first).
-template <typename S>
+template <typename S, class L>
 __global__ void __launch_bounds__(256) k_collide(int64_t N, CollisionParams cp, const S *in, S *out)
 {
+    constexpr int NQ = L::Q;
     const int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
     const int64_t n = t >> 1;
     const int pop = static_cast<int>(t & 1);
     if (n >= N) return;                    // both lanes of a pair leave together
-    const int64_t o = static_cast<int64_t>(pop) * Q * N + n;
+    const int64_t o = static_cast<int64_t>(pop) * NQ * N + n;
     const S *p = in + o;
-    S v[Q];
+    S v[NQ];
 #pragma unroll
-    for (int i = 0; i < Q; ++i) v[i] = p[static_cast<int64_t>(i) * N];
-    collide_half<S>(v, pop != 0, cp);
+    for (int i = 0; i < NQ; ++i) v[i] = p[static_cast<int64_t>(i) * N];
+    collide_half<L, S>(v, pop != 0, cp);
     // derive the store addresses afresh: otherwise the 45 load addresses stay
     // live through the collision (90 registers)
     S *d = out + o;
     asm volatile("" : "+v"(d));
 #pragma unroll
-    for (int i = 0; i < Q; ++i) d[static_cast<int64_t>(i) * N] = v[i];
+    for (int i = 0; i < NQ; ++i) d[static_cast<int64_t>(i) * N] = v[i];
 }
 
-template <typename S>
+// u: [D][N] (the lattice's dimension)
+template <typename S, class L>
 __global__ void __launch_bounds__(256) k_init_equilibrium(int64_t N, CollisionParams cp,
                                                           const double *__restrict__ rho,
                                                           const double *__restrict__ u,
@@ -43,40 +45,41 @@ __global__ void __launch_bounds__(256) k_init_equilibrium(int64_t N, CollisionPa
 {
     for (int64_t n = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; n < N;
          n += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-        const double r = rho[n], ux = u[n], uy = u[N + n], uz = u[2 * N + n], Tn = T[n];
+        const double r = rho[n], ux = u[n], uy = u[N + n], uz = L::D == 3 ? u[2 * N + n] : 0.0, Tn = T[n];
         const double u2 = ux * ux + uy * uy + uz * uz;
         const double th = Tn - 1.0;
         const double betaT = cp.beta * Tn;
 #pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            const double c = vs::T.xi[i][0] * ux + vs::T.xi[i][1] * uy + vs::T.xi[i][2] * uz;
-            const EqShell e = eq_shell(u2, th, vs::T.x2[i]);
+        for (int i = 0; i < L::Q; ++i) {
+            const double c = L::T.xi[i][0] * ux + L::T.xi[i][1] * uy + L::T.xi[i][2] * uz;
+            const EqShell e = eq_shell<L::D>(u2, th, L::T.x2[i]);
             const double br = fma(c, fma(c, fma(c, fma(c, 1.0 / 24.0, 1.0 / 6.0), e.a2), e.a1), e.a0);
-            const double feq = vs::T.w[i] * r * br;
+            const double feq = L::T.w[i] * r * br;
             state[static_cast<int64_t>(i) * N + n] = static_cast<S>(feq);
-            state[static_cast<int64_t>(Q + i) * N + n] = static_cast<S>(betaT * feq);
+            state[static_cast<int64_t>(L::Q + i) * N + n] = static_cast<S>(betaT * feq);
         }
     }
 }
 
-// rho, j, 2 rho E of node n (Eq. (7)), in double
-template <typename S>
+// rho, j, 2 rho E of node n (Eq. (7)), in double (jz = 0 in two dimensions)
+template <typename S, class L>
 __device__ __forceinline__ void node_sums(const S *__restrict__ state, int64_t N, int64_t n, double &rho,
                                           double &jx, double &jy, double &jz, double &twoE)
 {
     rho = jx = jy = jz = twoE = 0.0;
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
+    for (int i = 0; i < L::Q; ++i) {
         const double fi = static_cast<double>(state[static_cast<int64_t>(i) * N + n]);
         rho += fi;
-        jx = fma(fi, vs::T.xi[i][0], jx);
-        jy = fma(fi, vs::T.xi[i][1], jy);
-        jz = fma(fi, vs::T.xi[i][2], jz);
-        twoE = fma(fi, vs::T.x2[i], twoE) + static_cast<double>(state[static_cast<int64_t>(Q + i) * N + n]);
+        jx = fma(fi, L::T.xi[i][0], jx);
+        jy = fma(fi, L::T.xi[i][1], jy);
+        if constexpr (L::D == 3) jz = fma(fi, L::T.xi[i][2], jz);
+        twoE = fma(fi, L::T.x2[i], twoE) + static_cast<double>(state[static_cast<int64_t>(L::Q + i) * N + n]);
     }
 }
 
-template <typename S>
+// u: [D][N]
+template <typename S, class L>
 __global__ void __launch_bounds__(256) k_moments(int64_t N, CollisionParams cp, const S *__restrict__ state,
                                                  double *__restrict__ rho, double *__restrict__ u,
                                                  double *__restrict__ T)
@@ -84,13 +87,13 @@ __global__ void __launch_bounds__(256) k_moments(int64_t N, CollisionParams cp, 
     for (int64_t n = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; n < N;
          n += static_cast<int64_t>(gridDim.x) * blockDim.x) {
         double r, jx, jy, jz, twoE;
-        node_sums(state, N, n, r, jx, jy, jz, twoE);
+        node_sums<S, L>(state, N, n, r, jx, jy, jz, twoE);
         const double ux = jx / r, uy = jy / r, uz = jz / r;
         if (rho) rho[n] = r;
         if (u) {
             u[n] = ux;
             u[N + n] = uy;
-            u[2 * N + n] = uz;
+            if constexpr (L::D == 3) u[2 * N + n] = uz;
         }
         if (T) T[n] = (twoE / r - (ux * ux + uy * uy + uz * uz)) / (2.0 * cp.Cv);
     }
@@ -116,7 +119,7 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double *red)
 }
 
 // Stage 1 of the totals: per-block weighted sums of rho, rho u, rho E.
-template <typename S>
+template <typename S, class L>
 __global__ void __launch_bounds__(256) k_totals_partial(Geometry geo, const S *__restrict__ state,
                                                         const double *__restrict__ nodew,
                                                         double *__restrict__ partials)
@@ -133,7 +136,7 @@ __global__ void __launch_bounds__(256) k_totals_partial(Geometry geo, const S *_
         const int gz = static_cast<int>(r / geo.N[1]);
         const double W = wx[gx] * wy[gy] * wz[gz];
         double rho, jx, jy, jz, twoE;
-        node_sums(state, N, n, rho, jx, jy, jz, twoE);
+        node_sums<S, L>(state, N, n, rho, jx, jy, jz, twoE);
         acc[0] = fma(W, rho, acc[0]);
         acc[1] = fma(W, jx, acc[1]);
         acc[2] = fma(W, jy, acc[2]);
@@ -177,6 +180,44 @@ static int node_grid(int64_t N)
     return static_cast<int>(b < 8192 ? (b < 1 ? 1 : b) : 8192);
 }
 
+template <typename S, class L>
+static hipError_t collide_lat(const Geometry &g, const CollisionParams &cp, const S *in, S *out, hipStream_t st)
+{
+    const int64_t blocks = (2 * g.nodes + 255) / 256;
+    hipLaunchKernelGGL((k_collide<S, L>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, g.nodes, cp, in,
+                       out);
+    return hipGetLastError();
+}
+
+template <typename S, class L>
+static hipError_t init_lat(const Geometry &g, const CollisionParams &cp, const double *rho, const double *u,
+                           const double *T, S *state, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_init_equilibrium<S, L>), dim3(node_grid(g.nodes)), dim3(256), 0, st, g.nodes, cp, rho, u,
+                       T, state);
+    return hipGetLastError();
+}
+
+template <typename S, class L>
+static hipError_t moments_lat(const Geometry &g, const CollisionParams &cp, const S *state, double *rho, double *u,
+                              double *T, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_moments<S, L>), dim3(node_grid(g.nodes)), dim3(256), 0, st, g.nodes, cp, state, rho, u,
+                       T);
+    return hipGetLastError();
+}
+
+template <typename S, class L>
+static hipError_t totals_lat(const Geometry &g, const S *state, const double *nodew, double *partials, int nblocks,
+                             double *out5, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_totals_partial<S, L>), dim3(nblocks), dim3(256), 0, st, g, state, nodew, partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_reduce_partials<5>), dim3(1), dim3(256), 0, st, partials, nblocks, out5, 0);
+    return hipGetLastError();
+}
+
 template <typename S>
 hipError_t Launch<S>::collide_only(const Geometry &g, const CollisionParams &cp, S *state, hipStream_t st)
 {
@@ -186,41 +227,61 @@ hipError_t Launch<S>::collide_only(const Geometry &g, const CollisionParams &cp,
 template <typename S>
 hipError_t Launch<S>::collide_into(const Geometry &g, const CollisionParams &cp, const S *in, S *out, hipStream_t st)
 {
-    const int64_t blocks = (2 * g.nodes + 255) / 256;
-    hipLaunchKernelGGL((k_collide<S>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, g.nodes, cp, in, out);
-    return hipGetLastError();
+    return collide_lat<S, D3Q45>(g, cp, in, out, st);
 }
 
 template <typename S>
 hipError_t Launch<S>::init_equilibrium(const Geometry &g, const CollisionParams &cp, const double *rho,
                                        const double *u, const double *T, S *state, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_init_equilibrium<S>), dim3(node_grid(g.nodes)), dim3(256), 0, st, g.nodes, cp, rho, u,
-                       T, state);
-    return hipGetLastError();
+    return init_lat<S, D3Q45>(g, cp, rho, u, T, state, st);
 }
 
 template <typename S>
 hipError_t Launch<S>::moments(const Geometry &g, const CollisionParams &cp, const S *state, double *rho,
                               double *u, double *T, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_moments<S>), dim3(node_grid(g.nodes)), dim3(256), 0, st, g.nodes, cp, state, rho, u,
-                       T);
-    return hipGetLastError();
+    return moments_lat<S, D3Q45>(g, cp, state, rho, u, T, st);
 }
 
 template <typename S>
 hipError_t Launch<S>::totals(const Geometry &g, const CollisionParams &, const S *state, const double *nodew,
                              double *partials, int nblocks, double *out5, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_totals_partial<S>), dim3(nblocks), dim3(256), 0, st, g, state, nodew, partials);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_reduce_partials<5>), dim3(1), dim3(256), 0, st, partials, nblocks, out5, 0);
-    return hipGetLastError();
+    return totals_lat<S, D3Q45>(g, state, nodew, partials, nblocks, out5, st);
+}
+
+template <typename S>
+hipError_t Launch2D<S>::collide_into(const Geometry &g, const CollisionParams &cp, const S *in, S *out,
+                                     hipStream_t st)
+{
+    return collide_lat<S, D2Q19>(g, cp, in, out, st);
+}
+
+template <typename S>
+hipError_t Launch2D<S>::init_equilibrium(const Geometry &g, const CollisionParams &cp, const double *rho,
+                                         const double *u, const double *T, S *state, hipStream_t st)
+{
+    return init_lat<S, D2Q19>(g, cp, rho, u, T, state, st);
+}
+
+template <typename S>
+hipError_t Launch2D<S>::moments(const Geometry &g, const CollisionParams &cp, const S *state, double *rho,
+                                double *u, double *T, hipStream_t st)
+{
+    return moments_lat<S, D2Q19>(g, cp, state, rho, u, T, st);
+}
+
+template <typename S>
+hipError_t Launch2D<S>::totals(const Geometry &g, const S *state, const double *nodew, double *partials,
+                               int nblocks, double *out5, hipStream_t st)
+{
+    return totals_lat<S, D2Q19>(g, state, nodew, partials, nblocks, out5, st);
 }
 
 template struct Launch<double>;
 template struct Launch<float>;
+template struct Launch2D<double>;
+template struct Launch2D<float>;
 
 }  // namespace sllbm

@@ -13,6 +13,7 @@
 namespace sllbm {
 
 constexpr int Q = 45;        // discrete velocities (D3Q45)
+constexpr int Q2D = 19;      // discrete velocities of the two-dimensional set (D2Q19)
 constexpr int MAXP = 6;      // largest supported interpolation order
 constexpr int NPAIR = 22;    // velocity pairs (xi, -xi); velocity 0 is the rest velocity
 
@@ -22,12 +23,15 @@ constexpr int NPAIR = 22;    // velocity pairs (xi, -xi); velocity 0 is the rest
 // ---------------------------------------------------------------------------
 
 struct VelocitySet {
-    double xi[Q][3];
+    int q;                    // 45 (D3Q45) or 19 (D2Q19)
+    int dim;
+    double xi[Q][3];          // first q rows used; z = 0 in two dimensions
     double w[Q];
     int opposite[Q];          // index of -xi_i
 };
 
-void build_velocity_set(VelocitySet &vs);
+// set: SLLBM_D3Q45 or SLLBM_D2Q19; false for another value
+bool build_velocity_set(VelocitySet &vs, int set = SLLBM_D3Q45);
 void glc_points(int p, double *t);                       // t_k = (1 - cos(pi k/p))/2
 void lagrange_basis(int p, double s, double *ell);       // ell_k(s) on the GLC points
 void lagrange_basis_deriv(int p, double s, double *dl);  // d ell_k / ds
@@ -73,9 +77,9 @@ struct Geometry {
 // row that uses cell omin + 1 (p if none), w = the p x (p+1) Lagrange weights.
 template <typename S>
 struct CellTables {
-    const int32_t *omin;    // [Q][3]
-    const int32_t *lstar;   // [Q][3]
-    const S *w;             // [Q][3][p][p+1]
+    const int32_t *omin;    // [q][3]
+    const int32_t *lstar;   // [q][3]
+    const S *w;             // [q][3][p][p+1]
 };
 
 // Per-node departure tables of a graded mesh (build_node_tables), one set
@@ -136,6 +140,25 @@ struct Launch {
                                            const double *u, const double *T, const S *lam0, double *drho,
                                            double *du, double *dT, hipStream_t st);
 };
+
+// The same node-local operations on the two-dimensional D2Q19 lattice
+// (N_z = 1; velocity fields u are [2][N]; totals as out5 with zero z momentum).
+template <typename S>
+struct Launch2D {
+    static hipError_t collide_into(const Geometry &g, const CollisionParams &cp, const S *in, S *out,
+                                   hipStream_t st);
+    static hipError_t init_equilibrium(const Geometry &g, const CollisionParams &cp, const double *rho,
+                                       const double *u, const double *T, S *state, hipStream_t st);
+    static hipError_t moments(const Geometry &g, const CollisionParams &cp, const S *state, double *rho,
+                              double *u, double *T, hipStream_t st);
+    static hipError_t totals(const Geometry &g, const S *state, const double *nodew, double *partials, int nblocks,
+                             double *out5, hipStream_t st);
+};
+
+// two-dimensional streaming (stream2d.hip): per (velocity, population)
+// plane, x-strips marching along y
+template <typename S>
+hipError_t launch_stream_2d(const Geometry &g, const CellTables<S> &t, const S *in, S *out, hipStream_t st);
 
 // forward streaming, z-march per (velocity, population) plane and x-y tile (stream.hip)
 template <typename S>

@@ -18,15 +18,27 @@
 namespace sllbm {
 
 
-// Degree-nine D3Q45 rule (Sec. II B), from the compile-time table shared with
+// Degree-nine rules (Sec. II B), from the compile-time tables shared with
 // the kernels (velset.h).
-void build_velocity_set(VelocitySet &out)
+template <class L>
+static void copy_lattice(VelocitySet &out)
 {
-    for (int i = 0; i < Q; ++i) {
-        for (int k = 0; k < 3; ++k) out.xi[i][k] = vs::T.xi[i][k];
-        out.w[i] = vs::T.w[i];
-        out.opposite[i] = vs::T.opp[i];
+    out = VelocitySet{};
+    out.q = L::Q;
+    out.dim = L::D;
+    for (int i = 0; i < L::Q; ++i) {
+        for (int k = 0; k < 3; ++k) out.xi[i][k] = L::T.xi[i][k];
+        out.w[i] = L::T.w[i];
+        out.opposite[i] = L::T.opp[i];
     }
+}
+
+bool build_velocity_set(VelocitySet &out, int set)
+{
+    if (set == SLLBM_D3Q45) copy_lattice<D3Q45>(out);
+    else if (set == SLLBM_D2Q19) copy_lattice<D2Q19>(out);
+    else return false;
+    return true;
 }
 
 void glc_points(int p, double *t)
@@ -89,10 +101,11 @@ void build_cell_tables(const VelocitySet &vs, int p, const double h[3], double d
 {
     double t[MAXP + 1];
     glc_points(p, t);
-    omin.assign(Q * 3, 0);
-    lstar.assign(Q * 3, p);
-    w.assign(Q * 3 * p * (p + 1), 0.0);
-    for (int i = 0; i < Q; ++i) {
+    const int nq = vs.q;
+    omin.assign(nq * 3, 0);
+    lstar.assign(nq * 3, p);
+    w.assign(nq * 3 * p * (p + 1), 0.0);
+    for (int i = 0; i < nq; ++i) {
         for (int a = 0; a < 3; ++a) {
             // node l of a cell departs to t_l - xi dt / h (cell units): cell
             // floor of that, local coordinate its fractional part (Eq. (9))
@@ -127,9 +140,9 @@ void build_node_tables(const VelocitySet &vs, int p, int ne, double length, cons
                        int axis, double dt, std::vector<int32_t> &src, std::vector<double> &w)
 {
     const int N = ne * p;
-    src.assign(static_cast<size_t>(Q) * N, 0);
-    w.assign(static_cast<size_t>(Q) * N * (p + 1), 0.0);
-    for (int i = 0; i < Q; ++i) {
+    src.assign(static_cast<size_t>(vs.q) * N, 0);
+    w.assign(static_cast<size_t>(vs.q) * N * (p + 1), 0.0);
+    for (int i = 0; i < vs.q; ++i) {
         const double shift = vs.xi[i][axis] * dt;
         for (int g = 0; g < N; ++g) {
             const double X = axis_node_position(p, ne, length, faces, g) - shift;   // departure point

@@ -144,3 +144,64 @@ def perturbed_tgv(xs, ys, zs, Ma, gamma, modes, amplitudes=None):
 def random_populations(shape, seed, scale=1.0):
     """Seeded standard-normal array (for adjoint seeds and perturbations)."""
     return np.random.default_rng(seed).normal(0.0, scale, size=shape)
+
+
+# ---------------------------------------------------------------------------
+# Two-dimensional workloads (D2Q19 lattice; Sec. III A and III B).  The
+# paper's tubes and Riemann problems have open boundaries; these periodic
+# stand-ins keep the shapes, states and discretisations:
+#  * "sod": the coarse shock-tube setting (h = 0.01, p = 4, dt = 5e-4,
+#    mu = 2e-4, t = 0.1) doubled into a periodic tube of length 2 whose
+#    high-pressure state fills (0.5, 1.5); each discontinuity evolves as the
+#    paper's tube until t > 0.2, one cell across y;
+#  * "riemann": case 12 of the 2-D Riemann problems on 128^2 cells of p = 4
+#    (512^2 nodes) over [0, 1]^2 with the quadrant corner at (0.5, 0.5),
+#    t_end = 0.25; dt and mu are not given in the text, the values below
+#    (largest abscissa moves 0.11 cells a step, tau - 1/2 about 1) stand in.
+# Constant viscosity (the viscosity law is not stated for these cases).
+# ---------------------------------------------------------------------------
+WORKLOADS_2D = {
+    "sod": dict(n_el=(200, 1), p=4, length=(2.0, 0.01), dt=5e-4, mu_inf=2e-4, steps=200, gamma=1.4, Pr=0.71,
+                precision="fp64"),
+    "riemann": dict(n_el=(128, 128), p=4, length=(1.0, 1.0), dt=5e-4, mu_inf=5e-4, steps=500, gamma=1.4,
+                    Pr=0.71, precision="fp64"),
+}
+
+SOD_STATES = ((8.0, 0.0, 10.0), (1.0, 0.0, 1.0))          # (rho, u, P) inside, outside
+RIEMANN12 = {                                              # quadrant: (rho, u_x, u_y, P)
+    "ne": (0.5313, 0.0, 0.0, 0.4),
+    "nw": (1.0, 0.7276, 0.0, 1.0),
+    "sw": (0.8, 0.0, 0.0, 1.0),
+    "se": (1.0, 0.0, 0.7276, 1.0),
+}
+
+
+def mesh2d(xs, ys):
+    """2-D coordinate arrays (flattened, x fastest) from the 1-D node coordinates."""
+    Y, X = np.meshgrid(ys, xs, indexing="ij")
+    return X.ravel(), Y.ravel()
+
+
+def sod_fields(xs, ys):
+    """rho (N,), u (2, N), T (N,) of the periodic double shock tube (T = P / rho)."""
+    X, _ = mesh2d(xs, ys)
+    inside = (X > 0.5) & (X < 1.5)
+    (ri, ui, pi), (ro, uo, po) = SOD_STATES
+    rho = np.where(inside, ri, ro)
+    P = np.where(inside, pi, po)
+    u = np.zeros((2, X.size))
+    u[0] = np.where(inside, ui, uo)
+    return rho, u, P / rho
+
+
+def riemann_fields(xs, ys, corner=(0.5, 0.5)):
+    """rho, u (2, N), T of Riemann case 12 (x <= corner counts as west, y <= corner as south)."""
+    X, Y = mesh2d(xs, ys)
+    east, north = X > corner[0], Y > corner[1]
+    rho, P = np.empty(X.size), np.empty(X.size)
+    u = np.empty((2, X.size))
+    for key, mask in (("ne", east & north), ("nw", ~east & north), ("sw", ~east & ~north),
+                      ("se", east & ~north)):
+        r, ux, uy, p = RIEMANN12[key]
+        rho[mask], u[0, mask], u[1, mask], P[mask] = r, ux, uy, p
+    return rho, u, P / rho

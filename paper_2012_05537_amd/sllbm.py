@@ -13,7 +13,8 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsllbm.so")
 
-Q = 45
+Q = 45                      # velocities of the three-dimensional set
+D3Q45, D2Q19 = 45, 19       # velocity_set values (the value is the velocity count)
 OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ENONFINITE = range(6)
 SUTHERLAND, CONSTANT = 0, 1
 FP64, FP32_MIXED = 0, 1
@@ -54,6 +55,7 @@ _SIGS = {
     "sllbm_num_nodes": (ctypes.c_int64, [_VP]),
     "sllbm_state_bytes": (ctypes.c_int64, [_VP]),
     "sllbm_velocity_set": (ctypes.c_int, [_VP, _VP]),
+    "sllbm_lattice": (ctypes.c_int, [ctypes.c_int32, _VP, _VP]),
     "sllbm_node_coords": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
     "sllbm_set_viscosity": (ctypes.c_int, [_VP, ctypes.c_double]),
     "sllbm_set_mesh": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
@@ -104,6 +106,18 @@ def velocity_set():
     return torch.tensor(list(xi), dtype=torch.float64).reshape(Q, 3), torch.tensor(list(w), dtype=torch.float64)
 
 
+def lattice(velocity_set=D3Q45):
+    """(xi (Q, 3), w (Q,)) of D3Q45 or D2Q19 (z = 0) as float64 CPU tensors."""
+    lib = load_library()
+    xi = (ctypes.c_double * (3 * Q))()
+    w = (ctypes.c_double * Q)()
+    n = lib.sllbm_lattice(int(velocity_set), ctypes.addressof(xi), ctypes.addressof(w))
+    if n < 0:
+        raise ValueError("unknown velocity set %r" % (velocity_set,))
+    return (torch.tensor(list(xi)[:3 * n], dtype=torch.float64).reshape(n, 3),
+            torch.tensor(list(w)[:n], dtype=torch.float64))
+
+
 def _ptr(t):
     if t is None:
         return None
@@ -113,19 +127,27 @@ def _ptr(t):
 
 
 class SLLBM:
-    """One simulation context on one GPU (a thin owner of ``sllbm_ctx*``)."""
+    """One simulation context on one GPU (a thin owner of ``sllbm_ctx*``).
+
+    velocity_set=D2Q19 makes a two-dimensional context: n_el and length take
+    (x, y) values (z is set to one cell), states are (2, 19, N), velocity
+    fields (2, N)."""
 
     def __init__(self, n_el, order, dt, mu_inf, gamma=1.4, prandtl=0.71, length=2 * 3.141592653589793,
-                 viscosity_law=SUTHERLAND, precision=FP64, device=0):
+                 viscosity_law=SUTHERLAND, precision=FP64, device=0, velocity_set=D3Q45):
         lib = load_library()
+        dim = 2 if velocity_set == D2Q19 else 3
         if isinstance(n_el, int):
-            n_el = (n_el, n_el, n_el)
+            n_el = (n_el,) * dim
         if isinstance(length, (int, float)):
-            length = (length, length, length)
+            length = (length,) * dim
+        n_el, length = tuple(n_el), tuple(length)
+        if dim == 2:
+            n_el, length = n_el[:2] + (1,), length[:2] + (1.0,)
         cfg = Config()
         cfg.n_el[:] = [int(v) for v in n_el]
         cfg.order = int(order)
-        cfg.velocity_set = Q
+        cfg.velocity_set = int(velocity_set)
         cfg.viscosity_law = int(viscosity_law)
         cfg.precision = int(precision)
         cfg.device = int(device)
@@ -144,7 +166,11 @@ class SLLBM:
         self.device = torch.device("cuda", int(device))
         self.dtype = torch.float64 if precision == FP64 else torch.float32
         self.nodes = lib.sllbm_num_nodes(h)
-        self.shape = (cfg.n_el[2] * order, cfg.n_el[1] * order, cfg.n_el[0] * order)
+        self.q, self.dim = int(velocity_set), dim
+        if dim == 2:
+            self.shape = (cfg.n_el[1] * order, cfg.n_el[0] * order)
+        else:
+            self.shape = (cfg.n_el[2] * order, cfg.n_el[1] * order, cfg.n_el[0] * order)
         self.state_bytes = lib.sllbm_state_bytes(h)
         self._stream = None
 
@@ -171,19 +197,23 @@ class SLLBM:
             pass
 
     def empty_state(self):
-        return torch.empty((2, Q, self.nodes), dtype=self.dtype, device=self.device)
+        return torch.empty((2, self.q, self.nodes), dtype=self.dtype, device=self.device)
 
     def _state_arg(self, t):
-        if t.dtype != self.dtype or t.device != self.device or t.numel() != 2 * Q * self.nodes:
-            raise ValueError("state must be a contiguous (2, 45, N) tensor of the storage dtype on the device")
+        if t.dtype != self.dtype or t.device != self.device or t.numel() != 2 * self.q * self.nodes:
+            raise ValueError("state must be a contiguous (2, %d, N) tensor of the storage dtype on the device"
+                             % self.q)
         return _ptr(t)
 
     # -- C ABI, same names -------------------------------------------------
     def node_coords(self):
+        """1-D node coordinates per axis: (x, y, z), or (x, y) in two dimensions."""
         n = [self.cfg.n_el[a] * self.cfg.order for a in range(3)]
+        if self.dim == 2:
+            n[2] = 1
         arrs = [(ctypes.c_double * v)() for v in n]
         self._check(self._lib.sllbm_node_coords(self._h, *[ctypes.addressof(a) for a in arrs]))
-        return tuple(torch.tensor(list(a), dtype=torch.float64) for a in arrs)
+        return tuple(torch.tensor(list(a), dtype=torch.float64) for a in arrs[:self.dim])
 
     def set_viscosity(self, mu_inf):
         self._check(self._lib.sllbm_set_viscosity(self._h, float(mu_inf)))
@@ -210,6 +240,8 @@ class SLLBM:
         self._sync_stream()
         f64 = dict(dtype=torch.float64, device=self.device)
         rho, u, T = (x.to(**f64).contiguous() for x in (rho, u, T))
+        if rho.numel() != self.nodes or T.numel() != self.nodes or u.numel() != self.dim * self.nodes:
+            raise ValueError("rho, T need N values and u (%d, N)" % self.dim)
         self._check(self._lib.sllbm_init_equilibrium(self._h, _ptr(rho), _ptr(u), _ptr(T)))
 
     def set_state(self, state):
@@ -227,7 +259,7 @@ class SLLBM:
         self._check(self._lib.sllbm_step(self._h, int(n)))
 
     def step_record(self, n, states):
-        """states: (n, 2, 45, N) tensor receiving the pre-collision state after each step."""
+        """states: (n, 2, Q, N) tensor receiving the pre-collision state after each step."""
         self._sync_stream()
         if states.shape[0] < n or not states.is_contiguous() or states.dtype != self.dtype:
             raise ValueError("record buffer too small or wrong dtype")
@@ -248,7 +280,7 @@ class SLLBM:
         self._sync_stream()
         f64 = dict(dtype=torch.float64, device=self.device)
         rho = torch.empty(self.nodes, **f64)
-        u = torch.empty((3, self.nodes), **f64)
+        u = torch.empty((self.dim, self.nodes), **f64)
         T = torch.empty(self.nodes, **f64)
         self._check(self._lib.sllbm_moments(self._h, _ptr(rho), _ptr(u), _ptr(T)))
         return rho, u, T

@@ -39,6 +39,21 @@ def test_velocity_set_matches_oracle(oracle):
     assert np.allclose(w.numpy(), wo, rtol=0, atol=1e-17)
 
 
+def test_two_dimensional_lattice_matches_oracle():
+    from oracle import oracle2d
+    from paper_2012_05537_amd import sllbm
+    xi, w = sllbm.lattice(sllbm.D2Q19)
+    xo, wo = oracle2d.velocity_set()
+    assert xi.shape == (19, 3) and np.all(xi[:, 2].numpy() == 0)
+    # same values to a few ulp (the oracle evaluates cos/sin of the ring angles)
+    assert np.allclose(xi[:, :2].numpy(), xo, rtol=0, atol=4e-15)
+    assert np.allclose(w.numpy(), wo, rtol=1e-15, atol=0)
+    x3, w3 = sllbm.lattice(sllbm.D3Q45)
+    assert x3.shape == (45, 3)
+    with pytest.raises(ValueError):
+        sllbm.lattice(27)
+
+
 def _cfg(**kw):
     from paper_2012_05537_amd.sllbm import Config
     c = Config()
@@ -74,12 +89,31 @@ def test_invalid_config_is_rejected(lib, bad):
     assert len(lib.sllbm_last_error(None)) > 0
 
 
+@pytest.mark.parametrize("bad", [dict(n_el=[4, 4, 2]), dict(n_el=[0, 4, 1]), dict(length=[1.0, 0.0, 1.0])])
+def test_invalid_two_dimensional_config_is_rejected(lib, bad):
+    h = ctypes.c_void_p()
+    rc = lib.sllbm_create(ctypes.byref(_cfg(velocity_set=19, **bad)), ctypes.byref(h))
+    assert rc == 1 and h.value is None
+
+
+def test_two_dimensional_config_ignores_z_length(lib):
+    """A valid 2-D configuration passes validation (no device here: EDEVICE)."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a device is present")
+    h = ctypes.c_void_p()
+    rc = lib.sllbm_create(ctypes.byref(_cfg(velocity_set=19, n_el=[4, 3, 1], length=[1.0, 0.75, 0.0])),
+                          ctypes.byref(h))
+    assert rc == 3 and h.value is None
+
+
 def test_null_arguments(lib):
     assert lib.sllbm_create(None, None) == 1
     assert lib.sllbm_destroy(None) == 0
     assert lib.sllbm_num_nodes(None) == -1
     assert lib.sllbm_step(None, 1) == 1
     assert lib.sllbm_velocity_set(None, None) == 1
+    assert lib.sllbm_lattice(19, None, None) == -1
 
 
 def test_missing_library_fails_loudly(tmp_path):

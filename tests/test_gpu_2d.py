@@ -1,0 +1,224 @@
+"""GPU parity of the two-dimensional lattice (D2Q19, SLLBM_D2Q19 contexts)
+through the C ABI against the 2-D FP64 oracle.
+
+Bar: FP64 max |a - b| / max |b| <= 1e-12 (streaming, collision, moments,
+totals, steps); FP32-mixed <= 1e-5 (one step), as for the 3-D lattice.
+Cases: p = 1..6, ragged x-strips (N_x not a multiple of the 256-node strip),
+several y-chunks, one-cell axes, shifts of several cells, both load paths
+(16-byte window loads at even p in FP64, element loads at odd p), the full
+512^2-node Riemann workload and the periodic Sod tube.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import rel_err, require_gpu
+from paper_2012_05537_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+Q2 = 19
+TOL64 = 1e-12
+TOL_MIXED = 1e-5
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    require_gpu()
+
+
+@pytest.fixture(scope="module")
+def O2():
+    from oracle import oracle2d
+    return oracle2d
+
+
+def _pair(O2, n_el, p, dt, mu, length=1.0, law=1, precision=0, gamma=1.4, prandtl=0.71):
+    from paper_2012_05537_amd.sllbm import SLLBM, D2Q19
+    ctx = SLLBM(n_el, p, dt, mu, gamma=gamma, prandtl=prandtl, length=length, viscosity_law=law,
+                precision=precision, velocity_set=D2Q19)
+    cfg = O2.make_cfg(n_el, p, dt, mu, gamma=gamma, prandtl=prandtl, length=length, viscosity_law=law)
+    return ctx, cfg
+
+
+def _to_dev(ctx, f, g):
+    return torch.from_numpy(np.stack([f, g])).to(ctx.device, ctx.dtype).contiguous()
+
+
+def _to_np(state):
+    s = state.detach().to("cpu", torch.float64).numpy()
+    return s[0], s[1]
+
+
+def _init_both(O2, ctx, cfg, rho, u, T):
+    dev = ctx.device
+    ctx.init_equilibrium(*(torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in (rho, u, T)))
+    return O2.init_equilibrium(cfg, rho, u, T)
+
+
+def test_node_coords_and_sizes(O2):
+    ctx, cfg = _pair(O2, (5, 3), 4, 0.01, 1e-3, length=(2.0, 1.5))
+    x, y = ctx.node_coords()
+    xo, yo = O2.node_coords(cfg)
+    assert np.allclose(x.numpy(), xo, atol=1e-14) and np.allclose(y.numpy(), yo, atol=1e-14)
+    assert ctx.nodes == 20 * 12 and ctx.state_bytes == 2 * Q2 * 240 * 8
+    assert ctx.shape == (12, 20)
+
+
+# (n_el, p, dt, length): ragged strips, several y-chunks, one-cell axes,
+# shifts of several cells, odd and even p
+STREAM_CASES = [
+    ((70, 9), 4, 0.004, (1.0, 0.2)),        # N_x = 280: two strips, the second ragged; V = 2 loads
+    ((6, 40), 2, 0.03, (1.0, 1.0)),         # many y-chunks
+    ((5, 4), 3, 0.2, (1.0, 0.8)),           # shifts of several cells; element loads
+    ((1, 3), 4, 0.07, (0.3, 1.0)),          # one-cell x axis
+    ((4, 1), 5, 0.05, (1.0, 0.2)),          # one-cell y axis, p = 5
+    ((9, 7), 1, 0.02, (1.0, 1.0)),          # p = 1
+    ((3, 5), 6, 0.03, (1.0, 1.5)),          # p = 6
+    ((129, 8), 2, 0.01, (2.0, 0.25)),       # N_x = 258 (strip of 256 + 2)
+]
+
+
+@pytest.mark.parametrize("n_el,p,dt,length", STREAM_CASES)
+def test_stream_matches_oracle(O2, n_el, p, dt, length):
+    _say(f"2-D stream parity n_el={n_el} p={p} dt={dt}")
+    ctx, cfg = _pair(O2, n_el, p, dt, 1e-3, length=length)
+    rng = np.random.default_rng(sum(n_el) + 7 * p)
+    N = O2.num_nodes(cfg)
+    f, g = rng.normal(size=(Q2, N)), rng.normal(size=(Q2, N))
+    F, G = _to_np(ctx.stream(_to_dev(ctx, f, g)))
+    fo, go = O2.stream(cfg, f, g)
+    assert rel_err(F, fo) <= TOL64 and rel_err(G, go) <= TOL64, (rel_err(F, fo), rel_err(G, go))
+
+
+def test_stream_fp32(O2):
+    ctx, cfg = _pair(O2, (70, 9), 4, 0.004, 1e-3, length=(1.0, 0.2), precision=1)
+    rng = np.random.default_rng(3)
+    N = O2.num_nodes(cfg)
+    f, g = rng.normal(size=(Q2, N)), rng.normal(size=(Q2, N))
+    F, G = _to_np(ctx.stream(_to_dev(ctx, f.astype(np.float32), g.astype(np.float32))))
+    fo, go = O2.stream(cfg, f.astype(np.float32).astype(np.float64), g.astype(np.float32).astype(np.float64))
+    assert rel_err(F, fo) <= TOL_MIXED and rel_err(G, go) <= TOL_MIXED
+
+
+@pytest.mark.parametrize("law,prandtl", [(0, 0.71), (1, 1.0), (1, 2.5)])
+def test_collide_matches_oracle(O2, law, prandtl):
+    ctx, cfg = _pair(O2, (4, 3), 3, 0.002, 3e-3, law=law, prandtl=prandtl)
+    N = O2.num_nodes(cfg)
+    rng = np.random.default_rng(11)
+    rho = rng.uniform(0.6, 1.8, N)
+    u = rng.uniform(-0.4, 0.4, (2, N))
+    T = rng.uniform(0.8, 1.3, N)
+    f, g = O2.init_equilibrium(cfg, rho, u, T)
+    f = f * (1 + 0.05 * rng.normal(size=f.shape))
+    g = g * (1 + 0.05 * rng.normal(size=g.shape))
+    st = _to_dev(ctx, f, g)
+    F, G = _to_np(ctx.collide(st))
+    fo, go = O2.collide(cfg, f, g)
+    assert rel_err(F, fo) <= TOL64 and rel_err(G, go) <= TOL64, (rel_err(F, fo), rel_err(G, go))
+
+
+def test_init_moments_totals(O2):
+    ctx, cfg = _pair(O2, (6, 5), 4, 0.01, 1e-3, length=(1.2, 1.0))
+    x, y = O2.node_coords(cfg)
+    rho, u, T = inputs.riemann_fields(x, y, corner=(0.6, 0.5))
+    f, g = _init_both(O2, ctx, cfg, rho, u, T)
+    F, G = _to_np(ctx.get_state())
+    assert rel_err(F, f) <= TOL64 and rel_err(G, g) <= TOL64
+    r2, u2, T2 = (a.cpu().numpy() for a in ctx.moments())
+    ro, uo, To = O2.moments(cfg, f, g)
+    assert u2.shape == (2, ctx.nodes)
+    assert rel_err(r2, ro) <= TOL64 and rel_err(u2, uo) <= TOL64 and rel_err(T2, To) <= TOL64
+    tot = ctx.totals()
+    to = O2.totals(cfg, f, g)
+    assert tot[3] == 0.0
+    got = np.array([tot[0], tot[1], tot[2], tot[4]])
+    assert np.allclose(got, to, rtol=1e-12, atol=1e-12 * abs(to[0]))
+
+
+def test_steps_match_oracle(O2):
+    """Five steps of Riemann case 12 on a small mesh (discontinuous data)."""
+    ctx, cfg = _pair(O2, (12, 10), 4, 2e-3, 2e-3, length=(1.0, 0.9))
+    x, y = O2.node_coords(cfg)
+    rho, u, T = inputs.riemann_fields(x, y, corner=(0.5, 0.45))
+    f, g = _init_both(O2, ctx, cfg, rho, u, T)
+    ctx.step(5)
+    fo, go = O2.step(cfg, f, g, 5)
+    F, G = _to_np(ctx.get_state())
+    assert rel_err(F, fo) <= TOL64 and rel_err(G, go) <= TOL64, (rel_err(F, fo), rel_err(G, go))
+
+
+def test_step_record_matches_steps(O2):
+    ctx, cfg = _pair(O2, (8, 8), 2, 1e-3, 1e-3)
+    x, y = O2.node_coords(cfg)
+    _init_both(O2, ctx, cfg, *inputs.riemann_fields(x, y))
+    s0 = ctx.get_state()
+    rec = torch.empty((3,) + tuple(s0.shape), dtype=ctx.dtype, device=ctx.device)
+    ctx.step_record(3, rec)
+    last = ctx.get_state()
+    ctx.set_state(s0)
+    ctx.step(3)
+    assert torch.equal(ctx.get_state(), last) and torch.equal(rec[2], last)
+
+
+def test_sod_tube(O2):
+    """The periodic double tube for 50 steps: GPU against oracle, then both
+    close to the exact Riemann solution's shock position region."""
+    w = inputs.WORKLOADS_2D["sod"]
+    ctx, cfg = _pair(O2, w["n_el"], w["p"], w["dt"], w["mu_inf"], length=w["length"])
+    x, y = O2.node_coords(cfg)
+    f, g = _init_both(O2, ctx, cfg, *inputs.sod_fields(x, y))
+    ctx.step(50)
+    fo, go = O2.step(cfg, f, g, 50)
+    F, G = _to_np(ctx.get_state())
+    assert rel_err(F, fo) <= 1e-11 and rel_err(G, go) <= 1e-11, (rel_err(F, fo), rel_err(G, go))
+
+
+def test_riemann_fullsize_one_step(O2):
+    """The 512^2-node Riemann workload in the launch configuration the bench
+    times: one full step against the oracle at every node."""
+    w = inputs.WORKLOADS_2D["riemann"]
+    _say("2-D Riemann 512^2 one step")
+    ctx, cfg = _pair(O2, w["n_el"], w["p"], w["dt"], w["mu_inf"], length=w["length"])
+    x, y = O2.node_coords(cfg)
+    f, g = _init_both(O2, ctx, cfg, *inputs.riemann_fields(x, y))
+    ctx.step(1)
+    fo, go = O2.step(cfg, f, g, 1)
+    F, G = _to_np(ctx.get_state())
+    assert rel_err(F, fo) <= TOL64 and rel_err(G, go) <= TOL64, (rel_err(F, fo), rel_err(G, go))
+
+
+def test_fp32_step(O2):
+    ctx, cfg = _pair(O2, (16, 12), 4, 1e-3, 1e-3, precision=1)
+    x, y = O2.node_coords(cfg)
+    f, g = _init_both(O2, ctx, cfg, *inputs.riemann_fields(x, y))
+    ctx.step(1)
+    fo, go = O2.step(cfg, f, g, 1)
+    F, G = _to_np(ctx.get_state())
+    assert rel_err(F, fo) <= TOL_MIXED and rel_err(G, go) <= TOL_MIXED
+
+
+def test_three_dimensional_calls_are_refused(O2):
+    import ctypes
+    ctx, cfg = _pair(O2, (4, 4), 2, 1e-3, 1e-3)
+    lib, h = ctx._lib, ctx._h
+    x = torch.ones((2, Q2, ctx.nodes), dtype=torch.float64, device=ctx.device)
+    y = torch.empty_like(x)
+    ctx.set_state(x)
+    p = lambda t: ctypes.c_void_p(t.data_ptr())
+    d = (ctypes.c_double * 4)()
+    assert lib.sllbm_stream(h, p(x), p(y), 1) == 1
+    assert lib.sllbm_adjoint_step(h, p(x), p(x), p(y), None) == 1
+    assert lib.sllbm_loss(h, p(x), ctypes.addressof(d)) == 1
+    assert lib.sllbm_diagnostics(h, None, ctypes.addressof(d)) == 1
+    w = (ctypes.c_double * 4)(1, 1, 1, 1)
+    assert lib.sllbm_set_mesh(h, ctypes.addressof(w), None, None) == 1
+    assert "two-dimensional" in lib.sllbm_last_error(h).decode()
