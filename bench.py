@@ -7,6 +7,9 @@ quasi-equilibrium term, relaxation of all 90 populations of every node) and
 the streaming kernel (the order-p semi-Lagrangian interpolation of all 90
 populations).  The headline workload is the FP64 compressible Taylor-Green
 vortex on 16^3 cells of order 4 (64^3 nodes), Ma 1.25, Re 1600.
+``--workload riemann`` (or ``sod``) measures the two-dimensional D2Q19 step
+instead: 38 populations per node, case 12 of the 2-D Riemann problems on
+128^2 cells of order 4 (512^2 nodes).
 
 Prints ONE JSON line (see the ``--help`` of the options).
 """
@@ -29,6 +32,7 @@ KERNEL_SOURCES = {
     "k_stream_z": ("stream.hip", "tables.cpp"),
     "k_stream_graded": ("stream_graded.hip", "tables.cpp"),
     "k_collide": ("kernels.hip", "collision.h", "velset.h"),
+    "k_stream_y": ("stream2d.hip", "tables.cpp"),
 }
 
 
@@ -70,6 +74,29 @@ def run_gpu(args, wl, precision):
     rho, u, T = inputs.tgv_fields(xs, ys, zs, wl["Ma"], wl["gamma"])
     dev = ctx.device
     ctx.init_equilibrium(torch.from_numpy(rho).to(dev), torch.from_numpy(u).to(dev), torch.from_numpy(T).to(dev))
+    return measure_steps(args, ctx, "k_stream_graded" if args.mesh == "graded" else "k_stream_z")
+
+
+def run_gpu_2d(args, wl, precision):
+    """The two-dimensional (D2Q19) step on the periodic Sod tube or Riemann case 12."""
+    import torch
+    from paper_2012_05537_amd import inputs
+    from paper_2012_05537_amd.sllbm import SLLBM, D2Q19, CONSTANT
+
+    ctx = SLLBM(wl["n_el"], wl["p"], wl["dt"], wl["mu_inf"], gamma=wl["gamma"], prandtl=wl["Pr"],
+                length=wl["length"], viscosity_law=CONSTANT, precision=precision, velocity_set=D2Q19)
+    xs, ys = (t.numpy() for t in ctx.node_coords())
+    rho, u, T = (inputs.sod_fields if wl["name"] == "sod" else inputs.riemann_fields)(xs, ys)
+    dev = ctx.device
+    ctx.init_equilibrium(torch.from_numpy(rho).to(dev), torch.from_numpy(u).to(dev), torch.from_numpy(T).to(dev))
+    return measure_steps(args, ctx, "k_stream_y")
+
+
+def measure_steps(args, ctx, stream_kernel):
+    """Wall clock of args.steps steps, then kernel durations from HIP events."""
+    import torch
+    dev = ctx.device
+    precision = 0 if ctx.dtype == torch.float64 else 1
     if args.copy_calibration:
         # a plain copy kernel of one state's size (reads B, writes B; an elementwise
         # kernel, not a DMA copy), so that a counter run sees the HBM counters of a
@@ -106,11 +133,10 @@ def run_gpu(args, wl, precision):
     del start
     nodes = ctx.nodes
     elem = 8 if precision == 0 else 4
-    bytes_per_launch = 2 * 2 * Q * nodes * elem          # each kernel reads 90 and writes 90 values per node
+    bytes_per_launch = 2 * 2 * ctx.q * nodes * elem      # each kernel reads 2Q and writes 2Q values per node
     ctx.close()
     kernels = {name: {"ms": ms / max(n, 1), "launches": n} for name, (ms, n) in
-               (("k_collide", kt["collide"]),
-                ("k_stream_graded" if args.mesh == "graded" else "k_stream_z", kt["stream"]))}
+               (("k_collide", kt["collide"]), (stream_kernel, kt["stream"]))}
     return dict(nodes=nodes, wall=wall, kernels=kernels, bytes=bytes_per_launch, finite=ok, totals=tot)
 
 
@@ -192,12 +218,43 @@ def cpu_baseline(wl, budget_s, graded=False):
                        f"({O.num_nodes(cfg)} nodes), {el:.1f} s")
 
 
+def cpu_baseline_2d(wl, budget_s):
+    """The 2-D FP64 oracle on the host cores: whole-grid steps of the same workload."""
+    from oracle import oracle2d as O
+    from paper_2012_05537_amd import inputs
+
+    cfg = O.make_cfg(wl["n_el"], wl["p"], wl["dt"], wl["mu_inf"], gamma=wl["gamma"], prandtl=wl["Pr"],
+                     length=wl["length"], viscosity_law=O.CONSTANT)
+    x, y = O.node_coords(cfg)
+    rho, u, T = (inputs.sod_fields if wl["name"] == "sod" else inputs.riemann_fields)(x, y)
+    f, g = O.init_equilibrium(cfg, rho, u, T)
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        f, g = O.step(cfg, f, g, 1)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el > budget_s or el / steps * (steps + 1) > 2.0 * budget_s:
+            break
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return dict(value=O.num_nodes(cfg) * steps / el, unit="node-updates/s", cores=cores, kind="oracle",
+                sample=f"{steps} whole-grid FP64 2-D oracle step(s) of the same workload "
+                       f"({O.num_nodes(cfg)} nodes), {el:.1f} s")
+
+
+def workload_2d(name):
+    from paper_2012_05537_amd import inputs
+    w = dict(inputs.WORKLOADS_2D[name])
+    w["name"] = name
+    return w
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="c2", help="workload key (c1..c5)")
+    ap.add_argument("--workload", default="c2", help="workload key (c1..c5; sod or riemann: 2-D D2Q19)")
     ap.add_argument("--cfl", type=float, default=1.0)
     ap.add_argument("--mesh", choices=["equal", "graded"], default="equal",
                     help="equal cells, or the cosine-graded cells of every axis (streaming on per-node tables)")
@@ -218,11 +275,15 @@ def main():
         return 2
 
     from paper_2012_05537_amd import inputs
-    wl = inputs.workload(args.workload, cfl=args.cfl)
+    two_d = args.workload in inputs.WORKLOADS_2D
+    if two_d and args.mesh != "equal":
+        print("the two-dimensional workloads use equal cells", file=sys.stderr)
+        return 2
+    wl = workload_2d(args.workload) if two_d else inputs.workload(args.workload, cfl=args.cfl)
     wkey = args.workload if args.mesh == "equal" else args.workload + "-graded"
     prec_name = args.precision or wl["precision"]
     precision = 0 if prec_name == "fp64" else 1
-    r = run_gpu(args, wl, precision)
+    r = run_gpu_2d(args, wl, precision) if two_d else run_gpu(args, wl, precision)
     value = r["nodes"] * args.steps / r["wall"]
     dom = max(r["kernels"], key=lambda k: r["kernels"][k]["ms"])
     kms = r["kernels"][dom]["ms"]
@@ -232,8 +293,19 @@ def main():
         gbs = r["bytes"] / (v["ms"] * 1e-3) / 1e9 if v["ms"] > 0 else None
         kernels[k] = {"ms_per_launch": v["ms"], "launches": v["launches"], "algorithmic_GBps": gbs,
                       "traffic": measured_traffic(k, wkey, prec_name)}
+    if two_d:
+        nx, ny = wl["n_el"]
+        workload = (f"{wkey}: {'periodic double Sod tube' if wkey == 'sod' else 'Riemann case 12'} "
+                    f"{nx}x{ny} cells p={wl['p']} ({r['nodes']} nodes), D2Q19, dt {wl['dt']}, "
+                    f"mu {wl['mu_inf']}, {prec_name}")
+        data = "synthetic: piecewise-constant Riemann initial states (periodic stand-in)"
+    else:
+        workload = (f"{wkey}: TGV {wl['n_el']}^3 "
+                    f"{'cells' if args.mesh == 'equal' else 'cosine-graded cells (a = 0.3)'} p={wl['p']} "
+                    f"({r['nodes']} nodes), Ma {wl['Ma']}, Re {wl['Re']}, CFL {wl['cfl']}, {prec_name}")
+        data = "synthetic: closed-form compressible Taylor-Green vortex"
     out = {
-        "metric": "node-updates/s (D3V45 f+g)",
+        "metric": "node-updates/s (D2V19 f+g)" if two_d else "node-updates/s (D3V45 f+g)",
         "value": value,
         "unit": "node-updates/s",
         "n_gpus": 1,
@@ -244,13 +316,9 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64" if precision == 0 else "f32 (f64 moments)",
-        "data": "synthetic: closed-form compressible Taylor-Green vortex",
-        "config": {"workload": f"{wkey}: TGV {wl['n_el']}^3 "
-                               f"{'cells' if args.mesh == 'equal' else 'cosine-graded cells (a = 0.3)'} p={wl['p']} "
-                               f"({r['nodes']} nodes), Ma {wl['Ma']}, Re {wl['Re']}, CFL {wl['cfl']}, "
-                               f"{prec_name}",
-                   "nodes": r["nodes"], "order": wl["p"], "cfl": wl["cfl"], "dt": wl["dt"],
-                   "parallelism": "single GPU"},
+        "data": data,
+        "config": {"workload": workload, "nodes": r["nodes"], "order": wl["p"], "cfl": wl.get("cfl"),
+                   "dt": wl["dt"], "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": kernels[dom]["traffic"],
                      "kernel": dom, "kernel_ms": kms, "algorithmic_bytes_per_launch": r["bytes"],
@@ -258,14 +326,15 @@ def main():
         "kernels": kernels,
         "finite": r["finite"],
     }
-    if args.adjoint_workload != "none":
+    if args.adjoint_workload != "none" and not two_d:
         over = {} if args.adjoint_cfl is None else {"cfl": args.adjoint_cfl}
         if args.adjoint_steps is not None:
             over["steps"] = args.adjoint_steps
         wa = inputs.workload(args.adjoint_workload, **over)
         out["adjoint"] = run_adjoint(wa, 0 if wa["precision"] == "fp64" else 1, graded=args.mesh == "graded")
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_budget, graded=args.mesh == "graded")
+        out["cpu_baseline"] = (cpu_baseline_2d(wl, args.cpu_budget) if two_d else
+                               cpu_baseline(wl, args.cpu_budget, graded=args.mesh == "graded"))
     print(json.dumps(out), flush=True)
     return 0
 
