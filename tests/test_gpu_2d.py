@@ -126,6 +126,26 @@ def test_collide_matches_oracle(O2, law, prandtl):
     assert rel_err(F, fo) <= TOL64 and rel_err(G, go) <= TOL64, (rel_err(F, fo), rel_err(G, go))
 
 
+@pytest.mark.parametrize("n_el,p", [((1, 1), 1), ((3, 2), 1), ((5, 7), 3), ((33, 1), 4)])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_collide_tail_sizes(O2, n_el, p, precision):
+    """Node counts of 1, 6, 315 and 528: lane pairs past the end, and (FP64)
+    pairs that take a second node or none."""
+    ctx, cfg = _pair(O2, n_el, p, 0.002, 3e-3, law=0, precision=precision)
+    N = O2.num_nodes(cfg)
+    rng = np.random.default_rng(N)
+    f, g = O2.init_equilibrium(cfg, rng.uniform(0.6, 1.8, N), rng.uniform(-0.3, 0.3, (2, N)),
+                               rng.uniform(0.8, 1.3, N))
+    f = f * (1 + 0.05 * rng.normal(size=f.shape))
+    g = g * (1 + 0.05 * rng.normal(size=g.shape))
+    if precision:
+        f, g = f.astype(np.float32).astype(np.float64), g.astype(np.float32).astype(np.float64)
+    F, G = _to_np(ctx.collide(_to_dev(ctx, f, g)))
+    fo, go = O2.collide(cfg, f, g)
+    tol = TOL64 if precision == 0 else TOL_MIXED
+    assert rel_err(F, fo) <= tol and rel_err(G, go) <= tol, (rel_err(F, fo), rel_err(G, go))
+
+
 def test_init_moments_totals(O2):
     ctx, cfg = _pair(O2, (6, 5), 4, 0.01, 1e-3, length=(1.2, 1.0))
     x, y = O2.node_coords(cfg)
