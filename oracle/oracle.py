@@ -44,6 +44,7 @@ class Cfg(ctypes.Structure):
         ("mu_inf_im", ctypes.c_double),
         ("viscosity_law", ctypes.c_int),
         ("faces", ctypes.POINTER(ctypes.c_double) * 3),
+        ("disp", ctypes.POINTER(ctypes.c_double)),
     ]
 
 
@@ -65,9 +66,10 @@ def _ptr(a):
 
 
 def make_cfg(n_el, p, dt, mu_inf, gamma=1.4, prandtl=0.71, length=2 * np.pi,
-             viscosity_law=SUTHERLAND, mu_inf_im=0.0, widths=None):
+             viscosity_law=SUTHERLAND, mu_inf_im=0.0, widths=None, disp=None):
     """widths: None (equal cells) or, per axis, None or the n_el[a] cell widths
-    of a graded axis (their sum replaces length[a])."""
+    of a graded axis (their sum replaces length[a]).  disp: None or the (3, N)
+    node displacements of a distorted mesh (equal cells only)."""
     if np.isscalar(n_el):
         n_el = (n_el, n_el, n_el)
     if np.isscalar(length):
@@ -95,6 +97,14 @@ def make_cfg(n_el, p, dt, mu_inf, gamma=1.4, prandtl=0.71, length=2 * np.pi,
     c.mu_inf = float(mu_inf)
     c.mu_inf_im = float(mu_inf_im)
     c.viscosity_law = int(viscosity_law)
+    if disp is not None:
+        if widths is not None:
+            raise ValueError("a distorted mesh displaces the equal-cell grid")
+        d = np.ascontiguousarray(disp, dtype=np.float64).reshape(3, -1)
+        if d.shape[1] != num_nodes(c):
+            raise ValueError("disp must be (3, N)")
+        c._disp = d
+        c.disp = d.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     return c
 
 
@@ -302,3 +312,22 @@ def diagnostics(cfg, f, g):
     out = np.zeros(3, dt)
     getattr(_lib(cplx), _prefix(cplx) + "diagnostics")(ctypes.byref(cfg), _ptr(f), _ptr(g), _ptr(out))
     return out
+
+
+def is_mapped(cfg):
+    return bool(cfg.disp)
+
+
+def mapped_node_coords(cfg):
+    """(3, N) physical node positions of a distorted mesh (GLC grid + displacement)."""
+    xs, ys, zs = node_coords(cfg)
+    Z, Y, X = np.meshgrid(zs, ys, xs, indexing="ij")
+    ref = np.stack([X.reshape(-1), Y.reshape(-1), Z.reshape(-1)])
+    return ref + (cfg._disp if is_mapped(cfg) else 0.0)
+
+
+def mapped_node_weights(cfg):
+    """(N,) quadrature weight of every node of a distorted mesh (|det J| included)."""
+    w = np.zeros(num_nodes(cfg))
+    _lib().oracle_mapped_node_weights(ctypes.byref(cfg), _ptr(w))
+    return w

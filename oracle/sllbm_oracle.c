@@ -69,6 +69,8 @@ typedef struct {
     int viscosity_law;     /* 0 = Sutherland, 1 = constant mu = mu_inf */
     const double *faces[3];/* graded mesh: n_el[a] + 1 cell-face coordinates per axis,
                               faces[a][0] = 0, faces[a][n_el] = length[a]; NULL = equal cells */
+    const double *disp;    /* distorted mesh: node displacements [3][N] (periodic) added to the
+                              equal-cell GLC positions; NULL = undistorted */
 } oracle_cfg;
 
 /* ------------------------------------------------------------------------- */
@@ -276,6 +278,154 @@ void oracle_node_coords(const oracle_cfg *c, double *x, double *y, double *z)
         int n = c->n_el[a] * c->p;
         for (int g = 0; g < n; ++g) out[a][g] = axis_node_pos(c, a, g);
     }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Distorted meshes.  Node g of the equal-cell grid moves by the periodic    */
+/* displacement d(g); every cell becomes the image of its reference cube     */
+/* under the degree-p interpolant of its nodes' positions (isoparametric).   */
+/* Since the GLC positions interpolate the identity, the cell map is         */
+/* r -> r + D(r), D the cell-wise tensor interpolant of d.  Populations are  */
+/* interpolated in reference coordinates, so the departure point            */
+/* x_node + d_node - xi dt is located by solving r + D(r) = x_d (Newton, the */
+/* cell re-chosen from r at every iteration; periodic in r).                 */
+/* ------------------------------------------------------------------------- */
+
+/* D and I + dD/dr at local coordinates t of cell e (wrapped cell indices) */
+static void disp_cell(const oracle_cfg *c, const int *e, const double *t, double *D, double J[3][3])
+{
+    int p = c->p;
+    int N[3];
+    double h[3], ell[3][16], dl[3][16];
+    for (int a = 0; a < 3; ++a) {
+        N[a] = c->n_el[a] * p;
+        h[a] = c->length[a] / c->n_el[a];
+        oracle_lagrange(p, t[a], ell[a]);
+        oracle_lagrange_deriv(p, t[a], dl[a]);
+    }
+    long Nl = (long)N[0] * N[1] * N[2];
+    for (int a = 0; a < 3; ++a) {
+        D[a] = 0.0;
+        for (int b = 0; b < 3; ++b) J[a][b] = (a == b) ? 1.0 : 0.0;
+    }
+    if (!c->disp) return;                     /* undistorted: D = 0, J = I */
+    for (int kz = 0; kz <= p; ++kz)
+        for (int ky = 0; ky <= p; ++ky)
+            for (int kx = 0; kx <= p; ++kx) {
+                long node = ((long)((e[2] * p + kz) % N[2]) * N[1] + (e[1] * p + ky) % N[1]) * N[0]
+                          + (e[0] * p + kx) % N[0];
+                double v = ell[0][kx] * ell[1][ky] * ell[2][kz];
+                double gx = dl[0][kx] * ell[1][ky] * ell[2][kz] / h[0];
+                double gy = ell[0][kx] * dl[1][ky] * ell[2][kz] / h[1];
+                double gz = ell[0][kx] * ell[1][ky] * dl[2][kz] / h[2];
+                for (int a = 0; a < 3; ++a) {
+                    double d = c->disp[(long)a * Nl + node];
+                    D[a] += v * d;
+                    J[a][0] += gx * d;
+                    J[a][1] += gy * d;
+                    J[a][2] += gz * d;
+                }
+            }
+}
+
+/* the same at reference point r (unwrapped): the cell is floor(r/h) */
+static void disp_field(const oracle_cfg *c, const double *r, double *D, double J[3][3])
+{
+    int e[3];
+    double t[3];
+    for (int a = 0; a < 3; ++a) {
+        double h = c->length[a] / c->n_el[a];
+        double s = r[a] / h;
+        double E = floor(s);
+        t[a] = s - E;
+        long Ei = (long)E % c->n_el[a];
+        if (Ei < 0) Ei += c->n_el[a];
+        e[a] = (int)Ei;
+    }
+    disp_cell(c, e, t, D, J);
+}
+
+static double det3(double J[3][3])
+{
+    return J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) - J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0])
+         + J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+}
+
+/* reference point of the departure of node (gx, gy, gz) for displacement
+ * -shift: cell base node per axis (wrapped) and local coordinates */
+static void mapped_departure(const oracle_cfg *c, int gx, int gy, int gz, const double *shift, int *base,
+                             double *t)
+{
+    int p = c->p;
+    int N[3] = {c->n_el[0] * p, c->n_el[1] * p, c->n_el[2] * p};
+    long Nl = (long)N[0] * N[1] * N[2];
+    long n = ((long)gz * N[1] + gy) * N[0] + gx;
+    int gi[3] = {gx, gy, gz};
+    double xd[3], r[3];
+    for (int a = 0; a < 3; ++a) {
+        double r0 = node_pos(gi[a], p, c->length[a] / c->n_el[a]);
+        xd[a] = r0 + c->disp[(long)a * Nl + n] - shift[a];
+        r[a] = r0 - shift[a];                         /* start: the undistorted departure */
+    }
+    for (int it = 0; it < 100; ++it) {
+        double D[3], J[3][3], F[3];
+        disp_field(c, r, D, J);
+        for (int a = 0; a < 3; ++a) F[a] = r[a] + D[a] - xd[a];
+        /* r -= J^-1 F by Cramer's rule */
+        double dt = det3(J), dr[3];
+        for (int k = 0; k < 3; ++k) {
+            double M[3][3];
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) M[a][b] = (b == k) ? F[a] : J[a][b];
+            dr[k] = det3(M) / dt;
+        }
+        double sz = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            r[a] -= dr[a];
+            sz += fabs(dr[a]) / (c->length[a] / c->n_el[a]);
+        }
+        if (sz < 1e-15) break;
+    }
+    for (int a = 0; a < 3; ++a) {
+        double h = c->length[a] / c->n_el[a];
+        double s = r[a] / h;
+        double E = floor(s);
+        long Ei = (long)E % c->n_el[a];
+        if (Ei < 0) Ei += c->n_el[a];
+        base[a] = (int)(Ei * p);
+        t[a] = s - E;
+    }
+}
+
+/* Domain integral weights of a distorted mesh: per node, the sum over the
+ * cells that hold it of the tensor Clenshaw-Curtis weight of its local point
+ * times |det(I + dD/dr)| of that cell there.  w: [N]. */
+void oracle_mapped_node_weights(const oracle_cfg *c, double *w)
+{
+    int p = c->p;
+    int N[3] = {c->n_el[0] * p, c->n_el[1] * p, c->n_el[2] * p};
+    long Nl = (long)N[0] * N[1] * N[2];
+    double wcc[16], tg[16];
+    oracle_cc_weights(p, wcc);
+    oracle_glc_nodes(p, tg);
+    for (long n = 0; n < Nl; ++n) w[n] = 0.0;
+    double h[3] = {c->length[0] / c->n_el[0], c->length[1] / c->n_el[1], c->length[2] / c->n_el[2]};
+    for (int ez = 0; ez < c->n_el[2]; ++ez)
+        for (int ey = 0; ey < c->n_el[1]; ++ey)
+            for (int ex = 0; ex < c->n_el[0]; ++ex)
+                for (int kz = 0; kz <= p; ++kz)
+                    for (int ky = 0; ky <= p; ++ky)
+                        for (int kx = 0; kx <= p; ++kx) {
+                            /* the derivative of this cell's map at its point */
+                            double t[3] = {tg[kx], tg[ky], tg[kz]};
+                            int e[3] = {ex, ey, ez};
+                            double D[3], J[3][3];
+                            disp_cell(c, e, t, D, J);
+                            double W = 0.125 * h[0] * h[1] * h[2] * wcc[kx] * wcc[ky] * wcc[kz];
+                            long node = ((long)((ez * p + kz) % N[2]) * N[1] + (ey * p + ky) % N[1]) * N[0]
+                                      + (ex * p + kx) % N[0];
+                            w[node] += W * fabs(det3(J));
+                        }
 }
 
 /* ------------------------------------------------------------------------- */
@@ -507,10 +657,44 @@ static void departure_value(const oracle_cfg *c, const double *xi, int i, int gx
     *gv = sg;
 }
 
+static void mapped_departure(const oracle_cfg *c, int gx, int gy, int gz, const double *shift, int *base,
+                             double *t);
+
 void FN(stream)(const oracle_cfg *c, const R *f, const R *g, R *fo, R *go)
 {
     double xi[3 * Q], w[Q];
     oracle_velocity_set(xi, w);
+    if (c->disp) {
+        /* distorted mesh: departure cell and reference coordinates by Newton
+         * on the cell maps, then the same (p+1)^3 tensor Lagrange sum */
+        int p = c->p;
+        int N[3] = {c->n_el[0] * p, c->n_el[1] * p, c->n_el[2] * p};
+        long Nl = (long)N[0] * N[1] * N[2];
+#pragma omp parallel for collapse(2) schedule(dynamic)
+        for (int i = 0; i < Q; ++i) {
+            for (long n = 0; n < Nl; ++n) {
+                int gx = (int)(n % N[0]), gy = (int)((n / N[0]) % N[1]), gz = (int)(n / ((long)N[0] * N[1]));
+                double sh[3] = {xi[3 * i] * c->dt, xi[3 * i + 1] * c->dt, xi[3 * i + 2] * c->dt};
+                int base[3];
+                double t[3], ell[3][16];
+                mapped_departure(c, gx, gy, gz, sh, base, t);
+                for (int a = 0; a < 3; ++a) oracle_lagrange(p, t[a], ell[a]);
+                R sf = 0, sg = 0;
+                for (int kz = 0; kz <= p; ++kz)
+                    for (int ky = 0; ky <= p; ++ky)
+                        for (int kx = 0; kx <= p; ++kx) {
+                            long src = (long)i * Nl + ((long)((base[2] + kz) % N[2]) * N[1] + (base[1] + ky) % N[1])
+                                     * N[0] + (base[0] + kx) % N[0];
+                            double psi = ell[0][kx] * ell[1][ky] * ell[2][kz];
+                            sf += psi * f[src];
+                            sg += psi * g[src];
+                        }
+                fo[(long)i * Nl + n] = sf;
+                go[(long)i * Nl + n] = sg;
+            }
+        }
+        return;
+    }
     int Nx = c->n_el[0] * c->p, Ny = c->n_el[1] * c->p, Nz = c->n_el[2] * c->p;
     long N = n_nodes(c);
 #pragma omp parallel for collapse(2) schedule(static)
@@ -626,11 +810,16 @@ void FN(totals)(const oracle_cfg *c, const R *f, const R *g, R *out)
     int Nx = c->n_el[0] * p, Ny = c->n_el[1] * p, Nz = c->n_el[2] * p;
     long N = n_nodes(c);
     for (int k = 0; k < 5; ++k) out[k] = 0;
+    double *mw = NULL;                       /* distorted mesh: per-node weights */
+    if (c->disp) {
+        mw = (double *)malloc(sizeof(double) * N);
+        oracle_mapped_node_weights(c, mw);
+    }
     for (int gz = 0; gz < Nz; ++gz)
         for (int gy = 0; gy < Ny; ++gy)
             for (int gx = 0; gx < Nx; ++gx) {
                 long n = ((long)gz * Ny + gy) * Nx + gx;
-                double W = node_weight(c, 0, gx) * node_weight(c, 1, gy) * node_weight(c, 2, gz);
+                double W = mw ? mw[n] : node_weight(c, 0, gx) * node_weight(c, 1, gy) * node_weight(c, 2, gz);
                 R r = 0, j[3] = {0, 0, 0}, twoE = 0;
                 for (int i = 0; i < Q; ++i) {
                     R fi = f[(long)i * N + n];
@@ -643,6 +832,7 @@ void FN(totals)(const oracle_cfg *c, const R *f, const R *g, R *out)
                 for (int a = 0; a < 3; ++a) out[1 + a] += W * j[a];
                 out[4] += W * 0.5 * twoE;
             }
+    free(mw);
 }
 
 /* Flow functional used for gradients:

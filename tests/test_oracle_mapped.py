@@ -1,0 +1,177 @@
+"""Pins of the oracle on distorted meshes: the equal-cell GLC grid with
+periodic node displacements d, every cell the isoparametric (degree-p) image
+of its reference cube, populations interpolated in reference coordinates
+(Sec. II A: departure points traced through the cells once; the general
+case the paper calls memory-bound, subsection "Numerical efficiency").
+
+* Zero displacement reproduces the equal-cell oracle.
+* A shear d_x = a s(r_y) with s linear inside every cell is represented
+  exactly by the cell maps, and its inverse is explicit: r_y = y,
+  r_x = x - a s(y).  A field linear inside every reference cell then
+  streams exactly to its value at the departure point's reference
+  coordinates, computed here in closed form.
+* A coupled distortion (d_x = a s1(r_y), d_y = b s2(r_x)) has no explicit
+  inverse: the reference departure point comes from scipy's root finder on
+  the analytic map.
+* Smooth distortion and smooth field: the error against the field at the
+  physical departure point falls as h^(p+1).
+* A shear has |det J| = 1, so the node weights are those of equal cells;
+  on a smooth distortion the weights integrate 1 to the domain volume
+  exactly.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy.optimize import fsolve
+
+Q = 45
+
+
+def _pw(x, faces, vals):
+    """Periodic function linear between faces, value vals[e] at faces[e]."""
+    L = faces[-1]
+    xw = np.mod(x, L)
+    e = np.clip(np.searchsorted(faces, xw, side="right") - 1, 0, len(faces) - 2)
+    t = (xw - faces[e]) / (faces[e + 1] - faces[e])
+    v1 = np.append(vals, vals[0])
+    return v1[e] * (1 - t) + v1[e + 1] * t
+
+
+def _ref_coords(oracle, cfg):
+    xs, ys, zs = oracle.node_coords(cfg)
+    Z, Y, X = np.meshgrid(zs, ys, xs, indexing="ij")
+    return X.reshape(-1), Y.reshape(-1), Z.reshape(-1)
+
+
+def test_zero_displacement_matches_equal_cells(oracle):
+    n_el, p, dt = (3, 2, 4), 3, 0.37
+    cu = oracle.make_cfg(n_el, p, dt, 0.01)
+    N = oracle.num_nodes(cu)
+    cm = oracle.make_cfg(n_el, p, dt, 0.01, disp=np.zeros((3, N)))
+    rng = np.random.default_rng(1)
+    f, g = rng.normal(size=(Q, N)), rng.normal(size=(Q, N))
+    fu, gu = oracle.stream(cu, f, g)
+    fm, gm = oracle.stream(cm, f, g)
+    assert np.max(np.abs(fm - fu)) < 1e-13 * np.abs(fu).max()
+    assert np.max(np.abs(gm - gu)) < 1e-13 * np.abs(gu).max()
+    assert np.allclose(oracle.mapped_node_weights(cm), oracle.mapped_node_weights(cu), rtol=1e-14)
+
+
+@pytest.mark.parametrize("p,dt,a", [(2, 0.21, 0.25), (3, 0.6, 0.4), (4, 0.9, -0.3)])
+def test_sheared_mesh_streams_cell_linear_fields_exactly(oracle, p, dt, a):
+    n_el = (4, 5, 3)
+    L = 2 * math.pi
+    h = L / np.array(n_el)
+    faces = [np.arange(n + 1) * L / n for n in n_el]
+    rng = np.random.default_rng(p)
+    svals = rng.uniform(-1, 1, n_el[1]) * h[0]            # shear profile s(r_y), cell-wise linear
+    vals = [rng.uniform(0.5, 1.5, n) for n in n_el]
+    cfg0 = oracle.make_cfg(n_el, p, dt, 0.01)
+    X, Y, Z = _ref_coords(oracle, cfg0)
+    N = X.size
+    disp = np.zeros((3, N))
+    disp[0] = a * _pw(Y, faces[1], svals)
+    cfg = oracle.make_cfg(n_el, p, dt, 0.01, disp=disp)
+
+    def phi(rx, ry, rz):
+        return _pw(rx, faces[0], vals[0]) * _pw(ry, faces[1], vals[1]) * _pw(rz, faces[2], vals[2])
+
+    f = np.tile(phi(X, Y, Z), (Q, 1))
+    fo, go = oracle.stream(cfg, f, 2 * f)
+    xi, _ = oracle.velocity_set()
+    xphys = X + disp[0]
+    for i in range(Q):
+        yd, zd = Y - xi[i, 1] * dt, Z - xi[i, 2] * dt
+        rx = xphys - xi[i, 0] * dt - a * _pw(yd, faces[1], svals)
+        ref = phi(rx, yd, zd)
+        assert np.max(np.abs(fo[i] - ref)) < 1e-11, i
+        assert np.max(np.abs(go[i] - 2 * ref)) < 1e-11, i
+
+
+def test_coupled_distortion_against_root_finder(oracle):
+    n_el, p, dt = (4, 4, 2), 3, 0.45
+    L = 2 * math.pi
+    faces = [np.arange(n + 1) * L / n for n in n_el]
+    rng = np.random.default_rng(7)
+    s1 = rng.uniform(-0.15, 0.15, n_el[1])
+    s2 = rng.uniform(-0.15, 0.15, n_el[0])
+    vals = [rng.uniform(0.5, 1.5, n) for n in n_el]
+    cfg0 = oracle.make_cfg(n_el, p, dt, 0.01)
+    X, Y, Z = _ref_coords(oracle, cfg0)
+    disp = np.zeros((3, X.size))
+    disp[0] = _pw(Y, faces[1], s1)
+    disp[1] = _pw(X, faces[0], s2)
+    cfg = oracle.make_cfg(n_el, p, dt, 0.01, disp=disp)
+
+    def phi(rx, ry, rz):
+        return _pw(rx, faces[0], vals[0]) * _pw(ry, faces[1], vals[1]) * _pw(rz, faces[2], vals[2])
+
+    f = np.tile(phi(X, Y, Z), (Q, 1))
+    fo, _ = oracle.stream(cfg, f, f)
+    xi, _ = oracle.velocity_set()
+    rng2 = np.random.default_rng(8)
+    for i in rng2.choice(Q, 8, replace=False):
+        for n in rng2.choice(X.size, 12, replace=False):
+            xd = X[n] + disp[0, n] - xi[i, 0] * dt
+            yd = Y[n] + disp[1, n] - xi[i, 1] * dt
+
+            def F(r):
+                return [r[0] + _pw(np.array([r[1]]), faces[1], s1)[0] - xd,
+                        r[1] + _pw(np.array([r[0]]), faces[0], s2)[0] - yd]
+
+            r = fsolve(F, [X[n] - xi[i, 0] * dt, Y[n] - xi[i, 1] * dt], xtol=1e-13)
+            assert np.max(np.abs(F(r))) < 1e-12
+            ref = phi(np.array([r[0]]), np.array([r[1]]), np.array([Z[n] - xi[i, 2] * dt]))[0]
+            assert abs(fo[i, n] - ref) < 1e-11, (i, n)
+
+
+@pytest.mark.parametrize("p", [2, 3])
+def test_smooth_distortion_error_order(oracle, p):
+    L = 2 * math.pi
+    errs = []
+    for n in (8, 16):
+        dt = 0.4 * L / n / math.sqrt(15)
+        cfg0 = oracle.make_cfg((n, n, 1), p, dt, 0.01, length=(L, L, L / n))
+        X, Y, Z = _ref_coords(oracle, cfg0)
+        disp = np.zeros((3, X.size))
+        disp[0] = 0.15 * np.sin(Y) * np.cos(X)
+        disp[1] = 0.1 * np.sin(X + 0.3)
+        cfg = oracle.make_cfg((n, n, 1), p, dt, 0.01, length=(L, L, L / n), disp=disp)
+        P = oracle.mapped_node_coords(cfg)
+        fun = lambda x, y: np.sin(x) * np.cos(y) + 0.5 * np.cos(2 * y)
+        f = np.tile(fun(P[0], P[1]), (Q, 1))
+        fo, _ = oracle.stream(cfg, f, f)
+        xi, _ = oracle.velocity_set()
+        errs.append(max(np.max(np.abs(fo[i] - fun(P[0] - xi[i, 0] * dt, P[1] - xi[i, 1] * dt))) for i in range(Q)))
+    ratio = errs[0] / errs[1]
+    assert 0.7 * 2 ** (p + 1) < ratio < 1.4 * 2 ** (p + 1), (errs, ratio)
+
+
+def test_node_weights(oracle):
+    n_el, p = (4, 3, 2), 3
+    L = 2 * math.pi
+    faces = [np.arange(n + 1) * L / n for n in n_el]
+    cfg0 = oracle.make_cfg(n_el, p, 0.1, 0.01)
+    X, Y, Z = _ref_coords(oracle, cfg0)
+    disp = np.zeros((3, X.size))
+    disp[0] = 0.3 * _pw(Y, faces[1], np.random.default_rng(3).uniform(-1, 1, n_el[1]))
+    cfg = oracle.make_cfg(n_el, p, 0.1, 0.01, disp=disp)
+    w = oracle.mapped_node_weights(cfg)
+    # shear: det J = 1, the weights are those of equal cells
+    wx, wy, wz = (np.array([oracle.cc_weights(p)[g % p] * (2 if g % p == 0 else 1) for g in range(n * p)])
+                  for n in n_el)
+    h = L / np.array(n_el)
+    W0 = (np.einsum("k,j,i->kji", wz * h[2] / 2, wy * h[1] / 2, wx * h[0] / 2)).reshape(-1)
+    assert np.allclose(w, W0, rtol=1e-13)
+    # smooth distortion: the weights integrate 1 to the volume exactly (the
+    # Jacobian determinant of a periodic map is a sum of divergences, and the
+    # cell-wise rule telescopes them), while the weights themselves change
+    for n, p2 in ((4, 2), (5, 3)):
+        c0 = oracle.make_cfg((n, n, n), p2, 0.1, 0.01)
+        X, Y, Z = _ref_coords(oracle, c0)
+        d = np.stack([0.2 * np.sin(Y + Z), 0.2 * np.sin(Z) * np.cos(X), 0.15 * np.cos(X + Y)])
+        c = oracle.make_cfg((n, n, n), p2, 0.1, 0.01, disp=d)
+        wm, w0 = oracle.mapped_node_weights(c), oracle.mapped_node_weights(c0)
+        assert abs(wm.sum() - L ** 3) < 1e-12 * L ** 3
+        assert np.max(np.abs(wm - w0)) > 1e-3 * np.max(w0)
