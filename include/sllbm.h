@@ -140,6 +140,24 @@ int sllbm_set_viscosity(sllbm_ctx *ctx, double mu_inf);
  * ENOMEM, EDEVICE. */
 int sllbm_set_mesh(sllbm_ctx *ctx, const double *widths_x, const double *widths_y, const double *widths_z);
 
+/* Distorted mesh (Sec. II A: departure points traced once through the
+ * cells; the general, non-factorising case of subsection "Numerical
+ * efficiency").  d: host array [3][N] of periodic node displacements added to
+ * the equal-cell GLC positions; each cell becomes the degree-p
+ * (isoparametric) image of its reference cube, and populations are
+ * interpolated in reference coordinates.  For every velocity and node the
+ * departure point x + d - xi dt is located by Newton's method on the cell
+ * maps, and its cell and local coordinates are uploaded (28 bytes per
+ * velocity and node); totals then weight every node with the |det J| of the
+ * cells that hold it.  d = NULL returns to the undistorted mesh.  The state is
+ * kept; node coordinates stay those of the reference grid.  On a distorted
+ * mesh the transposed streaming, the adjoint step, the loss, its gradient and
+ * the diagnostics return EINVAL.  Synchronises the context's stream.
+ * Errors: EINVAL (2-D context, graded cells, non-finite d, a cell map that
+ * folds over (det J <= 0 at a support point), a departure search that does
+ * not converge), ENOMEM, EDEVICE; on error the previous mesh stays. */
+int sllbm_set_displacement(sllbm_ctx *ctx, const double *d);
+
 /* State := equilibrium of the given fields (Eq. (6); g^eq = (2C_v - D) T f^eq).
  * rho, u ([D][N]), T: device.  Errors: EINVAL on NULL. */
 int sllbm_init_equilibrium(sllbm_ctx *ctx, const double *rho, const double *u, const double *T);

@@ -62,6 +62,13 @@ struct sllbm_ctx {
     void *d_gw[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
     int gk[2] = {0, 0}, gwxm[2] = {0, 0}, gwym[2] = {0, 0};
     double *d_hw = nullptr;        // graded cell widths: x cells, then y, then z (loss, diagnostics)
+    // distorted mesh (sllbm_set_displacement): departure cells and local
+    // coordinates per velocity and node, per-node quadrature weights
+    bool mapped = false;
+    int32_t *d_mcell = nullptr;
+    double *d_mt = nullptr;
+    double *d_mw = nullptr;
+    GlcBasis glc{};
     std::string err;
 };
 
@@ -109,6 +116,9 @@ void free_ctx(sllbm_ctx *c)
             (void)hipFree(c->d_gw[d][a]);
         }
     (void)hipFree(c->d_hw);
+    (void)hipFree(c->d_mcell);
+    (void)hipFree(c->d_mt);
+    (void)hipFree(c->d_mw);
     (void)hipFree(c->d_omin);
     (void)hipFree(c->d_lstar);
     (void)hipFree(c->d_cw);
@@ -175,6 +185,15 @@ int refuse_2d(sllbm_ctx *c, const char *what)
 {
     return fail(c, SLLBM_EINVAL, std::string(what) + " is not available on the two-dimensional lattice (D2Q19)");
 }
+
+// calls defined for axis-aligned cells only (transposed streaming and what
+// builds on it, derivatives of the flow fields)
+int refuse_mapped(sllbm_ctx *c, const char *what)
+{
+    return fail(c, SLLBM_EINVAL, std::string(what) + " is not available on a distorted mesh");
+}
+
+MappedTables mapped_tables(const sllbm_ctx *c) { return MappedTables{c->d_mcell, c->d_mt, c->glc}; }
 
 const double *graded_hw(const sllbm_ctx *c) { return c->graded ? c->d_hw : nullptr; }
 
@@ -472,6 +491,7 @@ int sllbm_set_mesh(sllbm_ctx *ctx, const double *widths_x, const double *widths_
     if (!ctx) return SLLBM_EINVAL;
     const double *wd[3] = {widths_x, widths_y, widths_z};
     if (ctx->d2) return refuse_2d(ctx, "sllbm_set_mesh");
+    if (ctx->mapped) return refuse_mapped(ctx, "sllbm_set_mesh");
     if (!wd[0] && !wd[1] && !wd[2]) return fail(ctx, SLLBM_EINVAL, "set_mesh: no graded axis given");
     std::vector<double> faces[3];
     for (int a = 0; a < 3; ++a) {
@@ -511,6 +531,70 @@ int sllbm_set_mesh(sllbm_ctx *ctx, const double *widths_x, const double *widths_
     ctx->graded = was_graded && upload() == SLLBM_OK;
     ctx->err = msg;
     return rc;
+}
+
+int sllbm_set_displacement(sllbm_ctx *ctx, const double *d)
+{
+    if (!ctx) return SLLBM_EINVAL;
+    if (ctx->d2) return refuse_2d(ctx, "sllbm_set_displacement");
+    if (ctx->graded) return fail(ctx, SLLBM_EINVAL, "set_displacement: the mesh has graded cells");
+    DeviceGuard guard(ctx->cfg.device);
+    hipError_t e = ctx->stream ? hipStreamSynchronize(ctx->stream) : hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(ctx, e, "set_displacement");
+    auto drop = [&]() {
+        (void)hipFree(ctx->d_mcell);
+        (void)hipFree(ctx->d_mt);
+        (void)hipFree(ctx->d_mw);
+        ctx->d_mcell = nullptr;
+        ctx->d_mt = nullptr;
+        ctx->d_mw = nullptr;
+        ctx->mapped = false;
+    };
+    if (!d) {
+        drop();
+        return SLLBM_OK;
+    }
+    const int64_t N = ctx->geo.nodes;
+    for (int64_t k = 0; k < 3 * N; ++k)
+        if (!std::isfinite(d[k])) return fail(ctx, SLLBM_EINVAL, "set_displacement: non-finite displacement");
+    std::vector<int32_t> cell;
+    std::vector<double> tloc, nodew;
+    std::string why;
+    if (!build_mapped_tables(ctx->vs, ctx->geo.p, ctx->geo.nel, ctx->cfg.length, d, ctx->cfg.dt, cell, tloc, nodew,
+                             why))
+        return fail(ctx, SLLBM_EINVAL, why);
+    int32_t *dc = nullptr;
+    double *dt = nullptr, *dw = nullptr;
+    if ((e = dalloc(&dc, cell.size() * sizeof(int32_t))) != hipSuccess ||
+        (e = dalloc(&dt, tloc.size() * sizeof(double))) != hipSuccess ||
+        (e = dalloc(&dw, nodew.size() * sizeof(double))) != hipSuccess) {
+        (void)hipFree(dc);
+        (void)hipFree(dt);
+        (void)hipFree(dw);
+        return fail(ctx, SLLBM_ENOMEM, std::string("distorted-mesh tables: ") + hipGetErrorString(e));
+    }
+    if ((e = hipMemcpy(dc, cell.data(), cell.size() * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(dt, tloc.data(), tloc.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(dw, nodew.data(), nodew.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess) {
+        (void)hipFree(dc);
+        (void)hipFree(dt);
+        (void)hipFree(dw);
+        return hip_fail(ctx, e, "distorted-mesh table upload");
+    }
+    drop();
+    ctx->d_mcell = dc;
+    ctx->d_mt = dt;
+    ctx->d_mw = dw;
+    const int p = ctx->geo.p;
+    glc_points(p, ctx->glc.t);
+    for (int k = 0; k <= p; ++k) {
+        double den = 1.0;
+        for (int m = 0; m <= p; ++m)
+            if (m != k) den *= ctx->glc.t[k] - ctx->glc.t[m];
+        ctx->glc.inv_den[k] = 1.0 / den;
+    }
+    ctx->mapped = true;
+    return SLLBM_OK;
 }
 
 int sllbm_set_viscosity(sllbm_ctx *ctx, double mu_inf)
@@ -585,6 +669,13 @@ static hipError_t collide_into(sllbm_ctx *c, const void *in, void *out)
 
 static hipError_t stream_into(sllbm_ctx *c, const void *in, void *out)
 {
+    if (c->mapped) {
+        if (is_fp64(c))
+            return launch_stream_mapped<double>(c->geo, mapped_tables(c), static_cast<const double *>(in),
+                                                static_cast<double *>(out), c->stream);
+        return launch_stream_mapped<float>(c->geo, mapped_tables(c), static_cast<const float *>(in),
+                                           static_cast<float *>(out), c->stream);
+    }
     if (c->d2) {
         if (is_fp64(c))
             return launch_stream_2d<double>(c->geo, cell_tables<double>(c), static_cast<const double *>(in),
@@ -763,9 +854,11 @@ int sllbm_totals(sllbm_ctx *ctx, double *out)
                                                    ctx->d_partials, RED_BLOCKS, ctx->d_small, ctx->stream);
     else
         e = is_fp64(ctx) ? Launch<double>::totals(ctx->geo, ctx->cp, static_cast<const double *>(st), ctx->d_nodew,
-                                                  ctx->d_partials, RED_BLOCKS, ctx->d_small, ctx->stream)
+                                                  ctx->mapped ? ctx->d_mw : nullptr, ctx->d_partials, RED_BLOCKS,
+                                                  ctx->d_small, ctx->stream)
                          : Launch<float>::totals(ctx->geo, ctx->cp, static_cast<const float *>(st), ctx->d_nodew,
-                                                 ctx->d_partials, RED_BLOCKS, ctx->d_small, ctx->stream);
+                                                 ctx->mapped ? ctx->d_mw : nullptr, ctx->d_partials, RED_BLOCKS,
+                                                 ctx->d_small, ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "totals");
     if ((e = hipMemcpyAsync(out, ctx->d_small, 5 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream)) !=
             hipSuccess ||
@@ -781,6 +874,7 @@ int sllbm_stream(sllbm_ctx *ctx, const void *in, void *out, int32_t transpose)
     if (!ctx) return SLLBM_EINVAL;
     if (!in || !out || in == out) return fail(ctx, SLLBM_EINVAL, "bad stream buffers");
     if (transpose && ctx->d2) return refuse_2d(ctx, "transposed streaming");
+    if (transpose && ctx->mapped) return refuse_mapped(ctx, "transposed streaming");
     DeviceGuard guard(ctx->cfg.device);
     if (!transpose) return check_launch(ctx, stream_into(ctx, in, out), "stream");
     return check_launch(ctx, stream_t_into(ctx, in, out), "stream");
@@ -806,6 +900,7 @@ int sllbm_loss(sllbm_ctx *ctx, const void *state, double *out)
     if (!ctx) return SLLBM_EINVAL;
     if (!state || !out) return fail(ctx, SLLBM_EINVAL, "NULL argument");
     if (ctx->d2) return refuse_2d(ctx, "sllbm_loss");
+    if (ctx->mapped) return refuse_mapped(ctx, "sllbm_loss");
     DeviceGuard guard(ctx->cfg.device);
     hipError_t e = is_fp64(ctx)
         ? Launch<double>::loss(ctx->geo, static_cast<const double *>(state), ctx->d_dmat, ctx->d_ccw, ctx->h,
@@ -827,6 +922,7 @@ int sllbm_diagnostics(sllbm_ctx *ctx, const void *state, double *out)
     if (!ctx) return SLLBM_EINVAL;
     if (!out) return fail(ctx, SLLBM_EINVAL, "NULL out");
     if (ctx->d2) return refuse_2d(ctx, "sllbm_diagnostics");
+    if (ctx->mapped) return refuse_mapped(ctx, "sllbm_diagnostics");
     if (!state && !ctx->has_state) return fail(ctx, SLLBM_ESTATE, "no state set");
     DeviceGuard guard(ctx->cfg.device);
     const void *st = state ? state : ctx->buf[ctx->cur];
@@ -852,6 +948,7 @@ int sllbm_loss_grad(sllbm_ctx *ctx, const void *state, void *lam)
     if (!ctx) return SLLBM_EINVAL;
     if (!state || !lam || state == lam) return fail(ctx, SLLBM_EINVAL, "bad loss_grad buffers");
     if (ctx->d2) return refuse_2d(ctx, "sllbm_loss_grad");
+    if (ctx->mapped) return refuse_mapped(ctx, "sllbm_loss_grad");
     DeviceGuard guard(ctx->cfg.device);
     hipError_t e = is_fp64(ctx)
         ? Launch<double>::loss_grad(ctx->geo, static_cast<const double *>(state), ctx->d_dmat, ctx->d_ccw,
@@ -871,6 +968,7 @@ int sllbm_adjoint_step(sllbm_ctx *ctx, const void *state_n, const void *lam_next
     if (!state_n || !lam_next || !lam_out) return fail(ctx, SLLBM_EINVAL, "NULL argument");
     if (lam_out == lam_next || lam_out == state_n) return fail(ctx, SLLBM_EINVAL, "lam_out aliases an input");
     if (ctx->d2) return refuse_2d(ctx, "sllbm_adjoint_step");
+    if (ctx->mapped) return refuse_mapped(ctx, "sllbm_adjoint_step");
     DeviceGuard guard(ctx->cfg.device);
     hipError_t e = stream_t_into(ctx, lam_next, lam_out);
     if (e != hipSuccess) return hip_fail(ctx, e, "adjoint_step (transposed streaming)");

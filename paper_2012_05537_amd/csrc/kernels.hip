@@ -161,6 +161,7 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double *red)
 template <typename S, class L>
 __global__ void __launch_bounds__(256) k_totals_partial(Geometry geo, const S *__restrict__ state,
                                                         const double *__restrict__ nodew,
+                                                        const double *__restrict__ full_w,
                                                         double *__restrict__ partials)
 {
     __shared__ double red[5 * 256];
@@ -173,7 +174,7 @@ __global__ void __launch_bounds__(256) k_totals_partial(Geometry geo, const S *_
         const int64_t r = n / geo.N[0];
         const int gy = static_cast<int>(r % geo.N[1]);
         const int gz = static_cast<int>(r / geo.N[1]);
-        const double W = wx[gx] * wy[gy] * wz[gz];
+        const double W = full_w ? full_w[n] : wx[gx] * wy[gy] * wz[gz];
         double rho, jx, jy, jz, twoE;
         node_sums<S, L>(state, N, n, rho, jx, jy, jz, twoE);
         acc[0] = fma(W, rho, acc[0]);
@@ -255,10 +256,10 @@ static hipError_t moments_lat(const Geometry &g, const CollisionParams &cp, cons
 }
 
 template <typename S, class L>
-static hipError_t totals_lat(const Geometry &g, const S *state, const double *nodew, double *partials, int nblocks,
-                             double *out5, hipStream_t st)
+static hipError_t totals_lat(const Geometry &g, const S *state, const double *nodew, const double *full_w,
+                             double *partials, int nblocks, double *out5, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_totals_partial<S, L>), dim3(nblocks), dim3(256), 0, st, g, state, nodew, partials);
+    hipLaunchKernelGGL((k_totals_partial<S, L>), dim3(nblocks), dim3(256), 0, st, g, state, nodew, full_w, partials);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_reduce_partials<5>), dim3(1), dim3(256), 0, st, partials, nblocks, out5, 0);
@@ -293,9 +294,9 @@ hipError_t Launch<S>::moments(const Geometry &g, const CollisionParams &cp, cons
 
 template <typename S>
 hipError_t Launch<S>::totals(const Geometry &g, const CollisionParams &, const S *state, const double *nodew,
-                             double *partials, int nblocks, double *out5, hipStream_t st)
+                             const double *full_w, double *partials, int nblocks, double *out5, hipStream_t st)
 {
-    return totals_lat<S, D3Q45>(g, state, nodew, partials, nblocks, out5, st);
+    return totals_lat<S, D3Q45>(g, state, nodew, full_w, partials, nblocks, out5, st);
 }
 
 template <typename S>
@@ -323,7 +324,7 @@ template <typename S>
 hipError_t Launch2D<S>::totals(const Geometry &g, const S *state, const double *nodew, double *partials,
                                int nblocks, double *out5, hipStream_t st)
 {
-    return totals_lat<S, D2Q19>(g, state, nodew, partials, nblocks, out5, st);
+    return totals_lat<S, D2Q19>(g, state, nodew, nullptr, partials, nblocks, out5, st);
 }
 
 template struct Launch<double>;

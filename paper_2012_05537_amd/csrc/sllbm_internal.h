@@ -61,6 +61,17 @@ void build_node_tables(const VelocitySet &vs, int p, int ne, double length, cons
 void build_transposed_node_tables(int N, int p, const std::vector<int32_t> &src, const std::vector<double> &w,
                                   int kt, std::vector<int32_t> &srcT, std::vector<double> &wT, int &band);
 
+// Distorted meshes: node displacements d ([3][N], periodic) of the equal-cell
+// grid, each cell the degree-p interpolant of its nodes' positions.  For every
+// velocity i and node n: the departure point's cell (linear cell index,
+// x fastest) in cell[i*N + n] and its local coordinates in
+// tloc[(a*q + i)*N + n]; the quadrature weight of every node (|det J| of the
+// cells that hold it) in nodew.  false (with why) if a cell map folds over or
+// a departure search does not converge.
+bool build_mapped_tables(const VelocitySet &vs, int p, const int ne[3], const double length[3], const double *d,
+                         double dt, std::vector<int32_t> &cell, std::vector<double> &tloc, std::vector<double> &nodew,
+                         std::string &why);
+
 // ---------------------------------------------------------------------------
 // Device-side parameter blocks (passed by value to kernels)
 // ---------------------------------------------------------------------------
@@ -93,6 +104,20 @@ struct NodeTables {
     int wxm, wym;
 };
 
+// GLC points of a cell and 1 / prod_{m != k} (t_k - t_m): ell_k(t) =
+// inv_den[k] * prod_{m != k} (t - t_m)
+struct GlcBasis {
+    double t[MAXP + 1];
+    double inv_den[MAXP + 1];
+};
+
+// Device tables of a distorted mesh (build_mapped_tables)
+struct MappedTables {
+    const int32_t *cell;    // [Q][N] departure cell, x fastest
+    const double *tloc;     // [3][Q][N] local coordinates in [0, 1)
+    GlcBasis basis;
+};
+
 struct CollisionParams {
     double dt;
     double Cv;        // 1/(gamma - 1)
@@ -115,8 +140,10 @@ struct Launch {
                                        const double *u, const double *T, S *state, hipStream_t st);
     static hipError_t moments(const Geometry &g, const CollisionParams &cp, const S *state, double *rho,
                               double *u, double *T, hipStream_t st);
+    // nodew: the separable 1-D node weights; full_w (or NULL): per-node weights
+    // of a distorted mesh, used instead
     static hipError_t totals(const Geometry &g, const CollisionParams &cp, const S *state,
-                             const double *nodew, double *partials, int nblocks, double *out5,
+                             const double *nodew, const double *full_w, double *partials, int nblocks, double *out5,
                              hipStream_t st);
     // h: cell width per axis; hw: graded cell widths (x, then y, then z cells) or NULL
     static hipError_t loss(const Geometry &g, const S *state, const double *dmat, const double *ccw,
@@ -167,6 +194,9 @@ hipError_t launch_stream_z(const Geometry &g, const CellTables<S> &t, const S *i
 // with the forward cell tables (stream.hip); any number of cells per axis
 template <typename S>
 hipError_t launch_stream_zt(const Geometry &g, const CellTables<S> &t, const S *in, S *out, hipStream_t st);
+// streaming on a distorted mesh (stream_mapped.hip)
+template <typename S>
+hipError_t launch_stream_mapped(const Geometry &g, const MappedTables &t, const S *in, S *out, hipStream_t st);
 // streaming on a graded mesh (stream_graded.hip)
 template <typename S>
 hipError_t launch_stream_graded(const Geometry &g, const NodeTables<S> &t, const S *in, S *out, hipStream_t st);

@@ -1,0 +1,110 @@
+// Semi-Lagrangian streaming on a distorted mesh (Sec. II A: departure points
+// traced once through the cells; with distorted cells the interpolation does
+// not factorise per axis and the paper's subsection "Numerical efficiency"
+// expects a memory-bound kernel).
+//
+// The cells are the isoparametric images of the equal-cell reference grid
+// (node displacements, build_mapped_tables); populations are interpolated in
+// reference coordinates.  The host stores, per velocity and node, the
+// departure cell and the three local coordinates (28 bytes); the weights are
+// formed here ("matrix-free": 3 (P+1) Lagrange values instead of (P+1)^3
+// stored coefficients).  A thread owns one (velocity, node) pair and gathers
+// the (P+1)^3 support values of f and of g (the two populations share the
+// departure point); x-runs of P + 1 values are contiguous, neighbouring
+// threads read neighbouring runs, so the gathers are served by L1/L2.
+#include <hip/hip_runtime.h>
+
+#include "sllbm_internal.h"
+
+namespace sllbm {
+
+template <typename S, int P>
+__global__ void __launch_bounds__(256) k_stream_mapped(Geometry g, GlcBasis gb, const int32_t *__restrict__ cell,
+                                                       const double *__restrict__ tloc, const S *__restrict__ in,
+                                                       S *__restrict__ out)
+{
+    const int i = blockIdx.y;
+    const int64_t N = g.nodes;
+    const int64_t n = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+    if (n >= N) return;
+    const int Nx = g.N[0], Ny = g.N[1], Nz = g.N[2];
+    const int c = cell[static_cast<int64_t>(i) * N + n];
+    const int ex = c % g.nel[0], rest = c / g.nel[0];
+    const int ey = rest % g.nel[1], ez = rest / g.nel[1];
+    // Lagrange weights on the GLC points at the local coordinates
+    S w[3][P + 1];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double t = tloc[(static_cast<int64_t>(a) * Q + i) * N + n];
+#pragma unroll
+        for (int k = 0; k <= P; ++k) {
+            double v = gb.inv_den[k];
+#pragma unroll
+            for (int m = 0; m <= P; ++m)
+                if (m != k) v *= t - gb.t[m];
+            w[a][k] = static_cast<S>(v);
+        }
+    }
+    const S *fi = in + static_cast<int64_t>(i) * N;
+    const S *gi = in + static_cast<int64_t>(Q + i) * N;
+    S sf = 0, sg = 0;
+#pragma unroll
+    for (int kz = 0; kz <= P; ++kz) {
+        int zz = ez * P + kz;
+        zz = zz >= Nz ? zz - Nz : zz;
+#pragma unroll
+        for (int ky = 0; ky <= P; ++ky) {
+            int yy = ey * P + ky;
+            yy = yy >= Ny ? yy - Ny : yy;
+            const int64_t row = (static_cast<int64_t>(zz) * Ny + yy) * Nx;
+            S af = 0, ag = 0;
+#pragma unroll
+            for (int kx = 0; kx <= P; ++kx) {
+                int xx = ex * P + kx;
+                xx = xx >= Nx ? xx - Nx : xx;
+                af = fma(w[0][kx], fi[row + xx], af);
+                ag = fma(w[0][kx], gi[row + xx], ag);
+            }
+            const S wyz = w[1][ky] * w[2][kz];
+            sf = fma(wyz, af, sf);
+            sg = fma(wyz, ag, sg);
+        }
+    }
+    out[static_cast<int64_t>(i) * N + n] = sf;
+    out[static_cast<int64_t>(Q + i) * N + n] = sg;
+}
+
+namespace {
+
+template <typename S, int P>
+hipError_t launch_m(const Geometry &g, const MappedTables &t, const S *in, S *out, hipStream_t st)
+{
+    const int64_t bx = (g.nodes + 255) / 256;
+    if (bx > (int64_t(1) << 31) - 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_stream_mapped<S, P>), dim3(static_cast<unsigned>(bx), Q), dim3(256), 0, st, g, t.basis,
+                       t.cell, t.tloc, in, out);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+template <typename S>
+hipError_t launch_stream_mapped(const Geometry &g, const MappedTables &t, const S *in, S *out, hipStream_t st)
+{
+    switch (g.p) {
+    case 1: return launch_m<S, 1>(g, t, in, out, st);
+    case 2: return launch_m<S, 2>(g, t, in, out, st);
+    case 3: return launch_m<S, 3>(g, t, in, out, st);
+    case 4: return launch_m<S, 4>(g, t, in, out, st);
+    case 5: return launch_m<S, 5>(g, t, in, out, st);
+    case 6: return launch_m<S, 6>(g, t, in, out, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template hipError_t launch_stream_mapped<double>(const Geometry &, const MappedTables &, const double *, double *,
+                                                 hipStream_t);
+template hipError_t launch_stream_mapped<float>(const Geometry &, const MappedTables &, const float *, float *,
+                                                hipStream_t);
+
+}  // namespace sllbm

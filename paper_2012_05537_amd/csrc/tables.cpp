@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <cstdint>
 #include <cmath>
+#include <string>
 
 #include "sllbm_internal.h"
 #include "velset.h"
@@ -224,6 +225,174 @@ void build_transposed_node_tables(int N, int p, const std::vector<int32_t> &src,
                 wT[(static_cast<size_t>(i) * N + m) * kt + slot] = w[(static_cast<size_t>(i) * N + g) * (p + 1) + k];
         });
     }
+}
+
+
+
+// ---------------------------------------------------------------------------
+// Distorted meshes: the equal-cell GLC grid with periodic node displacements
+// d ([3][N]); each cell is the degree-p tensor interpolant of its nodes'
+// positions, i.e. the map r -> r + D(r) with D the cell-wise interpolant of d
+// (the GLC positions interpolate the identity).  Populations are interpolated
+// in reference coordinates, so each departure point x_g + d_g - xi dt is
+// located by Newton's method on r + D(r) = x_d.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct MapGrid {
+    int p, ne[3], N[3];
+    double h[3];
+    const double *d;   // [3][N]
+    int64_t nodes;
+};
+
+// D and I + dD/dr at local coordinates t of cell e (cell indices wrapped)
+void map_at(const MapGrid &m, const int e[3], const double t[3], double D[3], double J[3][3])
+{
+    const int p = m.p;
+    double l[3][MAXP + 1], dl[3][MAXP + 1];
+    for (int a = 0; a < 3; ++a) {
+        lagrange_basis(p, t[a], l[a]);
+        lagrange_basis_deriv(p, t[a], dl[a]);
+    }
+    for (int a = 0; a < 3; ++a) {
+        D[a] = 0.0;
+        for (int b = 0; b < 3; ++b) J[a][b] = a == b ? 1.0 : 0.0;
+    }
+    for (int kz = 0; kz <= p; ++kz) {
+        const int64_t zz = (e[2] * p + kz) % m.N[2];
+        for (int ky = 0; ky <= p; ++ky) {
+            const int64_t yy = (e[1] * p + ky) % m.N[1];
+            for (int kx = 0; kx <= p; ++kx) {
+                const int64_t node = (zz * m.N[1] + yy) * m.N[0] + (e[0] * p + kx) % m.N[0];
+                const double v = l[0][kx] * l[1][ky] * l[2][kz];
+                const double g[3] = {dl[0][kx] * l[1][ky] * l[2][kz] / m.h[0], l[0][kx] * dl[1][ky] * l[2][kz] / m.h[1],
+                                     l[0][kx] * l[1][ky] * dl[2][kz] / m.h[2]};
+                for (int a = 0; a < 3; ++a) {
+                    const double da = m.d[a * m.nodes + node];
+                    D[a] += v * da;
+                    for (int b = 0; b < 3; ++b) J[a][b] += g[b] * da;
+                }
+            }
+        }
+    }
+}
+
+double det3(const double J[3][3])
+{
+    return J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) - J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+           J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+}
+
+// cell (wrapped) and local coordinates of the unwrapped reference point r
+void locate(const MapGrid &m, const double r[3], int e[3], double t[3])
+{
+    for (int a = 0; a < 3; ++a) {
+        const double s = r[a] / m.h[a];
+        const double E = std::floor(s);
+        t[a] = s - E;
+        int64_t Ei = static_cast<int64_t>(E) % m.ne[a];
+        if (Ei < 0) Ei += m.ne[a];
+        e[a] = static_cast<int>(Ei);
+    }
+}
+
+}  // namespace
+
+bool build_mapped_tables(const VelocitySet &vs, int p, const int ne[3], const double length[3], const double *d,
+                         double dt, std::vector<int32_t> &cell, std::vector<double> &tloc, std::vector<double> &nodew,
+                         std::string &why)
+{
+    MapGrid m{};
+    m.p = p;
+    m.d = d;
+    for (int a = 0; a < 3; ++a) {
+        m.ne[a] = ne[a];
+        m.N[a] = ne[a] * p;
+        m.h[a] = length[a] / ne[a];
+    }
+    m.nodes = static_cast<int64_t>(m.N[0]) * m.N[1] * m.N[2];
+    const int64_t N = m.nodes;
+    double tg[MAXP + 1], cc[MAXP + 1];
+    glc_points(p, tg);
+    clenshaw_curtis(p, cc);
+    // node weights, with the check that every cell map keeps its orientation
+    nodew.assign(N, 0.0);
+    for (int ez = 0; ez < ne[2]; ++ez)
+        for (int ey = 0; ey < ne[1]; ++ey)
+            for (int ex = 0; ex < ne[0]; ++ex)
+                for (int kz = 0; kz <= p; ++kz)
+                    for (int ky = 0; ky <= p; ++ky)
+                        for (int kx = 0; kx <= p; ++kx) {
+                            const int e[3] = {ex, ey, ez};
+                            const double t[3] = {tg[kx], tg[ky], tg[kz]};
+                            double D[3], J[3][3];
+                            map_at(m, e, t, D, J);
+                            const double dj = det3(J);
+                            if (!(dj > 0.0)) {
+                                why = "distorted mesh: a cell map folds over (det J <= 0)";
+                                return false;
+                            }
+                            const int64_t node = ((static_cast<int64_t>(ez * p + kz) % m.N[2]) * m.N[1] +
+                                                  (ey * p + ky) % m.N[1]) * m.N[0] + (ex * p + kx) % m.N[0];
+                            nodew[node] += 0.125 * m.h[0] * m.h[1] * m.h[2] * cc[kx] * cc[ky] * cc[kz] * dj;
+                        }
+    // departure search, per velocity and node
+    cell.assign(static_cast<size_t>(vs.q) * N, 0);
+    tloc.assign(static_cast<size_t>(3) * vs.q * N, 0.0);
+    for (int i = 0; i < vs.q; ++i) {
+        for (int64_t n = 0; n < N; ++n) {
+            const int g[3] = {static_cast<int>(n % m.N[0]), static_cast<int>((n / m.N[0]) % m.N[1]),
+                              static_cast<int>(n / (static_cast<int64_t>(m.N[0]) * m.N[1]))};
+            double xd[3], r[3];
+            for (int a = 0; a < 3; ++a) {
+                const double r0 = (g[a] / p) * m.h[a] + m.h[a] * tg[g[a] % p];
+                const double sh = vs.xi[i][a] * dt;
+                xd[a] = r0 + d[a * N + n] - sh;
+                r[a] = r0 - sh;                   // start at the undistorted departure point
+            }
+            // Newton until the update stalls at rounding level, then the
+            // residual decides (in cell widths)
+            auto residual = [&](double F[3], double J[3][3]) {
+                int e[3];
+                double t[3], D[3];
+                locate(m, r, e, t);
+                map_at(m, e, t, D, J);
+                double res = 0.0;
+                for (int a = 0; a < 3; ++a) {
+                    F[a] = r[a] + D[a] - xd[a];
+                    res = std::max(res, std::fabs(F[a]) / m.h[a]);
+                }
+                return res;
+            };
+            for (int it = 0; it < 60; ++it) {
+                double F[3], J[3][3];
+                residual(F, J);
+                const double dj = det3(J);
+                double step = 0.0;
+                for (int k = 0; k < 3; ++k) {        // Cramer's rule for J dr = F
+                    double M[3][3];
+                    for (int a = 0; a < 3; ++a)
+                        for (int b = 0; b < 3; ++b) M[a][b] = b == k ? F[a] : J[a][b];
+                    const double drk = det3(M) / dj;
+                    r[k] -= drk;
+                    step += std::fabs(drk) / m.h[k];
+                }
+                if (step < 1e-15) break;
+            }
+            double F[3], J[3][3];
+            if (!(residual(F, J) < 1e-12)) {
+                why = "distorted mesh: the departure search did not converge (displacement too strong)";
+                return false;
+            }
+            int e[3];
+            double t[3];
+            locate(m, r, e, t);
+            cell[static_cast<size_t>(i) * N + n] = (e[2] * ne[1] + e[1]) * ne[0] + e[0];
+            for (int a = 0; a < 3; ++a) tloc[(static_cast<size_t>(a) * vs.q + i) * N + n] = t[a];
+        }
+    }
+    return true;
 }
 
 }  // namespace sllbm

@@ -59,6 +59,7 @@ _SIGS = {
     "sllbm_node_coords": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
     "sllbm_set_viscosity": (ctypes.c_int, [_VP, ctypes.c_double]),
     "sllbm_set_mesh": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
+    "sllbm_set_displacement": (ctypes.c_int, [_VP, _VP]),
     "sllbm_init_equilibrium": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
     "sllbm_set_state": (ctypes.c_int, [_VP, _VP]),
     "sllbm_get_state": (ctypes.c_int, [_VP, _VP]),
@@ -235,6 +236,18 @@ class SLLBM:
         for a, x in enumerate(arrs):
             if x is not None:
                 self.cfg.length[a] = float(sum(x))
+
+    def set_displacement(self, d=None):
+        """Distorted mesh: d (3, N) periodic node displacements (array or tensor), or None."""
+        self._sync_stream()
+        if d is None:
+            self._check(self._lib.sllbm_set_displacement(self._h, None))
+            return
+        import numpy as np
+        v = np.ascontiguousarray(d.cpu().numpy() if hasattr(d, "cpu") else d, dtype=np.float64)
+        if v.size != 3 * self.nodes:
+            raise ValueError("d must hold (3, N) displacements")
+        self._check(self._lib.sllbm_set_displacement(self._h, v.ctypes.data_as(_VP)))
 
     def init_equilibrium(self, rho, u, T):
         self._sync_stream()

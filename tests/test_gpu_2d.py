@@ -190,16 +190,26 @@ def test_step_record_matches_steps(O2):
 
 
 def test_sod_tube(O2):
-    """The periodic double tube for 50 steps: GPU against oracle, then both
-    close to the exact Riemann solution's shock position region."""
+    """The periodic double tube to the paper's t = 0.1 (200 steps): the GPU
+    state against the oracle's, and the GPU density and velocity against the
+    exact Riemann solution (the bar of the oracle's own pin)."""
+    from riemann_exact import sample as riemann_sample
     w = inputs.WORKLOADS_2D["sod"]
     ctx, cfg = _pair(O2, w["n_el"], w["p"], w["dt"], w["mu_inf"], length=w["length"])
     x, y = O2.node_coords(cfg)
     f, g = _init_both(O2, ctx, cfg, *inputs.sod_fields(x, y))
-    ctx.step(50)
-    fo, go = O2.step(cfg, f, g, 50)
+    ctx.step(w["steps"])
+    fo, go = O2.step(cfg, f, g, w["steps"])
     F, G = _to_np(ctx.get_state())
     assert rel_err(F, fo) <= 1e-11 and rel_err(G, go) <= 1e-11, (rel_err(F, fo), rel_err(G, go))
+    rho, u, T = (a.cpu().numpy() for a in ctx.moments())
+    nx = len(x)
+    t = w["steps"] * w["dt"]
+    right = x > 1.0
+    (ri, ui, pi), (ro, uo, po) = inputs.SOD_STATES
+    re, ue, pe = riemann_sample((ri, ui, pi), (ro, uo, po), w["gamma"], (x[right] - 1.5) / t)
+    assert np.sum(np.abs(rho[:nx][right] - re)) / np.sum(re) < 5e-3
+    assert np.mean(np.abs(u[0, :nx][right] - ue)) < 1e-2
 
 
 def test_riemann_fullsize_one_step(O2):
