@@ -33,6 +33,7 @@ KERNEL_SOURCES = {
     "k_stream_graded": ("stream_graded.hip", "tables.cpp"),
     "k_collide": ("kernels.hip", "collision.h", "velset.h"),
     "k_stream_y": ("stream2d.hip", "tables.cpp"),
+    "k_stream_mapped": ("stream_mapped.hip", "tables.cpp"),
 }
 
 
@@ -74,7 +75,13 @@ def run_gpu(args, wl, precision):
     rho, u, T = inputs.tgv_fields(xs, ys, zs, wl["Ma"], wl["gamma"])
     dev = ctx.device
     ctx.init_equilibrium(torch.from_numpy(rho).to(dev), torch.from_numpy(u).to(dev), torch.from_numpy(T).to(dev))
-    return measure_steps(args, ctx, "k_stream_graded" if args.mesh == "graded" else "k_stream_z")
+    table_bytes = 0
+    if args.mesh == "distorted":
+        X, Y, Z = inputs.mesh(xs, ys, zs)
+        ctx.set_displacement(inputs.distortion(X, Y, Z, 2 * math.pi / wl["n_el"], inputs.DISTORTED["amplitude"]))
+        table_bytes = Q * ctx.nodes * (4 + 3 * 8)      # departure cell and local coordinates per velocity and node
+    kern = {"graded": "k_stream_graded", "distorted": "k_stream_mapped"}.get(args.mesh, "k_stream_z")
+    return measure_steps(args, ctx, kern, table_bytes)
 
 
 def run_gpu_2d(args, wl, precision):
@@ -92,7 +99,7 @@ def run_gpu_2d(args, wl, precision):
     return measure_steps(args, ctx, "k_stream_y")
 
 
-def measure_steps(args, ctx, stream_kernel):
+def measure_steps(args, ctx, stream_kernel, table_bytes=0):
     """Wall clock of args.steps steps, then kernel durations from HIP events."""
     import torch
     dev = ctx.device
@@ -135,8 +142,9 @@ def measure_steps(args, ctx, stream_kernel):
     elem = 8 if precision == 0 else 4
     bytes_per_launch = 2 * 2 * ctx.q * nodes * elem      # each kernel reads 2Q and writes 2Q values per node
     ctx.close()
-    kernels = {name: {"ms": ms / max(n, 1), "launches": n} for name, (ms, n) in
-               (("k_collide", kt["collide"]), (stream_kernel, kt["stream"]))}
+    kernels = {name: {"ms": ms / max(n, 1), "launches": n, "bytes": b} for name, (ms, n), b in
+               (("k_collide", kt["collide"], bytes_per_launch),
+                (stream_kernel, kt["stream"], bytes_per_launch + table_bytes))}
     return dict(nodes=nodes, wall=wall, kernels=kernels, bytes=bytes_per_launch, finite=ok, totals=tot)
 
 
@@ -256,8 +264,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="c2", help="workload key (c1..c5; sod or riemann: 2-D D2Q19)")
     ap.add_argument("--cfl", type=float, default=1.0)
-    ap.add_argument("--mesh", choices=["equal", "graded"], default="equal",
-                    help="equal cells, or the cosine-graded cells of every axis (streaming on per-node tables)")
+    ap.add_argument("--mesh", choices=["equal", "graded", "distorted"], default="equal",
+                    help="equal cells, the cosine-graded cells of every axis (streaming on per-node tables), or "
+                         "the smoothly distorted cells of sllbm_set_displacement (no cpu_baseline)")
     ap.add_argument("--precision", choices=["fp64", "fp32"], default=None)
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -280,17 +289,18 @@ def main():
         print("the two-dimensional workloads use equal cells", file=sys.stderr)
         return 2
     wl = workload_2d(args.workload) if two_d else inputs.workload(args.workload, cfl=args.cfl)
-    wkey = args.workload if args.mesh == "equal" else args.workload + "-graded"
+    wkey = args.workload if args.mesh == "equal" else f"{args.workload}-{args.mesh}"
     prec_name = args.precision or wl["precision"]
     precision = 0 if prec_name == "fp64" else 1
     r = run_gpu_2d(args, wl, precision) if two_d else run_gpu(args, wl, precision)
     value = r["nodes"] * args.steps / r["wall"]
     dom = max(r["kernels"], key=lambda k: r["kernels"][k]["ms"])
     kms = r["kernels"][dom]["ms"]
-    achieved = r["bytes"] / (kms * 1e-3) / 1e9
+    dom_bytes = r["kernels"][dom]["bytes"]
+    achieved = dom_bytes / (kms * 1e-3) / 1e9
     kernels = {}
     for k, v in r["kernels"].items():
-        gbs = r["bytes"] / (v["ms"] * 1e-3) / 1e9 if v["ms"] > 0 else None
+        gbs = v["bytes"] / (v["ms"] * 1e-3) / 1e9 if v["ms"] > 0 else None
         kernels[k] = {"ms_per_launch": v["ms"], "launches": v["launches"], "algorithmic_GBps": gbs,
                       "traffic": measured_traffic(k, wkey, prec_name)}
     if two_d:
@@ -300,8 +310,9 @@ def main():
                     f"mu {wl['mu_inf']}, {prec_name}")
         data = "synthetic: piecewise-constant Riemann initial states (periodic stand-in)"
     else:
-        workload = (f"{wkey}: TGV {wl['n_el']}^3 "
-                    f"{'cells' if args.mesh == 'equal' else 'cosine-graded cells (a = 0.3)'} p={wl['p']} "
+        mdesc = {"equal": "cells", "graded": "cosine-graded cells (a = 0.3)",
+                 "distorted": f"distorted cells (displacement {inputs.DISTORTED['amplitude']} h)"}[args.mesh]
+        workload = (f"{wkey}: TGV {wl['n_el']}^3 {mdesc} p={wl['p']} "
                     f"({r['nodes']} nodes), Ma {wl['Ma']}, Re {wl['Re']}, CFL {wl['cfl']}, {prec_name}")
         data = "synthetic: closed-form compressible Taylor-Green vortex"
     out = {
@@ -321,7 +332,7 @@ def main():
                    "dt": wl["dt"], "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": kernels[dom]["traffic"],
-                     "kernel": dom, "kernel_ms": kms, "algorithmic_bytes_per_launch": r["bytes"],
+                     "kernel": dom, "kernel_ms": kms, "algorithmic_bytes_per_launch": dom_bytes,
                      "step_frac": r["bytes"] / (r["wall"] / args.steps) / 1e9 / HBM_PEAK_GBS},
         "kernels": kernels,
         "finite": r["finite"],
@@ -332,7 +343,7 @@ def main():
             over["steps"] = args.adjoint_steps
         wa = inputs.workload(args.adjoint_workload, **over)
         out["adjoint"] = run_adjoint(wa, 0 if wa["precision"] == "fp64" else 1, graded=args.mesh == "graded")
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.mesh != "distorted":
         out["cpu_baseline"] = (cpu_baseline_2d(wl, args.cpu_budget) if two_d else
                                cpu_baseline(wl, args.cpu_budget, graded=args.mesh == "graded"))
     print(json.dumps(out), flush=True)

@@ -11,14 +11,23 @@
 // stored coefficients).  A thread owns one (velocity, node) pair and gathers
 // the (P+1)^3 support values of f and of g (the two populations share the
 // departure point); x-runs of P + 1 values are contiguous, neighbouring
-// threads read neighbouring runs, so the gathers are served by L1/L2.
+// threads read neighbouring runs, so the gathers are served by L1/L2.  When
+// rows and planes start on 16-byte boundaries and P is a multiple of the
+// vector width V, the first P values of a run (never wrapped: the cell's
+// first node plus P - 1 stays inside the row) are read as 16-byte vectors
+// and only the last one, which wraps at the periodic end, on its own.
 #include <hip/hip_runtime.h>
 
 #include "sllbm_internal.h"
 
 namespace sllbm {
 
-template <typename S, int P>
+template <typename S, int V>
+struct MVec {
+    typedef S T __attribute__((ext_vector_type(V)));
+};
+
+template <typename S, int P, int V>
 __global__ void __launch_bounds__(256) k_stream_mapped(Geometry g, GlcBasis gb, const int32_t *__restrict__ cell,
                                                        const double *__restrict__ tloc, const S *__restrict__ in,
                                                        S *__restrict__ out)
@@ -58,12 +67,31 @@ __global__ void __launch_bounds__(256) k_stream_mapped(Geometry g, GlcBasis gb, 
             yy = yy >= Ny ? yy - Ny : yy;
             const int64_t row = (static_cast<int64_t>(zz) * Ny + yy) * Nx;
             S af = 0, ag = 0;
+            if constexpr (V > 1) {
+                using VT = typename MVec<S, V>::T;
+                const int64_t x0 = row + ex * P;
 #pragma unroll
-            for (int kx = 0; kx <= P; ++kx) {
-                int xx = ex * P + kx;
+                for (int k0 = 0; k0 < P; k0 += V) {
+                    const VT vf = *reinterpret_cast<const VT *>(fi + x0 + k0);
+                    const VT vg = *reinterpret_cast<const VT *>(gi + x0 + k0);
+#pragma unroll
+                    for (int c = 0; c < V; ++c) {
+                        af = fma(w[0][k0 + c], vf[c], af);
+                        ag = fma(w[0][k0 + c], vg[c], ag);
+                    }
+                }
+                int xx = ex * P + P;
                 xx = xx >= Nx ? xx - Nx : xx;
-                af = fma(w[0][kx], fi[row + xx], af);
-                ag = fma(w[0][kx], gi[row + xx], ag);
+                af = fma(w[0][P], fi[row + xx], af);
+                ag = fma(w[0][P], gi[row + xx], ag);
+            } else {
+#pragma unroll
+                for (int kx = 0; kx <= P; ++kx) {
+                    int xx = ex * P + kx;
+                    xx = xx >= Nx ? xx - Nx : xx;
+                    af = fma(w[0][kx], fi[row + xx], af);
+                    ag = fma(w[0][kx], gi[row + xx], ag);
+                }
             }
             const S wyz = w[1][ky] * w[2][kz];
             sf = fma(wyz, af, sf);
@@ -81,7 +109,19 @@ hipError_t launch_m(const Geometry &g, const MappedTables &t, const S *in, S *ou
 {
     const int64_t bx = (g.nodes + 255) / 256;
     if (bx > (int64_t(1) << 31) - 1) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_stream_mapped<S, P>), dim3(static_cast<unsigned>(bx), Q), dim3(256), 0, st, g, t.basis,
+    constexpr int V = 16 / sizeof(S);
+    // 16-byte loads: every plane (N values) and row (N_x values) starts on a
+    // 16-byte boundary, and a cell's first node is a multiple of V
+    const bool aligned = (g.nodes * sizeof(S)) % 16 == 0 && (g.N[0] * sizeof(S)) % 16 == 0 &&
+                         reinterpret_cast<uintptr_t>(in) % 16 == 0;
+    if constexpr (P % V == 0) {
+        if (aligned) {
+            hipLaunchKernelGGL((k_stream_mapped<S, P, V>), dim3(static_cast<unsigned>(bx), Q), dim3(256), 0, st, g,
+                               t.basis, t.cell, t.tloc, in, out);
+            return hipGetLastError();
+        }
+    }
+    hipLaunchKernelGGL((k_stream_mapped<S, P, 1>), dim3(static_cast<unsigned>(bx), Q), dim3(256), 0, st, g, t.basis,
                        t.cell, t.tloc, in, out);
     return hipGetLastError();
 }

@@ -54,6 +54,18 @@ def graded_widths(n, length=2 * math.pi, amplitude=0.3):
     return w * (length / w.sum())
 
 
+# Distorted-mesh variant of the 64^3-node workload: the equal-cell GLC nodes
+# displaced by a smooth periodic field of amplitude a times the cell width,
+# d = a h (sin(y + z), sin(z + x), sin(x + y)); |grad d| <= sqrt(2) a h keeps
+# every cell map orientation-preserving for the a used here.
+DISTORTED = dict(base="c2", amplitude=0.25)
+
+
+def distortion(X, Y, Z, h, amplitude=0.25):
+    """(3, N) node displacements of the distorted workload at reference coordinates X, Y, Z."""
+    return amplitude * h * np.stack([np.sin(Y + Z), np.sin(Z + X), np.sin(X + Y)])
+
+
 def velocity_scale(Ma, gamma):
     """U = Ma * adiabatic sound speed sqrt(gamma T0)."""
     return Ma * math.sqrt(gamma * T0)
