@@ -9,9 +9,11 @@
 // tensor product of three 1-D operators, each described by p rows of (p+1)
 // taps; these rows are all that is stored.
 #include <algorithm>
+#include <atomic>
 #include <cstdint>
 #include <cmath>
 #include <string>
+#include <thread>
 
 #include "sllbm_internal.h"
 #include "velset.h"
@@ -337,11 +339,13 @@ bool build_mapped_tables(const VelocitySet &vs, int p, const int ne[3], const do
                                                   (ey * p + ky) % m.N[1]) * m.N[0] + (ex * p + kx) % m.N[0];
                             nodew[node] += 0.125 * m.h[0] * m.h[1] * m.h[2] * cc[kx] * cc[ky] * cc[kz] * dj;
                         }
-    // departure search, per velocity and node
+    // departure search, per velocity and node; velocities are split over up to
+    // 16 host threads, each writing the slices of its own velocities
     cell.assign(static_cast<size_t>(vs.q) * N, 0);
     tloc.assign(static_cast<size_t>(3) * vs.q * N, 0.0);
-    for (int i = 0; i < vs.q; ++i) {
-        for (int64_t n = 0; n < N; ++n) {
+    std::atomic<bool> failed{false};
+    auto search = [&](int i) {
+        for (int64_t n = 0; n < N && !failed.load(std::memory_order_relaxed); ++n) {
             const int g[3] = {static_cast<int>(n % m.N[0]), static_cast<int>((n / m.N[0]) % m.N[1]),
                               static_cast<int>(n / (static_cast<int64_t>(m.N[0]) * m.N[1]))};
             double xd[3], r[3];
@@ -382,8 +386,8 @@ bool build_mapped_tables(const VelocitySet &vs, int p, const int ne[3], const do
             }
             double F[3], J[3][3];
             if (!(residual(F, J) < 1e-12)) {
-                why = "distorted mesh: the departure search did not converge (displacement too strong)";
-                return false;
+                failed = true;
+                return;
             }
             int e[3];
             double t[3];
@@ -391,6 +395,17 @@ bool build_mapped_tables(const VelocitySet &vs, int p, const int ne[3], const do
             cell[static_cast<size_t>(i) * N + n] = (e[2] * ne[1] + e[1]) * ne[0] + e[0];
             for (int a = 0; a < 3; ++a) tloc[(static_cast<size_t>(a) * vs.q + i) * N + n] = t[a];
         }
+    };
+    const int nt = static_cast<int>(std::max(1u, std::min(std::thread::hardware_concurrency(), 16u)));
+    std::vector<std::thread> pool;
+    for (int k = 0; k < nt; ++k)
+        pool.emplace_back([&, k]() {
+            for (int i = k; i < vs.q; i += nt) search(i);
+        });
+    for (auto &th : pool) th.join();
+    if (failed) {
+        why = "distorted mesh: the departure search did not converge (displacement too strong)";
+        return false;
     }
     return true;
 }
