@@ -150,9 +150,11 @@ int sllbm_set_mesh(sllbm_ctx *ctx, const double *widths_x, const double *widths_
  * maps, and its cell and local coordinates are uploaded (28 bytes per
  * velocity and node); totals then weight every node with the |det J| of the
  * cells that hold it.  d = NULL returns to the undistorted mesh.  The state is
- * kept; node coordinates stay those of the reference grid.  On a distorted
- * mesh the transposed streaming, the adjoint step, the loss, its gradient and
- * the diagnostics return EINVAL.  Synchronises the context's stream.
+ * kept; node coordinates stay those of the reference grid.  The transposed
+ * streaming (and so sllbm_adjoint_step) spreads every output's adjoint over
+ * its support values with atomic adds (results reproducible to rounding, not
+ * bit for bit); the loss, its gradient and the diagnostics return EINVAL on a
+ * distorted mesh.  Synchronises the context's stream.
  * Errors: EINVAL (2-D context, graded cells, non-finite d, a cell map that
  * folds over (det J <= 0 at a support point), a departure search that does
  * not converge), ENOMEM, EDEVICE; on error the previous mesh stays. */

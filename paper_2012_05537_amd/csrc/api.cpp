@@ -701,6 +701,13 @@ static hipError_t stream_into(sllbm_ctx *c, const void *in, void *out)
 // transposed per-node tables
 static hipError_t stream_t_into(sllbm_ctx *c, const void *in, void *out)
 {
+    if (c->mapped) {
+        if (is_fp64(c))
+            return launch_stream_mapped_t<double>(c->geo, mapped_tables(c), static_cast<const double *>(in),
+                                                  static_cast<double *>(out), c->stream);
+        return launch_stream_mapped_t<float>(c->geo, mapped_tables(c), static_cast<const float *>(in),
+                                             static_cast<float *>(out), c->stream);
+    }
     if (c->graded) {
         if (is_fp64(c))
             return launch_stream_graded<double>(c->geo, node_tables<double>(c, 1), static_cast<const double *>(in),
@@ -874,7 +881,6 @@ int sllbm_stream(sllbm_ctx *ctx, const void *in, void *out, int32_t transpose)
     if (!ctx) return SLLBM_EINVAL;
     if (!in || !out || in == out) return fail(ctx, SLLBM_EINVAL, "bad stream buffers");
     if (transpose && ctx->d2) return refuse_2d(ctx, "transposed streaming");
-    if (transpose && ctx->mapped) return refuse_mapped(ctx, "transposed streaming");
     DeviceGuard guard(ctx->cfg.device);
     if (!transpose) return check_launch(ctx, stream_into(ctx, in, out), "stream");
     return check_launch(ctx, stream_t_into(ctx, in, out), "stream");
@@ -968,7 +974,6 @@ int sllbm_adjoint_step(sllbm_ctx *ctx, const void *state_n, const void *lam_next
     if (!state_n || !lam_next || !lam_out) return fail(ctx, SLLBM_EINVAL, "NULL argument");
     if (lam_out == lam_next || lam_out == state_n) return fail(ctx, SLLBM_EINVAL, "lam_out aliases an input");
     if (ctx->d2) return refuse_2d(ctx, "sllbm_adjoint_step");
-    if (ctx->mapped) return refuse_mapped(ctx, "sllbm_adjoint_step");
     DeviceGuard guard(ctx->cfg.device);
     hipError_t e = stream_t_into(ctx, lam_next, lam_out);
     if (e != hipSuccess) return hip_fail(ctx, e, "adjoint_step (transposed streaming)");

@@ -197,6 +197,9 @@ hipError_t launch_stream_zt(const Geometry &g, const CellTables<S> &t, const S *
 // streaming on a distorted mesh (stream_mapped.hip)
 template <typename S>
 hipError_t launch_stream_mapped(const Geometry &g, const MappedTables &t, const S *in, S *out, hipStream_t st);
+// its transpose S^T (zeroes out, then adds each output's share atomically)
+template <typename S>
+hipError_t launch_stream_mapped_t(const Geometry &g, const MappedTables &t, const S *in, S *out, hipStream_t st);
 // streaming on a graded mesh (stream_graded.hip)
 template <typename S>
 hipError_t launch_stream_graded(const Geometry &g, const NodeTables<S> &t, const S *in, S *out, hipStream_t st);

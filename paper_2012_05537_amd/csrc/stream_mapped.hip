@@ -18,6 +18,8 @@
 // and only the last one, which wraps at the periodic end, on its own.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "sllbm_internal.h"
 
 namespace sllbm {
@@ -102,7 +104,88 @@ __global__ void __launch_bounds__(256) k_stream_mapped(Geometry g, GlcBasis gb, 
     out[static_cast<int64_t>(Q + i) * N + n] = sg;
 }
 
+// Transposed streaming S^T on a distorted mesh: each (velocity, node) output
+// of S spreads its adjoint over the (P+1)^3 support values it was gathered
+// from, with the same weights.  The departure cells of different nodes
+// overlap arbitrarily, so the spreading adds atomically (hardware FP64/FP32
+// adds on device memory; the summation order, hence the last bits, varies
+// between runs).  out must be zero on entry.
+template <typename S, int P>
+__global__ void __launch_bounds__(256) k_stream_mapped_t(Geometry g, GlcBasis gb, const int32_t *__restrict__ cell,
+                                                         const double *__restrict__ tloc, const S *__restrict__ in,
+                                                         S *__restrict__ out)
+{
+    const int i = blockIdx.y;
+    const int64_t N = g.nodes;
+    const int64_t n = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+    if (n >= N) return;
+    const int Nx = g.N[0], Ny = g.N[1], Nz = g.N[2];
+    const int c = cell[static_cast<int64_t>(i) * N + n];
+    const int ex = c % g.nel[0], rest = c / g.nel[0];
+    const int ey = rest % g.nel[1], ez = rest / g.nel[1];
+    S w[3][P + 1];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double t = tloc[(static_cast<int64_t>(a) * Q + i) * N + n];
+#pragma unroll
+        for (int k = 0; k <= P; ++k) {
+            double v = gb.inv_den[k];
+#pragma unroll
+            for (int m = 0; m <= P; ++m)
+                if (m != k) v *= t - gb.t[m];
+            w[a][k] = static_cast<S>(v);
+        }
+    }
+    const S lf = in[static_cast<int64_t>(i) * N + n];
+    const S lg = in[static_cast<int64_t>(Q + i) * N + n];
+    S *fo = out + static_cast<int64_t>(i) * N;
+    S *go = out + static_cast<int64_t>(Q + i) * N;
+#pragma unroll
+    for (int kz = 0; kz <= P; ++kz) {
+        int zz = ez * P + kz;
+        zz = zz >= Nz ? zz - Nz : zz;
+#pragma unroll
+        for (int ky = 0; ky <= P; ++ky) {
+            int yy = ey * P + ky;
+            yy = yy >= Ny ? yy - Ny : yy;
+            const int64_t row = (static_cast<int64_t>(zz) * Ny + yy) * Nx;
+            const S wyz = w[1][ky] * w[2][kz];
+            const S af = wyz * lf, ag = wyz * lg;
+#pragma unroll
+            for (int kx = 0; kx <= P; ++kx) {
+                int xx = ex * P + kx;
+                xx = xx >= Nx ? xx - Nx : xx;
+                unsafeAtomicAdd(fo + row + xx, w[0][kx] * af);
+                unsafeAtomicAdd(go + row + xx, w[0][kx] * ag);
+            }
+        }
+    }
+}
+
+template <typename S>
+__global__ void __launch_bounds__(256) k_fill_zero(int64_t n, S *__restrict__ out)
+{
+    for (int64_t k = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; k < n;
+         k += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        out[k] = S(0);
+}
+
 namespace {
+
+template <typename S, int P>
+hipError_t launch_mt(const Geometry &g, const MappedTables &t, const S *in, S *out, hipStream_t st)
+{
+    const int64_t bx = (g.nodes + 255) / 256;
+    if (bx > (int64_t(1) << 31) - 1) return hipErrorInvalidValue;
+    const int64_t total = 2 * static_cast<int64_t>(Q) * g.nodes;
+    const int64_t fb = std::min<int64_t>((total + 255) / 256, 8192);
+    hipLaunchKernelGGL((k_fill_zero<S>), dim3(static_cast<unsigned>(fb)), dim3(256), 0, st, total, out);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_stream_mapped_t<S, P>), dim3(static_cast<unsigned>(bx), Q), dim3(256), 0, st, g, t.basis,
+                       t.cell, t.tloc, in, out);
+    return hipGetLastError();
+}
 
 template <typename S, int P>
 hipError_t launch_m(const Geometry &g, const MappedTables &t, const S *in, S *out, hipStream_t st)
@@ -142,6 +225,24 @@ hipError_t launch_stream_mapped(const Geometry &g, const MappedTables &t, const 
     }
 }
 
+template <typename S>
+hipError_t launch_stream_mapped_t(const Geometry &g, const MappedTables &t, const S *in, S *out, hipStream_t st)
+{
+    switch (g.p) {
+    case 1: return launch_mt<S, 1>(g, t, in, out, st);
+    case 2: return launch_mt<S, 2>(g, t, in, out, st);
+    case 3: return launch_mt<S, 3>(g, t, in, out, st);
+    case 4: return launch_mt<S, 4>(g, t, in, out, st);
+    case 5: return launch_mt<S, 5>(g, t, in, out, st);
+    case 6: return launch_mt<S, 6>(g, t, in, out, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template hipError_t launch_stream_mapped_t<double>(const Geometry &, const MappedTables &, const double *, double *,
+                                                   hipStream_t);
+template hipError_t launch_stream_mapped_t<float>(const Geometry &, const MappedTables &, const float *, float *,
+                                                  hipStream_t);
 template hipError_t launch_stream_mapped<double>(const Geometry &, const MappedTables &, const double *, double *,
                                                  hipStream_t);
 template hipError_t launch_stream_mapped<float>(const Geometry &, const MappedTables &, const float *, float *,
