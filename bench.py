@@ -79,7 +79,8 @@ def run_gpu(args, wl, precision):
     if args.mesh == "distorted":
         X, Y, Z = inputs.mesh(xs, ys, zs)
         ctx.set_displacement(inputs.distortion(X, Y, Z, 2 * math.pi / wl["n_el"], inputs.DISTORTED["amplitude"]))
-        table_bytes = Q * ctx.nodes * (4 + 3 * 8)      # departure cell and local coordinates per velocity and node
+        elem = 8 if precision == 0 else 4
+        table_bytes = Q * ctx.nodes * (4 + 3 * elem)   # departure cell and local coordinates per velocity and node
     kern = {"graded": "k_stream_graded", "distorted": "k_stream_mapped"}.get(args.mesh, "k_stream_z")
     return measure_steps(args, ctx, kern, table_bytes)
 

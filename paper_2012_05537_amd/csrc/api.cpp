@@ -66,7 +66,7 @@ struct sllbm_ctx {
     // coordinates per velocity and node, per-node quadrature weights
     bool mapped = false;
     int32_t *d_mcell = nullptr;
-    double *d_mt = nullptr;
+    void *d_mt = nullptr;          // local coordinates, storage type
     double *d_mw = nullptr;
     GlcBasis glc{};
     std::string err;
@@ -564,9 +564,18 @@ int sllbm_set_displacement(sllbm_ctx *ctx, const double *d)
                              why))
         return fail(ctx, SLLBM_EINVAL, why);
     int32_t *dc = nullptr;
-    double *dt = nullptr, *dw = nullptr;
+    void *dt = nullptr;
+    double *dw = nullptr;
+    // local coordinates in the storage type
+    std::vector<float> tloc32;
+    const void *tsrc = tloc.data();
+    if (!is_fp64(ctx)) {
+        tloc32.assign(tloc.begin(), tloc.end());
+        tsrc = tloc32.data();
+    }
+    const size_t tbytes = tloc.size() * ctx->elem;
     if ((e = dalloc(&dc, cell.size() * sizeof(int32_t))) != hipSuccess ||
-        (e = dalloc(&dt, tloc.size() * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc(&dt, tbytes)) != hipSuccess ||
         (e = dalloc(&dw, nodew.size() * sizeof(double))) != hipSuccess) {
         (void)hipFree(dc);
         (void)hipFree(dt);
@@ -574,7 +583,7 @@ int sllbm_set_displacement(sllbm_ctx *ctx, const double *d)
         return fail(ctx, SLLBM_ENOMEM, std::string("distorted-mesh tables: ") + hipGetErrorString(e));
     }
     if ((e = hipMemcpy(dc, cell.data(), cell.size() * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess ||
-        (e = hipMemcpy(dt, tloc.data(), tloc.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(dt, tsrc, tbytes, hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(dw, nodew.data(), nodew.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess) {
         (void)hipFree(dc);
         (void)hipFree(dt);

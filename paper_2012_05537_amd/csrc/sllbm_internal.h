@@ -111,10 +111,12 @@ struct GlcBasis {
     double inv_den[MAXP + 1];
 };
 
-// Device tables of a distorted mesh (build_mapped_tables)
+// Device tables of a distorted mesh (build_mapped_tables); the local
+// coordinates are kept in the storage type (FP32 contexts: 16 bytes per
+// velocity and node instead of 28)
 struct MappedTables {
     const int32_t *cell;    // [Q][N] departure cell, x fastest
-    const double *tloc;     // [3][Q][N] local coordinates in [0, 1)
+    const void *tloc;       // [3][Q][N] local coordinates in [0, 1), storage type
     GlcBasis basis;
 };
 

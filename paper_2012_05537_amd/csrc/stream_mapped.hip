@@ -6,7 +6,8 @@
 // The cells are the isoparametric images of the equal-cell reference grid
 // (node displacements, build_mapped_tables); populations are interpolated in
 // reference coordinates.  The host stores, per velocity and node, the
-// departure cell and the three local coordinates (28 bytes); the weights are
+// departure cell and the three local coordinates (28 bytes in FP64, 16 in
+// FP32); the weights are
 // formed here ("matrix-free": 3 (P+1) Lagrange values instead of (P+1)^3
 // stored coefficients).  A thread owns one (velocity, node) pair and gathers
 // the (P+1)^3 support values of f and of g (the two populations share the
@@ -31,7 +32,7 @@ struct MVec {
 
 template <typename S, int P, int V>
 __global__ void __launch_bounds__(256) k_stream_mapped(Geometry g, GlcBasis gb, const int32_t *__restrict__ cell,
-                                                       const double *__restrict__ tloc, const S *__restrict__ in,
+                                                       const S *__restrict__ tloc, const S *__restrict__ in,
                                                        S *__restrict__ out)
 {
     const int i = blockIdx.y;
@@ -46,7 +47,7 @@ __global__ void __launch_bounds__(256) k_stream_mapped(Geometry g, GlcBasis gb, 
     S w[3][P + 1];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        const double t = tloc[(static_cast<int64_t>(a) * Q + i) * N + n];
+        const double t = static_cast<double>(tloc[(static_cast<int64_t>(a) * Q + i) * N + n]);
 #pragma unroll
         for (int k = 0; k <= P; ++k) {
             double v = gb.inv_den[k];
@@ -112,7 +113,7 @@ __global__ void __launch_bounds__(256) k_stream_mapped(Geometry g, GlcBasis gb, 
 // between runs).  out must be zero on entry.
 template <typename S, int P>
 __global__ void __launch_bounds__(256) k_stream_mapped_t(Geometry g, GlcBasis gb, const int32_t *__restrict__ cell,
-                                                         const double *__restrict__ tloc, const S *__restrict__ in,
+                                                         const S *__restrict__ tloc, const S *__restrict__ in,
                                                          S *__restrict__ out)
 {
     const int i = blockIdx.y;
@@ -126,7 +127,7 @@ __global__ void __launch_bounds__(256) k_stream_mapped_t(Geometry g, GlcBasis gb
     S w[3][P + 1];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        const double t = tloc[(static_cast<int64_t>(a) * Q + i) * N + n];
+        const double t = static_cast<double>(tloc[(static_cast<int64_t>(a) * Q + i) * N + n]);
 #pragma unroll
         for (int k = 0; k <= P; ++k) {
             double v = gb.inv_den[k];
@@ -183,7 +184,7 @@ hipError_t launch_mt(const Geometry &g, const MappedTables &t, const S *in, S *o
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_stream_mapped_t<S, P>), dim3(static_cast<unsigned>(bx), Q), dim3(256), 0, st, g, t.basis,
-                       t.cell, t.tloc, in, out);
+                       t.cell, static_cast<const S *>(t.tloc), in, out);
     return hipGetLastError();
 }
 
@@ -200,12 +201,12 @@ hipError_t launch_m(const Geometry &g, const MappedTables &t, const S *in, S *ou
     if constexpr (P % V == 0) {
         if (aligned) {
             hipLaunchKernelGGL((k_stream_mapped<S, P, V>), dim3(static_cast<unsigned>(bx), Q), dim3(256), 0, st, g,
-                               t.basis, t.cell, t.tloc, in, out);
+                               t.basis, t.cell, static_cast<const S *>(t.tloc), in, out);
             return hipGetLastError();
         }
     }
     hipLaunchKernelGGL((k_stream_mapped<S, P, 1>), dim3(static_cast<unsigned>(bx), Q), dim3(256), 0, st, g, t.basis,
-                       t.cell, t.tloc, in, out);
+                       t.cell, static_cast<const S *>(t.tloc), in, out);
     return hipGetLastError();
 }
 
