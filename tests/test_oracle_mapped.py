@@ -175,3 +175,18 @@ def test_node_weights(oracle):
         wm, w0 = oracle.mapped_node_weights(c), oracle.mapped_node_weights(c0)
         assert abs(wm.sum() - L ** 3) < 1e-12 * L ** 3
         assert np.max(np.abs(wm - w0)) > 1e-3 * np.max(w0)
+
+
+def test_uniform_state_is_fixed_on_a_distorted_mesh(oracle):
+    """A uniform equilibrium stays fixed through full steps on a distorted
+    mesh: the (p+1)^3 weights at any departure point sum to one and the
+    collision leaves an equilibrium unchanged."""
+    n_el, p, dt = (3, 3, 2), 3, 0.4
+    cfg0 = oracle.make_cfg(n_el, p, dt, 0.01)
+    X, Y, Z = _ref_coords(oracle, cfg0)
+    N = X.size
+    disp = np.stack([0.2 * np.sin(Y + Z), 0.15 * np.sin(X) * np.cos(Z), 0.1 * np.cos(X + Y)])
+    cfg = oracle.make_cfg(n_el, p, dt, 0.01, disp=disp)
+    f, g = oracle.init_equilibrium(cfg, np.full(N, 1.2), np.tile([[0.2], [-0.1], [0.05]], (1, N)), np.full(N, 1.1))
+    f2, g2 = oracle.step(cfg, f, g, 2)
+    assert np.max(np.abs(f2 - f)) < 1e-13 and np.max(np.abs(g2 - g)) < 1e-13
