@@ -271,3 +271,16 @@ def test_riemann_to_end_time():
     rho, u, T = ctx.moments()
     assert bool(torch.isfinite(rho).all()) and float(rho.min()) > 0 and float(T.min()) > 0
     assert abs(t1[0] - t0[0]) < 5e-4 * t0[0] and abs(t1[4] - t0[4]) < 5e-4 * t0[4], (t0, t1)
+
+
+def test_uniform_state_is_fixed(O2):
+    """A uniform moving equilibrium stays fixed through steps (2-D lattice)."""
+    ctx, cfg = _pair(O2, (10, 6), 4, 2e-3, 1e-3, length=(1.0, 0.6))
+    N = O2.num_nodes(cfg)
+    dev = ctx.device
+    u = np.tile([[0.3], [-0.2]], (1, N))
+    ctx.init_equilibrium(torch.full((N,), 1.3, dtype=torch.float64, device=dev), torch.from_numpy(u).to(dev),
+                         torch.full((N,), 1.1, dtype=torch.float64, device=dev))
+    s0 = ctx.get_state()
+    ctx.step(5)
+    assert rel_err(_to_np(ctx.get_state())[0], _to_np(s0)[0]) < 1e-13

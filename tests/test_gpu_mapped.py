@@ -246,3 +246,19 @@ def test_adjoint_step_against_complex_step(oracle):
     fc, gc = oracle.step(cfg, f0 + 1j * h * dX[0], g0 + 1j * h * dX[1], 1)
     ref = float((np.sum(lam[0] * fc.imag) + np.sum(lam[1] * gc.imag)) / h)
     assert abs(got - ref) <= 1e-10 * abs(ref), (got, ref)
+
+
+def test_uniform_state_is_fixed(oracle):
+    """A uniform equilibrium stays fixed through steps on the distorted mesh."""
+    n_el, p, dt = (4, 4, 4), 4, 0.3
+    ctx, cfg0 = make_pair(oracle, n_el, p, dt, 0.01)
+    X, Y, Z = _ref(oracle, cfg0)
+    N = X.size
+    ctx.set_displacement(_smooth_disp(X, Y, Z))
+    dev = ctx.device
+    u = np.tile([[0.2], [-0.1], [0.05]], (1, N))
+    ctx.init_equilibrium(torch.full((N,), 1.2, dtype=torch.float64, device=dev), torch.from_numpy(u).to(dev),
+                         torch.full((N,), 1.1, dtype=torch.float64, device=dev))
+    s0 = ctx.get_state()
+    ctx.step(3)
+    assert rel_err(to_np(ctx.get_state())[0], to_np(s0)[0]) < 1e-13
