@@ -1,0 +1,39 @@
+"""bench.py in each of its measurement modes (a few steps each): one JSON
+line with the contract's fields, a positive finite value and a roofline
+entry for the dominant kernel."""
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+from gpu_common import require_gpu
+
+pytestmark = pytest.mark.gpu
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.mark.parametrize("args,kernel,metric", [
+    (["--mesh", "graded"], "k_stream_graded", "node-updates/s (D3V45 f+g)"),
+    (["--mesh", "distorted"], "k_stream_mapped", "node-updates/s (D3V45 f+g)"),
+    (["--workload", "riemann"], None, "node-updates/s (D2V19 f+g)"),
+    (["--workload", "sod", "--precision", "fp32"], None, "node-updates/s (D2V19 f+g)"),
+])
+def test_bench_mode(args, kernel, metric):
+    require_gpu()
+    print("bench", args, flush=True)
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), *args, "--steps", "3", "--warmup", "1",
+                        "--no-cpu-baseline", "--adjoint-workload", "none"],
+                       capture_output=True, text=True, timeout=200)
+    assert r.returncode == 0, r.stderr[-2000:]
+    lines = [l for l in r.stdout.splitlines() if l.strip()]
+    assert len(lines) == 1
+    d = json.loads(lines[0])
+    for key in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better",
+                "scaling", "vs_baseline", "dtype", "data", "config", "roofline"):
+        assert key in d, key
+    assert d["metric"] == metric and d["value"] > 0 and d["finite"]
+    assert d["roofline"]["bound"] == "hbm" and 0 < d["roofline"]["frac"] < 1
+    if kernel:
+        assert d["roofline"]["kernel"] == kernel
