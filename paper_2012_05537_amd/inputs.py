@@ -11,7 +11,8 @@ Initial condition (Sec. III C, constant-temperature initial condition):
     u = U (sin x cos y cos z, -cos x sin y cos z, 0)
     P = rho0 T0 + rho0 U^2 / 16 (cos 2x + cos 2y)(cos 2z + 2),  rho = P / T0,  T = T0
 with U = Ma * sqrt(gamma T0), which reproduces the paper's rho = 1 + C/16(...)
-with C = gamma Ma^2.  mu_inf = rho0 U L / Re with L = 1, and
+with C = gamma Ma^2 (its Re = 1600 choice; tgv_fields also takes the C = 1 of
+its Re = 100 and 400 runs).  mu_inf = rho0 U L / Re with L = 1, and
 dt = CFL * (mean node spacing) / (largest abscissa speed).
 """
 import math
@@ -98,17 +99,62 @@ def mesh(xs, ys, zs):
     return X.ravel(), Y.ravel(), Z.ravel()
 
 
-def tgv_fields(xs, ys, zs, Ma, gamma):
-    """rho (N,), u (3, N), T (N,) of the compressible Taylor-Green vortex."""
+def tgv_fields(xs, ys, zs, Ma, gamma, numerator=None):
+    """rho (N,), u (3, N), T (N,) of the compressible Taylor-Green vortex.
+
+    numerator: the paper's C in rho = 1 + C/16 (cos 2x + cos 2y)(cos 2z + 2)
+    (Sec. III C); None gives C = gamma Ma^2, the closed-form TGV pressure
+    rho0 U^2/16 (...) at uniform T0 (the paper's choice at Re = 1600); the
+    paper uses C = 1 at Re = 100 and 400."""
     X, Y, Z = mesh(xs, ys, zs)
     U = velocity_scale(Ma, gamma)
     u = np.stack([U * np.sin(X) * np.cos(Y) * np.cos(Z),
                   -U * np.cos(X) * np.sin(Y) * np.cos(Z),
                   np.zeros_like(X)])
-    P = RHO0 * T0 + RHO0 * U * U / 16.0 * (np.cos(2 * X) + np.cos(2 * Y)) * (np.cos(2 * Z) + 2.0)
-    rho = P / T0
+    shape = (np.cos(2 * X) + np.cos(2 * Y)) * (np.cos(2 * Z) + 2.0)
+    if numerator is None:
+        rho = (RHO0 * T0 + RHO0 * U * U / 16.0 * shape) / T0
+    else:
+        rho = RHO0 * (1.0 + float(numerator) / 16.0 * shape)
     T = np.full_like(X, T0)
     return rho, u, T
+
+
+# The paper's own Taylor-Green runs (Sec. III C), in its units: velocity
+# amplitude 1, wavenumber-1 length, Re = 1/nu_inf, time step dt_paper in the
+# convective time L/U.  256^3 nodes (64^3 cells of p = 4), Pr = 0.7.  The
+# final times of the Re = 400 and Re = 100 runs are not in the text (their
+# figures are); t = 10 stands in.
+PAPER_TGV = {
+    "re1600_ma125": dict(Re=1600.0, Ma=1.25, dt_paper=0.009, t_end=20.0, numerator=None),
+    "re1600_ma100": dict(Re=1600.0, Ma=1.0, dt_paper=0.010, t_end=20.0, numerator=None),
+    "re400_ma050": dict(Re=400.0, Ma=0.5, dt_paper=0.017, t_end=10.0, numerator=1.0),
+    "re400_ma100": dict(Re=400.0, Ma=1.0, dt_paper=0.033, t_end=10.0, numerator=1.0),
+    "re400_ma150": dict(Re=400.0, Ma=1.5, dt_paper=0.018, t_end=10.0, numerator=1.0),
+    "re400_ma200": dict(Re=400.0, Ma=2.0, dt_paper=0.012, t_end=10.0, numerator=1.0),
+    "re100_ma250": dict(Re=100.0, Ma=2.5, dt_paper=0.015, t_end=10.0, numerator=1.0),
+    "re100_ma300": dict(Re=100.0, Ma=3.0, dt_paper=0.030, t_end=10.0, numerator=1.0),
+}
+PAPER_TGV_GRID = dict(n_el=64, p=4, gamma=1.4, Pr=0.7)
+
+
+def paper_tgv(case, **override):
+    """Parameters of one of the paper's TGV runs in lattice units.
+
+    The paper's time unit is L/U; with U = Ma sqrt(gamma T0) in lattice units
+    (c_s = 1, T0 = 1, L = 1) its time t_paper equals U t, so
+    dt = dt_paper / U, mu_inf = rho0 U / Re, and t_end / dt_paper steps."""
+    w = dict(PAPER_TGV_GRID)
+    w.update(PAPER_TGV[case])
+    w.update(override)
+    U = velocity_scale(w["Ma"], w["gamma"])
+    w["U"] = U
+    w["dt"] = w["dt_paper"] / U
+    w["mu_inf"] = RHO0 * U / w["Re"]
+    w["steps"] = int(round(w["t_end"] / w["dt_paper"]))
+    w["cfl"] = MAX_SPEED * w["dt"] / (2 * math.pi / (w["n_el"] * w["p"]))
+    w["name"] = case
+    return w
 
 
 def fourier_modes(seed, count, Ma, gamma, scale=0.01, kmax=2):
