@@ -18,9 +18,11 @@
 // velset.h); in two dimensions the z components are absent.
 //  * h* = (w/3!) Qbar : H^(3)(xi); odd in xi, so h*_-i = -h*_i.
 //  * Relaxation h' = h + (h^eq - h)/tau + (1/tau - 1/tau_Pr) h*.
-// In FP32-mixed storage (S = float) the moments, transport coefficients,
-// equilibrium coefficients and Qbar are double; the per-velocity polynomial,
-// the H^(3) contraction and the relaxation run in float.
+// In FP32-mixed storage (S = float) the populations are read and written in
+// float once per collision and every operation in between is double: on
+// gfx950 an unpacked float FMA issues at the rate of a double one, and the
+// per-velocity polynomial in float loses up to c^4/24 (about 50 at the
+// outer shell and Mach 1.25) times its ulp to cancellation.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -125,7 +127,7 @@ __host__ __device__ __forceinline__ EqShell eq_shell(double u2, double th, doubl
 template <class L, typename S>
 __device__ __forceinline__ void collide_half(S (&v)[L::Q], bool is_g, const CollisionParams &cp)
 {
-    using R = S;
+    using R = double;   // arithmetic type of the per-velocity terms (storage S is read and written once)
     constexpr bool D3 = L::D == 3;
     const RawMoments<L> rm = raw_moments<L>(v);
     const double ktr = D3 ? rm.m2[0] + rm.m2[3] + rm.m2[5] : rm.m2[0] + rm.m2[3];
