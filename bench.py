@@ -5,8 +5,12 @@ One "step" is the whole per-time-step update of the state over the grid: the
 collision kernel (moments, transport coefficients, equilibria,
 quasi-equilibrium term, relaxation of all 90 populations of every node) and
 the streaming kernel (the order-p semi-Lagrangian interpolation of all 90
-populations).  The headline workload is the FP64 compressible Taylor-Green
-vortex on 16^3 cells of order 4 (64^3 nodes), Ma 1.25, Re 1600.
+populations).  The headline workload is the largest single-GPU grid of the
+configurations: the FP64 compressible Taylor-Green vortex on 64^3 cells of
+order 4 (256^3 nodes), Ma 1.25, Re 1600, CFL 10 with the seeded velocity
+modes.  The FP32-mixed step on the same grid and the FP64 step on 16^3 cells
+(64^3 nodes) are reported beside it.  Every timing is the median of --reps
+repetitions of K steps, each from the same post-warmup state.
 ``--workload riemann`` (or ``sod``) measures the two-dimensional D2Q19 step
 instead: 38 populations per node, case 12 of the 2-D Riemann problems on
 128^2 cells of order 4 (512^2 nodes).
@@ -61,27 +65,30 @@ def measured_traffic(kernel, workload, dtype):
     return rec.get("bytes_per_launch")
 
 
-def run_gpu(args, wl, precision):
+def run_gpu(args, wl, precision, mesh="equal"):
     import torch
     from paper_2012_05537_amd import inputs
     from paper_2012_05537_amd.sllbm import SLLBM
 
     ctx = SLLBM(wl["n_el"], wl["p"], wl["dt"], wl["mu_inf"], gamma=wl["gamma"], prandtl=wl["Pr"],
                 precision=precision)
-    if args.mesh == "graded":
+    if mesh == "graded":
         w = inputs.graded_widths(wl["n_el"], amplitude=inputs.GRADED["amplitude"])
         ctx.set_mesh(w, w, w)
     xs, ys, zs = (t.numpy() for t in ctx.node_coords())
-    rho, u, T = inputs.tgv_fields(xs, ys, zs, wl["Ma"], wl["gamma"])
+    md = wl.get("modes")
+    modes = inputs.fourier_modes(md["seed"], md["count"], wl["Ma"], wl["gamma"], md["scale"]) if md else None
+    rho, u, T = inputs.perturbed_tgv(xs, ys, zs, wl["Ma"], wl["gamma"], modes)
     dev = ctx.device
     ctx.init_equilibrium(torch.from_numpy(rho).to(dev), torch.from_numpy(u).to(dev), torch.from_numpy(T).to(dev))
+    del rho, u, T
     table_bytes = 0
-    if args.mesh == "distorted":
+    if mesh == "distorted":
         X, Y, Z = inputs.mesh(xs, ys, zs)
         ctx.set_displacement(inputs.distortion(X, Y, Z, 2 * math.pi / wl["n_el"], inputs.DISTORTED["amplitude"]))
         elem = 8 if precision == 0 else 4
         table_bytes = Q * ctx.nodes * (4 + 3 * elem)   # departure cell and local coordinates per velocity and node
-    kern = {"graded": "k_stream_graded", "distorted": "k_stream_mapped"}.get(args.mesh, "k_stream_z")
+    kern = {"graded": "k_stream_graded", "distorted": "k_stream_mapped"}.get(mesh, "k_stream_z")
     return measure_steps(args, ctx, kern, table_bytes)
 
 
@@ -118,12 +125,17 @@ def measure_steps(args, ctx, stream_kernel, table_bytes=0):
     for _ in range(args.warmup):
         ctx.step(1)
     start = ctx.get_state()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        ctx.step(1)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    walls = []
+    for _ in range(max(1, args.reps)):
+        # every repetition times the same K steps from the post-warmup state
+        ctx.set_state(start)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            ctx.step(1)
+        torch.cuda.synchronize()
+        walls.append(time.perf_counter() - t0)
+    wall = sorted(walls)[len(walls) // 2]
     try:
         tot = ctx.totals()
         ok = all(math.isfinite(v) for v in tot)
@@ -146,7 +158,7 @@ def measure_steps(args, ctx, stream_kernel, table_bytes=0):
     kernels = {name: {"ms": ms / max(n, 1), "launches": n, "bytes": b} for name, (ms, n), b in
                (("k_collide", kt["collide"], bytes_per_launch),
                 (stream_kernel, kt["stream"], bytes_per_launch + table_bytes))}
-    return dict(nodes=nodes, wall=wall, kernels=kernels, bytes=bytes_per_launch, finite=ok, totals=tot)
+    return dict(nodes=nodes, wall=wall, walls=walls, kernels=kernels, bytes=bytes_per_launch, finite=ok, totals=tot)
 
 
 def run_adjoint(wl, precision, graded=False):
@@ -258,17 +270,65 @@ def workload_2d(name):
     return w
 
 
+def measure_line(args, wl, wkey, prec_name, two_d, mesh):
+    """Timings of one workload and precision: (summary dict, raw record)."""
+    from paper_2012_05537_amd import inputs
+    precision = 0 if prec_name == "fp64" else 1
+    r = run_gpu_2d(args, wl, precision) if two_d else run_gpu(args, wl, precision, mesh)
+    dom = max(r["kernels"], key=lambda k: r["kernels"][k]["ms"])
+    kms = r["kernels"][dom]["ms"]
+    dom_bytes = r["kernels"][dom]["bytes"]
+    achieved = dom_bytes / (kms * 1e-3) / 1e9
+    kernels = {}
+    for k, v in r["kernels"].items():
+        gbs = v["bytes"] / (v["ms"] * 1e-3) / 1e9 if v["ms"] > 0 else None
+        kernels[k] = {"ms_per_launch": v["ms"], "launches": v["launches"], "algorithmic_GBps": gbs,
+                      "traffic": measured_traffic(k, wkey, prec_name)}
+    if two_d:
+        nx, ny = wl["n_el"]
+        workload = (f"{wkey}: {'periodic double Sod tube' if wkey == 'sod' else 'Riemann case 12'} "
+                    f"{nx}x{ny} cells p={wl['p']} ({r['nodes']} nodes), D2Q19, dt {wl['dt']}, "
+                    f"mu {wl['mu_inf']}, {prec_name}")
+    else:
+        mdesc = {"equal": "cells", "graded": "cosine-graded cells (a = 0.3)",
+                 "distorted": f"distorted cells (displacement {inputs.DISTORTED['amplitude']} h)"}[mesh]
+        modes = " + 16 seeded velocity modes" if wl.get("modes") else ""
+        workload = (f"{wkey}: TGV{modes} {wl['n_el']}^3 {mdesc} p={wl['p']} "
+                    f"({r['nodes']} nodes), Ma {wl['Ma']}, Re {wl['Re']}, CFL {wl['cfl']}, {prec_name}")
+    step_s = r["wall"] / args.steps
+    line = {
+        "workload": workload,
+        "value": r["nodes"] / step_s,
+        "ms_per_step": step_s * 1e3,
+        "ms_per_step_reps": [w * 1e3 / args.steps for w in r["walls"]],
+        "dtype": "f64" if precision == 0 else "f32 (f64 moments)",
+        "nodes": r["nodes"], "order": wl["p"], "cfl": wl.get("cfl"), "dt": wl["dt"],
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": kernels[dom]["traffic"],
+                     "kernel": dom, "kernel_ms": kms, "algorithmic_bytes_per_launch": dom_bytes,
+                     "step_frac": r["bytes"] / step_s / 1e9 / HBM_PEAK_GBS},
+        "kernels": kernels,
+        "finite": r["finite"],
+    }
+    return line
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="c2", help="workload key (c1..c5; sod or riemann: 2-D D2Q19)")
-    ap.add_argument("--cfl", type=float, default=1.0)
+    ap.add_argument("--reps", type=int, default=5, help="repetitions of the K timed steps (median reported)")
+    ap.add_argument("--workload", default=None,
+                    help="workload key (c1..c5; sod or riemann: 2-D D2Q19); default c5 on equal cells, "
+                         "c2 on graded or distorted cells")
+    ap.add_argument("--cfl", type=float, default=None, help="CFL override (default: the workload's own)")
     ap.add_argument("--mesh", choices=["equal", "graded", "distorted"], default="equal",
                     help="equal cells, the cosine-graded cells of every axis (streaming on per-node tables), or "
                          "the smoothly distorted cells of sllbm_set_displacement (no cpu_baseline)")
-    ap.add_argument("--precision", choices=["fp64", "fp32"], default=None)
+    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="skip the FP32-mixed line on the same grid and the 64^3-node FP64 line")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--adjoint-workload", default="c4",
@@ -285,68 +345,65 @@ def main():
         return 2
 
     from paper_2012_05537_amd import inputs
+    if args.workload is None:
+        args.workload = "c5" if args.mesh == "equal" else "c2"
     two_d = args.workload in inputs.WORKLOADS_2D
     if two_d and args.mesh != "equal":
         print("the two-dimensional workloads use equal cells", file=sys.stderr)
         return 2
-    wl = workload_2d(args.workload) if two_d else inputs.workload(args.workload, cfl=args.cfl)
+    over = {} if args.cfl is None else {"cfl": args.cfl}
+    wl = workload_2d(args.workload) if two_d else inputs.workload(args.workload, **over)
     wkey = args.workload if args.mesh == "equal" else f"{args.workload}-{args.mesh}"
-    prec_name = args.precision or wl["precision"]
-    precision = 0 if prec_name == "fp64" else 1
-    r = run_gpu_2d(args, wl, precision) if two_d else run_gpu(args, wl, precision)
-    value = r["nodes"] * args.steps / r["wall"]
-    dom = max(r["kernels"], key=lambda k: r["kernels"][k]["ms"])
-    kms = r["kernels"][dom]["ms"]
-    dom_bytes = r["kernels"][dom]["bytes"]
-    achieved = dom_bytes / (kms * 1e-3) / 1e9
-    kernels = {}
-    for k, v in r["kernels"].items():
-        gbs = v["bytes"] / (v["ms"] * 1e-3) / 1e9 if v["ms"] > 0 else None
-        kernels[k] = {"ms_per_launch": v["ms"], "launches": v["launches"], "algorithmic_GBps": gbs,
-                      "traffic": measured_traffic(k, wkey, prec_name)}
+    head = measure_line(args, wl, wkey, args.precision, two_d, args.mesh)
     if two_d:
-        nx, ny = wl["n_el"]
-        workload = (f"{wkey}: {'periodic double Sod tube' if wkey == 'sod' else 'Riemann case 12'} "
-                    f"{nx}x{ny} cells p={wl['p']} ({r['nodes']} nodes), D2Q19, dt {wl['dt']}, "
-                    f"mu {wl['mu_inf']}, {prec_name}")
         data = "synthetic: piecewise-constant Riemann initial states (periodic stand-in)"
     else:
-        mdesc = {"equal": "cells", "graded": "cosine-graded cells (a = 0.3)",
-                 "distorted": f"distorted cells (displacement {inputs.DISTORTED['amplitude']} h)"}[args.mesh]
-        workload = (f"{wkey}: TGV {wl['n_el']}^3 {mdesc} p={wl['p']} "
-                    f"({r['nodes']} nodes), Ma {wl['Ma']}, Re {wl['Re']}, CFL {wl['cfl']}, {prec_name}")
         data = "synthetic: closed-form compressible Taylor-Green vortex"
     out = {
         "metric": "node-updates/s (D2V19 f+g)" if two_d else "node-updates/s (D3V45 f+g)",
-        "value": value,
+        "value": head["value"],
         "unit": "node-updates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": r["wall"] * 1e3 / args.steps,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if precision == 0 else "f32 (f64 moments)",
+        "dtype": head["dtype"],
         "data": data,
-        "config": {"workload": workload, "nodes": r["nodes"], "order": wl["p"], "cfl": wl.get("cfl"),
-                   "dt": wl["dt"], "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": kernels[dom]["traffic"],
-                     "kernel": dom, "kernel_ms": kms, "algorithmic_bytes_per_launch": dom_bytes,
-                     "step_frac": r["bytes"] / (r["wall"] / args.steps) / 1e9 / HBM_PEAK_GBS},
-        "kernels": kernels,
-        "finite": r["finite"],
+        "config": {"workload": head["workload"], "nodes": head["nodes"], "order": head["order"],
+                   "cfl": head["cfl"], "dt": head["dt"], "parallelism": "single GPU",
+                   "timing": f"median of {args.reps} repetitions of {args.steps} steps"},
+        "roofline": head["roofline"],
+        "kernels": head["kernels"],
+        "ms_per_step_reps": head["ms_per_step_reps"],
+        "finite": head["finite"],
     }
+    if not args.no_secondary and not two_d:
+        other = "fp32" if args.precision == "fp64" else "fp64"
+        sec = measure_line(args, wl, wkey, other, False, args.mesh)
+        out["fp32_mixed" if other == "fp32" else "fp64"] = sec
+        f32 = sec if other == "fp32" else head
+        f64 = head if other == "fp32" else sec
+        out["fp32_over_fp64"] = f32["value"] / f64["value"]
+        if args.workload != "c2" and args.mesh == "equal":
+            out["c2_fp64"] = measure_line(args, inputs.workload("c2"), "c2", "fp64", False, "equal")
     if args.adjoint_workload != "none" and not two_d:
-        over = {} if args.adjoint_cfl is None else {"cfl": args.adjoint_cfl}
+        aover = {} if args.adjoint_cfl is None else {"cfl": args.adjoint_cfl}
         if args.adjoint_steps is not None:
-            over["steps"] = args.adjoint_steps
-        wa = inputs.workload(args.adjoint_workload, **over)
+            aover["steps"] = args.adjoint_steps
+        wa = inputs.workload(args.adjoint_workload, **aover)
         out["adjoint"] = run_adjoint(wa, 0 if wa["precision"] == "fp64" else 1, graded=args.mesh == "graded")
     if not args.no_cpu_baseline and args.mesh != "distorted":
-        out["cpu_baseline"] = (cpu_baseline_2d(wl, args.cpu_budget) if two_d else
-                               cpu_baseline(wl, args.cpu_budget, graded=args.mesh == "graded"))
+        if two_d:
+            out["cpu_baseline"] = cpu_baseline_2d(wl, args.cpu_budget)
+        else:
+            # the oracle on the 16^3-cell subcase of the same workload (same Ma, Re, CFL)
+            sub = wl if wl["n_el"] <= 16 else inputs.workload(args.workload, n_el=16, **over)
+            out["cpu_baseline"] = cpu_baseline(sub, args.cpu_budget, graded=args.mesh == "graded")
+            if sub is not wl:
+                out["cpu_baseline"]["sample"] += f" (the 16^3-cell subcase of the {wl['n_el']}^3-cell grid)"
     print(json.dumps(out), flush=True)
     return 0
 

@@ -264,6 +264,24 @@ def step_at_nodes(cfg, f, g, nodes):
     return fo, go
 
 
+def stream_at_nodes(cfg, f, g, nodes):
+    """Streaming only, evaluated at the given node indices (equal or graded
+    cells): returns (fo, go), each (S, 45)."""
+    if is_mapped(cfg):
+        raise ValueError("stream_at_nodes: equal or graded cells only")
+    cplx = _is_cplx(f, g)
+    dt = _dt(cplx)
+    f = np.ascontiguousarray(f, dtype=dt)
+    g = np.ascontiguousarray(g, dtype=dt)
+    nodes = np.ascontiguousarray(nodes, dtype=np.int64)
+    S = len(nodes)
+    fo = np.zeros((S, Q), dt)
+    go = np.zeros((S, Q), dt)
+    getattr(_lib(cplx), _prefix(cplx) + "stream_at_nodes")(ctypes.byref(cfg), _ptr(f), _ptr(g), ctypes.c_int(S),
+                                                           _ptr(nodes), _ptr(fo), _ptr(go))
+    return fo, go
+
+
 def moments(cfg, f, g):
     cplx = _is_cplx(f, g)
     dt = _dt(cplx)

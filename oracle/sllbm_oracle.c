@@ -770,6 +770,25 @@ void FN(step_at_nodes)(const oracle_cfg *c, const R *f, const R *g, int nsamp, c
     }
 }
 
+/* Streaming only (Eq. (9)), evaluated at the listed nodes of an equal-cell
+ * or graded mesh: the whole-grid stream restricted to those nodes, the same
+ * direct (p+1)^3 gather per node and velocity.  out[45] f then out[45] g per
+ * sample. */
+void FN(stream_at_nodes)(const oracle_cfg *c, const R *f, const R *g, int nsamp, const long *nodes,
+                         R *fo, R *go)
+{
+    double xi[3 * Q], w[Q];
+    oracle_velocity_set(xi, w);
+    int N[3] = {c->n_el[0] * c->p, c->n_el[1] * c->p, c->n_el[2] * c->p};
+#pragma omp parallel for schedule(static)
+    for (int s = 0; s < nsamp; ++s) {
+        long n = nodes[s];
+        int gx = (int)(n % N[0]), gy = (int)((n / N[0]) % N[1]), gz = (int)(n / ((long)N[0] * N[1]));
+        for (int i = 0; i < Q; ++i)
+            departure_value(c, xi, i, gx, gy, gz, f, g, &fo[(long)s * Q + i], &go[(long)s * Q + i]);
+    }
+}
+
 /* rho, u (stored [3][N]) and T at every node, Eq. (7). */
 void FN(moments)(const oracle_cfg *c, const R *f, const R *g, R *rho, R *u, R *T)
 {

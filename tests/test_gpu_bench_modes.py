@@ -24,7 +24,7 @@ def test_bench_mode(args, kernel, metric):
     require_gpu()
     print("bench", args, flush=True)
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), *args, "--steps", "3", "--warmup", "1",
-                        "--no-cpu-baseline", "--adjoint-workload", "none"],
+                        "--reps", "1", "--no-secondary", "--no-cpu-baseline", "--adjoint-workload", "none"],
                        capture_output=True, text=True, timeout=200)
     assert r.returncode == 0, r.stderr[-2000:]
     lines = [l for l in r.stdout.splitlines() if l.strip()]
@@ -37,3 +37,24 @@ def test_bench_mode(args, kernel, metric):
     assert d["roofline"]["bound"] == "hbm" and 0 < d["roofline"]["frac"] < 1
     if kernel:
         assert d["roofline"]["kernel"] == kernel
+
+
+def test_bench_default_headline_and_secondary_lines():
+    """The default run: the 256^3-node FP64 headline, the FP32-mixed line on
+    the same grid and the 64^3-node FP64 line, each a median of repetitions."""
+    require_gpu()
+    print("bench default (256^3 nodes, fp64 + fp32 + c2)", flush=True)
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--steps", "2", "--warmup", "1",
+                        "--reps", "3", "--no-cpu-baseline", "--adjoint-workload", "none"],
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr[-2000:]
+    lines = [l for l in r.stdout.splitlines() if l.strip()]
+    assert len(lines) == 1
+    d = json.loads(lines[0])
+    assert d["config"]["nodes"] == 256 ** 3 and d["dtype"] == "f64"
+    assert len(d["ms_per_step_reps"]) == 3 and d["ms_per_step"] in d["ms_per_step_reps"]
+    assert d["fp32_mixed"]["nodes"] == 256 ** 3 and d["fp32_mixed"]["dtype"].startswith("f32")
+    assert d["c2_fp64"]["nodes"] == 64 ** 3
+    assert d["fp32_over_fp64"] > 1.0
+    for line in (d, d["fp32_mixed"], d["c2_fp64"]):
+        assert 0 < line["roofline"]["frac"] < 1 and 0 < line["roofline"]["step_frac"] < 1

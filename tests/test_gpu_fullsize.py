@@ -67,6 +67,45 @@ def test_one_step_sampled_full_size(oracle, name):
     ctx.close()
 
 
+@pytest.mark.parametrize("name", ["c3", "c5"])
+def test_whole_z_planes_stream_and_collide_full_size(oracle, name):
+    """One sllbm_stream and one sllbm_collide of a full-size FP32 state (two
+    steps into the flow) against the oracle's stream and collide on three
+    whole z-planes (the periodic seam, an interior plane, the last plane):
+    every node and population of those planes, element by element."""
+    _say(f"{name}: whole z-planes of one stream and one collide at full size")
+    w, ctx, cfg = workload_pair(oracle, name)
+    _init_gpu(ctx, w)
+    ctx.step(2)
+    X0 = ctx.get_state()
+    Nz, Ny, Nx = ctx.shape
+    P = Nx * Ny
+    planes = [0, Nz // 2 + 1, Nz - 1]
+    Xs = ctx.stream(X0)
+    Xc = X0.clone()
+    ctx.collide(Xc)
+    torch.cuda.synchronize()
+    f0, g0 = to_np(X0)
+    n_el = w["n_el"]
+    plane_cfg = oracle.make_cfg((n_el, n_el // w["p"], 1), w["p"], w["dt"], w["mu_inf"], gamma=w["gamma"],
+                                prandtl=w["Pr"])
+    assert oracle.num_nodes(plane_cfg) == P
+    for z in planes:
+        nodes = z * P + np.arange(P)
+        fs, gs = oracle.stream_at_nodes(cfg, f0, g0, nodes)
+        F = Xs[0][:, z * P:(z + 1) * P].double().cpu().numpy().T
+        G = Xs[1][:, z * P:(z + 1) * P].double().cpu().numpy().T
+        es = max(np.max(np.abs(F - fs)) / np.abs(fs).max(), np.max(np.abs(G - gs)) / np.abs(gs).max())
+        fc, gc = oracle.collide(plane_cfg, f0[:, z * P:(z + 1) * P].copy(), g0[:, z * P:(z + 1) * P].copy())
+        F = Xc[0][:, z * P:(z + 1) * P].double().cpu().numpy()
+        G = Xc[1][:, z * P:(z + 1) * P].double().cpu().numpy()
+        ec = max(np.max(np.abs(F - fc)) / np.abs(fc).max(), np.max(np.abs(G - gc)) / np.abs(gc).max())
+        _say(f"{name} plane z={z}: stream max rel error {es:.2e}, collide {ec:.2e}")
+        assert es < 1e-5 and ec < 1e-5
+    del f0, g0
+    ctx.close()
+
+
 def _collide_vjp_at(oracle, cfg_small, f, g, yf, yg):
     """J_C^T y for a set of nodes held as a small grid (collision is node-local)."""
     n = f.shape[1]

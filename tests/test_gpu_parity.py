@@ -226,6 +226,32 @@ def test_c2_first_steps_full_grid(oracle):
     assert rel_err(F, fo) < TOL64 and rel_err(G, go) < TOL64
 
 
+@pytest.mark.parametrize("cfl", [5.0, 10.0])
+def test_c2_full_grid_every_step_until_non_finite(oracle, cfl):
+    """64^3 nodes at CFL 5 and 10 (tau - 1/2 = 0.0073 and 0.0036): the whole
+    grid against the oracle after every step, until the flow itself goes
+    non-finite (steps 16 and 14 here).  Every finite step agrees to 1e-12
+    (the one-ulp floor of the flow stays near 1e-14 over these steps), and
+    both implementations go non-finite at the same step."""
+    _say(f"c2 full-grid parity every step, cfl={cfl}")
+    w, ctx, cfg = workload_pair(oracle, "c2", cfl=cfl)
+    f, g = tgv_init(oracle, ctx, cfg, w["Ma"], w["gamma"])
+    for n in range(1, 21):
+        ctx.step(1)
+        f, g = oracle.step(cfg, f, g, 1)
+        F, G = to_np(ctx.get_state())
+        gpu_ok = bool(np.isfinite(F).all() and np.isfinite(G).all())
+        ora_ok = bool(np.isfinite(f).all() and np.isfinite(g).all())
+        assert gpu_ok == ora_ok, f"step {n}: GPU finite {gpu_ok}, oracle finite {ora_ok}"
+        if not gpu_ok:
+            _say(f"c2 cfl={cfl}: both non-finite at step {n}")
+            break
+        err = max(rel_err(F, f), rel_err(G, g))
+        assert err < TOL64, f"step {n}: {err:.3e}"
+    assert n > 5
+    ctx.close()
+
+
 def test_deterministic(oracle):
     w, ctx, cfg = workload_pair(oracle, "c1")
     tgv_init(oracle, ctx, cfg, w["Ma"], w["gamma"])

@@ -118,6 +118,27 @@ def test_step_at_nodes_matches_full_step(oracle):
     assert np.allclose(gs, g1[:, nodes].T, rtol=0, atol=1e-15)
 
 
+@pytest.mark.parametrize("graded", [False, True])
+def test_stream_at_nodes_is_the_whole_grid_stream_restricted(oracle, graded):
+    """stream_at_nodes (the oracle's plain gather at listed nodes) gives the
+    whole-grid stream's values at every node, on a ragged grid with a shift
+    of more than a cell, equal or graded cells."""
+    n_el, p = (3, 2, 4), 3
+    widths = None
+    if graded:
+        rng = np.random.default_rng(4)
+        widths = [w / w.sum() * 2 * np.pi for w in (1 + 0.4 * rng.uniform(-1, 1, n) for n in n_el)]
+    cfg = oracle.make_cfg(n_el, p, 1.1, 0.01, widths=widths)
+    rng = np.random.default_rng(9)
+    N = oracle.num_nodes(cfg)
+    f = rng.normal(size=(45, N))
+    g = rng.normal(size=(45, N))
+    fo, go = oracle.stream(cfg, f, g)
+    nodes = np.arange(N)[::-1].copy()
+    fs, gs = oracle.stream_at_nodes(cfg, f, g, nodes)
+    assert np.array_equal(fs, fo[:, nodes].T) and np.array_equal(gs, go[:, nodes].T)
+
+
 def test_collide_then_stream_conserves_mass_to_interpolation_accuracy(oracle):
     """Collision conserves exactly; GLC streaming is not exactly conservative but
     its mass error is small for a smooth field."""
