@@ -256,6 +256,28 @@ int sllbm_stream(sllbm_ctx *ctx, const void *in, void *out, int32_t transpose);
  * in place (device, storage type). */
 int sllbm_collide(sllbm_ctx *ctx, void *state);
 
+/* ---- allocation-free entry point ---------------------------------------- */
+
+/* For callers that cannot allocate device memory (work under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the totals
+ * of sllbm_totals (Clenshaw-Curtis integrals of rho, rho u_x, rho u_y,
+ * rho u_z, rho E) of a caller state, without a context.
+ *   cfg    host; the equal-cell periodic mesh and lattice of the state
+ *          (n_el, order, length, velocity_set, precision, device; the other
+ *          fields are not read).
+ *   state  device, [2][Q][N] of cfg's storage type, on cfg->device.
+ *   out    device, 5 doubles, written in the order of sllbm_totals.
+ *   stream the hipStream_t to run on (NULL: the null stream); asynchronous,
+ *          no finiteness check.
+ * The library allocates nothing here: the reduction partials and node weights
+ * live in a static device array of 256 KB per device (held until the process
+ * ends), which limits the grid to N_x + N_y + N_z <= 24576 nodes (EINVAL
+ * beyond).  Calls that overlap on one device share that array and race.
+ * Same kernels and summation order as sllbm_totals, so the same bits.
+ * Errors: EINVAL (configuration, NULL pointer, size), EDEVICE (runtime);
+ * the message is sllbm_last_error(NULL). */
+int sllbm_totals_noalloc(const sllbm_config *cfg, const void *state, double *out, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

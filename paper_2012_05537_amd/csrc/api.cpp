@@ -94,6 +94,17 @@ int fail(sllbm_ctx *c, int code, const std::string &msg)
     return code;
 }
 
+}  // namespace
+
+// message of a failed call without a context (sllbm_last_error(NULL))
+int sllbm::set_global_error(int code, const std::string &msg)
+{
+    g_create_error = msg;
+    return code;
+}
+
+namespace {
+
 int hip_fail(sllbm_ctx *c, hipError_t e, const char *what)
 {
     return fail(c, SLLBM_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));

@@ -76,6 +76,10 @@ bool build_mapped_tables(const VelocitySet &vs, int p, const int ne[3], const do
 // Device-side parameter blocks (passed by value to kernels)
 // ---------------------------------------------------------------------------
 
+// Records the message of a failed call that has no context (returned by
+// sllbm_last_error(NULL)); returns code.
+int set_global_error(int code, const std::string &msg);
+
 struct Geometry {
     int N[3];        // nodes per axis
     int nel[3];      // cells per axis

@@ -77,6 +77,7 @@ _SIGS = {
     "sllbm_init_equilibrium_vjp": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
     "sllbm_stream": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int32]),
     "sllbm_collide": (ctypes.c_int, [_VP, _VP]),
+    "sllbm_totals_noalloc": (ctypes.c_int, [ctypes.POINTER(Config), _VP, _VP, _VP]),
 }
 
 EXPORTED = tuple(_SIGS)
@@ -117,6 +118,21 @@ def lattice(velocity_set=D3Q45):
         raise ValueError("unknown velocity set %r" % (velocity_set,))
     return (torch.tensor(list(xi)[:3 * n], dtype=torch.float64).reshape(n, 3),
             torch.tensor(list(w)[:n], dtype=torch.float64))
+
+
+def totals_noalloc(cfg, state, out, stream=None):
+    """sllbm_totals_noalloc: totals of a device state into the device tensor out (5 doubles).
+
+    cfg: a Config (e.g. SLLBM(...).cfg); stream: a torch.cuda.Stream or None
+    (the current stream of the state's device)."""
+    lib = load_library()
+    if out.dtype != torch.float64 or out.numel() < 5 or not out.is_contiguous():
+        raise ValueError("out must hold 5 contiguous float64 values")
+    s = stream if stream is not None else torch.cuda.current_stream(state.device)
+    rc = lib.sllbm_totals_noalloc(ctypes.byref(cfg), _ptr(state), _ptr(out), s.cuda_stream)
+    if rc != OK:
+        raise SllbmError(rc, lib.sllbm_last_error(None).decode())
+    return out
 
 
 def _ptr(t):
