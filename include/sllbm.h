@@ -246,6 +246,20 @@ int sllbm_moments_vjp(sllbm_ctx *ctx, const double *drho, const double *du, cons
 int sllbm_init_equilibrium_vjp(sllbm_ctx *ctx, const double *rho, const double *u, const double *T,
                                const void *lam0, double *drho, double *du, double *dT);
 
+/* Mode algebra of the gradient workload: velocity modes added to a base
+ * flow (the perturbed Taylor-Green initial state of Sec. III C used for
+ * gradients).  base, out: device double [D][N] (D = 3, or 2 for D2Q19);
+ * basis: device double [m][D][N]; amps: host double [m]; 0 <= m <= 64.
+ *   sllbm_superpose: out = base + sum_j amps[j] basis[j]  (asynchronous;
+ *                    out may equal base).
+ *   sllbm_project:   out[j] = sum over the D*N components of basis[j] v
+ *                    (host out[m]); deterministic fixed-order reduction;
+ *                    synchronises the stream.
+ * EINVAL for NULL pointers or m out of range. */
+int sllbm_superpose(sllbm_ctx *ctx, const double *base, const double *basis, int32_t m, const double *amps,
+                    double *out);
+int sllbm_project(sllbm_ctx *ctx, const double *basis, int32_t m, const double *v, double *out);
+
 /* ---- building blocks exposed for testing -------------------------------- */
 
 /* Streaming only (Eq. (9)) of a caller state: out = S(in) (forward) or

@@ -16,9 +16,10 @@ steps; the backward pass replays each segment from its checkpoint (one
 sllbm_step_record call) and walks it backwards.  ``checkpoint="sqrt"`` uses
 ceil(sqrt(n)) steps per segment, so about 2 sqrt(n) states are resident.
 
-Every step of the path runs in the library's kernels; this module only
-allocates buffers, orders the calls and does the final projection on the
-modes (one dense product on the device).
+Every step of the path runs in the library's kernels, the mode
+superposition and the final projection on the modes included
+(sllbm_superpose, sllbm_project); this module only allocates buffers, orders
+the calls and scales the 17 host results by the upstream gradient.
 """
 import math
 
@@ -45,7 +46,7 @@ class _RolloutFn(torch.autograd.Function):
     def forward(fctx, amps, mu_inf, roll):
         sim = roll.sim
         sim.set_viscosity(float(mu_inf))
-        u0 = roll.u0(amps.to(roll.basis.device))
+        u0 = roll.u0(amps)
         sim.init_equilibrium(roll.rho0, u0, roll.T0)
         checkpoints = []
         for s0, s1 in roll.segments:
@@ -67,8 +68,7 @@ class _RolloutFn(torch.autograd.Function):
         roll = fctx.roll
         sim = roll.sim
         sim.set_viscosity(fctx.mu_inf)
-        lam = sim.loss_grad(fctx.final)
-        lam.mul_(grad.to(lam.dtype))
+        lam = sim.loss_grad(fctx.final)        # the gradient is linear in lam: scaled by grad at the end
         other = torch.empty_like(lam)
         dmu = torch.zeros(1, dtype=torch.float64, device=lam.device)
         seg_max = max((s1 - s0 for s0, s1 in roll.segments), default=1)
@@ -83,8 +83,11 @@ class _RolloutFn(torch.autograd.Function):
                 sim.adjoint_step(x_n, lam, other, dmu)
                 lam, other = other, lam
         _, du, _ = sim.init_equilibrium_vjp(roll.rho0, fctx.u0, roll.T0, lam)
-        damps = roll.basis.reshape(roll.basis.shape[0], -1) @ du.reshape(-1)
-        return damps.to(fctx.amps_device), dmu[0].to(fctx.mu_device), None
+        g = float(grad)
+        damps = torch.tensor([g * x for x in sim.project(roll.basis, du)], dtype=torch.float64,
+                             device=fctx.amps_device)
+        dmu_v = torch.tensor(g * float(dmu[0]), dtype=torch.float64, device=fctx.mu_device)
+        return damps, dmu_v, None
 
 
 class Rollout:
@@ -109,7 +112,8 @@ class Rollout:
         self.segments = segment_bounds(self.n_steps, checkpoint)
 
     def u0(self, amps):
-        return (self.u_base + torch.tensordot(amps.to(self.basis.dtype), self.basis, dims=([0], [0]))).contiguous()
+        """u_base + sum_m amps[m] basis[m] (sllbm_superpose)."""
+        return self.sim.superpose(self.u_base, self.basis, amps.detach().cpu().tolist())
 
     def __call__(self, amps, mu_inf):
         mu = mu_inf if torch.is_tensor(mu_inf) else torch.tensor(float(mu_inf), dtype=torch.float64)

@@ -1035,4 +1035,38 @@ int sllbm_init_equilibrium_vjp(sllbm_ctx *ctx, const double *rho, const double *
     return check_launch(ctx, e, "init_equilibrium_vjp");
 }
 
+int sllbm_superpose(sllbm_ctx *ctx, const double *base, const double *basis, int32_t m, const double *amps,
+                    double *out)
+{
+    if (!ctx) return SLLBM_EINVAL;
+    if (!base || !out || (m > 0 && (!basis || !amps))) return fail(ctx, SLLBM_EINVAL, "NULL argument");
+    if (m < 0 || m > MAX_MODES) return fail(ctx, SLLBM_EINVAL, "mode count must be in 0..64");
+    DeviceGuard guard(ctx->cfg.device);
+    ModeAmplitudes am{};
+    for (int j = 0; j < m; ++j) am.a[j] = amps[j];
+    const int64_t n = static_cast<int64_t>(ctx->d2 ? 2 : 3) * ctx->geo.nodes;
+    return check_launch(ctx, launch_superpose(n, m, am, base, basis, out, ctx->stream), "superpose");
+}
+
+int sllbm_project(sllbm_ctx *ctx, const double *basis, int32_t m, const double *v, double *out)
+{
+    if (!ctx) return SLLBM_EINVAL;
+    if (!v || !out || (m > 0 && !basis)) return fail(ctx, SLLBM_EINVAL, "NULL argument");
+    if (m < 0 || m > MAX_MODES) return fail(ctx, SLLBM_EINVAL, "mode count must be in 0..64");
+    DeviceGuard guard(ctx->cfg.device);
+    const int64_t n = static_cast<int64_t>(ctx->d2 ? 2 : 3) * ctx->geo.nodes;
+    hipError_t e = hipSuccess;
+    for (int m0 = 0; m0 < m; m0 += 8) {
+        const int mc = std::min(8, m - m0);
+        if ((e = launch_project_chunk(n, m0, mc, basis, v, ctx->d_partials, RED_BLOCKS, ctx->d_small, ctx->stream)) !=
+            hipSuccess)
+            return hip_fail(ctx, e, "project");
+        if ((e = hipMemcpyAsync(out + m0, ctx->d_small, mc * sizeof(double), hipMemcpyDeviceToHost, ctx->stream)) !=
+            hipSuccess)
+            return hip_fail(ctx, e, "project copy");
+    }
+    if ((e = hipStreamSynchronize(ctx->stream)) != hipSuccess) return hip_fail(ctx, e, "project");
+    return SLLBM_OK;
+}
+
 }  // extern "C"

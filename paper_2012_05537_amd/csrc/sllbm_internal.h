@@ -190,6 +190,19 @@ struct Launch2D {
 
 // two-dimensional streaming (stream2d.hip): per (velocity, population)
 // plane, x-strips marching along y
+// Mode algebra of the gradient workload (modes.hip).
+constexpr int MAX_MODES = 64;
+struct ModeAmplitudes {
+    double a[MAX_MODES];
+};
+// out[k] = base[k] + sum_j am.a[j] basis[j n + k], k < n
+hipError_t launch_superpose(int64_t n, int m, const ModeAmplitudes &am, const double *base, const double *basis,
+                            double *out, hipStream_t st);
+// out8[j] = sum_k basis[(m0 + j) n + k] v[k] for j < mc <= 8 (deterministic;
+// partials holds nblocks * 8 doubles)
+hipError_t launch_project_chunk(int64_t n, int m0, int mc, const double *basis, const double *v, double *partials,
+                                int nblocks, double *out8, hipStream_t st);
+
 template <typename S>
 hipError_t launch_stream_2d(const Geometry &g, const CellTables<S> &t, const S *in, S *out, hipStream_t st);
 

@@ -78,6 +78,8 @@ _SIGS = {
     "sllbm_stream": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int32]),
     "sllbm_collide": (ctypes.c_int, [_VP, _VP]),
     "sllbm_totals_noalloc": (ctypes.c_int, [ctypes.POINTER(Config), _VP, _VP, _VP]),
+    "sllbm_superpose": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int32, _VP, _VP]),
+    "sllbm_project": (ctypes.c_int, [_VP, _VP, ctypes.c_int32, _VP, _VP]),
 }
 
 EXPORTED = tuple(_SIGS)
@@ -365,6 +367,28 @@ class SLLBM:
         self._check(self._lib.sllbm_init_equilibrium_vjp(self._h, _ptr(rho), _ptr(u), _ptr(T),
                                                          self._state_arg(lam0), _ptr(drho), _ptr(du), _ptr(dT)))
         return drho, du, dT
+
+    def superpose(self, base, basis, amps, out=None):
+        """base + sum_j amps[j] basis[j]: base (D, N), basis (M, D, N) device float64; amps M host values."""
+        self._sync_stream()
+        a = [float(x) for x in (amps.tolist() if hasattr(amps, "tolist") else amps)]
+        m = len(a)
+        if basis.shape[0] != m or base.numel() != self.dim * self.nodes or basis.numel() != m * base.numel():
+            raise ValueError("base (D, N), basis (M, D, N) and M amplitudes")
+        out = torch.empty_like(base) if out is None else out
+        arr = (ctypes.c_double * max(m, 1))(*a)
+        self._check(self._lib.sllbm_superpose(self._h, _ptr(base), _ptr(basis), m, ctypes.addressof(arr), _ptr(out)))
+        return out
+
+    def project(self, basis, v):
+        """[<basis[j], v>] over all D*N components, a list of M floats (host)."""
+        self._sync_stream()
+        m = basis.shape[0]
+        if v.numel() != self.dim * self.nodes or basis.numel() != m * v.numel():
+            raise ValueError("basis (M, D, N) and v (D, N)")
+        out = (ctypes.c_double * max(m, 1))()
+        self._check(self._lib.sllbm_project(self._h, _ptr(basis), m, _ptr(v), ctypes.addressof(out)))
+        return list(out)[:m]
 
     def stream(self, state, transpose=False, out=None):
         self._sync_stream()
