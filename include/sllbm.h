@@ -153,8 +153,11 @@ int sllbm_set_mesh(sllbm_ctx *ctx, const double *widths_x, const double *widths_
  * kept; node coordinates stay those of the reference grid.  The transposed
  * streaming (and so sllbm_adjoint_step) spreads every output's adjoint over
  * its support values with atomic adds (results reproducible to rounding, not
- * bit for bit); the loss, its gradient and the diagnostics return EINVAL on a
- * distorted mesh.  Synchronises the context's stream.
+ * bit for bit).  The loss, its gradient and the diagnostics take derivatives
+ * in physical coordinates through each cell's map (d u/d x = (d u/d r) J^-1,
+ * J = I + dD/dr at the cell's support points) and weight the quadrature with
+ * |det J|; J^-1 and |det J| of every cell point are uploaded here (80 bytes
+ * per cell point).  Synchronises the context's stream.
  * Errors: EINVAL (2-D context, graded cells, non-finite d, a cell map that
  * folds over (det J <= 0 at a support point), a departure search that does
  * not converge), ENOMEM, EDEVICE; on error the previous mesh stays. */

@@ -397,6 +397,28 @@ static void mapped_departure(const oracle_cfg *c, int gx, int gy, int gz, const 
     }
 }
 
+/* J = I + dD/dr of cell e at its support point k3, its inverse and |det J|
+ * (J = I, |det J| = 1 on undistorted meshes). */
+static void cell_point_jacobian(const oracle_cfg *c, const int *e, const int *k3, double Ji[3][3], double *adet)
+{
+    double tg[16], t[3], D[3], J[3][3];
+    oracle_glc_nodes(c->p, tg);
+    for (int a = 0; a < 3; ++a) t[a] = tg[k3[a]];
+    disp_cell(c, e, t, D, J);
+    double dt = det3(J);
+    /* inverse by cofactors: Ji[a][b] = cof(J)[b][a] / det J */
+    Ji[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) / dt;
+    Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / dt;
+    Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / dt;
+    Ji[1][0] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) / dt;
+    Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / dt;
+    Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / dt;
+    Ji[2][0] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) / dt;
+    Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / dt;
+    Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / dt;
+    *adet = fabs(dt);
+}
+
 /* Domain integral weights of a distorted mesh: per node, the sum over the
  * cells that hold it of the tensor Clenshaw-Curtis weight of its local point
  * times |det(I + dD/dr)| of that cell there.  w: [N]. */
@@ -859,7 +881,9 @@ void FN(totals)(const oracle_cfg *c, const R *f, const R *g, R *out)
  *       (1/2) rho |u|^2 + (div u)^2,
  * with div u from the derivative of each cell's own interpolation polynomial
  * (so it is discontinuous across cell faces, as in Sec. III C); on a graded
- * mesh each cell uses its own width. */
+ * mesh each cell uses its own width; on a distorted mesh the derivatives are
+ * taken in physical coordinates through the cell map (d u/d x = (d u/d r)
+ * J^-1, J = I + dD/dr) and every quadrature weight carries |det J|. */
 R FN(loss)(const oracle_cfg *c, const R *f, const R *g)
 {
     int p = c->p;
@@ -886,21 +910,28 @@ R FN(loss)(const oracle_cfg *c, const R *f, const R *g)
                             int k3[3] = {kx, ky, kz}, e3[3] = {ex, ey, ez};
                             long n = ((long)((ez * p + kz) % N[2]) * N[1] + (ey * p + ky) % N[1]) * N[0]
                                    + (ex * p + kx) % N[0];
-                            R div = 0;
-                            for (int a = 0; a < 3; ++a) {
-                                /* d u_a / d x_a along axis a inside this cell */
-                                R d = 0;
-                                for (int m = 0; m <= p; ++m) {
-                                    int gg[3] = {e3[0] * p + k3[0], e3[1] * p + k3[1], e3[2] * p + k3[2]};
-                                    gg[a] = e3[a] * p + m;
-                                    long nm = ((long)(gg[2] % N[2]) * N[1] + gg[1] % N[1]) * N[0] + gg[0] % N[0];
-                                    d += Dm[k3[a]][m] * u[(long)a * Nl + nm];
+                            /* reference gradient d u_a / d r_b inside this cell, then the
+                             * physical one through the cell map: d u / d x = (d u / d r) J^-1 */
+                            R gr[3][3];
+                            for (int a = 0; a < 3; ++a)
+                                for (int b = 0; b < 3; ++b) {
+                                    R d = 0;
+                                    for (int m = 0; m <= p; ++m) {
+                                        int gg[3] = {e3[0] * p + k3[0], e3[1] * p + k3[1], e3[2] * p + k3[2]};
+                                        gg[b] = e3[b] * p + m;
+                                        long nm = ((long)(gg[2] % N[2]) * N[1] + gg[1] % N[1]) * N[0] + gg[0] % N[0];
+                                        d += Dm[k3[b]][m] * u[(long)a * Nl + nm];
+                                    }
+                                    gr[a][b] = d / h[b];
                                 }
-                                div += d / h[a];
-                            }
+                            double Ji[3][3], adet;
+                            cell_point_jacobian(c, e3, k3, Ji, &adet);
+                            R div = 0;
+                            for (int a = 0; a < 3; ++a)
+                                for (int b = 0; b < 3; ++b) div += gr[a][b] * Ji[b][a];
                             R ke = 0;
                             for (int a = 0; a < 3; ++a) ke += u[(long)a * Nl + n] * u[(long)a * Nl + n];
-                            double W = (0.5 * h[0] * wcc[kx]) * (0.5 * h[1] * wcc[ky]) * (0.5 * h[2] * wcc[kz]);
+                            double W = (0.5 * h[0] * wcc[kx]) * (0.5 * h[1] * wcc[ky]) * (0.5 * h[2] * wcc[kz]) * adet;
                             L += W * (0.5 * rho[n] * ke + div * div);
                         }
             }
@@ -915,7 +946,8 @@ R FN(loss)(const oracle_cfg *c, const R *f, const R *g)
  *   out[1] = solenoidal dissipation int mu(T) |curl u|^2
  *   out[2] = dilatational dissipation (4/3) int mu(T) (div u)^2
  * (the paper's 1/(rho_ref Re) prefactor is the mu_inf inside mu(T)); on a
- * graded mesh each cell uses its own width. */
+ * graded mesh each cell uses its own width; on a distorted mesh derivatives
+ * and weights go through the cell map as in FN(loss). */
 void FN(diagnostics)(const oracle_cfg *c, const R *f, const R *g, R *out)
 {
     int p = c->p;
@@ -942,7 +974,7 @@ void FN(diagnostics)(const oracle_cfg *c, const R *f, const R *g, R *out)
                             int k3[3] = {kx, ky, kz}, e3[3] = {ex, ey, ez};
                             long n = ((long)((ez * p + kz) % N[2]) * N[1] + (ey * p + ky) % N[1]) * N[0]
                                    + (ex * p + kx) % N[0];
-                            R grad[3][3];             /* grad[a][b] = d u_a / d x_b inside this cell */
+                            R gr[3][3];               /* gr[a][b] = d u_a / d r_b inside this cell */
                             for (int a = 0; a < 3; ++a)
                                 for (int b = 0; b < 3; ++b) {
                                     R d = 0;
@@ -952,14 +984,20 @@ void FN(diagnostics)(const oracle_cfg *c, const R *f, const R *g, R *out)
                                         long nm = ((long)(gg[2] % N[2]) * N[1] + gg[1] % N[1]) * N[0] + gg[0] % N[0];
                                         d += Dm[k3[b]][m] * u[(long)a * Nl + nm];
                                     }
-                                    grad[a][b] = d / h[b];
+                                    gr[a][b] = d / h[b];
                                 }
+                            double Ji[3][3], adet;    /* cell map: d u / d x = (d u / d r) J^-1 */
+                            cell_point_jacobian(c, e3, k3, Ji, &adet);
+                            R grad[3][3];             /* grad[a][b] = d u_a / d x_b */
+                            for (int a = 0; a < 3; ++a)
+                                for (int b = 0; b < 3; ++b)
+                                    grad[a][b] = gr[a][0] * Ji[0][b] + gr[a][1] * Ji[1][b] + gr[a][2] * Ji[2][b];
                             R w0 = grad[2][1] - grad[1][2], w1 = grad[0][2] - grad[2][0], w2 = grad[1][0] - grad[0][1];
                             R div = grad[0][0] + grad[1][1] + grad[2][2];
                             R ke = 0;
                             for (int a = 0; a < 3; ++a) ke += u[(long)a * Nl + n] * u[(long)a * Nl + n];
                             R mu = mu_of_T(c, T[n]);
-                            double W = (0.5 * h[0] * wcc[kx]) * (0.5 * h[1] * wcc[ky]) * (0.5 * h[2] * wcc[kz]);
+                            double W = (0.5 * h[0] * wcc[kx]) * (0.5 * h[1] * wcc[ky]) * (0.5 * h[2] * wcc[kz]) * adet;
                             ek += W * 0.5 * rho[n] * ke;
                             es += W * mu * (w0 * w0 + w1 * w1 + w2 * w2);
                             ec += W * (4.0 / 3.0) * mu * div * div;

@@ -454,6 +454,8 @@ struct CellGeo {
     int64_t nodes;
     double h[3];                 // cell width per axis (equal cells)
     const double *hw;            // graded mesh: widths of the x, then y, then z cells (NULL: equal cells)
+    const double *jac;           // distorted mesh: per cell point J^-1 (row-major) and |det J| (NULL: J = I)
+    const double *full_w;        // distorted mesh: per-node quadrature weights (NULL: separable weights)
 };
 
 // width of cell e along axis a
@@ -494,14 +496,33 @@ __global__ void __launch_bounds__(256) k_loss_cells(CellGeo g, const double *__r
         const int gx = ex * p + kx, gy = ey * p + ky, gz = ez * p + kz;
         const double hx = cell_h(g, 0, ex), hy = cell_h(g, 1, ey), hz = cell_h(g, 2, ez);
         double div = 0.0;
-        for (int m = 0; m <= p; ++m) {
-            div += dmat[kx * p1 + m] * u[node_of(g, ex * p + m, gy, gz)] / hx;
-            div += dmat[ky * p1 + m] * u[g.nodes + node_of(g, gx, ey * p + m, gz)] / hy;
-            div += dmat[kz * p1 + m] * u[2 * g.nodes + node_of(g, gx, gy, ez * p + m)] / hz;
+        double W = (0.5 * hx * ccw[kx]) * (0.5 * hy * ccw[ky]) * (0.5 * hz * ccw[kz]);
+        if (!g.jac) {
+            for (int m = 0; m <= p; ++m) {
+                div += dmat[kx * p1 + m] * u[node_of(g, ex * p + m, gy, gz)] / hx;
+                div += dmat[ky * p1 + m] * u[g.nodes + node_of(g, gx, ey * p + m, gz)] / hy;
+                div += dmat[kz * p1 + m] * u[2 * g.nodes + node_of(g, gx, gy, ez * p + m)] / hz;
+            }
+        } else {
+            // distorted cell: div u = sum_ab (d u_a / d r_b) (J^-1)_ba
+            double gr[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+            for (int m = 0; m <= p; ++m) {
+                const int64_t nx = node_of(g, ex * p + m, gy, gz), ny = node_of(g, gx, ey * p + m, gz),
+                              nz = node_of(g, gx, gy, ez * p + m);
+                const double dx = dmat[kx * p1 + m] / hx, dy = dmat[ky * p1 + m] / hy, dz = dmat[kz * p1 + m] / hz;
+                for (int a = 0; a < 3; ++a) {
+                    gr[a][0] = fma(dx, u[a * g.nodes + nx], gr[a][0]);
+                    gr[a][1] = fma(dy, u[a * g.nodes + ny], gr[a][1]);
+                    gr[a][2] = fma(dz, u[a * g.nodes + nz], gr[a][2]);
+                }
+            }
+            const double *Ji = g.jac + c * 10;
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) div = fma(gr[a][b], Ji[b * 3 + a], div);
+            W *= Ji[9];
         }
         const int64_t n = node_of(g, gx, gy, gz);
         const double ux = u[n], uy = u[g.nodes + n], uz = u[2 * g.nodes + n];
-        const double W = (0.5 * hx * ccw[kx]) * (0.5 * hy * ccw[ky]) * (0.5 * hz * ccw[kz]);
         acc += W * (0.5 * rho[n] * (ux * ux + uy * uy + uz * uz) + div * div);
         if (sdiv) sdiv[c] = 2.0 * W * div;
     }
@@ -553,12 +574,23 @@ __global__ void __launch_bounds__(256) k_diag_cells(CellGeo g, CollisionParams c
                 grad[a][2] = fma(dz, u[a * g.nodes + nz], grad[a][2]);
             }
         }
+        double W = (0.5 * hx * ccw[k[0]]) * (0.5 * hy * ccw[k[1]]) * (0.5 * hz * ccw[k[2]]);
+        if (g.jac) {
+            // distorted cell: physical gradient (d u / d r) J^-1, weight times |det J|
+            const double *Ji = g.jac + c * 10;
+            double gp[3][3];
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b)
+                    gp[a][b] = grad[a][0] * Ji[b] + grad[a][1] * Ji[3 + b] + grad[a][2] * Ji[6 + b];
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) grad[a][b] = gp[a][b];
+            W *= Ji[9];
+        }
         const int64_t n = node_of(g, gx, gy, gz);
         const double w0 = grad[2][1] - grad[1][2], w1 = grad[0][2] - grad[2][0], w2 = grad[1][0] - grad[0][1];
         const double div = grad[0][0] + grad[1][1] + grad[2][2];
         const double ux = u[n], uy = u[g.nodes + n], uz = u[2 * g.nodes + n];
         const double mu = viscosity_of(cp, T[n]);
-        const double W = (0.5 * hx * ccw[k[0]]) * (0.5 * hy * ccw[k[1]]) * (0.5 * hz * ccw[k[2]]);
         acc[0] = fma(W, 0.5 * rho[n] * (ux * ux + uy * uy + uz * uz), acc[0]);
         acc[1] = fma(W, mu * (w0 * w0 + w1 * w1 + w2 * w2), acc[1]);
         acc[2] = fma(W, (4.0 / 3.0) * mu * div * div, acc[2]);
@@ -606,7 +638,7 @@ __global__ void __launch_bounds__(256) k_loss_grad(CellGeo g, const double *__re
     const int p = g.p, p1 = p + 1;
     const int gi[3] = {static_cast<int>(n % g.N[0]), static_cast<int>((n / g.N[0]) % g.N[1]),
                        static_cast<int>(n / (static_cast<int64_t>(g.N[0]) * g.N[1]))};
-    const double W = nodew[gi[0]] * nodew[g.N[0] + gi[1]] * nodew[g.N[0] + g.N[1] + gi[2]];
+    const double W = g.full_w ? g.full_w[n] : nodew[gi[0]] * nodew[g.N[0] + gi[1]] * nodew[g.N[0] + g.N[1] + gi[2]];
     const double r = rho[n];
     const double uu[3] = {u[n], u[g.nodes + n], u[2 * g.nodes + n]};
     double du[3];
@@ -624,25 +656,33 @@ __global__ void __launch_bounds__(256) k_loss_grad(CellGeo g, const double *__re
             nopt[a] = 2;
         }
     }
+    // component a of u enters div u at the cell points whose derivative
+    // stencil along axis d holds the node: on undistorted cells only d = a,
+    // on distorted cells every d, with the factor (J^-1)_da of the point
     for (int a = 0; a < 3; ++a) {
-        const int b = (a + 1) % 3, c = (a + 2) % 3;
         double s = 0.0;
-        for (int oa = 0; oa < nopt[a]; ++oa)             // cell along a and the node's index m in it
-            for (int ob = 0; ob < nopt[b]; ++ob)
-                for (int oc = 0; oc < nopt[c]; ++oc)
-                    for (int ka = 0; ka <= p; ++ka) {      // cell point along a
-                        int E[3], kk[3];
-                        E[a] = ce[a][oa];
-                        kk[a] = ka;
-                        E[b] = ce[b][ob];
-                        kk[b] = ck[b][ob];
-                        E[c] = ce[c][oc];
-                        kk[c] = ck[c][oc];
-                        const int64_t cp = ((static_cast<int64_t>(E[2]) * g.nel[1] + E[1]) * g.nel[0] + E[0]) *
-                                               (p1 * p1 * p1) +
-                                           (kk[2] * p1 + kk[1]) * p1 + kk[0];
-                        s += sdiv[cp] * dmat[ka * p1 + ck[a][oa]] / cell_h(g, a, E[a]);
-                    }
+        for (int d = 0; d < 3; ++d) {
+            if (!g.jac && d != a) continue;
+            const int b = (d + 1) % 3, c = (d + 2) % 3;
+            for (int od = 0; od < nopt[d]; ++od)           // cell along d and the node's index in it
+                for (int ob = 0; ob < nopt[b]; ++ob)
+                    for (int oc = 0; oc < nopt[c]; ++oc)
+                        for (int kd = 0; kd <= p; ++kd) {    // cell point along d
+                            int E[3], kk[3];
+                            E[d] = ce[d][od];
+                            kk[d] = kd;
+                            E[b] = ce[b][ob];
+                            kk[b] = ck[b][ob];
+                            E[c] = ce[c][oc];
+                            kk[c] = ck[c][oc];
+                            const int64_t cp =
+                                ((static_cast<int64_t>(E[2]) * g.nel[1] + E[1]) * g.nel[0] + E[0]) * (p1 * p1 * p1) +
+                                (kk[2] * p1 + kk[1]) * p1 + kk[0];
+                            double f = dmat[kd * p1 + ck[d][od]] / cell_h(g, d, E[d]);
+                            if (g.jac) f *= g.jac[cp * 10 + d * 3 + a];
+                            s += sdiv[cp] * f;
+                        }
+        }
         du[a] = r * uu[a] * W + s;
     }
     const double drho = 0.5 * (uu[0] * uu[0] + uu[1] * uu[1] + uu[2] * uu[2]) * W -
@@ -660,7 +700,8 @@ __global__ void __launch_bounds__(256) k_loss_grad(CellGeo g, const double *__re
 // Launchers
 // ---------------------------------------------------------------------------
 
-static CellGeo cell_geo(const Geometry &g, const double *hh, const double *hw)
+static CellGeo cell_geo(const Geometry &g, const double *hh, const double *hw, const double *jac = nullptr,
+                        const double *full_w = nullptr)
 {
     CellGeo c;
     for (int a = 0; a < 3; ++a) {
@@ -669,6 +710,8 @@ static CellGeo cell_geo(const Geometry &g, const double *hh, const double *hw)
         c.h[a] = hh[a];
     }
     c.hw = hw;
+    c.jac = jac;
+    c.full_w = full_w;
     c.p = g.p;
     c.nodes = g.nodes;
     return c;
@@ -676,16 +719,15 @@ static CellGeo cell_geo(const Geometry &g, const double *hh, const double *hw)
 
 template <typename S>
 hipError_t Launch<S>::loss(const Geometry &g, const S *state, const double *dmat, const double *ccw, const double *h,
-                           const double *hw, double *scratch_rho, double *scratch_u, double *partials, int nblocks,
-                           double *out1,
-                           hipStream_t st)
+                           const double *hw, const double *cjac, double *scratch_rho, double *scratch_u,
+                           double *partials, int nblocks, double *out1, hipStream_t st)
 {
     const unsigned nb = static_cast<unsigned>((g.nodes + 255) / 256);
     hipLaunchKernelGGL((k_rho_u<S>), dim3(nb), dim3(256), 0, st, g.nodes, state, scratch_rho, scratch_u);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_loss_cells, dim3(nblocks), dim3(256), 0, st, cell_geo(g, h, hw), dmat, ccw, scratch_rho,
-                       scratch_u, static_cast<double *>(nullptr), partials);
+    hipLaunchKernelGGL(k_loss_cells, dim3(nblocks), dim3(256), 0, st, cell_geo(g, h, hw, cjac), dmat, ccw,
+                       scratch_rho, scratch_u, static_cast<double *>(nullptr), partials);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_accumulate, dim3(1), dim3(256), 0, st, partials, nblocks, out1, 0);
     return hipGetLastError();
@@ -693,32 +735,33 @@ hipError_t Launch<S>::loss(const Geometry &g, const S *state, const double *dmat
 
 template <typename S>
 hipError_t Launch<S>::loss_grad(const Geometry &g, const S *state, const double *dmat, const double *ccw,
-                                const double *nodew, const double *h, const double *hw, double *scratch_rho,
-                                double *scratch_u, double *scratch_div, double *partials, int nblocks, S *lam,
-                                hipStream_t st)
+                                const double *nodew, const double *h, const double *hw, const double *cjac,
+                                const double *full_w, double *scratch_rho, double *scratch_u, double *scratch_div,
+                                double *partials, int nblocks, S *lam, hipStream_t st)
 {
     const unsigned nb = static_cast<unsigned>((g.nodes + 255) / 256);
     hipLaunchKernelGGL((k_rho_u<S>), dim3(nb), dim3(256), 0, st, g.nodes, state, scratch_rho, scratch_u);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_loss_cells, dim3(nblocks), dim3(256), 0, st, cell_geo(g, h, hw), dmat, ccw, scratch_rho,
-                       scratch_u, scratch_div, partials);
+    const CellGeo cg = cell_geo(g, h, hw, cjac, full_w);
+    hipLaunchKernelGGL(k_loss_cells, dim3(nblocks), dim3(256), 0, st, cg, dmat, ccw, scratch_rho, scratch_u,
+                       scratch_div, partials);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL((k_loss_grad<S>), dim3(nb), dim3(256), 0, st, cell_geo(g, h, hw), dmat, nodew, scratch_rho,
-                       scratch_u, scratch_div, lam);
+    hipLaunchKernelGGL((k_loss_grad<S>), dim3(nb), dim3(256), 0, st, cg, dmat, nodew, scratch_rho, scratch_u,
+                       scratch_div, lam);
     return hipGetLastError();
 }
 
 template <typename S>
 hipError_t Launch<S>::diagnostics(const Geometry &g, const CollisionParams &cp, const S *state, const double *dmat,
-                                  const double *ccw, const double *h, const double *hw, double *scratch_rho,
-                                  double *scratch_u, double *scratch_T, double *partials, int nblocks, double *out3,
-                                  hipStream_t st)
+                                  const double *ccw, const double *h, const double *hw, const double *cjac,
+                                  double *scratch_rho, double *scratch_u, double *scratch_T, double *partials,
+                                  int nblocks, double *out3, hipStream_t st)
 {
     hipError_t e = moments(g, cp, state, scratch_rho, scratch_u, scratch_T, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_diag_cells, dim3(nblocks), dim3(256), 0, st, cell_geo(g, h, hw), cp, dmat, ccw, scratch_rho,
-                       scratch_u, scratch_T, partials);
+    hipLaunchKernelGGL(k_diag_cells, dim3(nblocks), dim3(256), 0, st, cell_geo(g, h, hw, cjac), cp, dmat, ccw,
+                       scratch_rho, scratch_u, scratch_T, partials);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_sum3, dim3(1), dim3(256), 0, st, partials, nblocks, out3);
     return hipGetLastError();

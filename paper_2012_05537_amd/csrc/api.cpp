@@ -68,6 +68,9 @@ struct sllbm_ctx {
     int32_t *d_mcell = nullptr;
     void *d_mt = nullptr;          // local coordinates, storage type
     double *d_mw = nullptr;
+    double *d_cjac = nullptr;      // per cell point J^-1 and |det J| of the cell map (loss, diagnostics)
+    int32_t *d_mwin = nullptr;     // per (velocity, node tile) source window of the streaming
+    int mwin_nodes = 0;            // largest staged window (nodes per population)
     GlcBasis glc{};
     std::string err;
 };
@@ -130,6 +133,8 @@ void free_ctx(sllbm_ctx *c)
     (void)hipFree(c->d_mcell);
     (void)hipFree(c->d_mt);
     (void)hipFree(c->d_mw);
+    (void)hipFree(c->d_cjac);
+    (void)hipFree(c->d_mwin);
     (void)hipFree(c->d_omin);
     (void)hipFree(c->d_lstar);
     (void)hipFree(c->d_cw);
@@ -199,12 +204,18 @@ int refuse_2d(sllbm_ctx *c, const char *what)
 
 // calls defined for axis-aligned cells only (transposed streaming and what
 // builds on it, derivatives of the flow fields)
+// per cell point J^-1 and |det J| of a distorted mesh (NULL otherwise)
+const double *mapped_jac(const sllbm_ctx *c) { return c->mapped ? c->d_cjac : nullptr; }
+
 int refuse_mapped(sllbm_ctx *c, const char *what)
 {
     return fail(c, SLLBM_EINVAL, std::string(what) + " is not available on a distorted mesh");
 }
 
-MappedTables mapped_tables(const sllbm_ctx *c) { return MappedTables{c->d_mcell, c->d_mt, c->glc}; }
+MappedTables mapped_tables(const sllbm_ctx *c)
+{
+    return MappedTables{c->d_mcell, c->d_mt, c->glc, c->d_mwin, c->mwin_nodes};
+}
 
 const double *graded_hw(const sllbm_ctx *c) { return c->graded ? c->d_hw : nullptr; }
 
@@ -556,9 +567,14 @@ int sllbm_set_displacement(sllbm_ctx *ctx, const double *d)
         (void)hipFree(ctx->d_mcell);
         (void)hipFree(ctx->d_mt);
         (void)hipFree(ctx->d_mw);
+        (void)hipFree(ctx->d_cjac);
+        (void)hipFree(ctx->d_mwin);
         ctx->d_mcell = nullptr;
         ctx->d_mt = nullptr;
         ctx->d_mw = nullptr;
+        ctx->d_cjac = nullptr;
+        ctx->d_mwin = nullptr;
+        ctx->mwin_nodes = 0;
         ctx->mapped = false;
     };
     if (!d) {
@@ -569,14 +585,18 @@ int sllbm_set_displacement(sllbm_ctx *ctx, const double *d)
     for (int64_t k = 0; k < 3 * N; ++k)
         if (!std::isfinite(d[k])) return fail(ctx, SLLBM_EINVAL, "set_displacement: non-finite displacement");
     std::vector<int32_t> cell;
-    std::vector<double> tloc, nodew;
+    std::vector<double> tloc, nodew, cjac;
     std::string why;
     if (!build_mapped_tables(ctx->vs, ctx->geo.p, ctx->geo.nel, ctx->cfg.length, d, ctx->cfg.dt, cell, tloc, nodew,
-                             why))
+                             cjac, why))
         return fail(ctx, SLLBM_EINVAL, why);
-    int32_t *dc = nullptr;
+    std::vector<int32_t> mwin;
+    const int tile[3] = {MAPPED_TX, MAPPED_TY, MAPPED_TZ};
+    const int win_nodes = build_mapped_windows(ctx->vs.q, ctx->geo.p, ctx->geo.nel, cell, tile,
+                                               MAPPED_WINDOW_BYTES / (2 * static_cast<int>(ctx->elem)), mwin);
+    int32_t *dc = nullptr, *dwin = nullptr;
     void *dt = nullptr;
-    double *dw = nullptr;
+    double *dw = nullptr, *dj = nullptr;
     // local coordinates in the storage type
     std::vector<float> tloc32;
     const void *tsrc = tloc.data();
@@ -587,24 +607,35 @@ int sllbm_set_displacement(sllbm_ctx *ctx, const double *d)
     const size_t tbytes = tloc.size() * ctx->elem;
     if ((e = dalloc(&dc, cell.size() * sizeof(int32_t))) != hipSuccess ||
         (e = hipMalloc(&dt, tbytes)) != hipSuccess ||
-        (e = dalloc(&dw, nodew.size() * sizeof(double))) != hipSuccess) {
+        (e = dalloc(&dw, nodew.size() * sizeof(double))) != hipSuccess ||
+        (e = dalloc(&dj, cjac.size() * sizeof(double))) != hipSuccess ||
+        (e = dalloc(&dwin, mwin.size() * sizeof(int32_t))) != hipSuccess) {
         (void)hipFree(dc);
         (void)hipFree(dt);
         (void)hipFree(dw);
+        (void)hipFree(dj);
+        (void)hipFree(dwin);
         return fail(ctx, SLLBM_ENOMEM, std::string("distorted-mesh tables: ") + hipGetErrorString(e));
     }
     if ((e = hipMemcpy(dc, cell.data(), cell.size() * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(dt, tsrc, tbytes, hipMemcpyHostToDevice)) != hipSuccess ||
-        (e = hipMemcpy(dw, nodew.data(), nodew.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess) {
+        (e = hipMemcpy(dw, nodew.data(), nodew.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(dj, cjac.data(), cjac.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(dwin, mwin.data(), mwin.size() * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess) {
         (void)hipFree(dc);
         (void)hipFree(dt);
         (void)hipFree(dw);
+        (void)hipFree(dj);
+        (void)hipFree(dwin);
         return hip_fail(ctx, e, "distorted-mesh table upload");
     }
     drop();
     ctx->d_mcell = dc;
     ctx->d_mt = dt;
     ctx->d_mw = dw;
+    ctx->d_cjac = dj;
+    ctx->d_mwin = dwin;
+    ctx->mwin_nodes = win_nodes;
     const int p = ctx->geo.p;
     glc_points(p, ctx->glc.t);
     for (int k = 0; k <= p; ++k) {
@@ -926,15 +957,14 @@ int sllbm_loss(sllbm_ctx *ctx, const void *state, double *out)
     if (!ctx) return SLLBM_EINVAL;
     if (!state || !out) return fail(ctx, SLLBM_EINVAL, "NULL argument");
     if (ctx->d2) return refuse_2d(ctx, "sllbm_loss");
-    if (ctx->mapped) return refuse_mapped(ctx, "sllbm_loss");
     DeviceGuard guard(ctx->cfg.device);
     hipError_t e = is_fp64(ctx)
         ? Launch<double>::loss(ctx->geo, static_cast<const double *>(state), ctx->d_dmat, ctx->d_ccw, ctx->h,
-                               graded_hw(ctx), ctx->d_scr_rho, ctx->d_scr_u, ctx->d_partials, RED_BLOCKS, ctx->d_small,
-                               ctx->stream)
+                               graded_hw(ctx), mapped_jac(ctx), ctx->d_scr_rho, ctx->d_scr_u, ctx->d_partials,
+                               RED_BLOCKS, ctx->d_small, ctx->stream)
         : Launch<float>::loss(ctx->geo, static_cast<const float *>(state), ctx->d_dmat, ctx->d_ccw, ctx->h,
-                              graded_hw(ctx), ctx->d_scr_rho, ctx->d_scr_u, ctx->d_partials, RED_BLOCKS, ctx->d_small,
-                              ctx->stream);
+                              graded_hw(ctx), mapped_jac(ctx), ctx->d_scr_rho, ctx->d_scr_u, ctx->d_partials,
+                              RED_BLOCKS, ctx->d_small, ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "loss");
     if ((e = hipMemcpyAsync(out, ctx->d_small, sizeof(double), hipMemcpyDeviceToHost, ctx->stream)) != hipSuccess ||
         (e = hipStreamSynchronize(ctx->stream)) != hipSuccess)
@@ -948,17 +978,16 @@ int sllbm_diagnostics(sllbm_ctx *ctx, const void *state, double *out)
     if (!ctx) return SLLBM_EINVAL;
     if (!out) return fail(ctx, SLLBM_EINVAL, "NULL out");
     if (ctx->d2) return refuse_2d(ctx, "sllbm_diagnostics");
-    if (ctx->mapped) return refuse_mapped(ctx, "sllbm_diagnostics");
     if (!state && !ctx->has_state) return fail(ctx, SLLBM_ESTATE, "no state set");
     DeviceGuard guard(ctx->cfg.device);
     const void *st = state ? state : ctx->buf[ctx->cur];
     hipError_t e = is_fp64(ctx)
         ? Launch<double>::diagnostics(ctx->geo, ctx->cp, static_cast<const double *>(st), ctx->d_dmat, ctx->d_ccw,
-                                      ctx->h, graded_hw(ctx), ctx->d_scr_rho, ctx->d_scr_u, ctx->d_scr_T,
-                                      ctx->d_partials, RED_BLOCKS, ctx->d_small, ctx->stream)
+                                      ctx->h, graded_hw(ctx), mapped_jac(ctx), ctx->d_scr_rho, ctx->d_scr_u,
+                                      ctx->d_scr_T, ctx->d_partials, RED_BLOCKS, ctx->d_small, ctx->stream)
         : Launch<float>::diagnostics(ctx->geo, ctx->cp, static_cast<const float *>(st), ctx->d_dmat, ctx->d_ccw,
-                                     ctx->h, graded_hw(ctx), ctx->d_scr_rho, ctx->d_scr_u, ctx->d_scr_T,
-                                     ctx->d_partials, RED_BLOCKS, ctx->d_small, ctx->stream);
+                                     ctx->h, graded_hw(ctx), mapped_jac(ctx), ctx->d_scr_rho, ctx->d_scr_u,
+                                     ctx->d_scr_T, ctx->d_partials, RED_BLOCKS, ctx->d_small, ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "diagnostics");
     if ((e = hipMemcpyAsync(out, ctx->d_small, 3 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream)) !=
             hipSuccess ||
@@ -974,17 +1003,16 @@ int sllbm_loss_grad(sllbm_ctx *ctx, const void *state, void *lam)
     if (!ctx) return SLLBM_EINVAL;
     if (!state || !lam || state == lam) return fail(ctx, SLLBM_EINVAL, "bad loss_grad buffers");
     if (ctx->d2) return refuse_2d(ctx, "sllbm_loss_grad");
-    if (ctx->mapped) return refuse_mapped(ctx, "sllbm_loss_grad");
     DeviceGuard guard(ctx->cfg.device);
     hipError_t e = is_fp64(ctx)
         ? Launch<double>::loss_grad(ctx->geo, static_cast<const double *>(state), ctx->d_dmat, ctx->d_ccw,
-                                    ctx->d_nodew, ctx->h, graded_hw(ctx), ctx->d_scr_rho, ctx->d_scr_u,
-                                    ctx->d_scr_div, ctx->d_partials, RED_BLOCKS, static_cast<double *>(lam),
-                                    ctx->stream)
+                                    ctx->d_nodew, ctx->h, graded_hw(ctx), mapped_jac(ctx),
+                                    ctx->mapped ? ctx->d_mw : nullptr, ctx->d_scr_rho, ctx->d_scr_u, ctx->d_scr_div,
+                                    ctx->d_partials, RED_BLOCKS, static_cast<double *>(lam), ctx->stream)
         : Launch<float>::loss_grad(ctx->geo, static_cast<const float *>(state), ctx->d_dmat, ctx->d_ccw,
-                                   ctx->d_nodew, ctx->h, graded_hw(ctx), ctx->d_scr_rho, ctx->d_scr_u,
-                                   ctx->d_scr_div, ctx->d_partials, RED_BLOCKS, static_cast<float *>(lam),
-                                   ctx->stream);
+                                   ctx->d_nodew, ctx->h, graded_hw(ctx), mapped_jac(ctx),
+                                   ctx->mapped ? ctx->d_mw : nullptr, ctx->d_scr_rho, ctx->d_scr_u, ctx->d_scr_div,
+                                   ctx->d_partials, RED_BLOCKS, static_cast<float *>(lam), ctx->stream);
     return check_launch(ctx, e, "loss_grad");
 }
 

@@ -68,9 +68,22 @@ void build_transposed_node_tables(int N, int p, const std::vector<int32_t> &src,
 // tloc[(a*q + i)*N + n]; the quadrature weight of every node (|det J| of the
 // cells that hold it) in nodew.  false (with why) if a cell map folds over or
 // a departure search does not converge.
+// Source windows of the distorted-mesh streaming (MAPPED_TILE node tiles, x
+// fastest): per velocity and tile, the departure cells of the tile's nodes
+// unwrapped next to each node's own cell span [lo, hi] per axis; win holds
+// the origin cell lo (wrapped) per axis and the window size in nodes
+// ((hi - lo + 1) p + 1 per axis) packed as nx | ny << 10 | nz << 20, or 0 if
+// the window exceeds max_nodes (that block gathers from global memory).
+// Returns the largest window (nodes) of the blocks that stage one.
+int build_mapped_windows(int q, int p, const int ne[3], const std::vector<int32_t> &cell, const int tile[3],
+                         int max_nodes, std::vector<int32_t> &win);
+
+// cjac: per cell point (cells x fastest, points x fastest within a cell) the
+// inverse of the cell map's Jacobian J = I + dD/dr (9 values, row-major) and
+// |det J|, for derivatives and quadrature in physical coordinates
 bool build_mapped_tables(const VelocitySet &vs, int p, const int ne[3], const double length[3], const double *d,
                          double dt, std::vector<int32_t> &cell, std::vector<double> &tloc, std::vector<double> &nodew,
-                         std::string &why);
+                         std::vector<double> &cjac, std::string &why);
 
 // ---------------------------------------------------------------------------
 // Device-side parameter blocks (passed by value to kernels)
@@ -118,10 +131,17 @@ struct GlcBasis {
 // Device tables of a distorted mesh (build_mapped_tables); the local
 // coordinates are kept in the storage type (FP32 contexts: 16 bytes per
 // velocity and node instead of 28)
+// Node tiles of the distorted-mesh streaming: one block per (tile, velocity)
+// stages the source window of its departure cells in LDS.
+constexpr int MAPPED_TX = 8, MAPPED_TY = 8, MAPPED_TZ = 4;   // 256 nodes
+constexpr int MAPPED_WINDOW_BYTES = 48 * 1024;                // LDS for the f and g windows of a block
+
 struct MappedTables {
     const int32_t *cell;    // [Q][N] departure cell, x fastest
     const void *tloc;       // [3][Q][N] local coordinates in [0, 1), storage type
     GlcBasis basis;
+    const int32_t *win;     // [Q][tiles][4] source window per (velocity, tile), or NULL
+    int win_nodes;          // largest window (nodes per population) of the blocks that use LDS
 };
 
 struct CollisionParams {
@@ -151,19 +171,22 @@ struct Launch {
     static hipError_t totals(const Geometry &g, const CollisionParams &cp, const S *state,
                              const double *nodew, const double *full_w, double *partials, int nblocks, double *out5,
                              hipStream_t st);
-    // h: cell width per axis; hw: graded cell widths (x, then y, then z cells) or NULL
+    // h: cell width per axis; hw: graded cell widths (x, then y, then z cells) or NULL;
+    // cjac: distorted mesh, per cell point J^-1 (9, row-major) and |det J| of the
+    // cell map (build_mapped_tables), or NULL; full_w: per-node weights of a
+    // distorted mesh (NULL: the separable nodew)
     static hipError_t loss(const Geometry &g, const S *state, const double *dmat, const double *ccw,
-                           const double *h, const double *hw, double *scratch_rho, double *scratch_u,
-                           double *partials, int nblocks, double *out1, hipStream_t st);
+                           const double *h, const double *hw, const double *cjac, double *scratch_rho,
+                           double *scratch_u, double *partials, int nblocks, double *out1, hipStream_t st);
     static hipError_t loss_grad(const Geometry &g, const S *state, const double *dmat, const double *ccw,
-                                const double *nodew, const double *h, const double *hw, double *scratch_rho,
-                                double *scratch_u, double *scratch_div, double *partials, int nblocks, S *lam,
-                                hipStream_t st);
+                                const double *nodew, const double *h, const double *hw, const double *cjac,
+                                const double *full_w, double *scratch_rho, double *scratch_u, double *scratch_div,
+                                double *partials, int nblocks, S *lam, hipStream_t st);
     // kinetic energy, solenoidal and dilatational dissipation (device out3)
     static hipError_t diagnostics(const Geometry &g, const CollisionParams &cp, const S *state, const double *dmat,
-                                  const double *ccw, const double *h, const double *hw, double *scratch_rho,
-                                  double *scratch_u, double *scratch_T, double *partials, int nblocks, double *out3,
-                                  hipStream_t st);
+                                  const double *ccw, const double *h, const double *hw, const double *cjac,
+                                  double *scratch_rho, double *scratch_u, double *scratch_T, double *partials,
+                                  int nblocks, double *out3, hipStream_t st);
     // lam <- J_C(X_n)^T lam in place; dL/dmu_inf added to *dmu if not NULL
     static hipError_t collide_vjp(const Geometry &g, const CollisionParams &cp, const S *state_n, S *lam,
                                   double *dmu_partials, int nblocks, double *dmu, hipStream_t st);

@@ -105,6 +105,117 @@ __global__ void __launch_bounds__(256) k_stream_mapped(Geometry g, GlcBasis gb, 
     out[static_cast<int64_t>(Q + i) * N + n] = sg;
 }
 
+// The same streaming with the source values staged in LDS: a block owns one
+// velocity and a tile of MAPPED_TX x MAPPED_TY x MAPPED_TZ nodes; the host
+// has found the box of cells that holds the departure cells of all of them
+// (build_mapped_windows), the block loads that window of f and g once
+// (coalesced rows, each value once from L2 instead of once per reading
+// thread through L1), and every thread gathers its (P+1)^3 support values
+// from LDS.  A block whose window exceeds the LDS budget gathers from global
+// memory instead; both paths sum in the same order, so they give the same
+// bits.
+template <typename S, int P>
+__global__ void __launch_bounds__(256) k_stream_mapped_win(Geometry g, GlcBasis gb, const int32_t *__restrict__ cell,
+                                                           const S *__restrict__ tloc, const int32_t *__restrict__ win,
+                                                           int ntx, int nty, const S *__restrict__ in,
+                                                           S *__restrict__ out)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int i = blockIdx.y;
+    const int t = blockIdx.x;
+    const int ntiles = static_cast<int>(gridDim.x);
+    const int64_t N = g.nodes;
+    const int Nx = g.N[0], Ny = g.N[1], Nz = g.N[2];
+    const int32_t *w = win + (static_cast<int64_t>(i) * ntiles + t) * 4;
+    const int ocx = w[0], ocy = w[1], ocz = w[2], dims = w[3];
+    const int gx = (t % ntx) * MAPPED_TX + (threadIdx.x % MAPPED_TX);
+    const int gy = ((t / ntx) % nty) * MAPPED_TY + (threadIdx.x / MAPPED_TX) % MAPPED_TY;
+    const int gz = (t / (ntx * nty)) * MAPPED_TZ + threadIdx.x / (MAPPED_TX * MAPPED_TY);
+    const bool own = gx < Nx && gy < Ny && gz < Nz;
+    const S *fi = in + static_cast<int64_t>(i) * N;
+    const S *gi = in + static_cast<int64_t>(Q + i) * N;
+    const int wx = dims & 1023, wy = (dims >> 10) & 1023, wz = dims >> 20;
+    S *lf = reinterpret_cast<S *>(smem);
+    S *lg = lf + wx * wy * wz;
+    if (dims != 0) {
+        const int wt = wx * wy * wz;
+        const int ox = ocx * P, oy = ocy * P, oz = ocz * P;
+        for (int k = threadIdx.x; k < wt; k += blockDim.x) {
+            const int x = k % wx, r = k / wx;
+            const int y = r % wy, z = r / wy;
+            const int64_t node = (static_cast<int64_t>((oz + z) % Nz) * Ny + (oy + y) % Ny) * Nx + (ox + x) % Nx;
+            lf[k] = fi[node];
+            lg[k] = gi[node];
+        }
+        __syncthreads();
+    }
+    if (!own) return;
+    const int64_t n = (static_cast<int64_t>(gz) * Ny + gy) * Nx + gx;
+    const int c = cell[static_cast<int64_t>(i) * N + n];
+    const int ex = c % g.nel[0], rest = c / g.nel[0];
+    const int ey = rest % g.nel[1], ez = rest / g.nel[1];
+    S wt3[3][P + 1];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double tt = static_cast<double>(tloc[(static_cast<int64_t>(a) * Q + i) * N + n]);
+#pragma unroll
+        for (int k = 0; k <= P; ++k) {
+            double v = gb.inv_den[k];
+#pragma unroll
+            for (int m = 0; m <= P; ++m)
+                if (m != k) v *= tt - gb.t[m];
+            wt3[a][k] = static_cast<S>(v);
+        }
+    }
+    S sf = 0, sg = 0;
+    if (dims != 0) {
+        int bx = ex - ocx, by = ey - ocy, bz = ez - ocz;       // the departure cell inside the window
+        bx += bx < 0 ? g.nel[0] : 0;
+        by += by < 0 ? g.nel[1] : 0;
+        bz += bz < 0 ? g.nel[2] : 0;
+#pragma unroll
+        for (int kz = 0; kz <= P; ++kz)
+#pragma unroll
+            for (int ky = 0; ky <= P; ++ky) {
+                const int base = ((bz * P + kz) * wy + by * P + ky) * wx + bx * P;
+                S af = 0, ag = 0;
+#pragma unroll
+                for (int kx = 0; kx <= P; ++kx) {
+                    af = fma(wt3[0][kx], lf[base + kx], af);
+                    ag = fma(wt3[0][kx], lg[base + kx], ag);
+                }
+                const S wyz = wt3[1][ky] * wt3[2][kz];
+                sf = fma(wyz, af, sf);
+                sg = fma(wyz, ag, sg);
+            }
+    } else {
+#pragma unroll
+        for (int kz = 0; kz <= P; ++kz) {
+            int zz = ez * P + kz;
+            zz = zz >= Nz ? zz - Nz : zz;
+#pragma unroll
+            for (int ky = 0; ky <= P; ++ky) {
+                int yy = ey * P + ky;
+                yy = yy >= Ny ? yy - Ny : yy;
+                const int64_t row = (static_cast<int64_t>(zz) * Ny + yy) * Nx;
+                S af = 0, ag = 0;
+#pragma unroll
+                for (int kx = 0; kx <= P; ++kx) {
+                    int xx = ex * P + kx;
+                    xx = xx >= Nx ? xx - Nx : xx;
+                    af = fma(wt3[0][kx], fi[row + xx], af);
+                    ag = fma(wt3[0][kx], gi[row + xx], ag);
+                }
+                const S wyz = wt3[1][ky] * wt3[2][kz];
+                sf = fma(wyz, af, sf);
+                sg = fma(wyz, ag, sg);
+            }
+        }
+    }
+    out[static_cast<int64_t>(i) * N + n] = sf;
+    out[static_cast<int64_t>(Q + i) * N + n] = sg;
+}
+
 // Transposed streaming S^T on a distorted mesh: each (velocity, node) output
 // of S spreads its adjoint over the (P+1)^3 support values it was gathered
 // from, with the same weights.  The departure cells of different nodes
@@ -191,6 +302,16 @@ hipError_t launch_mt(const Geometry &g, const MappedTables &t, const S *in, S *o
 template <typename S, int P>
 hipError_t launch_m(const Geometry &g, const MappedTables &t, const S *in, S *out, hipStream_t st)
 {
+    if (t.win) {
+        const int ntx = (g.N[0] + MAPPED_TX - 1) / MAPPED_TX, nty = (g.N[1] + MAPPED_TY - 1) / MAPPED_TY,
+                  ntz = (g.N[2] + MAPPED_TZ - 1) / MAPPED_TZ;
+        const int64_t ntiles = static_cast<int64_t>(ntx) * nty * ntz;
+        if (ntiles > (int64_t(1) << 31) - 1) return hipErrorInvalidValue;
+        const size_t lds = 2 * static_cast<size_t>(t.win_nodes) * sizeof(S);
+        hipLaunchKernelGGL((k_stream_mapped_win<S, P>), dim3(static_cast<unsigned>(ntiles), Q), dim3(256), lds, st,
+                           g, t.basis, t.cell, static_cast<const S *>(t.tloc), t.win, ntx, nty, in, out);
+        return hipGetLastError();
+    }
     const int64_t bx = (g.nodes + 255) / 256;
     if (bx > (int64_t(1) << 31) - 1) return hipErrorInvalidValue;
     constexpr int V = 16 / sizeof(S);

@@ -9,6 +9,7 @@
 // tensor product of three 1-D operators, each described by p rows of (p+1)
 // taps; these rows are all that is stored.
 #include <algorithm>
+#include <climits>
 #include <atomic>
 #include <cstdint>
 #include <cmath>
@@ -303,7 +304,7 @@ void locate(const MapGrid &m, const double r[3], int e[3], double t[3])
 
 bool build_mapped_tables(const VelocitySet &vs, int p, const int ne[3], const double length[3], const double *d,
                          double dt, std::vector<int32_t> &cell, std::vector<double> &tloc, std::vector<double> &nodew,
-                         std::string &why)
+                         std::vector<double> &cjac, std::string &why)
 {
     MapGrid m{};
     m.p = p;
@@ -318,8 +319,12 @@ bool build_mapped_tables(const VelocitySet &vs, int p, const int ne[3], const do
     double tg[MAXP + 1], cc[MAXP + 1];
     glc_points(p, tg);
     clenshaw_curtis(p, cc);
-    // node weights, with the check that every cell map keeps its orientation
+    // node weights, with the check that every cell map keeps its orientation;
+    // per cell point (cells x fastest, points x fastest within a cell) the
+    // inverse of J = I + dD/dr (row-major) and |det J|
     nodew.assign(N, 0.0);
+    cjac.clear();
+    cjac.reserve(static_cast<size_t>(ne[0]) * ne[1] * ne[2] * (p + 1) * (p + 1) * (p + 1) * 10);
     for (int ez = 0; ez < ne[2]; ++ez)
         for (int ey = 0; ey < ne[1]; ++ey)
             for (int ex = 0; ex < ne[0]; ++ex)
@@ -338,6 +343,18 @@ bool build_mapped_tables(const VelocitySet &vs, int p, const int ne[3], const do
                             const int64_t node = ((static_cast<int64_t>(ez * p + kz) % m.N[2]) * m.N[1] +
                                                   (ey * p + ky) % m.N[1]) * m.N[0] + (ex * p + kx) % m.N[0];
                             nodew[node] += 0.125 * m.h[0] * m.h[1] * m.h[2] * cc[kx] * cc[ky] * cc[kz] * dj;
+                            // inverse by cofactors: Ji[a][b] = cof(J)[b][a] / det J
+                            const double Ji[9] = {(J[1][1] * J[2][2] - J[1][2] * J[2][1]) / dj,
+                                                  (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / dj,
+                                                  (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / dj,
+                                                  (J[1][2] * J[2][0] - J[1][0] * J[2][2]) / dj,
+                                                  (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / dj,
+                                                  (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / dj,
+                                                  (J[1][0] * J[2][1] - J[1][1] * J[2][0]) / dj,
+                                                  (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / dj,
+                                                  (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / dj};
+                            cjac.insert(cjac.end(), Ji, Ji + 9);
+                            cjac.push_back(dj);
                         }
     // departure search, per velocity and node; velocities are split over up to
     // 16 host threads, each writing the slices of its own velocities
@@ -408,6 +425,56 @@ bool build_mapped_tables(const VelocitySet &vs, int p, const int ne[3], const do
         return false;
     }
     return true;
+}
+
+int build_mapped_windows(int q, int p, const int ne[3], const std::vector<int32_t> &cell, const int tile[3],
+                         int max_nodes, std::vector<int32_t> &win)
+{
+    const int N[3] = {ne[0] * p, ne[1] * p, ne[2] * p};
+    const int64_t nodes = static_cast<int64_t>(N[0]) * N[1] * N[2];
+    const int nt[3] = {(N[0] + tile[0] - 1) / tile[0], (N[1] + tile[1] - 1) / tile[1], (N[2] + tile[2] - 1) / tile[2]};
+    const int64_t ntiles = static_cast<int64_t>(nt[0]) * nt[1] * nt[2];
+    win.assign(static_cast<size_t>(q) * ntiles * 4, 0);
+    int largest = 0;
+    for (int i = 0; i < q; ++i)
+        for (int64_t t = 0; t < ntiles; ++t) {
+            const int tc[3] = {static_cast<int>(t % nt[0]), static_cast<int>((t / nt[0]) % nt[1]),
+                               static_cast<int>(t / (static_cast<int64_t>(nt[0]) * nt[1]))};
+            int lo[3] = {INT32_MAX, INT32_MAX, INT32_MAX}, hi[3] = {INT32_MIN, INT32_MIN, INT32_MIN};
+            for (int z = tc[2] * tile[2]; z < std::min(N[2], (tc[2] + 1) * tile[2]); ++z)
+                for (int y = tc[1] * tile[1]; y < std::min(N[1], (tc[1] + 1) * tile[1]); ++y)
+                    for (int x = tc[0] * tile[0]; x < std::min(N[0], (tc[0] + 1) * tile[0]); ++x) {
+                        const int64_t n = (static_cast<int64_t>(z) * N[1] + y) * N[0] + x;
+                        const int c = cell[static_cast<size_t>(i) * nodes + n];
+                        const int dep[3] = {c % ne[0], (c / ne[0]) % ne[1], c / (ne[0] * ne[1])};
+                        const int own[3] = {x / p, y / p, z / p};
+                        for (int a = 0; a < 3; ++a) {
+                            // departure cell unwrapped next to the node's own cell
+                            int d = (dep[a] - own[a]) % ne[a];
+                            if (d < 0) d += ne[a];
+                            if (2 * d >= ne[a]) d -= ne[a];
+                            const int u = own[a] + d;
+                            lo[a] = std::min(lo[a], u);
+                            hi[a] = std::max(hi[a], u);
+                        }
+                    }
+            int32_t *w = &win[(static_cast<size_t>(i) * ntiles + t) * 4];
+            int wn[3];
+            for (int a = 0; a < 3; ++a) {
+                int o = lo[a] % ne[a];
+                if (o < 0) o += ne[a];
+                w[a] = o;                                         // origin cell (wrapped)
+                wn[a] = (hi[a] - lo[a] + 1) * p + 1;             // window nodes along the axis
+            }
+            const int64_t total = static_cast<int64_t>(wn[0]) * wn[1] * wn[2];
+            if (total <= max_nodes && wn[0] < 1024 && wn[1] < 1024 && wn[2] < 1024) {
+                w[3] = wn[0] | (wn[1] << 10) | (wn[2] << 20);
+                largest = std::max(largest, static_cast<int>(total));
+            } else {
+                w[3] = 0;                                         // gather from global memory
+            }
+        }
+    return largest;
 }
 
 }  // namespace sllbm

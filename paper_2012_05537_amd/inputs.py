@@ -190,12 +190,16 @@ def mode_basis(xs, ys, zs, modes):
 
 
 def perturbed_tgv(xs, ys, zs, Ma, gamma, modes, amplitudes=None):
-    """TGV fields with the velocity modes added (amplitudes default to the drawn ones)."""
+    """TGV fields with the velocity modes added (amplitudes default to the
+    drawn ones), one mode at a time (no (M, 3, N) basis in memory)."""
     rho, u, T = tgv_fields(xs, ys, zs, Ma, gamma)
     if modes:
         amps = np.array([m[3] for m in modes]) if amplitudes is None else np.asarray(amplitudes)
-        B = mode_basis(xs, ys, zs, modes)
-        u = u + np.tensordot(amps, B, axes=(0, 0))
+        X, Y, Z = mesh(xs, ys, zs)
+        for a, (k, e, ph, _) in zip(amps, modes):
+            s = a * np.sin(k[0] * X + k[1] * Y + k[2] * Z + ph)
+            for c in range(3):
+                u[c] += e[c] * s
     return rho, u, T
 
 

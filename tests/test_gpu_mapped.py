@@ -169,8 +169,9 @@ def test_refusals(oracle):
     ctx.set_state(x)
     pp = lambda t: ctypes.c_void_p(t.data_ptr())
     d = (ctypes.c_double * 4)()
-    assert lib.sllbm_loss(h, pp(x), ctypes.addressof(d)) == 1
-    assert lib.sllbm_diagnostics(h, None, ctypes.addressof(d)) == 1
+    # the functional and the diagnostics work on distorted meshes
+    assert lib.sllbm_loss(h, pp(x), ctypes.addressof(d)) == 0
+    assert lib.sllbm_diagnostics(h, None, ctypes.addressof(d)) == 0
     wd = (ctypes.c_double * 3)(1, 1, 1)
     assert lib.sllbm_set_mesh(h, ctypes.addressof(wd), None, None) == 1
     assert "distorted" in lib.sllbm_last_error(h).decode()
@@ -221,7 +222,8 @@ def test_transposed_stream_is_adjoint(oracle, precision, tol):
     rhs = float((x.double() * sty.double()).sum())
     assert abs(lhs - rhs) <= tol * max(abs(lhs), 1.0) * 10, (lhs, rhs)
     again = ctx.stream(y, transpose=True)
-    assert rel_err(to_np(again)[0], to_np(sty)[0]) <= (1e-13 if precision == 0 else 1e-5)
+    for k in range(2):
+        assert rel_err(to_np(again)[k], to_np(sty)[k]) <= (1e-13 if precision == 0 else 1e-5)
 
 
 def test_adjoint_step_against_complex_step(oracle):
@@ -261,4 +263,74 @@ def test_uniform_state_is_fixed(oracle):
                          torch.full((N,), 1.1, dtype=torch.float64, device=dev))
     s0 = ctx.get_state()
     ctx.step(3)
-    assert rel_err(to_np(ctx.get_state())[0], to_np(s0)[0]) < 1e-13
+    for k in range(2):
+        assert rel_err(to_np(ctx.get_state())[k], to_np(s0)[k]) < 1e-13
+
+
+@pytest.mark.parametrize("n_el,p,scale", [((3, 2, 3), 3, 1.0), ((2, 2, 2), 4, 0.7), ((2, 3, 1), 2, 1.0)])
+def test_loss_diagnostics_and_loss_gradient_match_oracle(oracle, n_el, p, scale):
+    """The flow functional, its state gradient and the TGV diagnostics on a
+    distorted mesh (derivatives in physical coordinates through each cell's
+    map, Jacobian-weighted quadrature) against the oracle, whose
+    distorted-mesh loss and diagnostics are pinned by closed forms; the
+    gradient along random directions against complex-step derivatives of the
+    oracle's loss."""
+    _say(f"distorted loss/diagnostics n_el={n_el} p={p}")
+    dt, mu = 0.3, 0.02
+    ctx, cfg0 = make_pair(oracle, n_el, p, dt, mu)
+    X, Y, Z = _ref(oracle, cfg0)
+    disp = _smooth_disp(X, Y, Z, scale)
+    ctx.set_displacement(disp)
+    cfg = oracle.make_cfg(n_el, p, dt, mu, disp=disp)
+    f, g = tgv_init(oracle, ctx, cfg, 0.6, 1.4)
+    rng = np.random.default_rng(p)
+    f = f * (1 + 0.02 * rng.normal(size=f.shape))
+    g = g * (1 + 0.02 * rng.normal(size=g.shape))
+    st = to_dev(ctx, f, g)
+    L = ctx.loss(st)
+    assert L == pytest.approx(oracle.loss(cfg, f, g), rel=TOL64)
+    d = np.array(ctx.diagnostics(st))
+    do = np.array(oracle.diagnostics(cfg, f, g))
+    assert np.max(np.abs(d - do) / np.abs(do)) < TOL64, (d, do)
+    lam = ctx.loss_grad(st).double().cpu().numpy()
+    h = 1e-30
+    for k in range(3):
+        dX = rng.normal(size=(2, Q, X.size))
+        ref = float(oracle.loss(cfg, f + 1j * h * dX[0], g + 1j * h * dX[1]).imag / h)
+        got = float(np.sum(lam * dX))
+        assert got == pytest.approx(ref, rel=1e-11), (k, got, ref)
+
+
+def test_rollout_gradient_on_distorted_mesh(oracle):
+    """A 3-step rollout on a distorted mesh, differentiated in two mode
+    amplitudes and mu_inf through the library's reverse steps (the transposed
+    distorted streaming, the collision VJP, the functional's gradient),
+    against complex-step derivatives of the oracle rollout."""
+    from paper_2012_05537_amd import inputs
+    from paper_2012_05537_amd.adjoint import Rollout
+    n_el, p, dt, mu = (2, 3, 2), 3, 0.25, 0.02
+    ctx, cfg0 = make_pair(oracle, n_el, p, dt, mu)
+    X, Y, Z = _ref(oracle, cfg0)
+    disp = _smooth_disp(X, Y, Z, 0.6)
+    ctx.set_displacement(disp)
+    xs, ys, zs = oracle.node_coords(cfg0)
+    rho, u, T = inputs.tgv_fields(xs, ys, zs, 0.5, 1.4)
+    modes = inputs.fourier_modes(7, 2, 0.5, 1.4, scale=0.05)
+    B = inputs.mode_basis(xs, ys, zs, modes)
+    amps = np.array([m[3] for m in modes])
+    roll = Rollout(ctx, rho, u, T, B, 3, checkpoint=2)
+    a = torch.tensor(amps, dtype=torch.float64, requires_grad=True)
+    m = torch.tensor(mu, dtype=torch.float64, requires_grad=True)
+    roll(a, m).backward()
+    h = 1e-30
+
+    def cs(da, dmu):
+        c = oracle.make_cfg(n_el, p, dt, mu, mu_inf_im=h * dmu, disp=disp)
+        uc = u + np.tensordot(amps + 1j * h * da, B, axes=(0, 0))
+        fc, gc = oracle.init_equilibrium(c, rho.astype(complex), uc, T.astype(complex))
+        fc, gc = oracle.step(c, fc, gc, 3)
+        return oracle.loss(c, fc, gc).imag / h
+
+    ref = np.array([cs(np.eye(2)[k], 0.0) for k in range(2)] + [cs(np.zeros(2), 1.0)])
+    got = np.concatenate([a.grad.numpy(), [m.grad.item()]])
+    assert np.max(np.abs(got - ref)) / np.max(np.abs(ref)) < 1e-10, (got, ref)

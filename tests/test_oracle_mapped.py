@@ -190,3 +190,68 @@ def test_uniform_state_is_fixed_on_a_distorted_mesh(oracle):
     f, g = oracle.init_equilibrium(cfg, np.full(N, 1.2), np.tile([[0.2], [-0.1], [0.05]], (1, N)), np.full(N, 1.1))
     f2, g2 = oracle.step(cfg, f, g, 2)
     assert np.max(np.abs(f2 - f)) < 1e-13 and np.max(np.abs(g2 - g)) < 1e-13
+
+
+def test_zero_displacement_loss_and_diagnostics_match_equal_cells(oracle):
+    from paper_2012_05537_amd.inputs import tgv_fields
+    n_el, p = (3, 2, 4), 3
+    cu = oracle.make_cfg(n_el, p, 0.2, 0.01)
+    cm = oracle.make_cfg(n_el, p, 0.2, 0.01, disp=np.zeros((3, oracle.num_nodes(cu))))
+    rho, u, T = tgv_fields(*oracle.node_coords(cu), 0.7, 1.4)
+    f, g = oracle.init_equilibrium(cu, rho, u, T)
+    assert oracle.loss(cm, f, g) == pytest.approx(oracle.loss(cu, f, g), rel=1e-14)
+    assert np.allclose(oracle.diagnostics(cm, f, g), oracle.diagnostics(cu, f, g), rtol=1e-14, atol=0)
+
+
+@pytest.mark.parametrize("p,a,b", [(2, 0.3, 0.0), (3, 0.25, 0.2), (4, -0.2, 0.3)])
+def test_distorted_loss_and_diagnostics_closed_form(oracle, p, a, b):
+    """Cells distorted by d_x = a s1(r_y), d_y = b s2(r_x) (s1, s2 linear inside
+    every cell: the cell maps represent them exactly, J = [[1, a s1', 0],
+    [b s2', 1, 0], [0, 0, 1]] per cell pair, det J = 1 - a b s1' s2'), and the
+    flow rho = 1, T = 1, u = (0, g v(r_x), 0) with v linear inside every cell.
+    Physical derivatives d u/d x = (d u/d r) J^-1 give, per cell pair,
+    d u_y/d x = g v'/det, d u_y/d y = -a s1' g v'/det, so
+      div u = -a s1' g v'/det,  |curl u|^2 = (g v'/det)^2,
+    and every integral is a sum over cell pairs weighted by det J (the
+    quadratic v^2 is integrated exactly by the rule for p >= 2)."""
+    n_el = (4, 5, 3)
+    L = 2 * math.pi
+    h = L / np.array(n_el)
+    faces = [np.arange(n + 1) * L / n for n in n_el]
+    rng = np.random.default_rng(10 + p)
+    s1 = rng.uniform(-1, 1, n_el[1]) * h[0]             # s1(r_y) at the y faces
+    s2 = rng.uniform(-1, 1, n_el[0]) * h[1]             # s2(r_x) at the x faces
+    vv = rng.uniform(-1, 1, n_el[0])                    # v(r_x) at the x faces
+    gam, mu = 0.3, 0.01
+    cfg0 = oracle.make_cfg(n_el, p, 0.1, mu)
+    X, Y, Z = _ref_coords(oracle, cfg0)
+    N = X.size
+    disp = np.zeros((3, N))
+    disp[0] = a * _pw(Y, faces[1], s1)
+    disp[1] = b * _pw(X, faces[0], s2)
+    cfg = oracle.make_cfg(n_el, p, 0.1, mu, disp=disp)
+    u = np.zeros((3, N))
+    u[1] = gam * _pw(X, faces[0], vv)
+    f, g = oracle.init_equilibrium(cfg, np.ones(N), u, np.ones(N))
+    # closed forms over the cell pairs (ex, ey); every z cell alike
+    d1 = (np.roll(s1, -1) - s1) / h[1]                  # s1' per y cell
+    d2 = (np.roll(s2, -1) - s2) / h[0]                  # s2' per x cell
+    dv = (np.roll(vv, -1) - vv) / h[0]                  # v' per x cell
+    v0, v1 = vv, np.roll(vv, -1)
+    int_v2 = h[0] * (v0 * v0 + v0 * v1 + v1 * v1) / 3   # integral of v^2 over each x cell
+    det = 1.0 - a * b * np.outer(d1, d2)                # [ey, ex]
+    area = h[1] * L                                      # y width times the z extent
+    ke = 0.5 * gam ** 2 * np.sum(det * int_v2[None, :]) * area
+    curl2 = (gam * dv[None, :] / det) ** 2
+    div2 = (a * d1[:, None] * gam * dv[None, :] / det) ** 2
+    eps_s = mu * np.sum(curl2 * det) * h[0] * area
+    eps_c = 4.0 / 3.0 * mu * np.sum(div2 * det) * h[0] * area
+    loss = ke + np.sum(div2 * det) * h[0] * area
+    got = oracle.diagnostics(cfg, f, g)
+    assert got[0] == pytest.approx(ke, rel=1e-12)
+    assert got[1] == pytest.approx(eps_s, rel=1e-12)
+    if a == 0.0:
+        assert abs(got[2]) < 1e-20
+    else:
+        assert got[2] == pytest.approx(eps_c, rel=1e-12)
+    assert oracle.loss(cfg, f, g) == pytest.approx(loss, rel=1e-12)
