@@ -37,7 +37,7 @@ KERNEL_SOURCES = {
     "k_stream_graded": ("stream_graded.hip", "tables.cpp"),
     "k_collide": ("kernels.hip", "collision.h", "velset.h"),
     "k_stream_y": ("stream2d.hip", "tables.cpp"),
-    "k_stream_mapped": ("stream_mapped.hip", "tables.cpp"),
+    "k_stream_mapped": ("stream_mapped.hip", "tables_mapped.cpp"),
 }
 
 

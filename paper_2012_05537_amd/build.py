@@ -14,7 +14,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libsllbm.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
-SOURCES = ["tables.cpp", "kernels.hip", "stream.hip", "stream_graded.hip", "stream2d.hip", "stream_mapped.hip", "adjoint.hip", "modes.hip", "noalloc.hip", "api.cpp"]
+SOURCES = ["tables.cpp", "tables_mapped.cpp", "kernels.hip", "stream.hip", "stream_graded.hip", "stream2d.hip", "stream_mapped.hip", "adjoint.hip", "modes.hip", "noalloc.hip", "api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -128,14 +128,15 @@ struct GlcBasis {
     double inv_den[MAXP + 1];
 };
 
-// Device tables of a distorted mesh (build_mapped_tables); the local
-// coordinates are kept in the storage type (FP32 contexts: 16 bytes per
-// velocity and node instead of 28)
 // Node tiles of the distorted-mesh streaming: one block per (tile, velocity)
 // stages the source window of its departure cells in LDS.
 constexpr int MAPPED_TX = 8, MAPPED_TY = 8, MAPPED_TZ = 4;   // 256 nodes
 constexpr int MAPPED_WINDOW_BYTES = 48 * 1024;                // LDS for the f and g windows of a block
+constexpr int MAPPED_MIN_WAVES = 5;                           // waves per SIMD the kernel is compiled for
 
+// Device tables of a distorted mesh (build_mapped_tables); the local
+// coordinates are kept in the storage type (FP32 contexts: 16 bytes per
+// velocity and node instead of 28)
 struct MappedTables {
     const int32_t *cell;    // [Q][N] departure cell, x fastest
     const void *tloc;       // [3][Q][N] local coordinates in [0, 1), storage type

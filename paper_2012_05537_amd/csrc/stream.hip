@@ -21,6 +21,7 @@
 #include <type_traits>
 
 #include "sllbm_internal.h"
+#include "xcd.h"
 
 namespace sllbm {
 
@@ -30,13 +31,6 @@ __device__ __forceinline__ int wrapi(int x, int n)
 {
     int r = x % n;
     return r < 0 ? r + n : r;
-}
-
-__device__ __forceinline__ int xcd_linear(int b, int nb)
-{
-    const int xcd = b & 7, slot = b >> 3;
-    const int per = nb >> 3, rem = nb & 7;
-    return xcd < rem ? xcd * (per + 1) + slot : rem * (per + 1) + (xcd - rem) * per + slot;
 }
 
 constexpr int64_t ZCHUNK_TARGET_BLOCKS = 2048;

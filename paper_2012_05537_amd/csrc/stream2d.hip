@@ -23,6 +23,7 @@
 #include <type_traits>
 
 #include "sllbm_internal.h"
+#include "xcd.h"
 
 namespace sllbm {
 
@@ -35,14 +36,6 @@ __device__ __forceinline__ int wrap2(int x, int n)
 {
     int r = x % n;
     return r < 0 ? r + n : r;
-}
-
-// consecutive logical blocks on one XCD (blocks are dealt round-robin to 8 XCDs)
-__device__ __forceinline__ int xcd_block(int b, int nb)
-{
-    const int xcd = b & 7, slot = b >> 3;
-    const int per = nb >> 3, rem = nb & 7;
-    return xcd < rem ? xcd * (per + 1) + slot : rem * (per + 1) + (xcd - rem) * per + slot;
 }
 
 template <int P, int V>
@@ -78,7 +71,7 @@ __global__ void __launch_bounds__(256) k_stream_y(Geometry g, CellTables<S> tab,
     __shared__ __align__(16) S pl[2][P + 1][WXP];
 
     const int tid = threadIdx.x;
-    const int L = __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x));
+    const int L = __builtin_amdgcn_readfirstlane(xcd_linear(blockIdx.x, gridDim.x));
     const int q = L / (nstrip * nchunk);
     const int rem = L - q * nstrip * nchunk;
     const int chunk = rem / nstrip, strip = rem - chunk * nstrip;

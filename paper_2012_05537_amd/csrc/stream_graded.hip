@@ -20,6 +20,7 @@
 #include <algorithm>
 
 #include "sllbm_internal.h"
+#include "xcd.h"
 
 namespace sllbm {
 
@@ -29,13 +30,6 @@ __device__ __forceinline__ int wrapg(int x, int n)
 {
     int r = x % n;
     return r < 0 ? r + n : r;
-}
-
-__device__ __forceinline__ int xcd_order(int b, int nb)
-{
-    const int xcd = b & 7, slot = b >> 3;
-    const int per = nb >> 3, rem = nb & 7;
-    return xcd < rem ? xcd * (per + 1) + slot : rem * (per + 1) + (xcd - rem) * per + slot;
 }
 
 constexpr int GTX = 32, GTY = 8, GNT = GTX * GTY;
@@ -69,7 +63,7 @@ __global__ void __launch_bounds__(GNT) k_stream_graded(Geometry g, NodeTables<S>
     S *ring = A + RB * AP;                                 // [RZ][GNT]     x-y interpolated source rows
 
     const int tid = threadIdx.x;
-    const int L = __builtin_amdgcn_readfirstlane(xcd_order(blockIdx.x, gridDim.x));
+    const int L = __builtin_amdgcn_readfirstlane(xcd_linear(blockIdx.x, gridDim.x));
     const int q = L / (ntiles * nchunk);
     const int rem = L - q * ntiles * nchunk;
     const int chunk = rem / ntiles, tile = rem - chunk * ntiles;

@@ -22,6 +22,7 @@
 #include <algorithm>
 
 #include "sllbm_internal.h"
+#include "xcd.h"
 
 namespace sllbm {
 
@@ -108,22 +109,24 @@ __global__ void __launch_bounds__(256) k_stream_mapped(Geometry g, GlcBasis gb, 
 // The same streaming with the source values staged in LDS: a block owns one
 // velocity and a tile of MAPPED_TX x MAPPED_TY x MAPPED_TZ nodes; the host
 // has found the box of cells that holds the departure cells of all of them
-// (build_mapped_windows), the block loads that window of f and g once
-// (coalesced rows, each value once from L2 instead of once per reading
-// thread through L1), and every thread gathers its (P+1)^3 support values
-// from LDS.  A block whose window exceeds the LDS budget gathers from global
-// memory instead; both paths sum in the same order, so they give the same
-// bits.
+// (build_mapped_windows), the block loads that window once (coalesced rows,
+// each value once from L2 instead of once per reading thread through L1),
+// f and g of a node side by side so that one LDS read returns both, and every
+// thread gathers its (P+1)^3 support pairs from LDS.  The blocks run in
+// XCD-aware order (consecutive tiles of a velocity on one XCD, where their
+// overlapping windows and the table lines they share meet in one L2).  A
+// block whose window exceeds the LDS budget gathers from global memory
+// instead; both paths sum in the same order, so they give the same bits.
 template <typename S, int P>
-__global__ void __launch_bounds__(256) k_stream_mapped_win(Geometry g, GlcBasis gb, const int32_t *__restrict__ cell,
-                                                           const S *__restrict__ tloc, const int32_t *__restrict__ win,
-                                                           int ntx, int nty, const S *__restrict__ in,
-                                                           S *__restrict__ out)
+__global__ void __launch_bounds__(256, MAPPED_MIN_WAVES) k_stream_mapped_win(
+    Geometry g, GlcBasis gb, const int32_t *__restrict__ cell, const S *__restrict__ tloc,
+    const int32_t *__restrict__ win, int ntiles, int ntx, int nty, const S *__restrict__ in, S *__restrict__ out)
 {
+    using S2 = typename MVec<S, 2>::T;
     extern __shared__ __align__(16) unsigned char smem[];
-    const int i = blockIdx.y;
-    const int t = blockIdx.x;
-    const int ntiles = static_cast<int>(gridDim.x);
+    const int L = __builtin_amdgcn_readfirstlane(xcd_linear(blockIdx.x, gridDim.x));
+    const int i = L / ntiles;
+    const int t = L - i * ntiles;
     const int64_t N = g.nodes;
     const int Nx = g.N[0], Ny = g.N[1], Nz = g.N[2];
     const int32_t *w = win + (static_cast<int64_t>(i) * ntiles + t) * 4;
@@ -135,17 +138,29 @@ __global__ void __launch_bounds__(256) k_stream_mapped_win(Geometry g, GlcBasis 
     const S *fi = in + static_cast<int64_t>(i) * N;
     const S *gi = in + static_cast<int64_t>(Q + i) * N;
     const int wx = dims & 1023, wy = (dims >> 10) & 1023, wz = dims >> 20;
-    S *lf = reinterpret_cast<S *>(smem);
-    S *lg = lf + wx * wy * wz;
+    S2 *lw = reinterpret_cast<S2 *>(smem);
     if (dims != 0) {
         const int wt = wx * wy * wz;
         const int ox = ocx * P, oy = ocy * P, oz = ocz * P;
+        const float rx = 1.0f / static_cast<float>(wx), ry = 1.0f / static_cast<float>(wy);
         for (int k = threadIdx.x; k < wt; k += blockDim.x) {
-            const int x = k % wx, r = k / wx;
-            const int y = r % wy, z = r / wy;
-            const int64_t node = (static_cast<int64_t>((oz + z) % Nz) * Ny + (oy + y) % Ny) * Nx + (ox + x) % Nx;
-            lf[k] = fi[node];
-            lg[k] = gi[node];
+            // k = (z wy + y) wx + x.  The quotients in single precision are
+            // exact: (k + 1/2)/wx lies at least 1/(2 wx) from an integer, and
+            // the two roundings move it by less than that while k < 2^21
+            // (a window holds at most a few thousand nodes).
+            const int r = static_cast<int>((static_cast<float>(k) + 0.5f) * rx);
+            const int z = static_cast<int>((static_cast<float>(r) + 0.5f) * ry);
+            const int x = k - r * wx, y = r - z * wy;
+            // origin node < N and window extent <= N + 1 along every axis
+            int xx = ox + x, yy = oy + y, zz = oz + z;
+            xx -= xx >= Nx ? Nx : 0;
+            yy -= yy >= Ny ? Ny : 0;
+            zz -= zz >= Nz ? Nz : 0;
+            const int64_t node = (static_cast<int64_t>(zz) * Ny + yy) * Nx + xx;
+            S2 v;
+            v.x = fi[node];
+            v.y = gi[node];
+            lw[k] = v;
         }
         __syncthreads();
     }
@@ -181,8 +196,9 @@ __global__ void __launch_bounds__(256) k_stream_mapped_win(Geometry g, GlcBasis 
                 S af = 0, ag = 0;
 #pragma unroll
                 for (int kx = 0; kx <= P; ++kx) {
-                    af = fma(wt3[0][kx], lf[base + kx], af);
-                    ag = fma(wt3[0][kx], lg[base + kx], ag);
+                    const S2 v = lw[base + kx];
+                    af = fma(wt3[0][kx], v.x, af);
+                    ag = fma(wt3[0][kx], v.y, ag);
                 }
                 const S wyz = wt3[1][ky] * wt3[2][kz];
                 sf = fma(wyz, af, sf);
@@ -306,10 +322,11 @@ hipError_t launch_m(const Geometry &g, const MappedTables &t, const S *in, S *ou
         const int ntx = (g.N[0] + MAPPED_TX - 1) / MAPPED_TX, nty = (g.N[1] + MAPPED_TY - 1) / MAPPED_TY,
                   ntz = (g.N[2] + MAPPED_TZ - 1) / MAPPED_TZ;
         const int64_t ntiles = static_cast<int64_t>(ntx) * nty * ntz;
-        if (ntiles > (int64_t(1) << 31) - 1) return hipErrorInvalidValue;
+        if (ntiles * Q > (int64_t(1) << 31) - 1) return hipErrorInvalidValue;
         const size_t lds = 2 * static_cast<size_t>(t.win_nodes) * sizeof(S);
-        hipLaunchKernelGGL((k_stream_mapped_win<S, P>), dim3(static_cast<unsigned>(ntiles), Q), dim3(256), lds, st,
-                           g, t.basis, t.cell, static_cast<const S *>(t.tloc), t.win, ntx, nty, in, out);
+        hipLaunchKernelGGL((k_stream_mapped_win<S, P>), dim3(static_cast<unsigned>(ntiles * Q)), dim3(256), lds, st,
+                           g, t.basis, t.cell, static_cast<const S *>(t.tloc), t.win, static_cast<int>(ntiles), ntx,
+                           nty, in, out);
         return hipGetLastError();
     }
     const int64_t bx = (g.nodes + 255) / 256;
