@@ -164,7 +164,9 @@ __global__ void __launch_bounds__((ZTile<P, V>::NT)) k_stream_z(Geometry g, Cell
     // this block's output cells [ez0, ez1) along z; source rows in march
     // order: z = (ez0 + omz) * P + k (mod Nz), k = 0 .. P + (ez1 - ez0) * P
     const int ez0 = chunk * zcells, ez1 = min(g.nel[2], ez0 + zcells);
-    const int zb = (ez0 + omz) * P;
+    // row k < P + 1 + (ez1 - ez0) P <= Nz + P + 1 and zb < Nz, so two
+    // conditional subtractions wrap zb + k (no integer division per row)
+    const int zb = wrapi((ez0 + omz) * P, Nz);
     // two register buffers of source rows: the rows of the cell after next are
     // in flight while a cell is processed
     VT rawA[P + 1][LK], rawB[P][LK];
@@ -172,7 +174,10 @@ __global__ void __launch_bounds__((ZTile<P, V>::NT)) k_stream_z(Geometry g, Cell
 #pragma unroll
         for (int r = 0; r <= P; ++r) {
             if (r < nr && r < static_cast<int>(sizeof(raw) / sizeof(raw[0]))) {
-                const int64_t zo = static_cast<int64_t>(wrapi(zb + k0 + r, Nz)) * NP;
+                int z = zb + k0 + r;
+                z -= z >= Nz ? Nz : 0;
+                z -= z >= Nz ? Nz : 0;
+                const int64_t zo = static_cast<int64_t>(z) * NP;
 #pragma unroll
                 for (int j = 0; j < LK; ++j) raw[r][j] = *reinterpret_cast<const VT *>(src + zo + loff[j]);
             }
@@ -379,13 +384,18 @@ __global__ void __launch_bounds__((ZTileT<P, V>::NT))
 
     // input rows in march order: z = (ez0 - omz - 2)*P + lsz + k (mod Nz), k = 0 .. P + nel*P - 1
     const int ez0 = chunk * zcells, ez1 = min(g.nel[2], ez0 + zcells);
-    const int zb = (ez0 - omz - 2) * P + lsz;
+    // row k < P + (ez1 - ez0) P <= Nz + P and zb < Nz: two conditional
+    // subtractions wrap zb + k
+    const int zb = wrapi((ez0 - omz - 2) * P + lsz, Nz);
     VT rawA[P][LK], rawB[P][LK];
     auto load_rows = [&](auto &raw, int k0, int nr) {
 #pragma unroll
         for (int r = 0; r < P; ++r) {
             if (r < nr) {
-                const int64_t zo = static_cast<int64_t>(wrapi(zb + k0 + r, Nz)) * NP;
+                int z = zb + k0 + r;
+                z -= z >= Nz ? Nz : 0;
+                z -= z >= Nz ? Nz : 0;
+                const int64_t zo = static_cast<int64_t>(z) * NP;
 #pragma unroll
                 for (int j = 0; j < LK; ++j) raw[r][j] = *reinterpret_cast<const VT *>(src + zo + loff[j]);
             }
