@@ -6,6 +6,7 @@
 #include <cmath>
 
 #include "collision.h"
+#include "nt.h"
 #include "sllbm_internal.h"
 #include "velset.h"
 
@@ -13,8 +14,9 @@ namespace sllbm {
 
 // Collision of a whole state (Eq. (5) right-hand side with App. D), two
 // lanes per node (f on the even lane, g on the odd one).  in and out may be
-// the same buffer (each lane reads its 45 values first).
-template <typename S, class L>
+// the same buffer (each lane reads its 45 values first).  NTH: non-temporal
+// loads and stores (states larger than the Infinity Cache).
+template <typename S, class L, bool NTH>
 __global__ void __launch_bounds__(256) k_collide(int64_t N, CollisionParams cp, const S *in, S *out)
 {
     constexpr int NQ = L::Q;
@@ -26,14 +28,14 @@ __global__ void __launch_bounds__(256) k_collide(int64_t N, CollisionParams cp, 
     const S *p = in + o;
     S v[NQ];
 #pragma unroll
-    for (int i = 0; i < NQ; ++i) v[i] = p[static_cast<int64_t>(i) * N];
+    for (int i = 0; i < NQ; ++i) v[i] = load_hint<NTH>(&p[static_cast<int64_t>(i) * N]);
     collide_half<L, S>(v, pop != 0, cp);
     // derive the store addresses afresh: otherwise the 45 load addresses stay
     // live through the collision (90 registers)
     S *d = out + o;
     asm volatile("" : "+v"(d));
 #pragma unroll
-    for (int i = 0; i < NQ; ++i) d[static_cast<int64_t>(i) * N] = v[i];
+    for (int i = 0; i < NQ; ++i) store_hint<NTH>(&d[static_cast<int64_t>(i) * N], v[i]);
 }
 
 // The same collision with each lane pair taking nodes n, n + G, ... (G lane
@@ -232,8 +234,12 @@ static hipError_t collide_lat(const Geometry &g, const CollisionParams &cp, cons
         return hipGetLastError();
     }
     const int64_t blocks = (2 * g.nodes + 255) / 256;
-    hipLaunchKernelGGL((k_collide<S, L>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, g.nodes, cp, in,
-                       out);
+    if (use_nontemporal(2 * L::Q * g.nodes * static_cast<int64_t>(sizeof(S))))
+        hipLaunchKernelGGL((k_collide<S, L, true>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, g.nodes, cp,
+                           in, out);
+    else
+        hipLaunchKernelGGL((k_collide<S, L, false>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, g.nodes,
+                           cp, in, out);
     return hipGetLastError();
 }
 

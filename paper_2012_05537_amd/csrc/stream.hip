@@ -20,6 +20,7 @@
 #include <algorithm>
 #include <type_traits>
 
+#include "nt.h"
 #include "sllbm_internal.h"
 #include "xcd.h"
 
@@ -93,7 +94,8 @@ __device__ __forceinline__ auto vcomp(const VT &v, int c)
 
 }  // namespace
 
-template <typename S, int P, int V>
+// NTH: non-temporal output stores (states larger than the Infinity Cache)
+template <typename S, int P, int V, bool NTH>
 __global__ void __launch_bounds__((ZTile<P, V>::NT)) k_stream_z(Geometry g, CellTables<S> tab, const S *__restrict__ in,
                                                      S *__restrict__ out, int ntile_x, int ntiles, int zcells,
                                                      int nchunk)
@@ -237,7 +239,7 @@ __global__ void __launch_bounds__((ZTile<P, V>::NT)) k_stream_z(Geometry g, Cell
                 S acc = 0;
 #pragma unroll
                 for (int r = 0; r <= P; ++r) acc = fma(wz[l][r], hi ? a[P + r] : a[r], acc);
-                dst[static_cast<int64_t>(ez * P + l) * NP + oxy] = acc;
+                store_hint<NTH>(&dst[static_cast<int64_t>(ez * P + l) * NP + oxy], acc);
             }
         }
 #pragma unroll
@@ -271,8 +273,12 @@ static hipError_t launch_zv(const Geometry &g, const CellTables<S> &t, const S *
     const int zcells = (g.nel[2] + nchunk - 1) / nchunk;
     const int64_t nb = static_cast<int64_t>(ntiles) * 90 * nchunk;
     if (nb > (int64_t(1) << 31) - 1) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_stream_z<S, P, V>), dim3(static_cast<unsigned>(nb)), dim3(Z::NT), 0, st, g, t, in, out, ntx,
-                       ntiles, zcells, nchunk);
+    if (use_nontemporal(90 * g.nodes * static_cast<int64_t>(sizeof(S))))
+        hipLaunchKernelGGL((k_stream_z<S, P, V, true>), dim3(static_cast<unsigned>(nb)), dim3(Z::NT), 0, st, g, t, in,
+                           out, ntx, ntiles, zcells, nchunk);
+    else
+        hipLaunchKernelGGL((k_stream_z<S, P, V, false>), dim3(static_cast<unsigned>(nb)), dim3(Z::NT), 0, st, g, t, in,
+                           out, ntx, ntiles, zcells, nchunk);
     return hipGetLastError();
 }
 
