@@ -124,8 +124,10 @@ __host__ __device__ __forceinline__ EqShell eq_shell(double u2, double th, doubl
 // parts (tr M2[f] and M0[g]); each lane then builds Qbar of its own
 // population and relaxes it (g^eq = (2 C_v - D) T f^eq).  Both lanes of a
 // pair must be active.
-template <class L, typename S>
-__device__ __forceinline__ void collide_half(S (&v)[L::Q], bool is_g, const CollisionParams &cp)
+// sink(i, value) receives every post-collision value as soon as it is formed
+// (v holds them all on return as well).
+template <class L, typename S, class Sink>
+__device__ __forceinline__ void collide_half_s(S (&v)[L::Q], bool is_g, const CollisionParams &cp, Sink &&sink)
 {
     using R = double;   // arithmetic type of the per-velocity terms (storage S is read and written once)
     constexpr bool D3 = L::D == 3;
@@ -171,6 +173,7 @@ __device__ __forceinline__ void collide_half(S (&v)[L::Q], bool is_g, const Coll
         const R heq = eqs * static_cast<R>(L::T.w[0]) * A0[0];
         const R vi = v[0];
         v[0] = fma(om, heq - vi, vi);
+        sink(0, v[0]);
     }
 #pragma unroll
     for (int q = 0; q < L::NPAIR; ++q) {
@@ -188,7 +191,15 @@ __device__ __forceinline__ void collide_half(S (&v)[L::Q], bool is_g, const Coll
         const R vi = v[i], vj = v[j];
         v[i] = fma(kap, hs, fma(om, fma(we, even, we * odd) - vi, vi));
         v[j] = fma(-kap, hs, fma(om, fma(we, even, -we * odd) - vj, vj));
+        sink(i, v[i]);
+        sink(j, v[j]);
     }
+}
+
+template <class L, typename S>
+__device__ __forceinline__ void collide_half(S (&v)[L::Q], bool is_g, const CollisionParams &cp)
+{
+    collide_half_s<L, S>(v, is_g, cp, [](int, S) {});
 }
 
 }  // namespace sllbm

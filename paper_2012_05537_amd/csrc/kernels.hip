@@ -29,13 +29,22 @@ __global__ void __launch_bounds__(256) k_collide(int64_t N, CollisionParams cp, 
     S v[NQ];
 #pragma unroll
     for (int i = 0; i < NQ; ++i) v[i] = load_hint<NTH>(&p[static_cast<int64_t>(i) * N]);
-    collide_half<L, S>(v, pop != 0, cp);
     // derive the store addresses afresh: otherwise the 45 load addresses stay
     // live through the collision (90 registers)
     S *d = out + o;
-    asm volatile("" : "+v"(d));
+    if constexpr (sizeof(S) == 4) {
+        // FP32 storage: store every value as the relaxation forms it; the
+        // collision is bound by instruction issue here, and stores spread
+        // over it measured 7 % faster at 256^3 nodes (no gain in FP64)
+        asm volatile("" : "+v"(d));
+        collide_half_s<L, S>(v, pop != 0, cp,
+                             [d, N](int i, S x) { store_hint<NTH>(&d[static_cast<int64_t>(i) * N], x); });
+    } else {
+        collide_half<L, S>(v, pop != 0, cp);
+        asm volatile("" : "+v"(d));
 #pragma unroll
-    for (int i = 0; i < NQ; ++i) store_hint<NTH>(&d[static_cast<int64_t>(i) * N], v[i]);
+        for (int i = 0; i < NQ; ++i) store_hint<NTH>(&d[static_cast<int64_t>(i) * N], v[i]);
+    }
 }
 
 // The same collision with each lane pair taking nodes n, n + G, ... (G lane
