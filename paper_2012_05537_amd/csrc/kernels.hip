@@ -34,8 +34,8 @@ __global__ void __launch_bounds__(256) k_collide(int64_t N, CollisionParams cp, 
     S *d = out + o;
     if constexpr (sizeof(S) == 4) {
         // FP32 storage: store every value as the relaxation forms it; the
-        // collision is bound by instruction issue here, and stores spread
-        // over it measured 7 % faster at 256^3 nodes (no gain in FP64)
+        // collision is latency-bound here (two waves per SIMD), and stores
+        // spread over it measured 7 % faster at 256^3 nodes (no gain in FP64)
         asm volatile("" : "+v"(d));
         collide_half_s<L, S>(v, pop != 0, cp,
                              [d, N](int i, S x) { store_hint<NTH>(&d[static_cast<int64_t>(i) * N], x); });
