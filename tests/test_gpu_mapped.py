@@ -68,6 +68,30 @@ def test_stream_matches_oracle(oracle, n_el, p, dt):
     assert rel_err(F, fo) <= TOL64 and rel_err(G, go) <= TOL64, (rel_err(F, fo), rel_err(G, go))
 
 
+# grids on which the staged kernel's source windows are in use: (6, 6, 5) cells
+# at p = 4, dt = 0.8 mixes staged blocks with blocks whose window exceeds the
+# LDS budget or spans an axis (global gather); (5, 6, 4) at p = 3 stages every
+# block over ragged tiles (the host test pins both counts)
+STAGED = [((6, 6, 5), 4, 0.8, 0, TOL64), ((5, 6, 4), 3, 0.5, 0, TOL64), ((6, 6, 5), 4, 0.8, 1, TOL_MIXED)]
+
+
+@pytest.mark.parametrize("n_el,p,dt,precision,tol", STAGED)
+def test_staged_stream_matches_oracle(oracle, n_el, p, dt, precision, tol):
+    _say(f"distorted staged stream parity n_el={n_el} p={p} dt={dt} precision={precision}")
+    ctx, cfg0 = make_pair(oracle, n_el, p, dt, 0.01, precision=precision)
+    X, Y, Z = _ref(oracle, cfg0)
+    disp = _smooth_disp(X, Y, Z)
+    ctx.set_displacement(disp)
+    cfg = oracle.make_cfg(n_el, p, dt, 0.01, disp=disp)
+    rng = np.random.default_rng(11 + p)
+    f, g = rng.normal(size=(Q, X.size)), rng.normal(size=(Q, X.size))
+    if precision:
+        f, g = f.astype(np.float32).astype(np.float64), g.astype(np.float32).astype(np.float64)
+    F, G = to_np(ctx.stream(to_dev(ctx, f, g)))
+    fo, go = oracle.stream(cfg, f, g)
+    assert rel_err(F, fo) <= tol and rel_err(G, go) <= tol, (rel_err(F, fo), rel_err(G, go))
+
+
 def test_stream_fp32(oracle):
     n_el, p, dt = (3, 3, 2), 4, 0.5
     ctx, cfg0 = make_pair(oracle, n_el, p, dt, 0.01, precision=1)

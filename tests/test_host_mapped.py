@@ -180,3 +180,27 @@ def test_staged_windows_reproduce_oracle_streaming(oracle, driver, p, n_el, dt, 
     if max_nodes == 800 or p == 6:
         assert (dims == 0).any()                    # some blocks take the direct gather
     assert np.max(np.abs(got - ref)) < 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("n_el,p,dt,max_nodes,mixed", [((6, 6, 5), 4, 0.8, 3072, True), ((6, 6, 5), 4, 0.8, 6144, True),
+                                                       ((5, 6, 4), 3, 0.5, 3072, False)])
+def test_window_mix_of_gpu_staged_cases(oracle, driver, n_el, p, dt, max_nodes, mixed):
+    """The grids of the GPU staged-streaming parity test use the windows as
+    stated there: a mixture of staged and global-gather blocks at the FP64
+    (3072 nodes) and FP32 (6144 nodes) budgets, or every block staged."""
+    L = (2 * math.pi,) * 3
+    cfg0 = oracle.make_cfg(n_el, p, dt, 0.01)
+    xs, ys, zs = oracle.node_coords(cfg0)
+    Z, Y, X = (v.reshape(-1) for v in np.meshgrid(zs, ys, xs, indexing="ij"))
+    disp = np.stack([0.2 * np.sin(Y + 0.5 * Z), 0.15 * np.cos(X) * np.sin(Z), 0.1 * np.sin(X + Y)])
+    r = _run(driver, p, n_el, L, dt, disp, max_nodes)
+    assert r.returncode == 0, r.stdout[:200] + r.stderr
+    vals = r.stdout.split()
+    N = X.size
+    win = np.array(vals[4 * Q * N + N + 1:], dtype=np.int64).reshape(Q, -1, 4)
+    staged = int((win[:, :, 3] != 0).sum())
+    total = win.shape[0] * win.shape[1]
+    if mixed:
+        assert 0 < staged < total, (staged, total)
+    else:
+        assert staged == total, (staged, total)
