@@ -151,9 +151,12 @@ int sllbm_set_mesh(sllbm_ctx *ctx, const double *widths_x, const double *widths_
  * velocity and node); totals then weight every node with the |det J| of the
  * cells that hold it.  d = NULL returns to the undistorted mesh.  The state is
  * kept; node coordinates stay those of the reference grid.  The transposed
- * streaming (and so sllbm_adjoint_step) spreads every output's adjoint over
- * its support values with atomic adds (results reproducible to rounding, not
- * bit for bit).  The loss, its gradient and the diagnostics take derivatives
+ * streaming (and so sllbm_adjoint_step) sums every support value's adjoint
+ * in a fixed order (per departure cell, then over the cells that share a
+ * node; no atomics), so it is bitwise reproducible; for it the call also
+ * uploads the nodes of every velocity grouped by departure cell (4 bytes per
+ * velocity and node) and allocates partial sums of at most one state's
+ * size.  The loss, its gradient and the diagnostics take derivatives
  * in physical coordinates through each cell's map (d u/d x = (d u/d r) J^-1,
  * J = I + dD/dr at the cell's support points) and weight the quadrature with
  * |det J|; J^-1 and |det J| of every cell point are uploaded here (80 bytes

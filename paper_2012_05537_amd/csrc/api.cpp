@@ -71,6 +71,10 @@ struct sllbm_ctx {
     double *d_cjac = nullptr;      // per cell point J^-1 and |det J| of the cell map (loss, diagnostics)
     int32_t *d_mwin = nullptr;     // per (velocity, node tile) source window of the streaming
     int mwin_nodes = 0;            // largest staged window (nodes per population)
+    int32_t *d_minv = nullptr;     // nodes by departure cell per velocity (transposed streaming)
+    int32_t *d_minv_start = nullptr;
+    void *d_mpart = nullptr;       // partial sums of the transposed streaming, mqchunk velocities
+    int mqchunk = 0;
     GlcBasis glc{};
     std::string err;
 };
@@ -135,6 +139,9 @@ void free_ctx(sllbm_ctx *c)
     (void)hipFree(c->d_mw);
     (void)hipFree(c->d_cjac);
     (void)hipFree(c->d_mwin);
+    (void)hipFree(c->d_minv);
+    (void)hipFree(c->d_minv_start);
+    (void)hipFree(c->d_mpart);
     (void)hipFree(c->d_omin);
     (void)hipFree(c->d_lstar);
     (void)hipFree(c->d_cw);
@@ -214,7 +221,8 @@ int refuse_mapped(sllbm_ctx *c, const char *what)
 
 MappedTables mapped_tables(const sllbm_ctx *c)
 {
-    return MappedTables{c->d_mcell, c->d_mt, c->glc, c->d_mwin, c->mwin_nodes};
+    return MappedTables{c->d_mcell, c->d_mt,        c->glc,  c->d_mwin, c->mwin_nodes,
+                        c->d_minv,  c->d_minv_start, c->d_mpart, c->mqchunk};
 }
 
 const double *graded_hw(const sllbm_ctx *c) { return c->graded ? c->d_hw : nullptr; }
@@ -569,12 +577,19 @@ int sllbm_set_displacement(sllbm_ctx *ctx, const double *d)
         (void)hipFree(ctx->d_mw);
         (void)hipFree(ctx->d_cjac);
         (void)hipFree(ctx->d_mwin);
+        (void)hipFree(ctx->d_minv);
+        (void)hipFree(ctx->d_minv_start);
+        (void)hipFree(ctx->d_mpart);
         ctx->d_mcell = nullptr;
         ctx->d_mt = nullptr;
         ctx->d_mw = nullptr;
         ctx->d_cjac = nullptr;
         ctx->d_mwin = nullptr;
         ctx->mwin_nodes = 0;
+        ctx->d_minv = nullptr;
+        ctx->d_minv_start = nullptr;
+        ctx->d_mpart = nullptr;
+        ctx->mqchunk = 0;
         ctx->mapped = false;
     };
     if (!d) {
@@ -594,9 +609,25 @@ int sllbm_set_displacement(sllbm_ctx *ctx, const double *d)
     const int tile[3] = {MAPPED_TX, MAPPED_TY, MAPPED_TZ};
     const int win_nodes = build_mapped_windows(ctx->vs.q, ctx->geo.p, ctx->geo.nel, cell, tile,
                                                MAPPED_WINDOW_BYTES / (2 * static_cast<int>(ctx->elem)), mwin);
-    int32_t *dc = nullptr, *dwin = nullptr;
-    void *dt = nullptr;
+    const int ncells = ctx->geo.nel[0] * ctx->geo.nel[1] * ctx->geo.nel[2];
+    std::vector<int32_t> minv, minv_start;
+    build_mapped_inverse(ctx->vs.q, N, ncells, cell, minv, minv_start);
+    const int qchunk = mapped_t_chunk(ctx->vs.q, ctx->geo.p);
+    const int k3 = (ctx->geo.p + 1) * (ctx->geo.p + 1) * (ctx->geo.p + 1);
+    const size_t pbytes = static_cast<size_t>(qchunk) * ncells * 2 * k3 * ctx->elem;
+    int32_t *dc = nullptr, *dwin = nullptr, *dinv = nullptr, *dinvs = nullptr;
+    void *dt = nullptr, *dpart = nullptr;
     double *dw = nullptr, *dj = nullptr;
+    auto free_new = [&]() {
+        (void)hipFree(dc);
+        (void)hipFree(dt);
+        (void)hipFree(dw);
+        (void)hipFree(dj);
+        (void)hipFree(dwin);
+        (void)hipFree(dinv);
+        (void)hipFree(dinvs);
+        (void)hipFree(dpart);
+    };
     // local coordinates in the storage type
     std::vector<float> tloc32;
     const void *tsrc = tloc.data();
@@ -609,24 +640,22 @@ int sllbm_set_displacement(sllbm_ctx *ctx, const double *d)
         (e = hipMalloc(&dt, tbytes)) != hipSuccess ||
         (e = dalloc(&dw, nodew.size() * sizeof(double))) != hipSuccess ||
         (e = dalloc(&dj, cjac.size() * sizeof(double))) != hipSuccess ||
-        (e = dalloc(&dwin, mwin.size() * sizeof(int32_t))) != hipSuccess) {
-        (void)hipFree(dc);
-        (void)hipFree(dt);
-        (void)hipFree(dw);
-        (void)hipFree(dj);
-        (void)hipFree(dwin);
+        (e = dalloc(&dwin, mwin.size() * sizeof(int32_t))) != hipSuccess ||
+        (e = dalloc(&dinv, minv.size() * sizeof(int32_t))) != hipSuccess ||
+        (e = dalloc(&dinvs, minv_start.size() * sizeof(int32_t))) != hipSuccess ||
+        (e = hipMalloc(&dpart, pbytes)) != hipSuccess) {
+        free_new();
         return fail(ctx, SLLBM_ENOMEM, std::string("distorted-mesh tables: ") + hipGetErrorString(e));
     }
     if ((e = hipMemcpy(dc, cell.data(), cell.size() * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(dt, tsrc, tbytes, hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(dw, nodew.data(), nodew.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(dj, cjac.data(), cjac.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess ||
-        (e = hipMemcpy(dwin, mwin.data(), mwin.size() * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess) {
-        (void)hipFree(dc);
-        (void)hipFree(dt);
-        (void)hipFree(dw);
-        (void)hipFree(dj);
-        (void)hipFree(dwin);
+        (e = hipMemcpy(dwin, mwin.data(), mwin.size() * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(dinv, minv.data(), minv.size() * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(dinvs, minv_start.data(), minv_start.size() * sizeof(int32_t), hipMemcpyHostToDevice)) !=
+            hipSuccess) {
+        free_new();
         return hip_fail(ctx, e, "distorted-mesh table upload");
     }
     drop();
@@ -636,6 +665,10 @@ int sllbm_set_displacement(sllbm_ctx *ctx, const double *d)
     ctx->d_cjac = dj;
     ctx->d_mwin = dwin;
     ctx->mwin_nodes = win_nodes;
+    ctx->d_minv = dinv;
+    ctx->d_minv_start = dinvs;
+    ctx->d_mpart = dpart;
+    ctx->mqchunk = qchunk;
     const int p = ctx->geo.p;
     glc_points(p, ctx->glc.t);
     for (int k = 0; k <= p; ++k) {

@@ -61,13 +61,6 @@ void build_node_tables(const VelocitySet &vs, int p, int ne, double length, cons
 void build_transposed_node_tables(int N, int p, const std::vector<int32_t> &src, const std::vector<double> &w,
                                   int kt, std::vector<int32_t> &srcT, std::vector<double> &wT, int &band);
 
-// Distorted meshes: node displacements d ([3][N], periodic) of the equal-cell
-// grid, each cell the degree-p interpolant of its nodes' positions.  For every
-// velocity i and node n: the departure point's cell (linear cell index,
-// x fastest) in cell[i*N + n] and its local coordinates in
-// tloc[(a*q + i)*N + n]; the quadrature weight of every node (|det J| of the
-// cells that hold it) in nodew.  false (with why) if a cell map folds over or
-// a departure search does not converge.
 // Source windows of the distorted-mesh streaming (MAPPED_TILE node tiles, x
 // fastest): per velocity and tile, the departure cells of the tile's nodes
 // unwrapped next to each node's own cell span [lo, hi] per axis; win holds
@@ -78,13 +71,34 @@ void build_transposed_node_tables(int N, int p, const std::vector<int32_t> &src,
 int build_mapped_windows(int q, int p, const int ne[3], const std::vector<int32_t> &cell, const int tile[3],
                          int max_nodes, std::vector<int32_t> &win);
 
-// cjac: per cell point (cells x fastest, points x fastest within a cell) the
-// inverse of the cell map's Jacobian J = I + dD/dr (9 values, row-major) and
-// |det J|, for derivatives and quadrature in physical coordinates
+// Distorted meshes: node displacements d ([3][N], periodic) of the equal-cell
+// grid, each cell the degree-p interpolant of its nodes' positions.  For every
+// velocity i and node n: the departure point's cell (linear cell index,
+// x fastest) in cell[i*N + n] and its local coordinates in
+// tloc[(a*q + i)*N + n]; the quadrature weight of every node (|det J| of the
+// cells that hold it) in nodew; cjac: per cell point (cells x fastest, points
+// x fastest within a cell) the inverse of the cell map's Jacobian
+// J = I + dD/dr (9 values, row-major) and |det J|, for derivatives and
+// quadrature in physical coordinates.  false (with why) if a cell map folds
+// over or a departure search does not converge.
 bool build_mapped_tables(const VelocitySet &vs, int p, const int ne[3], const double length[3], const double *d,
                          double dt, std::vector<int32_t> &cell, std::vector<double> &tloc, std::vector<double> &nodew,
                          std::vector<double> &cjac, std::string &why);
 
+// Inverse departure lists of a distorted mesh (for the transposed
+// streaming): per velocity i the nodes grouped by departure cell, increasing
+// node index within a cell (a stable counting sort); the nodes departing into
+// cell c are order[i*N + k] for k in [start[i*(C+1) + c], start[i*(C+1) + c + 1]),
+// C = ncells.
+void build_mapped_inverse(int q, int64_t nodes, int ncells, const std::vector<int32_t> &cell,
+                          std::vector<int32_t> &order, std::vector<int32_t> &start);
+
+// Velocities per pass of the transposed distorted-mesh streaming: the partial
+// sums of a pass (2 (p+1)^3 values per cell and velocity) take at most the
+// bytes of one state (90 values per node)
+int mapped_t_chunk(int q, int p);
+
+// ---------------------------------------------------------------------------
 // ---------------------------------------------------------------------------
 // Device-side parameter blocks (passed by value to kernels)
 // ---------------------------------------------------------------------------
@@ -143,6 +157,10 @@ struct MappedTables {
     GlcBasis basis;
     const int32_t *win;     // [Q][tiles][4] source window per (velocity, tile), or NULL
     int win_nodes;          // largest window (nodes per population) of the blocks that use LDS
+    const int32_t *inv_order;   // [Q][N] nodes by departure cell (build_mapped_inverse)
+    const int32_t *inv_start;   // [Q][C + 1]
+    void *partial;              // [qchunk][C][2][(p+1)^3] partial sums of the transposed streaming
+    int qchunk;                 // velocities per pass (mapped_t_chunk)
 };
 
 struct CollisionParams {
@@ -240,7 +258,8 @@ hipError_t launch_stream_zt(const Geometry &g, const CellTables<S> &t, const S *
 // streaming on a distorted mesh (stream_mapped.hip)
 template <typename S>
 hipError_t launch_stream_mapped(const Geometry &g, const MappedTables &t, const S *in, S *out, hipStream_t st);
-// its transpose S^T (zeroes out, then adds each output's share atomically)
+// its transpose S^T (partial sums per departure cell, then per node; fixed
+// order, no atomics; t.inv_order, t.partial required)
 template <typename S>
 hipError_t launch_stream_mapped_t(const Geometry &g, const MappedTables &t, const S *in, S *out, hipStream_t st);
 // streaming on a graded mesh (stream_graded.hip)

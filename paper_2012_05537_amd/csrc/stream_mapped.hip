@@ -232,70 +232,119 @@ __global__ void __launch_bounds__(256, MAPPED_MIN_WAVES) k_stream_mapped_win(
     out[static_cast<int64_t>(Q + i) * N + n] = sg;
 }
 
-// Transposed streaming S^T on a distorted mesh: each (velocity, node) output
-// of S spreads its adjoint over the (P+1)^3 support values it was gathered
-// from, with the same weights.  The departure cells of different nodes
-// overlap arbitrarily, so the spreading adds atomically (hardware FP64/FP32
-// adds on device memory; the summation order, hence the last bits, varies
-// between runs).  out must be zero on entry.
-template <typename S, int P>
-__global__ void __launch_bounds__(256) k_stream_mapped_t(Geometry g, GlcBasis gb, const int32_t *__restrict__ cell,
-                                                         const S *__restrict__ tloc, const S *__restrict__ in,
-                                                         S *__restrict__ out)
+// Transposed streaming S^T on a distorted mesh, summed in a fixed order.
+// Output n of velocity i read the (P+1)^3 support values of its departure
+// cell c with the weights l_a(t_x) l_b(t_y) l_c(t_z); transposed, support
+// point (a, b, c) of cell c receives the sum, over the nodes n departing into
+// c, of the same weight times the adjoint of n.
+//   Pass 1 (k_stream_mapped_t_cells): one block per (cell, velocity) forms
+//   these (P+1)^3 partial sums for f and g, walking the cell's inverse list
+//   (build_mapped_inverse) in increasing node order.
+//   Pass 2 (k_stream_mapped_t_nodes): every node adds the partial sums of the
+//   1, 2, 4 or 8 cells that share it, in a fixed order.
+// No atomics: the result is the same bit for bit on every run.
+template <int P>
+constexpr int mt_threads()
 {
-    const int i = blockIdx.y;
+    return ((P + 1) * (P + 1) * (P + 1) + 63) / 64 * 64;
+}
+
+template <typename S, int P>
+__global__ void __launch_bounds__(mt_threads<P>()) k_stream_mapped_t_cells(
+    Geometry g, GlcBasis gb, const int32_t *__restrict__ order, const int32_t *__restrict__ start,
+    const S *__restrict__ tloc, const S *__restrict__ in, S *__restrict__ partial, int i0)
+{
+    constexpr int K = P + 1, K3 = K * K * K;
+    constexpr int CH = 64;                                 // list entries staged per round
+    __shared__ S lw[CH][3][K];
+    __shared__ S ly[CH][2];
+    const int c = blockIdx.x;
+    const int C = static_cast<int>(gridDim.x);
+    const int i = i0 + static_cast<int>(blockIdx.y);
     const int64_t N = g.nodes;
-    const int64_t n = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
-    if (n >= N) return;
-    const int Nx = g.N[0], Ny = g.N[1], Nz = g.N[2];
-    const int c = cell[static_cast<int64_t>(i) * N + n];
-    const int ex = c % g.nel[0], rest = c / g.nel[0];
-    const int ey = rest % g.nel[1], ez = rest / g.nel[1];
-    S w[3][P + 1];
+    const int32_t *st = start + static_cast<int64_t>(i) * (C + 1);
+    const int b0 = st[c], b1 = st[c + 1];
+    const int tid = threadIdx.x;
+    const int a = tid % K, b = (tid / K) % K, e = tid / (K * K);   // this thread's support point
+    S accf = 0, accg = 0;
+    for (int base = b0; base < b1; base += CH) {
+        const int nb = min(CH, b1 - base);
+        if (tid < nb) {
+            const int64_t n = order[static_cast<int64_t>(i) * N + base + tid];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const double t = static_cast<double>(tloc[(static_cast<int64_t>(a) * Q + i) * N + n]);
+            for (int ax = 0; ax < 3; ++ax) {
+                const double tt = static_cast<double>(tloc[(static_cast<int64_t>(ax) * Q + i) * N + n]);
 #pragma unroll
-        for (int k = 0; k <= P; ++k) {
-            double v = gb.inv_den[k];
+                for (int k = 0; k <= P; ++k) {
+                    double v = gb.inv_den[k];
 #pragma unroll
-            for (int m = 0; m <= P; ++m)
-                if (m != k) v *= t - gb.t[m];
-            w[a][k] = static_cast<S>(v);
+                    for (int m = 0; m <= P; ++m)
+                        if (m != k) v *= tt - gb.t[m];
+                    lw[tid][ax][k] = static_cast<S>(v);
+                }
+            }
+            ly[tid][0] = in[static_cast<int64_t>(i) * N + n];
+            ly[tid][1] = in[static_cast<int64_t>(Q + i) * N + n];
         }
-    }
-    const S lf = in[static_cast<int64_t>(i) * N + n];
-    const S lg = in[static_cast<int64_t>(Q + i) * N + n];
-    S *fo = out + static_cast<int64_t>(i) * N;
-    S *go = out + static_cast<int64_t>(Q + i) * N;
-#pragma unroll
-    for (int kz = 0; kz <= P; ++kz) {
-        int zz = ez * P + kz;
-        zz = zz >= Nz ? zz - Nz : zz;
-#pragma unroll
-        for (int ky = 0; ky <= P; ++ky) {
-            int yy = ey * P + ky;
-            yy = yy >= Ny ? yy - Ny : yy;
-            const int64_t row = (static_cast<int64_t>(zz) * Ny + yy) * Nx;
-            const S wyz = w[1][ky] * w[2][kz];
-            const S af = wyz * lf, ag = wyz * lg;
-#pragma unroll
-            for (int kx = 0; kx <= P; ++kx) {
-                int xx = ex * P + kx;
-                xx = xx >= Nx ? xx - Nx : xx;
-                unsafeAtomicAdd(fo + row + xx, w[0][kx] * af);
-                unsafeAtomicAdd(go + row + xx, w[0][kx] * ag);
+        __syncthreads();
+        if (tid < K3) {
+            for (int k = 0; k < nb; ++k) {
+                const S w = lw[k][0][a] * (lw[k][1][b] * lw[k][2][e]);
+                accf = fma(w, ly[k][0], accf);
+                accg = fma(w, ly[k][1], accg);
             }
         }
+        __syncthreads();
+    }
+    if (tid < K3) {
+        S *pp = partial + (static_cast<int64_t>(blockIdx.y) * C + c) * 2 * K3;
+        pp[tid] = accf;
+        pp[K3 + tid] = accg;
     }
 }
 
-template <typename S>
-__global__ void __launch_bounds__(256) k_fill_zero(int64_t n, S *__restrict__ out)
+template <typename S, int P>
+__global__ void __launch_bounds__(256) k_stream_mapped_t_nodes(Geometry g, const S *__restrict__ partial,
+                                                               S *__restrict__ out, int i0)
 {
-    for (int64_t k = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; k < n;
-         k += static_cast<int64_t>(gridDim.x) * blockDim.x)
-        out[k] = S(0);
+    constexpr int K = P + 1, K3 = K * K * K;
+    const int i = i0 + static_cast<int>(blockIdx.y);
+    const int64_t N = g.nodes;
+    const int64_t m = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+    if (m >= N) return;
+    const int Nx = g.N[0], Ny = g.N[1];
+    const int64_t NP = static_cast<int64_t>(Nx) * Ny;
+    const int gz = static_cast<int>(m / NP), gy = static_cast<int>((m / Nx) % Ny), gx = static_cast<int>(m % Nx);
+    const int C = g.nel[0] * g.nel[1] * g.nel[2];
+    // along an axis node q lies in cell q / P at local point q % P, and when
+    // q % P == 0 also in the previous cell (wrapped) at local point P
+    int cs[3][2], ls[3][2], nc[3];
+    const int gq[3] = {gx, gy, gz};
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        const int e = gq[ax] / P, l = gq[ax] - e * P;
+        nc[ax] = 1;
+        cs[ax][0] = e;
+        ls[ax][0] = l;
+        if (l == 0) {
+            cs[ax][1] = e == 0 ? g.nel[ax] - 1 : e - 1;
+            ls[ax][1] = P;
+            nc[ax] = 2;
+        }
+    }
+    const S *pb = partial + static_cast<int64_t>(blockIdx.y) * C * 2 * K3;
+    S sf = 0, sg = 0;
+    for (int z = 0; z < nc[2]; ++z)
+        for (int y = 0; y < nc[1]; ++y)
+            for (int x = 0; x < nc[0]; ++x) {
+                const int c = (cs[2][z] * g.nel[1] + cs[1][y]) * g.nel[0] + cs[0][x];
+                const int k = (ls[2][z] * K + ls[1][y]) * K + ls[0][x];
+                const S *pp = pb + static_cast<int64_t>(c) * 2 * K3;
+                sf += pp[k];
+                sg += pp[K3 + k];
+            }
+    out[static_cast<int64_t>(i) * N + m] = sf;
+    out[static_cast<int64_t>(Q + i) * N + m] = sg;
 }
 
 namespace {
@@ -303,16 +352,22 @@ namespace {
 template <typename S, int P>
 hipError_t launch_mt(const Geometry &g, const MappedTables &t, const S *in, S *out, hipStream_t st)
 {
+    const int64_t cells = static_cast<int64_t>(g.nel[0]) * g.nel[1] * g.nel[2];
     const int64_t bx = (g.nodes + 255) / 256;
-    if (bx > (int64_t(1) << 31) - 1) return hipErrorInvalidValue;
-    const int64_t total = 2 * static_cast<int64_t>(Q) * g.nodes;
-    const int64_t fb = std::min<int64_t>((total + 255) / 256, 8192);
-    hipLaunchKernelGGL((k_fill_zero<S>), dim3(static_cast<unsigned>(fb)), dim3(256), 0, st, total, out);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_stream_mapped_t<S, P>), dim3(static_cast<unsigned>(bx), Q), dim3(256), 0, st, g, t.basis,
-                       t.cell, static_cast<const S *>(t.tloc), in, out);
-    return hipGetLastError();
+    if (bx > (int64_t(1) << 31) - 1 || cells > (int64_t(1) << 31) - 1 || !t.inv_order || !t.partial)
+        return hipErrorInvalidValue;
+    for (int i0 = 0; i0 < Q; i0 += t.qchunk) {
+        const int qc = std::min(t.qchunk, Q - i0);
+        hipLaunchKernelGGL((k_stream_mapped_t_cells<S, P>), dim3(static_cast<unsigned>(cells), qc),
+                           dim3(mt_threads<P>()), 0, st, g, t.basis, t.inv_order, t.inv_start,
+                           static_cast<const S *>(t.tloc), in, static_cast<S *>(t.partial), i0);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_stream_mapped_t_nodes<S, P>), dim3(static_cast<unsigned>(bx), qc), dim3(256), 0, st, g,
+                           static_cast<const S *>(t.partial), out, i0);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 template <typename S, int P>

@@ -264,4 +264,27 @@ int build_mapped_windows(int q, int p, const int ne[3], const std::vector<int32_
     return largest;
 }
 
+void build_mapped_inverse(int q, int64_t nodes, int ncells, const std::vector<int32_t> &cell,
+                          std::vector<int32_t> &order, std::vector<int32_t> &start)
+{
+    order.assign(static_cast<size_t>(q) * nodes, 0);
+    start.assign(static_cast<size_t>(q) * (ncells + 1), 0);
+    for (int i = 0; i < q; ++i) {
+        const int32_t *ci = &cell[static_cast<size_t>(i) * nodes];
+        int32_t *st = &start[static_cast<size_t>(i) * (ncells + 1)];
+        for (int64_t n = 0; n < nodes; ++n) ++st[ci[n] + 1];
+        for (int c = 0; c < ncells; ++c) st[c + 1] += st[c];
+        std::vector<int32_t> next(st, st + ncells);
+        int32_t *oi = &order[static_cast<size_t>(i) * nodes];
+        for (int64_t n = 0; n < nodes; ++n) oi[next[ci[n]]++] = static_cast<int32_t>(n);
+    }
+}
+
+int mapped_t_chunk(int q, int p)
+{
+    const int k3 = (p + 1) * (p + 1) * (p + 1);
+    // a pass holds 2 k3 values per cell and velocity; a state 2 q p^3 per cell
+    return std::max(1, std::min(q, (2 * q * p * p * p) / (2 * k3)));
+}
+
 }  // namespace sllbm
