@@ -170,7 +170,7 @@ def measure_steps(args, ctx, stream_kernel, table_bytes=0):
     return dict(nodes=nodes, wall=wall, walls=walls, kernels=kernels, bytes=bytes_per_launch, finite=ok, totals=tot)
 
 
-def run_adjoint(wl, precision, graded=False):
+def run_adjoint(wl, precision, mesh="equal"):
     """Wall time of a checkpointed rollout gradient of the workload (forward
     rollout with checkpoints, then the reverse sweep with segment replay), and
     the ratio backward / forward."""
@@ -182,10 +182,13 @@ def run_adjoint(wl, precision, graded=False):
 
     ctx = SLLBM(wl["n_el"], wl["p"], wl["dt"], wl["mu_inf"], gamma=wl["gamma"], prandtl=wl["Pr"],
                 precision=precision)
-    if graded:
+    if mesh == "graded":
         w = inputs.graded_widths(wl["n_el"], amplitude=inputs.GRADED["amplitude"])
         ctx.set_mesh(w, w, w)
     xs, ys, zs = (t.numpy() for t in ctx.node_coords())
+    if mesh == "distorted":
+        X, Y, Z = inputs.mesh(xs, ys, zs)
+        ctx.set_displacement(inputs.distortion(X, Y, Z, 2 * math.pi / wl["n_el"], inputs.DISTORTED["amplitude"]))
     md = wl.get("modes") or dict(seed=2012, count=16, scale=0.01)
     modes = inputs.fourier_modes(md["seed"], md["count"], wl["Ma"], wl["gamma"], md["scale"])
     rho, u, T = inputs.tgv_fields(xs, ys, zs, wl["Ma"], wl["gamma"])
@@ -210,8 +213,9 @@ def run_adjoint(wl, precision, graded=False):
     # checkpoints, segment record and adjoint buffers (torch) plus the library's two state buffers
     peak_gb = (torch.cuda.max_memory_allocated() + 2 * ctx.state_bytes) / 1e9
     ctx.close()
-    cells = "cosine-graded cells" if graded else "cells"
-    return {"workload": f"{wl['name']}{'-graded' if graded else ''}: {wl['n_el']}^3 {cells} p={wl['p']} "
+    cells = {"equal": "cells", "graded": "cosine-graded cells",
+             "distorted": f"distorted cells (displacement {inputs.DISTORTED['amplitude']} h)"}[mesh]
+    return {"workload": f"{wl['name']}{'' if mesh == 'equal' else '-' + mesh}: {wl['n_el']}^3 {cells} p={wl['p']} "
                         f"({ctx.nodes} nodes), {steps} steps, "
                         f"{len(modes)} modes + mu_inf, checkpoint {wl.get('checkpoint', 10)}",
             "forward_s": t1 - t0, "backward_s": t2 - t1, "backward_over_forward": (t2 - t1) / (t1 - t0),
@@ -403,7 +407,7 @@ def main():
         if args.adjoint_steps is not None:
             aover["steps"] = args.adjoint_steps
         wa = inputs.workload(args.adjoint_workload, **aover)
-        out["adjoint"] = run_adjoint(wa, 0 if wa["precision"] == "fp64" else 1, graded=args.mesh == "graded")
+        out["adjoint"] = run_adjoint(wa, 0 if wa["precision"] == "fp64" else 1, mesh=args.mesh)
     if not args.no_cpu_baseline and args.mesh != "distorted":
         if two_d:
             out["cpu_baseline"] = cpu_baseline_2d(wl, args.cpu_budget)

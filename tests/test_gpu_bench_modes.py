@@ -58,3 +58,18 @@ def test_bench_default_headline_and_secondary_lines():
     assert d["fp32_over_fp64"] > 1.0
     for line in (d, d["fp32_mixed"], d["c2_fp64"]):
         assert 0 < line["roofline"]["frac"] < 1 and 0 < line["roofline"]["step_frac"] < 1
+
+
+@pytest.mark.parametrize("mesh", ["graded", "distorted"])
+def test_bench_adjoint_on_mesh(mesh):
+    """The rollout-gradient timing follows the mesh of the bench line."""
+    require_gpu()
+    print("bench adjoint on", mesh, flush=True)
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--mesh", mesh, "--steps", "2", "--warmup", "1",
+                        "--reps", "1", "--no-secondary", "--no-cpu-baseline", "--adjoint-workload", "c4",
+                        "--adjoint-steps", "6"], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr[-2000:]
+    d = json.loads([l for l in r.stdout.splitlines() if l.strip()][-1])
+    a = d["adjoint"]
+    assert a["workload"].startswith(f"c4-{mesh}:") and a["grad_finite"]
+    assert a["forward_s"] > 0 and a["backward_s"] > 0
