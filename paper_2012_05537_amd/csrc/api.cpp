@@ -612,7 +612,7 @@ int sllbm_set_displacement(sllbm_ctx *ctx, const double *d)
     const int ncells = ctx->geo.nel[0] * ctx->geo.nel[1] * ctx->geo.nel[2];
     std::vector<int32_t> minv, minv_start;
     build_mapped_inverse(ctx->vs.q, N, ncells, cell, minv, minv_start);
-    const int qchunk = mapped_t_chunk(ctx->vs.q, ctx->geo.p);
+    const int qchunk = mapped_t_chunk(ctx->vs.q, ctx->geo.p, ncells, ctx->elem);
     const int k3 = (ctx->geo.p + 1) * (ctx->geo.p + 1) * (ctx->geo.p + 1);
     const size_t pbytes = static_cast<size_t>(qchunk) * ncells * 2 * k3 * ctx->elem;
     int32_t *dc = nullptr, *dwin = nullptr, *dinv = nullptr, *dinvs = nullptr;

@@ -94,9 +94,9 @@ void build_mapped_inverse(int q, int64_t nodes, int ncells, const std::vector<in
                           std::vector<int32_t> &order, std::vector<int32_t> &start);
 
 // Velocities per pass of the transposed distorted-mesh streaming: the partial
-// sums of a pass (2 (p+1)^3 values per cell and velocity) take at most the
-// bytes of one state (90 values per node)
-int mapped_t_chunk(int q, int p);
+// sums of a pass (2 (p+1)^3 values of elem bytes per cell and velocity) take
+// at most the bytes of one state, or 256 MB if that is more
+int mapped_t_chunk(int q, int p, int64_t ncells, size_t elem);
 
 // ---------------------------------------------------------------------------
 // ---------------------------------------------------------------------------

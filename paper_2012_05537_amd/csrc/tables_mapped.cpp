@@ -280,11 +280,14 @@ void build_mapped_inverse(int q, int64_t nodes, int ncells, const std::vector<in
     }
 }
 
-int mapped_t_chunk(int q, int p)
+int mapped_t_chunk(int q, int p, int64_t ncells, size_t elem)
 {
-    const int k3 = (p + 1) * (p + 1) * (p + 1);
-    // a pass holds 2 k3 values per cell and velocity; a state 2 q p^3 per cell
-    return std::max(1, std::min(q, (2 * q * p * p * p) / (2 * k3)));
+    const int64_t k3 = static_cast<int64_t>(p + 1) * (p + 1) * (p + 1);
+    const int64_t per_velocity = ncells * 2 * k3 * static_cast<int64_t>(elem);
+    // a pass may hold one state's bytes (2 q p^3 values per cell), or 256 MB
+    // on small grids, where fewer passes mean fewer launches
+    const int64_t budget = std::max<int64_t>(ncells * 2 * q * p * p * p * static_cast<int64_t>(elem), int64_t(256) << 20);
+    return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(q, budget / per_velocity)));
 }
 
 }  // namespace sllbm
