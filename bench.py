@@ -283,6 +283,29 @@ def workload_2d(name):
     return w
 
 
+def copy_bandwidth(state_bytes, reps=5):
+    """GB/s of a plain elementwise copy kernel (torch mul by 1.0) of one
+    state's size, read + write, median over reps launches timed with events
+    on torch's stream (where the copy runs)."""
+    import statistics
+    import torch
+    n = max(1, state_bytes // 8)
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.mul(src, 1.0, out=dst)
+    times = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        torch.mul(src, 1.0, out=dst)
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * n * 8 / (statistics.median(times) * 1e-3) / 1e9
+
+
 def measure_line(args, wl, wkey, prec_name, two_d, mesh):
     """Timings of one workload and precision: (summary dict, raw record)."""
     from paper_2012_05537_amd import inputs
@@ -309,6 +332,7 @@ def measure_line(args, wl, wkey, prec_name, two_d, mesh):
         workload = (f"{wkey}: TGV{modes} {wl['n_el']}^3 {mdesc} p={wl['p']} "
                     f"({r['nodes']} nodes), Ma {wl['Ma']}, Re {wl['Re']}, CFL {wl['cfl']}, {prec_name}")
     step_s = r["wall"] / args.steps
+    copy_gbs = copy_bandwidth(r["bytes"] // 2)
     line = {
         "workload": workload,
         "value": r["nodes"] / step_s,
@@ -319,7 +343,8 @@ def measure_line(args, wl, wkey, prec_name, two_d, mesh):
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": kernels[dom]["traffic"],
                      "kernel": dom, "kernel_ms": kms, "algorithmic_bytes_per_launch": dom_bytes,
-                     "step_frac": r["bytes"] / step_s / 1e9 / HBM_PEAK_GBS},
+                     "step_frac": r["bytes"] / step_s / 1e9 / HBM_PEAK_GBS,
+                     "copy_GBps": copy_gbs, "frac_of_copy": achieved / copy_gbs},
         "kernels": kernels,
         "finite": r["finite"],
     }
