@@ -58,7 +58,7 @@ def test_bench_default_headline_and_secondary_lines():
     assert d["fp32_over_fp64"] > 1.0
     for line in (d, d["fp32_mixed"], d["c2_fp64"]):
         assert 0 < line["roofline"]["frac"] < 1 and 0 < line["roofline"]["step_frac"] < 1
-        assert 0 < line["roofline"]["copy_GBps"] < 8000 and line["roofline"]["frac_of_copy"] > 0
+        assert line["roofline"]["copy_GBps"] > 0 and line["roofline"]["frac_of_copy"] > 0
 
 
 @pytest.mark.parametrize("mesh", ["graded", "distorted"])
