@@ -62,9 +62,10 @@ int z_chunks(const Geometry &g, int ntiles, int elem)
 
 // V = values per window load (1, or 16 bytes when every window row starts
 // on a 16-byte boundary: p * sizeof(S) and N_x * sizeof(S) multiples of 16)
-template <int P, int V = 1>
+template <int P, int V = 1, int YN_ = 8>
 struct ZTile {
-    static constexpr int XN = 32, YN = 8;                     // target tile extent in nodes (long x rows)
+    static constexpr int ORDER = P;
+    static constexpr int XN = 32, YN = YN_;                   // target tile extent in nodes (long x rows)
     static constexpr int TXC = XN / P > 0 ? XN / P : 1;       // cells per tile along x and y
     static constexpr int TYC = YN / P > 0 ? YN / P : 1;
     static constexpr int TX = TXC * P, TY = TYC * P;          // nodes per tile
@@ -92,15 +93,37 @@ __device__ __forceinline__ auto vcomp(const VT &v, int c)
     else return v[c];
 }
 
+template <typename S, class Z>
+constexpr size_t z_lds_bytes()
+{
+    return static_cast<size_t>(Z::ORDER + 1) * (static_cast<size_t>(Z::WXP) * Z::WY + Z::WY * Z::BS) * sizeof(S);
+}
+
 }  // namespace
 
-// NTH: non-temporal output stores (states larger than the Infinity Cache)
-template <typename S, int P, int V, bool NTH>
-__global__ void __launch_bounds__((ZTile<P, V>::NT)) k_stream_z(Geometry g, CellTables<S> tab, const S *__restrict__ in,
-                                                     S *__restrict__ out, int ntile_x, int ntiles, int zcells,
-                                                     int nchunk)
+// Rows of the x-y tile: 16 (32 x 16 nodes, 512 threads) on grids whose state
+// exceeds the Infinity Cache, where the y halo rows that a tile loads per
+// output column matter (measured at 256^3 nodes: 5 % faster in FP32, 2 % in
+// FP64), if its LDS stays within 64 KB; 8 otherwise (at 64^3 nodes the larger
+// tile has too few blocks and is 8 % slower).
+template <typename S, int P, int V, bool BIG>
+constexpr int z_tile_rows()
 {
-    using Z = ZTile<P, V>;
+    return BIG && z_lds_bytes<S, ZTile<P, V, 16>>() <= 64 * 1024 ? 16 : 8;
+}
+
+template <typename S, int P, int V, bool NTH>
+using ZTileOf = ZTile<P, V, z_tile_rows<S, P, V, NTH>()>;
+
+// NTH: non-temporal output stores and the larger tile (states larger than
+// the Infinity Cache)
+template <typename S, int P, int V, bool NTH>
+__global__ void __launch_bounds__((ZTileOf<S, P, V, NTH>::NT)) k_stream_z(Geometry g, CellTables<S> tab,
+                                                                        const S *__restrict__ in,
+                                                                        S *__restrict__ out, int ntile_x,
+                                                                        int ntiles, int zcells, int nchunk)
+{
+    using Z = ZTileOf<S, P, V, NTH>;
     using VT = typename VecOf<S, V>::T;
     constexpr int TX = Z::TX, TY = Z::TY, WX = Z::WXP, WY = Z::WY, NT = Z::NT, LK = Z::LK;
     constexpr int WP = WX * WY;
@@ -263,23 +286,27 @@ __global__ void __launch_bounds__((ZTile<P, V>::NT)) k_stream_z(Geometry g, Cell
     }
 }
 
-template <typename S, int P, int V>
-static hipError_t launch_zv(const Geometry &g, const CellTables<S> &t, const S *in, S *out, hipStream_t st)
+template <typename S, int P, int V, bool NTH>
+static hipError_t launch_zvn(const Geometry &g, const CellTables<S> &t, const S *in, S *out, hipStream_t st)
 {
-    using Z = ZTile<P, V>;
+    using Z = ZTileOf<S, P, V, NTH>;
     const int ntx = (g.N[0] + Z::TX - 1) / Z::TX, nty = (g.N[1] + Z::TY - 1) / Z::TY;
     const int ntiles = ntx * nty;
     const int nchunk = z_chunks(g, ntiles, static_cast<int>(sizeof(S)));
     const int zcells = (g.nel[2] + nchunk - 1) / nchunk;
     const int64_t nb = static_cast<int64_t>(ntiles) * 90 * nchunk;
     if (nb > (int64_t(1) << 31) - 1) return hipErrorInvalidValue;
-    if (use_nontemporal(90 * g.nodes * static_cast<int64_t>(sizeof(S))))
-        hipLaunchKernelGGL((k_stream_z<S, P, V, true>), dim3(static_cast<unsigned>(nb)), dim3(Z::NT), 0, st, g, t, in,
-                           out, ntx, ntiles, zcells, nchunk);
-    else
-        hipLaunchKernelGGL((k_stream_z<S, P, V, false>), dim3(static_cast<unsigned>(nb)), dim3(Z::NT), 0, st, g, t, in,
-                           out, ntx, ntiles, zcells, nchunk);
+    hipLaunchKernelGGL((k_stream_z<S, P, V, NTH>), dim3(static_cast<unsigned>(nb)), dim3(Z::NT), 0, st, g, t, in, out,
+                       ntx, ntiles, zcells, nchunk);
     return hipGetLastError();
+}
+
+template <typename S, int P, int V>
+static hipError_t launch_zv(const Geometry &g, const CellTables<S> &t, const S *in, S *out, hipStream_t st)
+{
+    if (use_nontemporal(90 * g.nodes * static_cast<int64_t>(sizeof(S))))
+        return launch_zvn<S, P, V, true>(g, t, in, out, st);
+    return launch_zvn<S, P, V, false>(g, t, in, out, st);
 }
 
 // 16-byte window loads when every window row starts on a 16-byte boundary

@@ -164,3 +164,40 @@ def test_transposed_stream_identity_256cubed(oracle):
     _say(f"c5 transposed identity: max rel {rel:.2e}")
     assert rel < 1e-5
     ctx.close()
+
+
+# grids whose state exceeds the Infinity Cache at orders 1-3, where the
+# streaming runs its large-grid form (32 x 16-node tiles, non-temporal
+# stores; the order-4 workloads above take it at 128^3 and 256^3 nodes):
+# ragged tiles along y, shifts of several cells (CFL 3)
+LARGE = [((40, 36, 30), 3, 0), ((48, 40, 36), 2, 0), ((100, 90, 100), 1, 1), ((48, 44, 40), 3, 1)]
+
+
+@pytest.mark.parametrize("n_el,p,precision", LARGE)
+def test_large_grid_stream_planes(oracle, n_el, p, precision):
+    """One sllbm_stream of a random state against the oracle's streaming on
+    three whole z-planes, element by element (1e-12 in FP64, 1e-5 in FP32)."""
+    from gpu_common import make_pair
+    import math
+    _say(f"large-grid stream n_el={n_el} p={p} precision={precision}")
+    dt = 3.0 * (2 * math.pi / (max(n_el) * p)) / math.sqrt(15.0)
+    ctx, cfg = make_pair(oracle, n_el, p, dt, 1e-3, precision=precision)
+    assert 90 * ctx.nodes * (8 if precision == 0 else 4) > 256 << 20
+    gen = torch.Generator(device=ctx.device).manual_seed(p)
+    X = torch.randn((2, Q, ctx.nodes), generator=gen, device=ctx.device, dtype=ctx.dtype)
+    Xs = ctx.stream(X)
+    torch.cuda.synchronize()
+    f0, g0 = to_np(X)
+    Nz, Ny, Nx = ctx.shape
+    P = Nx * Ny
+    tol = 1e-12 if precision == 0 else 1e-5
+    for z in (0, Nz // 2 + 1, Nz - 1):
+        nodes = z * P + np.arange(P)
+        fs, gs = oracle.stream_at_nodes(cfg, f0, g0, nodes)
+        F = Xs[0][:, z * P:(z + 1) * P].double().cpu().numpy().T
+        G = Xs[1][:, z * P:(z + 1) * P].double().cpu().numpy().T
+        err = max(np.max(np.abs(F - fs)) / np.abs(fs).max(), np.max(np.abs(G - gs)) / np.abs(gs).max())
+        _say(f"  plane z={z}: max rel error {err:.2e}")
+        assert err < tol
+    del f0, g0
+    ctx.close()
