@@ -30,6 +30,7 @@
 #include <algorithm>
 
 #include "collision.h"
+#include "nt.h"
 #include "sllbm_internal.h"
 #include "velset.h"
 
@@ -97,7 +98,8 @@ __device__ __forceinline__ double bder(const Bracket &b, double c)    // d b / d
 // Grid-stride over lane pairs; the whole block runs the same number of
 // iterations, so every shuffle partner is live.  mu and lam may be the same
 // buffer: each lane reads its 45 values before writing them.
-template <typename S>
+// NTH: non-temporal loads and stores (states larger than the Infinity Cache)
+template <typename S, bool NTH>
 __global__ void __launch_bounds__(256) k_collide_vjp(int64_t N, CollisionParams cp, const S *__restrict__ X,
                                                      const S *mu, S *lam, double *__restrict__ dmu_part)
 {
@@ -122,8 +124,8 @@ __global__ void __launch_bounds__(256) k_collide_vjp(int64_t N, CollisionParams 
         double h[vs::Q];
 #pragma unroll
         for (int i = 0; i < vs::Q; ++i) {
-            h[i] = static_cast<double>(X[off + static_cast<int64_t>(i) * N]);
-            al[i] = static_cast<double>(mu[off + static_cast<int64_t>(i) * N]);
+            h[i] = static_cast<double>(load_hint<NTH>(&X[off + static_cast<int64_t>(i) * N]));
+            al[i] = static_cast<double>(load_hint<NTH>(&mu[off + static_cast<int64_t>(i) * N]));
         }
         rm = raw_moments<D3Q45>(h);
 #pragma unroll
@@ -279,7 +281,7 @@ __global__ void __launch_bounds__(256) k_collide_vjp(int64_t N, CollisionParams 
         {   // rest velocity: xi = 0
             double r = one_m * al[0] - T0 + kg;
             if (!is_g) r += base_f;
-            lp[0] = static_cast<S>(r);
+            store_hint<NTH>(&lp[0], static_cast<S>(r));
         }
 #pragma unroll
         for (int q = 0; q < 22; ++q) {
@@ -295,8 +297,8 @@ __global__ void __launch_bounds__(256) k_collide_vjp(int64_t N, CollisionParams 
             const double common = kg + x2g * (base_f + K_bar * vs::T.x2[i]);
             const double ri = one_m * al[i] + common + jx + (T3 - T2 + T1 - T0);
             const double rj = one_m * al[j] + common - jx - (T3 + T2 + T1 + T0);
-            lp[static_cast<int64_t>(i) * N] = static_cast<S>(ri);
-            lp[static_cast<int64_t>(j) * N] = static_cast<S>(rj);
+            store_hint<NTH>(&lp[static_cast<int64_t>(i) * N], static_cast<S>(ri));
+            store_hint<NTH>(&lp[static_cast<int64_t>(j) * N], static_cast<S>(rj));
         }
     }
 
@@ -773,8 +775,12 @@ hipError_t Launch<S>::collide_vjp(const Geometry &g, const CollisionParams &cp, 
 {
     // lam <- J_C(X_n)^T lam in place
     const int blocks = static_cast<int>(std::min<int64_t>((2 * g.nodes + 255) / 256, nblocks));
-    hipLaunchKernelGGL((k_collide_vjp<S>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, g.nodes, cp,
-                       state_n, lam, lam, dmu_partials);
+    if (use_nontemporal(90 * g.nodes * static_cast<int64_t>(sizeof(S))))
+        hipLaunchKernelGGL((k_collide_vjp<S, true>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, g.nodes,
+                           cp, state_n, lam, lam, dmu_partials);
+    else
+        hipLaunchKernelGGL((k_collide_vjp<S, false>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, g.nodes,
+                           cp, state_n, lam, lam, dmu_partials);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (dmu) {

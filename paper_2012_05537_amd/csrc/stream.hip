@@ -349,7 +349,8 @@ struct ZTileT {
     static constexpr int BS = TX % 2 ? TX : TX + 1;
 };
 
-template <typename S, int P, int V>
+// NTH: non-temporal output stores (states larger than the Infinity Cache)
+template <typename S, int P, int V, bool NTH>
 __global__ void __launch_bounds__((ZTileT<P, V>::NT))
     k_stream_zt(Geometry g, CellTables<S> tab, const S *__restrict__ in, S *__restrict__ out, int ntile_x,
                 int ntiles, int zcells, int nchunk)
@@ -498,7 +499,7 @@ __global__ void __launch_bounds__((ZTileT<P, V>::NT))
 #pragma unroll
                     for (int j = 0; j < P; ++j) acc = fma(wzu[j][P], a[j], acc);
                 }
-                dst[static_cast<int64_t>(ez * P + k) * NP + oxy] = acc;
+                store_hint<NTH>(&dst[static_cast<int64_t>(ez * P + k) * NP + oxy], acc);
             }
         }
 #pragma unroll
@@ -530,8 +531,12 @@ static hipError_t launch_ztv(const Geometry &g, const CellTables<S> &t, const S 
     const int zcells = (g.nel[2] + nchunk - 1) / nchunk;
     const int64_t nb = static_cast<int64_t>(ntiles) * 90 * nchunk;
     if (nb > (int64_t(1) << 31) - 1) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_stream_zt<S, P, V>), dim3(static_cast<unsigned>(nb)), dim3(Z::NT), 0, st, g, t, in, out,
-                       ntx, ntiles, zcells, nchunk);
+    if (use_nontemporal(90 * g.nodes * static_cast<int64_t>(sizeof(S))))
+        hipLaunchKernelGGL((k_stream_zt<S, P, V, true>), dim3(static_cast<unsigned>(nb)), dim3(Z::NT), 0, st, g, t,
+                           in, out, ntx, ntiles, zcells, nchunk);
+    else
+        hipLaunchKernelGGL((k_stream_zt<S, P, V, false>), dim3(static_cast<unsigned>(nb)), dim3(Z::NT), 0, st, g, t,
+                           in, out, ntx, ntiles, zcells, nchunk);
     return hipGetLastError();
 }
 
