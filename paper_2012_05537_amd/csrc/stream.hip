@@ -36,26 +36,28 @@ __device__ __forceinline__ int wrapi(int x, int n)
 
 constexpr int64_t ZCHUNK_TARGET_BLOCKS = 2048;
 constexpr int ZCHUNK_MIN_CELLS = 4;
-constexpr int ZCHUNK_MAX_CELL_BYTES = 64;   // cells per chunk times the element size
+constexpr int ZCHUNK_MAX_CELL_BYTES = 64;   // cells per chunk times the element size (8 x 32-node tiles)
+constexpr int ZCHUNK_MAX_CELLS_LARGE = 32;  // cells per chunk with the 32 x 16-node tiles of large grids
 
 // Number of z-chunks of a march over ntiles x-y tiles and 90 planes.  Small
 // grids split the march until the grid has a few blocks per CU slot.  Every
-// grid caps a chunk at ZCHUNK_MAX_CELL_BYTES / elem cells (8 in FP64, 16 in
-// FP32): blocks of one plane start in (chunk, tile) order, so neighbouring
-// tiles march through the same z-rows at nearly the same time and more of the
-// x-y halo rows that one tile loads are still in L2 when its neighbours read
-// them; blocks that marched the whole axis drift apart on large grids.
-// Measured at 256^3 nodes (FP64): reads of 1.87x the algorithmic bytes with
-// whole-axis marches, 1.31x with 8-cell chunks (1.59x and 1.10x at 128^3).
-// Each chunk re-reads P + 1 rows.
-int z_chunks(const Geometry &g, int ntiles, int elem)
+// grid caps a chunk at max_cells cells: blocks of one plane start in
+// (chunk, tile) order, so neighbouring tiles march through the same z-rows at
+// nearly the same time and more of the x-y halo rows that one tile loads are
+// still in L2 when its neighbours read them; blocks that marched the whole
+// axis drift apart on large grids.  Each chunk re-reads P + 1 rows.
+// Measured at 256^3 nodes (FP64) with 32 x 8-node tiles: reads of 1.87x the
+// algorithmic bytes with whole-axis marches, 1.31x with 8-cell chunks (1.59x
+// and 1.10x at 128^3), hence ZCHUNK_MAX_CELL_BYTES / elem cells (8 in FP64,
+// 16 in FP32).  The 32 x 16-node tiles of large grids have half the x-y halo
+// per output, and there 32-cell chunks are 2-4 % faster than 8 or 16 cells.
+int z_chunks(const Geometry &g, int ntiles, int max_cells)
 {
     int nchunk = 1;
     while (nchunk < g.nel[2] && static_cast<int64_t>(ntiles) * 90 * nchunk < ZCHUNK_TARGET_BLOCKS &&
            g.nel[2] / (2 * nchunk) >= ZCHUNK_MIN_CELLS)
         nchunk *= 2;
-    const int cap = ZCHUNK_MAX_CELL_BYTES / elem;
-    nchunk = std::max(nchunk, (g.nel[2] + cap - 1) / cap);
+    nchunk = std::max(nchunk, (g.nel[2] + max_cells - 1) / max_cells);
     const int zcells = (g.nel[2] + nchunk - 1) / nchunk;
     return (g.nel[2] + zcells - 1) / zcells;
 }
@@ -292,7 +294,8 @@ static hipError_t launch_zvn(const Geometry &g, const CellTables<S> &t, const S 
     using Z = ZTileOf<S, P, V, NTH>;
     const int ntx = (g.N[0] + Z::TX - 1) / Z::TX, nty = (g.N[1] + Z::TY - 1) / Z::TY;
     const int ntiles = ntx * nty;
-    const int nchunk = z_chunks(g, ntiles, static_cast<int>(sizeof(S)));
+    const int nchunk = z_chunks(g, ntiles, Z::YN == 16 ? ZCHUNK_MAX_CELLS_LARGE
+                                                     : ZCHUNK_MAX_CELL_BYTES / static_cast<int>(sizeof(S)));
     const int zcells = (g.nel[2] + nchunk - 1) / nchunk;
     const int64_t nb = static_cast<int64_t>(ntiles) * 90 * nchunk;
     if (nb > (int64_t(1) << 31) - 1) return hipErrorInvalidValue;
@@ -527,7 +530,7 @@ static hipError_t launch_ztv(const Geometry &g, const CellTables<S> &t, const S 
     using Z = ZTileT<P, V>;
     const int ntx = (g.N[0] + Z::TX - 1) / Z::TX, nty = (g.N[1] + Z::TY - 1) / Z::TY;
     const int ntiles = ntx * nty;
-    const int nchunk = z_chunks(g, ntiles, static_cast<int>(sizeof(S)));   // each chunk re-reads P rows
+    const int nchunk = z_chunks(g, ntiles, ZCHUNK_MAX_CELL_BYTES / static_cast<int>(sizeof(S)));   // each chunk re-reads P rows
     const int zcells = (g.nel[2] + nchunk - 1) / nchunk;
     const int64_t nb = static_cast<int64_t>(ntiles) * 90 * nchunk;
     if (nb > (int64_t(1) << 31) - 1) return hipErrorInvalidValue;
