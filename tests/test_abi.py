@@ -118,7 +118,6 @@ def test_null_arguments(lib):
 
 def test_missing_library_fails_loudly(tmp_path):
     """The binding has no fallback: a missing libsllbm.so is an error."""
-    import importlib
     import paper_2012_05537_amd.sllbm as S
     saved = S._lib
     try:

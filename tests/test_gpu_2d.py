@@ -8,7 +8,6 @@ several y-chunks, one-cell axes, shifts of several cells, both load paths
 (16-byte window loads at even p in FP64, element loads at odd p), the full
 512^2-node Riemann workload and the periodic Sod tube.
 """
-import math
 import sys
 
 import numpy as np
