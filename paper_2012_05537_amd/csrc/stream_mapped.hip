@@ -1,17 +1,21 @@
 // Semi-Lagrangian streaming on a distorted mesh (Sec. II A: departure points
 // traced once through the cells; with distorted cells the interpolation does
 // not factorise per axis and the paper's subsection "Numerical efficiency"
-// expects a memory-bound kernel).
+// expects a memory-bound kernel), and its transpose.
 //
 // The cells are the isoparametric images of the equal-cell reference grid
 // (node displacements, build_mapped_tables); populations are interpolated in
 // reference coordinates.  The host stores, per velocity and node, the
 // departure cell and the three local coordinates (28 bytes in FP64, 16 in
-// FP32); the weights are
-// formed here ("matrix-free": 3 (P+1) Lagrange values instead of (P+1)^3
-// stored coefficients).  A thread owns one (velocity, node) pair and gathers
-// the (P+1)^3 support values of f and of g (the two populations share the
-// departure point); x-runs of P + 1 values are contiguous, neighbouring
+// FP32); the weights are formed here ("matrix-free": 3 (P+1) Lagrange values
+// instead of (P+1)^3 stored coefficients).  Three kernels:
+//   * k_stream_mapped_win (the forward streaming): a block per velocity and
+//     node tile stages the tile's source window in LDS and gathers from it;
+//   * k_stream_mapped: the same gather straight from global memory, one
+//     thread per (velocity, node) (the blocks of k_stream_mapped_win whose
+//     window does not fit use the same summation);
+//   * k_stream_mapped_t_cells / _nodes: the transpose in a fixed order.
+// In k_stream_mapped, x-runs of P + 1 values are contiguous and neighbouring
 // threads read neighbouring runs, so the gathers are served by L1/L2.  When
 // rows and planes start on 16-byte boundaries and P is a multiple of the
 // vector width V, the first P values of a run (never wrapped: the cell's
