@@ -171,11 +171,13 @@ def test_transposed_stream_identity_256cubed(oracle):
     ctx.close()
 
 
-# grids whose state exceeds the Infinity Cache at orders 1-3, where the
-# streaming runs its large-grid form (32 x 16-node tiles, non-temporal
-# stores; the order-4 workloads above take it at 128^3 and 256^3 nodes):
-# ragged tiles along y, shifts of several cells (CFL 3)
-LARGE = [((40, 36, 30), 3, 0), ((48, 40, 36), 2, 0), ((100, 90, 100), 1, 1), ((48, 44, 40), 3, 1)]
+# grids whose state exceeds the Infinity Cache at orders 1-3, 5 and 6, where
+# the streaming runs its large-grid form (non-temporal stores; 32 x 16-node
+# tiles except at orders 5 and 6 in FP64, whose LDS keeps 8-row tiles; the
+# order-4 workloads above take it at 128^3 and 256^3 nodes): ragged tiles
+# along y, shifts of several cells (CFL 3)
+LARGE = [((40, 36, 30), 3, 0), ((48, 40, 36), 2, 0), ((100, 90, 100), 1, 1), ((48, 44, 40), 3, 1),
+         ((24, 20, 18), 5, 0), ((16, 16, 16), 6, 0), ((28, 24, 20), 5, 1)]
 
 
 @pytest.mark.parametrize("n_el,p,precision", LARGE)
