@@ -183,7 +183,9 @@ LARGE = [((40, 36, 30), 3, 0), ((48, 40, 36), 2, 0), ((100, 90, 100), 1, 1), ((4
 @pytest.mark.parametrize("n_el,p,precision", LARGE)
 def test_large_grid_stream_planes(oracle, n_el, p, precision):
     """One sllbm_stream of a random state against the oracle's streaming on
-    three whole z-planes, element by element (1e-12 in FP64, 1e-5 in FP32)."""
+    three whole z-planes, element by element (1e-12 in FP64, 1e-5 in FP32),
+    and the transposed streaming's identity <S x, y> = <x, S^T y> per
+    population and velocity."""
     from gpu_common import make_pair
     import math
     _say(f"large-grid stream n_el={n_el} p={p} precision={precision}")
@@ -207,4 +209,13 @@ def test_large_grid_stream_planes(oracle, n_el, p, precision):
         _say(f"  plane z={z}: max rel error {err:.2e}")
         assert err < tol
     del f0, g0
+    # the transposed z-march in its large-grid form: <S x, y> = <x, S^T y>
+    yv = torch.randn((2, Q, ctx.nodes), generator=gen, device=ctx.device, dtype=ctx.dtype)
+    STy = ctx.stream(yv, transpose=True)
+    lhs = (Xs.double() * yv.double()).sum(dim=2)
+    rhs = (X.double() * STy.double()).sum(dim=2)
+    scale = (Xs.double().abs() * yv.double().abs()).sum(dim=2)
+    rel = float(((lhs - rhs).abs() / scale).max())
+    _say(f"  transposed identity: max rel {rel:.2e}")
+    assert rel < (1e-13 if precision == 0 else 1e-5)
     ctx.close()
