@@ -340,9 +340,10 @@ static hipError_t launch_z(const Geometry &g, const CellTables<S> &t, const S *i
 // that gather along x, y (LDS) and z (a register window of 2P rows sliding by
 // one cell).
 // ---------------------------------------------------------------------------
-template <int P, int V = 1>
+template <int P, int V = 1, int YN_ = 8>
 struct ZTileT {
-    static constexpr int XN = 32, YN = 8;
+    static constexpr int ORDER = P;
+    static constexpr int XN = 32, YN = YN_;
     static constexpr int TXC = XN / P > 0 ? XN / P : 1, TYC = YN / P > 0 ? YN / P : 1;
     static constexpr int TX = TXC * P, TY = TYC * P;
     static constexpr int WXC = (TX + P + V - 1 + V - 1) / V;  // loads per window row (V-aligned start)
@@ -352,13 +353,32 @@ struct ZTileT {
     static constexpr int BS = TX % 2 ? TX : TX + 1;
 };
 
-// NTH: non-temporal output stores (states larger than the Infinity Cache)
+// Tile rows of the transposed march, chosen as in the forward one: 16 on
+// grids larger than the Infinity Cache if the LDS stays within 64 KB
+template <typename S, class Z>
+constexpr size_t zt_lds_bytes()
+{
+    constexpr int WXO = Z::WX % 2 ? Z::WX : Z::WX + 1;
+    return static_cast<size_t>(Z::ORDER) * (static_cast<size_t>(WXO) * Z::WY + Z::WY * Z::BS) * sizeof(S);
+}
+
+template <typename S, int P, int V, bool BIG>
+constexpr int zt_tile_rows()
+{
+    return BIG && zt_lds_bytes<S, ZTileT<P, V, 16>>() <= 64 * 1024 ? 16 : 8;
+}
+
 template <typename S, int P, int V, bool NTH>
-__global__ void __launch_bounds__((ZTileT<P, V>::NT))
+using ZTileTOf = ZTileT<P, V, zt_tile_rows<S, P, V, NTH>()>;
+
+// NTH: non-temporal output stores and the larger tile (states larger than
+// the Infinity Cache)
+template <typename S, int P, int V, bool NTH>
+__global__ void __launch_bounds__((ZTileTOf<S, P, V, NTH>::NT))
     k_stream_zt(Geometry g, CellTables<S> tab, const S *__restrict__ in, S *__restrict__ out, int ntile_x,
                 int ntiles, int zcells, int nchunk)
 {
-    using Z = ZTileT<P, V>;
+    using Z = ZTileTOf<S, P, V, NTH>;
     using VT = typename VecOf<S, V>::T;
     constexpr int TX = Z::TX, TY = Z::TY, WY = Z::WY, NT = Z::NT, LK = Z::LK, BS = Z::BS;
     constexpr int WX = Z::WX % 2 ? Z::WX : Z::WX + 1;      // odd LDS row stride
@@ -524,23 +544,29 @@ __global__ void __launch_bounds__((ZTileT<P, V>::NT))
     }
 }
 
-template <typename S, int P, int V>
-static hipError_t launch_ztv(const Geometry &g, const CellTables<S> &t, const S *in, S *out, hipStream_t st)
+template <typename S, int P, int V, bool NTH>
+static hipError_t launch_ztvn(const Geometry &g, const CellTables<S> &t, const S *in, S *out, hipStream_t st)
 {
-    using Z = ZTileT<P, V>;
+    using Z = ZTileTOf<S, P, V, NTH>;
     const int ntx = (g.N[0] + Z::TX - 1) / Z::TX, nty = (g.N[1] + Z::TY - 1) / Z::TY;
     const int ntiles = ntx * nty;
-    const int nchunk = z_chunks(g, ntiles, ZCHUNK_MAX_CELL_BYTES / static_cast<int>(sizeof(S)));   // each chunk re-reads P rows
+    // each chunk re-reads P rows
+    const int nchunk = z_chunks(g, ntiles, Z::YN == 16 ? ZCHUNK_MAX_CELLS_LARGE
+                                                     : ZCHUNK_MAX_CELL_BYTES / static_cast<int>(sizeof(S)));
     const int zcells = (g.nel[2] + nchunk - 1) / nchunk;
     const int64_t nb = static_cast<int64_t>(ntiles) * 90 * nchunk;
     if (nb > (int64_t(1) << 31) - 1) return hipErrorInvalidValue;
-    if (use_nontemporal(90 * g.nodes * static_cast<int64_t>(sizeof(S))))
-        hipLaunchKernelGGL((k_stream_zt<S, P, V, true>), dim3(static_cast<unsigned>(nb)), dim3(Z::NT), 0, st, g, t,
-                           in, out, ntx, ntiles, zcells, nchunk);
-    else
-        hipLaunchKernelGGL((k_stream_zt<S, P, V, false>), dim3(static_cast<unsigned>(nb)), dim3(Z::NT), 0, st, g, t,
-                           in, out, ntx, ntiles, zcells, nchunk);
+    hipLaunchKernelGGL((k_stream_zt<S, P, V, NTH>), dim3(static_cast<unsigned>(nb)), dim3(Z::NT), 0, st, g, t, in,
+                       out, ntx, ntiles, zcells, nchunk);
     return hipGetLastError();
+}
+
+template <typename S, int P, int V>
+static hipError_t launch_ztv(const Geometry &g, const CellTables<S> &t, const S *in, S *out, hipStream_t st)
+{
+    if (use_nontemporal(90 * g.nodes * static_cast<int64_t>(sizeof(S))))
+        return launch_ztvn<S, P, V, true>(g, t, in, out, st);
+    return launch_ztvn<S, P, V, false>(g, t, in, out, st);
 }
 
 // 16-byte window loads need V-aligned window starts: tiles and rows of a
