@@ -366,7 +366,9 @@ def main():
                          "the smoothly distorted cells of sllbm_set_displacement (no cpu_baseline)")
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
     ap.add_argument("--no-secondary", action="store_true",
-                    help="skip the FP32-mixed line on the same grid and the 64^3-node FP64 line")
+                    help="skip the secondary lines (FP32-mixed on the same grid; with the default workload also "
+                         "FP64 on 64^3 and 128^3 nodes, on the graded and distorted 64^3-node meshes and on the 2-D "
+                         "Riemann workload)")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--adjoint-workload", default="c4",
@@ -427,6 +429,13 @@ def main():
         out["fp32_over_fp64"] = f32["value"] / f64["value"]
         if args.workload != "c2" and args.mesh == "equal":
             out["c2_fp64"] = measure_line(args, inputs.workload("c2"), "c2", "fp64", False, "equal")
+        if args.workload == "c5" and args.mesh == "equal":
+            # the other grids and meshes of the path, FP64, so that one run reports them all
+            out["c3_fp64"] = measure_line(args, inputs.workload("c3"), "c3", "fp64", False, "equal")
+            out["c2_graded_fp64"] = measure_line(args, inputs.workload("c2"), "c2-graded", "fp64", False, "graded")
+            out["c2_distorted_fp64"] = measure_line(args, inputs.workload("c2"), "c2-distorted", "fp64", False,
+                                                    "distorted")
+            out["riemann_fp64"] = measure_line(args, workload_2d("riemann"), "riemann", "fp64", True, "equal")
     if args.adjoint_workload != "none" and not two_d:
         aover = {} if args.adjoint_cfl is None else {"cfl": args.adjoint_cfl}
         if args.adjoint_steps is not None:

@@ -41,7 +41,9 @@ def test_bench_mode(args, kernel, metric):
 
 def test_bench_default_headline_and_secondary_lines():
     """The default run: the 256^3-node FP64 headline, the FP32-mixed line on
-    the same grid and the 64^3-node FP64 line, each a median of repetitions."""
+    the same grid, and FP64 lines on the 64^3- and 128^3-node grids, the
+    graded and distorted meshes and the 2-D workload, each a median of
+    repetitions."""
     require_gpu()
     print("bench default (256^3 nodes, fp64 + fp32 + c2)", flush=True)
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--steps", "2", "--warmup", "1",
@@ -55,8 +57,13 @@ def test_bench_default_headline_and_secondary_lines():
     assert len(d["ms_per_step_reps"]) == 3 and d["ms_per_step"] in d["ms_per_step_reps"]
     assert d["fp32_mixed"]["nodes"] == 256 ** 3 and d["fp32_mixed"]["dtype"].startswith("f32")
     assert d["c2_fp64"]["nodes"] == 64 ** 3
+    assert d["c3_fp64"]["nodes"] == 128 ** 3
+    assert d["c2_graded_fp64"]["roofline"]["kernel"] == "k_stream_graded"
+    assert d["c2_distorted_fp64"]["roofline"]["kernel"] == "k_stream_mapped"
+    assert d["riemann_fp64"]["roofline"]["kernel"] in ("k_stream_y", "k_collide")
     assert d["fp32_over_fp64"] > 1.0
-    for line in (d, d["fp32_mixed"], d["c2_fp64"]):
+    for line in (d, d["fp32_mixed"], d["c2_fp64"], d["c3_fp64"], d["c2_graded_fp64"], d["c2_distorted_fp64"],
+                 d["riemann_fp64"]):
         assert 0 < line["roofline"]["frac"] < 1 and 0 < line["roofline"]["step_frac"] < 1
         assert line["roofline"]["copy_GBps"] > 0 and line["roofline"]["frac_of_copy"] > 0
 
