@@ -191,27 +191,28 @@ __global__ void __launch_bounds__(256) k_collide_vjp(int64_t N, CollisionParams 
         const int i = vs::PAIRS.a[q], j = vs::PAIRS.b[q];
         const Bracket &b = br[vs::T.shell[i]];
         const double w = vs::T.w[i];
-        const double c = vs::T.xi[i][0] * u[0] + vs::T.xi[i][1] * u[1] + vs::T.xi[i][2] * u[2];
+        const double c = fma_nz(vs::T.xi[i][2], u[2],
+                                fma_nz(vs::T.xi[i][1], u[1], vs::T.xi[i][0] == 0.0 ? 0.0 : vs::T.xi[i][0] * u[0]));
         const double feq_i = w * rho * bval(b, c), feq_j = w * rho * bval(b, -c);
         const double heq_i = eqs * feq_i, heq_j = eqs * feq_j;
         double hs = 0.0;
 #pragma unroll
-        for (int m = 0; m < 10; ++m) hs = fma(vs::H3.c[i][m], qb[m], hs);
+        for (int m = 0; m < 10; ++m) hs = fma_nz(vs::H3.c[i][m], qb[m], hs);
         const double ai = al[i], aj = al[j];
         s_ka += (ai - aj) * hs;
         s_heq += ai * heq_i + aj * heq_j;
         s_eqT += ai * feq_i + aj * feq_j;
         const double wre = w * rho * eqs;
         const double gu = wre * (ai * bder(b, c) - aj * bder(b, -c));      // d/du through c
-        ubar[0] = fma(gu, vs::T.xi[i][0], ubar[0]);
-        ubar[1] = fma(gu, vs::T.xi[i][1], ubar[1]);
-        ubar[2] = fma(gu, vs::T.xi[i][2], ubar[2]);
+        ubar[0] = fma_nz(vs::T.xi[i][0], gu, ubar[0]);
+        ubar[1] = fma_nz(vs::T.xi[i][1], gu, ubar[1]);
+        ubar[2] = fma_nz(vs::T.xi[i][2], gu, ubar[2]);
         const double sp = ai + aj, sm = ai - aj;
         const double x2 = vs::SHELL_X2[vs::T.shell[i]];
         s_u2 += wre * (sp * (b.d0u + c * c * D2U) + sm * c * D1U);
         s_th += wre * (sp * (b.d0t + c * c * d2t_of(x2)) + sm * c * d1t_of(x2));
 #pragma unroll
-        for (int m = 0; m < 10; ++m) abar[m] = fma(sm, vs::H3.c[i][m], abar[m]);
+        for (int m = 0; m < 10; ++m) abar[m] = fma_nz(vs::H3.c[i][m], sm, abar[m]);
     }
 #pragma unroll
     for (int m = 0; m < 10; ++m) abar[m] *= kap;
@@ -289,7 +290,7 @@ __global__ void __launch_bounds__(256) k_collide_vjp(int64_t N, CollisionParams 
             const double x = vs::T.xi[i][0], y = vs::T.xi[i][1], z = vs::T.xi[i][2];
             double T3 = 0.0;
 #pragma unroll
-            for (int m = 0; m < 10; ++m) T3 = fma(abar[m], vs::H3.mono[i][m], T3);
+            for (int m = 0; m < 10; ++m) T3 = fma_nz(vs::H3.mono[i][m], abar[m], T3);
             const double T2 = Bs[0] * (x * x) + Bs[1] * (x * y) + Bs[2] * (x * z) + Bs[3] * (y * y) +
                               Bs[4] * (y * z) + Bs[5] * (z * z);
             const double T1 = Cu[0] * x + Cu[1] * y + Cu[2] * z;
