@@ -61,11 +61,11 @@ struct RawMoments {
 
 constexpr int IDX2[6][2] = {{0, 0}, {0, 1}, {0, 2}, {1, 1}, {1, 2}, {2, 2}};
 
-template <class L, typename S>
-__device__ __forceinline__ RawMoments<L> raw_moments(const S (&h)[L::Q])
+template <class L, class Get>
+__device__ __forceinline__ RawMoments<L> raw_moments_of(Get &&h)
 {
     RawMoments<L> r;
-    r.m0 = static_cast<double>(h[0]);
+    r.m0 = static_cast<double>(h(0));
 #pragma unroll
     for (int k = 0; k < 3; ++k) r.m1[k] = 0.0;
 #pragma unroll
@@ -75,7 +75,7 @@ __device__ __forceinline__ RawMoments<L> raw_moments(const S (&h)[L::Q])
 #pragma unroll
     for (int q = 0; q < L::NPAIR; ++q) {
         const int i = L::PAIRS.a[q], j = L::PAIRS.b[q];
-        const double hi = static_cast<double>(h[i]), hj = static_cast<double>(h[j]);
+        const double hi = static_cast<double>(h(i)), hj = static_cast<double>(h(j));
         const double s = hi + hj, d = hi - hj;
         const double *x = L::T.xi[i];
         r.m0 += s;
@@ -88,6 +88,12 @@ __device__ __forceinline__ RawMoments<L> raw_moments(const S (&h)[L::Q])
         for (int m = 0; m < L::NM3; ++m) r.m3[m] = fma_nz(L::H3.mono[i][m], d, r.m3[m]);
     }
     return r;
+}
+
+template <class L, typename S>
+__device__ __forceinline__ RawMoments<L> raw_moments(const S (&h)[L::Q])
+{
+    return raw_moments_of<L>([&](int i) { return h[i]; });
 }
 
 // index of (a, b) in the 6 unique components xx xy xz yy yz zz
@@ -127,27 +133,31 @@ __host__ __device__ __forceinline__ EqShell eq_shell(double u2, double th, doubl
     return e;
 }
 
-
-// Collision of one node whose two populations are held by a lane pair: the
-// even lane holds f (is_g = false), the odd lane g.  Each lane forms the raw
-// moments of its own population; the pair exchanges rho, j, and the energy
-// parts (tr M2[f] and M0[g]); each lane then builds Qbar of its own
-// population and relaxes it (g^eq = (2 C_v - D) T f^eq).  Both lanes of a
-// pair must be active.
-// sink(i, value) receives every post-collision value as soon as it is formed
-// (v holds them all on return as well).
-template <class L, typename S, class Sink>
-__device__ __forceinline__ void collide_half_s(S (&v)[L::Q], bool is_g, const CollisionParams &cp, Sink &&sink)
+// Collision of one node whose two populations are held by a lane pair,
+// lanes l and l ^ XM: the lane with is_g = false holds f, its partner g.
+// Each lane forms the raw moments of its own population; the pair exchanges
+// rho, j, and the energy parts (tr M2[f] and M0[g]); each lane then builds
+// Qbar of its own population and relaxes it (g^eq = (2 C_v - D) T f^eq).
+// Both lanes of a pair must be active.
+// get(i) returns the pre-collision value of velocity i (storage type S).  It
+// is called twice per velocity, for the moments and for the relaxation, with
+// fence() in between: a source in memory is then read again rather than held
+// in registers through the collision.
+// sink(i, value) receives every post-collision value as soon as it is formed.
+template <class L, typename S, int XM = 1, class Get, class Fence, class Sink>
+__device__ __forceinline__ void collide_core(Get &&get, Fence &&fence, bool is_g, const CollisionParams &cp,
+                                             Sink &&sink)
 {
     using R = double;   // arithmetic type of the per-velocity terms (storage S is read and written once)
     constexpr bool D3 = L::D == 3;
-    const RawMoments<L> rm = raw_moments<L>(v);
+    const RawMoments<L> rm = raw_moments_of<L>(get);
+    fence();
     const double ktr = D3 ? rm.m2[0] + rm.m2[3] + rm.m2[5] : rm.m2[0] + rm.m2[3];
-    const double p_m0 = __shfl_xor(rm.m0, 1);
-    const double p_j0 = __shfl_xor(rm.m1[0], 1);
-    const double p_j1 = __shfl_xor(rm.m1[1], 1);
-    const double p_j2 = D3 ? __shfl_xor(rm.m1[2], 1) : 0.0;
-    const double p_tr = __shfl_xor(ktr, 1);
+    const double p_m0 = __shfl_xor(rm.m0, XM);
+    const double p_j0 = __shfl_xor(rm.m1[0], XM);
+    const double p_j1 = __shfl_xor(rm.m1[1], XM);
+    const double p_j2 = D3 ? __shfl_xor(rm.m1[2], XM) : 0.0;
+    const double p_tr = __shfl_xor(ktr, XM);
     const double rho = is_g ? p_m0 : rm.m0;
     const double ir = 1.0 / rho;
     const double u[3] = {(is_g ? p_j0 : rm.m1[0]) * ir, (is_g ? p_j1 : rm.m1[1]) * ir,
@@ -181,9 +191,8 @@ __device__ __forceinline__ void collide_half_s(S (&v)[L::Q], bool is_g, const Co
     const R ux = static_cast<R>(u[0]), uy = static_cast<R>(u[1]), uz = static_cast<R>(u[2]);
     {
         const R heq = eqs * static_cast<R>(L::T.w[0]) * A0[0];
-        const R vi = v[0];
-        v[0] = fma(om, heq - vi, vi);
-        sink(0, v[0]);
+        const R vi = get(0);
+        sink(0, static_cast<S>(fma(om, heq - vi, vi)));
     }
 #pragma unroll
     for (int q = 0; q < L::NPAIR; ++q) {
@@ -198,12 +207,22 @@ __device__ __forceinline__ void collide_half_s(S (&v)[L::Q], bool is_g, const Co
         R hs = 0;
 #pragma unroll
         for (int m = 0; m < L::NM3; ++m) hs = fma_nz(L::H3.c[i][m], qr[m], hs);
-        const R vi = v[i], vj = v[j];
-        v[i] = fma(kap, hs, fma(om, fma(we, even, we * odd) - vi, vi));
-        v[j] = fma(-kap, hs, fma(om, fma(we, even, -we * odd) - vj, vj));
-        sink(i, v[i]);
-        sink(j, v[j]);
+        const R vi = get(i), vj = get(j);
+        sink(i, static_cast<S>(fma(kap, hs, fma(om, fma(we, even, we * odd) - vi, vi))));
+        sink(j, static_cast<S>(fma(-kap, hs, fma(om, fma(we, even, -we * odd) - vj, vj))));
     }
+}
+
+// The same on values held in registers: sink(i, value) receives every
+// post-collision value as soon as it is formed, and v holds them all on
+// return as well.
+template <class L, typename S, class Sink>
+__device__ __forceinline__ void collide_half_s(S (&v)[L::Q], bool is_g, const CollisionParams &cp, Sink &&sink)
+{
+    collide_core<L, S>([&](int i) { return v[i]; }, [] {}, is_g, cp, [&](int i, S x) {
+        v[i] = x;
+        sink(i, x);
+    });
 }
 
 template <class L, typename S>

@@ -9,13 +9,16 @@
 #include "nt.h"
 #include "sllbm_internal.h"
 #include "velset.h"
+#include "xcd.h"
 
 namespace sllbm {
 
 // Collision of a whole state (Eq. (5) right-hand side with App. D), two
-// lanes per node (f on the even lane, g on the odd one).  in and out may be
-// the same buffer (each lane reads its 45 values first).  NTH: non-temporal
-// loads and stores (states larger than the Infinity Cache).
+// lanes per node (f on the even lane, g on the odd one), the values in
+// registers: FP64 storage, and FP32 storage where k_collide_lds below does
+// not apply (D2Q19, or N not a multiple of 4).  in and out may be the same
+// buffer (each lane reads its values first).  NTH: non-temporal loads and
+// stores (states larger than the Infinity Cache).
 template <typename S, class L, bool NTH>
 __global__ void __launch_bounds__(256) k_collide(int64_t N, CollisionParams cp, const S *in, S *out)
 {
@@ -34,8 +37,9 @@ __global__ void __launch_bounds__(256) k_collide(int64_t N, CollisionParams cp, 
     S *d = out + o;
     if constexpr (sizeof(S) == 4) {
         // FP32 storage: store every value as the relaxation forms it; the
-        // collision is latency-bound here (two waves per SIMD), and stores
-        // spread over it measured 7 % faster at 256^3 nodes (no gain in FP64)
+        // D3Q45 collision is latency-bound here (two waves per SIMD), and
+        // stores spread over it measured 7 % faster at 256^3 nodes (no gain
+        // in FP64)
         asm volatile("" : "+v"(d));
         collide_half_s<L, S>(v, pop != 0, cp,
                              [d, N](int i, S x) { store_hint<NTH>(&d[static_cast<int64_t>(i) * N], x); });
@@ -45,6 +49,59 @@ __global__ void __launch_bounds__(256) k_collide(int64_t N, CollisionParams cp, 
 #pragma unroll
         for (int i = 0; i < NQ; ++i) store_hint<NTH>(&d[static_cast<int64_t>(i) * N], v[i]);
     }
+}
+
+// DMA copy of 16 bytes per lane from g into LDS at l + 16 * lane (l is
+// wave-uniform).  A device function of its own: the 16-byte form exists on
+// gfx950 only, and the host pass drops the launch stub of a kernel whose
+// body names it.
+template <int AUX>
+__device__ __forceinline__ void dma16(const float *g, float *l)
+{
+    __builtin_amdgcn_global_load_lds(g, l, 16, 0, AUX);
+}
+
+// The D3Q45 collision in FP32 storage for N a multiple of 4.  A block of 4
+// waves collides 128 consecutive nodes (blocks in XCD order).  Their 90 rows
+// of 128 values (row r = pop * 45 + i, 512 contiguous bytes of plane r) are
+// copied from memory into LDS by DMA, 16 bytes per lane, so one instruction
+// moves two rows (1 KB) and no register holds them; every value is then read
+// from LDS for the moments and again for the relaxation.  Lane l of wave w
+// holds node w * 32 + (l & 31) of the block and population l >> 5 (partner
+// lane l ^ 32).  The collision of k_collide with its 45 values in registers
+// needs 224 VGPRs (2 waves per SIMD) and reads 128-byte segments per plane;
+// this one needs 136 VGPRs and 45 KB of LDS per block (3 waves per SIMD).
+// in may equal out: every copy has landed before the barrier, and a block
+// writes only its own nodes.  NTH: non-temporal copies and stores.
+template <class L, bool NTH>
+__global__ void __launch_bounds__(256, 3) k_collide_lds(int64_t N, CollisionParams cp, const float *in, float *out)
+{
+    constexpr int NQ = L::Q, ROWS = 2 * NQ, NB = 128;
+    __shared__ float tile[ROWS][NB];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t nb = static_cast<int64_t>(xcd_linear(blockIdx.x, gridDim.x)) * NB;
+    {
+        // instruction m of the block copies rows 2m (lanes 0-31) and 2m + 1
+        // (lanes 32-63), 4 nodes per lane; a lane's 4 nodes are all below N
+        // or all beyond it (N % 4 == 0)
+        const int64_t col = nb + 4 * (lane & 31);
+        if (col < N) {
+            const float *src = in + static_cast<int64_t>(lane >> 5) * N + col;
+            for (int m = w; m < ROWS / 2; m += 4)
+                dma16<NTH ? 2 : 0>(src + static_cast<int64_t>(2 * m) * N, &tile[2 * m][0]);
+        }
+    }
+    __builtin_amdgcn_s_waitcnt(0);               // this wave's copies have landed
+    __syncthreads();                             // and every other wave's
+    const int pop = lane >> 5;
+    const int c = w * 32 + (lane & 31);
+    const int64_t n = nb + c;
+    if (n >= N) return;                          // both lanes of a pair leave together
+    const float *sl = &tile[pop * NQ][c];
+    float *d = out + static_cast<int64_t>(pop) * NQ * N + n;
+    asm volatile("" : "+v"(d));
+    collide_core<L, float, 32>([&](int i) { return sl[i * NB]; }, [] { asm volatile("" ::: "memory"); }, pop != 0,
+                               cp, [d, N](int i, float x) { store_hint<NTH>(&d[static_cast<int64_t>(i) * N], x); });
 }
 
 // The same collision with each lane pair taking nodes n, n + G, ... (G lane
@@ -241,6 +298,20 @@ static hipError_t collide_lat(const Geometry &g, const CollisionParams &cp, cons
         hipLaunchKernelGGL((k_collide_pf<S, L>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, g.nodes, cp,
                            in, out);
         return hipGetLastError();
+    }
+    if constexpr (L::Q == 45 && sizeof(S) == 4) {
+        // LDS-staged form (measured at 256^3 nodes: 3.02 -> 2.29 ms; for
+        // D2Q19 no faster than the register form)
+        if (g.nodes % 4 == 0) {
+            const int64_t b = (g.nodes + 127) / 128;
+            if (use_nontemporal(2 * L::Q * g.nodes * static_cast<int64_t>(sizeof(S))))
+                hipLaunchKernelGGL((k_collide_lds<L, true>), dim3(static_cast<unsigned>(b)), dim3(256), 0, st,
+                                   g.nodes, cp, in, out);
+            else
+                hipLaunchKernelGGL((k_collide_lds<L, false>), dim3(static_cast<unsigned>(b)), dim3(256), 0, st,
+                                   g.nodes, cp, in, out);
+            return hipGetLastError();
+        }
     }
     const int64_t blocks = (2 * g.nodes + 255) / 256;
     if (use_nontemporal(2 * L::Q * g.nodes * static_cast<int64_t>(sizeof(S))))

@@ -123,6 +123,34 @@ def test_collide_matches_oracle(oracle, law, pr):
     assert rel_err(F, fo) < TOL64 and rel_err(G, go) < TOL64
 
 
+# FP32-mixed storage: the collision reads FP32 values, computes in FP64 and
+# rounds each result once, so every output lies within half an FP32 ulp
+# (2^-24 relative) of the oracle's FP64 collision of the same values.  Node
+# counts: 96 (one partial block of the LDS-staged kernel), 1792 (whole
+# blocks), 8640 (a ragged last block) and 729 (not a multiple of 4: the
+# register form).
+FP32_COLLIDE_CASES = [((3, 2, 2), 2), ((7, 2, 2), 4), ((9, 5, 3), 4), ((3, 3, 3), 3)]
+
+
+@pytest.mark.parametrize("n_el,p", FP32_COLLIDE_CASES)
+def test_collide_fp32_rounds_the_fp64_collision(oracle, n_el, p):
+    _say(f"fp32 collide n_el={n_el} p={p}")
+    ctx, cfg = make_pair(oracle, n_el, p, 0.07, 0.013, precision=1)
+    xs, ys, zs = oracle.node_coords(cfg)
+    rho, u, T = inputs.tgv_fields(xs, ys, zs, 0.9, 1.4)
+    f, g = oracle.init_equilibrium(cfg, rho, u, T)
+    rng = np.random.default_rng(5)
+    f = (f * (1 + 0.03 * rng.normal(size=f.shape))).astype(np.float32).astype(np.float64)
+    g = (g * (1 + 0.03 * rng.normal(size=g.shape))).astype(np.float32).astype(np.float64)
+    st = to_dev(ctx, f, g)
+    ctx.collide(st)
+    fo, go = oracle.collide(cfg, f, g)
+    for got, ref in zip(to_np(st), (fo, go)):
+        assert np.all(np.abs(ref) > 0)
+        err = float(np.max(np.abs(got - ref) / np.abs(ref)))
+        assert err <= 2.0 ** -24 * (1 + 1e-4), err
+
+
 def test_init_and_moments_match_oracle(oracle):
     w, ctx, cfg = workload_pair(oracle, "c1")
     f, g = tgv_init(oracle, ctx, cfg, w["Ma"], w["gamma"])
@@ -172,13 +200,16 @@ def test_step_split_equals_step_total(oracle):
     assert torch.equal(ctx2.get_state(), a)
 
 
-def test_step_record_matches_get_state(oracle):
-    w, ctx, cfg = workload_pair(oracle, "c1")
+@pytest.mark.parametrize("precision", [0, 1])
+def test_step_record_matches_get_state(oracle, precision):
+    """step_record collides into the spare buffer, step in place: bitwise equal."""
+    w, ctx, cfg = workload_pair(oracle, "c1", precision=precision)
     tgv_init(oracle, ctx, cfg, w["Ma"], w["gamma"])
     rec = torch.empty((4, 2, Q, ctx.nodes), dtype=ctx.dtype, device=ctx.device)
     s0 = ctx.get_state()
     ctx.step_record(4, rec)
-    ctx2 = make_pair(oracle, w["n_el"], w["p"], w["dt"], w["mu_inf"], gamma=w["gamma"], prandtl=w["Pr"])[0]
+    ctx2 = make_pair(oracle, w["n_el"], w["p"], w["dt"], w["mu_inf"], gamma=w["gamma"], prandtl=w["Pr"],
+                     precision=precision)[0]
     ctx2.set_state(s0)
     for k in range(4):
         ctx2.step(1)
