@@ -32,7 +32,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, vendor figure
 Q = 45
 
-# sources that determine each timed kernel (a change voids committed counters)
+# sources that determine each timed kernel, besides the headers of csrc/ that
+# they include (a change in any of them voids committed counters)
 KERNEL_SOURCES = {
     "k_stream_z": ("stream.hip", "tables.cpp"),
     "k_stream_graded": ("stream_graded.hip", "tables.cpp"),
@@ -50,9 +51,24 @@ def _code_only(text):
     return " ".join(text.split())
 
 
+def kernel_source_files(kernel):
+    """The kernel's sources and, transitively, the csrc/ headers they include."""
+    csrc = os.path.join(ROOT, "paper_2012_05537_amd", "csrc")
+    seen, todo = [], list(KERNEL_SOURCES[kernel])
+    while todo:
+        f = todo.pop(0)
+        path = os.path.join(csrc, f)
+        if f in seen or not os.path.exists(path):     # the public header lives in include/
+            continue
+        seen.append(f)
+        with open(path, encoding="utf-8") as fh:
+            todo += re.findall(r'^\s*#include "([^"]+)"', fh.read(), flags=re.M)
+    return sorted(seen)
+
+
 def kernel_source_hash(kernel):
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES[kernel]:
+    for f in kernel_source_files(kernel):
         with open(os.path.join(ROOT, "paper_2012_05537_amd", "csrc", f), encoding="utf-8") as fh:
             h.update(_code_only(fh.read()).encode())
     return h.hexdigest()[:16]
