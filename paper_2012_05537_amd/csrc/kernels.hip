@@ -61,7 +61,8 @@ __device__ __forceinline__ void dma16(const float *g, float *l)
     __builtin_amdgcn_global_load_lds(g, l, 16, 0, AUX);
 }
 
-// The D3Q45 collision in FP32 storage for N a multiple of 4.  A block of 4
+// The D3Q45 collision in FP32 storage for N a multiple of 4 and a 16-byte
+// aligned input.  A block of 4
 // waves collides 128 consecutive nodes (blocks in XCD order).  Their 90 rows
 // of 128 values (row r = pop * 45 + i, 512 contiguous bytes of plane r) are
 // copied from memory into LDS by DMA, 16 bytes per lane, so one instruction
@@ -301,8 +302,9 @@ static hipError_t collide_lat(const Geometry &g, const CollisionParams &cp, cons
     }
     if constexpr (L::Q == 45 && sizeof(S) == 4) {
         // LDS-staged form (measured at 256^3 nodes: 3.02 -> 2.29 ms; for
-        // D2Q19 no faster than the register form)
-        if (g.nodes % 4 == 0) {
+        // D2Q19 no faster than the register form); its 16-byte copies need
+        // 16-byte aligned rows
+        if (g.nodes % 4 == 0 && reinterpret_cast<uintptr_t>(in) % 16 == 0) {
             const int64_t b = (g.nodes + 127) / 128;
             if (use_nontemporal(2 * L::Q * g.nodes * static_cast<int64_t>(sizeof(S))))
                 hipLaunchKernelGGL((k_collide_lds<L, true>), dim3(static_cast<unsigned>(b)), dim3(256), 0, st,

@@ -151,6 +151,30 @@ def test_collide_fp32_rounds_the_fp64_collision(oracle, n_el, p):
         assert err <= 2.0 ** -24 * (1 + 1e-4), err
 
 
+def test_collide_fp32_state_at_any_word_offset(oracle):
+    """A caller state that starts one float past a 16-byte boundary (the
+    register form of the FP32 collision; aligned states take the LDS-staged
+    form) gives the same half-ulp result."""
+    ctx, cfg = make_pair(oracle, (7, 2, 2), 4, 0.07, 0.013, precision=1)
+    xs, ys, zs = oracle.node_coords(cfg)
+    f, g = oracle.init_equilibrium(cfg, *inputs.tgv_fields(xs, ys, zs, 0.9, 1.4))
+    rng = np.random.default_rng(6)
+    f = (f * (1 + 0.03 * rng.normal(size=f.shape))).astype(np.float32).astype(np.float64)
+    g = (g * (1 + 0.03 * rng.normal(size=g.shape))).astype(np.float32).astype(np.float64)
+    n = 2 * Q * ctx.nodes
+    flat = torch.zeros(n + 1, dtype=torch.float32, device=ctx.device)
+    st = flat[1:].view(2, Q, ctx.nodes)
+    st.copy_(to_dev(ctx, f, g))
+    al = to_dev(ctx, f, g)
+    ctx.collide(st)
+    ctx.collide(al)
+    assert float(flat[0]) == 0.0
+    fo, go = oracle.collide(cfg, f, g)
+    for s in (st, al):
+        for got, ref in zip(to_np(s), (fo, go)):
+            assert float(np.max(np.abs(got - ref) / np.abs(ref))) <= 2.0 ** -24 * (1 + 1e-4)
+
+
 def test_init_and_moments_match_oracle(oracle):
     w, ctx, cfg = workload_pair(oracle, "c1")
     f, g = tgv_init(oracle, ctx, cfg, w["Ma"], w["gamma"])
