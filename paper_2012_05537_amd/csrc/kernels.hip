@@ -15,8 +15,9 @@ namespace sllbm {
 
 // Collision of a whole state (Eq. (5) right-hand side with App. D), two
 // lanes per node (f on the even lane, g on the odd one), the values in
-// registers: FP64 storage, and FP32 storage where k_collide_lds below does
-// not apply (D2Q19, or N not a multiple of 4).  in and out may be the same
+// registers: D3Q45 in FP64, D2Q19 in FP32, and the cases that k_collide_lds
+// below does not take (N not a multiple of 16 / sizeof(S), an input not
+// 16-byte aligned).  in and out may be the same
 // buffer (each lane reads its values first).  NTH: non-temporal loads and
 // stores (states larger than the Infinity Cache).
 template <typename S, class L, bool NTH>
@@ -55,40 +56,42 @@ __global__ void __launch_bounds__(256) k_collide(int64_t N, CollisionParams cp, 
 // wave-uniform).  A device function of its own: the 16-byte form exists on
 // gfx950 only, and the host pass drops the launch stub of a kernel whose
 // body names it.
-template <int AUX>
-__device__ __forceinline__ void dma16(const float *g, float *l)
+template <int AUX, typename T>
+__device__ __forceinline__ void dma16(const T *g, T *l)
 {
     __builtin_amdgcn_global_load_lds(g, l, 16, 0, AUX);
 }
 
-// The D3Q45 collision in FP32 storage for N a multiple of 4 and a 16-byte
-// aligned input.  A block of 4
-// waves collides 128 consecutive nodes (blocks in XCD order).  Their 90 rows
-// of 128 values (row r = pop * 45 + i, 512 contiguous bytes of plane r) are
-// copied from memory into LDS by DMA, 16 bytes per lane, so one instruction
-// moves two rows (1 KB) and no register holds them; every value is then read
-// from LDS for the moments and again for the relaxation.  Lane l of wave w
-// holds node w * 32 + (l & 31) of the block and population l >> 5 (partner
-// lane l ^ 32).  The collision of k_collide with its 45 values in registers
-// needs 224 VGPRs (2 waves per SIMD) and reads 128-byte segments per plane;
-// this one needs 136 VGPRs and 45 KB of LDS per block (3 waves per SIMD).
+// The collision with its values staged in LDS; used for D3Q45 in FP32
+// storage and D2Q19 in FP64, for N a multiple of 16 / sizeof(S) and a
+// 16-byte aligned input.  A block collides NB = 512 / sizeof(S) consecutive
+// nodes (128 in FP32, 64 in FP64; blocks in XCD order) with NB / 32 waves.
+// Their 2Q rows of NB values (row r = pop * Q + i, 512 contiguous bytes of
+// plane r) are copied from memory into LDS by DMA, 16 bytes per lane, so
+// one instruction moves two rows (1 KB) and no register holds them; every
+// value is then read from LDS for the moments and again for the relaxation.
+// Lane l of wave w holds node w * 32 + (l & 31) of the block and population
+// l >> 5 (partner lane l ^ 32).  For D3Q45 in FP32: 136 VGPRs and 45 KB of
+// LDS per block (3 waves per SIMD), where the register form needs 224 VGPRs
+// (2 waves) and reads 128-byte segments per plane and half-wave.
 // in may equal out: every copy has landed before the barrier, and a block
 // writes only its own nodes.  NTH: non-temporal copies and stores.
-template <class L, bool NTH>
-__global__ void __launch_bounds__(256, 3) k_collide_lds(int64_t N, CollisionParams cp, const float *in, float *out)
+template <typename S, class L, bool NTH>
+__global__ void __launch_bounds__(1024 / sizeof(S), 3) k_collide_lds(int64_t N, CollisionParams cp, const S *in,
+                                                                     S *out)
 {
-    constexpr int NQ = L::Q, ROWS = 2 * NQ, NB = 128;
-    __shared__ float tile[ROWS][NB];
+    constexpr int NQ = L::Q, ROWS = 2 * NQ, NB = 512 / sizeof(S), NW = NB / 32, VL = 16 / sizeof(S);
+    __shared__ S tile[ROWS][NB];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t nb = static_cast<int64_t>(xcd_linear(blockIdx.x, gridDim.x)) * NB;
     {
         // instruction m of the block copies rows 2m (lanes 0-31) and 2m + 1
-        // (lanes 32-63), 4 nodes per lane; a lane's 4 nodes are all below N
-        // or all beyond it (N % 4 == 0)
-        const int64_t col = nb + 4 * (lane & 31);
+        // (lanes 32-63), VL nodes per lane; a lane's nodes are all below N or
+        // all beyond it (N % VL == 0)
+        const int64_t col = nb + VL * (lane & 31);
         if (col < N) {
-            const float *src = in + static_cast<int64_t>(lane >> 5) * N + col;
-            for (int m = w; m < ROWS / 2; m += 4)
+            const S *src = in + static_cast<int64_t>(lane >> 5) * N + col;
+            for (int m = w; m < ROWS / 2; m += NW)
                 dma16<NTH ? 2 : 0>(src + static_cast<int64_t>(2 * m) * N, &tile[2 * m][0]);
         }
     }
@@ -98,17 +101,18 @@ __global__ void __launch_bounds__(256, 3) k_collide_lds(int64_t N, CollisionPara
     const int c = w * 32 + (lane & 31);
     const int64_t n = nb + c;
     if (n >= N) return;                          // both lanes of a pair leave together
-    const float *sl = &tile[pop * NQ][c];
-    float *d = out + static_cast<int64_t>(pop) * NQ * N + n;
+    const S *sl = &tile[pop * NQ][c];
+    S *d = out + static_cast<int64_t>(pop) * NQ * N + n;
     asm volatile("" : "+v"(d));
-    collide_core<L, float, 32>([&](int i) { return sl[i * NB]; }, [] { asm volatile("" ::: "memory"); }, pop != 0,
-                               cp, [d, N](int i, float x) { store_hint<NTH>(&d[static_cast<int64_t>(i) * N], x); });
+    collide_core<L, S, 32>([&](int i) { return sl[i * NB]; }, [] { asm volatile("" ::: "memory"); }, pop != 0, cp,
+                           [d, N](int i, S x) { store_hint<NTH>(&d[static_cast<int64_t>(i) * N], x); });
 }
 
 // The same collision with each lane pair taking nodes n, n + G, ... (G lane
 // pairs in the grid): the next node's values are loaded while the current
-// node collides.  For the 19-velocity set in FP64 (216 VGPRs, 2 waves/SIMD)
-// this hides the load latency better than one node per pair at 4 waves/SIMD
+// node collides.  The D2Q19 FP64 collision where k_collide_lds does not
+// apply; there (216 VGPRs, 2 waves/SIMD) it hides the load latency better
+// than one node per pair at 4 waves/SIMD
 // (a launch of that form has only two rounds of waves at 512^2 nodes); with
 // 45 velocities the second set of registers does not fit.  in may equal out:
 // node n + G belongs to this lane pair only.
@@ -292,28 +296,30 @@ static int node_grid(int64_t N)
 template <typename S, class L>
 static hipError_t collide_lat(const Geometry &g, const CollisionParams &cp, const S *in, S *out, hipStream_t st)
 {
+    if constexpr ((L::Q == 45 && sizeof(S) == 4) || (L::Q == Q2D && sizeof(S) == 8)) {
+        // LDS-staged form, measured against the register forms: D3Q45 FP32
+        // at 256^3 nodes 3.02 -> 2.29 ms, D2Q19 FP64 at 512^2 nodes 34 ->
+        // 28 us (no faster for D2Q19 in FP32, slower for D3Q45 in FP64 at
+        // 128^3 and 256^3 nodes); its 16-byte copies need aligned rows
+        constexpr int NB = 512 / sizeof(S), VL = 16 / sizeof(S);
+        if (g.nodes % VL == 0 && reinterpret_cast<uintptr_t>(in) % 16 == 0) {
+            const int64_t b = (g.nodes + NB - 1) / NB;
+            if (use_nontemporal(2 * L::Q * g.nodes * static_cast<int64_t>(sizeof(S))))
+                hipLaunchKernelGGL((k_collide_lds<S, L, true>), dim3(static_cast<unsigned>(b)), dim3(2 * NB), 0, st,
+                                   g.nodes, cp, in, out);
+            else
+                hipLaunchKernelGGL((k_collide_lds<S, L, false>), dim3(static_cast<unsigned>(b)), dim3(2 * NB), 0,
+                                   st, g.nodes, cp, in, out);
+            return hipGetLastError();
+        }
+    }
     if constexpr (L::Q == Q2D && sizeof(S) == 8) {
-        // two nodes per lane pair (measured 12 % faster at 512^2 nodes; in
-        // FP32 the one-node form is faster)
+        // otherwise two nodes per lane pair (measured 12 % faster at 512^2
+        // nodes than one; in FP32 the one-node form is faster)
         const int64_t blocks = (g.nodes + 255) / 256;
         hipLaunchKernelGGL((k_collide_pf<S, L>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, g.nodes, cp,
                            in, out);
         return hipGetLastError();
-    }
-    if constexpr (L::Q == 45 && sizeof(S) == 4) {
-        // LDS-staged form (measured at 256^3 nodes: 3.02 -> 2.29 ms; for
-        // D2Q19 no faster than the register form); its 16-byte copies need
-        // 16-byte aligned rows
-        if (g.nodes % 4 == 0 && reinterpret_cast<uintptr_t>(in) % 16 == 0) {
-            const int64_t b = (g.nodes + 127) / 128;
-            if (use_nontemporal(2 * L::Q * g.nodes * static_cast<int64_t>(sizeof(S))))
-                hipLaunchKernelGGL((k_collide_lds<L, true>), dim3(static_cast<unsigned>(b)), dim3(256), 0, st,
-                                   g.nodes, cp, in, out);
-            else
-                hipLaunchKernelGGL((k_collide_lds<L, false>), dim3(static_cast<unsigned>(b)), dim3(256), 0, st,
-                                   g.nodes, cp, in, out);
-            return hipGetLastError();
-        }
     }
     const int64_t blocks = (2 * g.nodes + 255) / 256;
     if (use_nontemporal(2 * L::Q * g.nodes * static_cast<int64_t>(sizeof(S))))

@@ -128,8 +128,10 @@ def test_collide_matches_oracle(O2, law, prandtl):
 @pytest.mark.parametrize("n_el,p", [((1, 1), 1), ((3, 2), 1), ((5, 7), 3), ((33, 1), 4)])
 @pytest.mark.parametrize("precision", [0, 1])
 def test_collide_tail_sizes(O2, n_el, p, precision):
-    """Node counts of 1, 6, 315 and 528: lane pairs past the end, and (FP64)
-    pairs that take a second node or none."""
+    """Node counts of 1, 6, 315 and 528: lane pairs past the end; in FP64 the
+    even counts take the LDS-staged collision (one partial block of 64 nodes,
+    a ragged last block) and the odd ones the two-node form (pairs that take
+    a second node or none)."""
     ctx, cfg = _pair(O2, n_el, p, 0.002, 3e-3, law=0, precision=precision)
     N = O2.num_nodes(cfg)
     rng = np.random.default_rng(N)
