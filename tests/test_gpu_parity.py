@@ -154,7 +154,8 @@ def test_collide_fp32_rounds_the_fp64_collision(oracle, n_el, p):
 def test_collide_fp32_state_at_any_word_offset(oracle):
     """A caller state that starts one float past a 16-byte boundary (the
     register form of the FP32 collision; aligned states take the LDS-staged
-    form) gives the same half-ulp result."""
+    form) gives the same half-ulp result, bit for bit (both forms run the
+    same FP64 arithmetic and round once)."""
     ctx, cfg = make_pair(oracle, (7, 2, 2), 4, 0.07, 0.013, precision=1)
     xs, ys, zs = oracle.node_coords(cfg)
     f, g = oracle.init_equilibrium(cfg, *inputs.tgv_fields(xs, ys, zs, 0.9, 1.4))
@@ -169,6 +170,7 @@ def test_collide_fp32_state_at_any_word_offset(oracle):
     ctx.collide(st)
     ctx.collide(al)
     assert float(flat[0]) == 0.0
+    assert torch.equal(st, al)
     fo, go = oracle.collide(cfg, f, g)
     for s in (st, al):
         for got, ref in zip(to_np(s), (fo, go)):
