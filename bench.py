@@ -239,10 +239,47 @@ def run_adjoint(wl, precision, mesh="equal"):
             "device_memory_GB": peak_gb}
 
 
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def _time_oracle(O, step, nodes, budget_s, what):
+    """Whole-grid oracle steps (step() advances the state by one) until about
+    budget_s seconds have run on all the oracle's OpenMP threads, then on one
+    thread for about half that (at least one step)."""
+    lib = O._lib()
+    threads = int(lib.omp_get_max_threads())
+    out = {}
+    for n_threads, budget in ((threads, budget_s), (1, 0.5 * budget_s)):
+        lib.omp_set_num_threads(n_threads)
+        steps = 0
+        t0 = time.perf_counter()
+        while True:
+            step()
+            steps += 1
+            el = time.perf_counter() - t0
+            if el > budget or el / steps * (steps + 1) > 2.0 * budget:
+                break
+        out[n_threads] = (nodes * steps / el, steps, el)
+    lib.omp_set_num_threads(threads)
+    value, steps, el = out[threads]
+    return dict(value=value, unit="node-updates/s", cores=threads, kind="oracle",
+                sample=f"{steps} whole-grid FP64 {what} step(s) of the same workload ({nodes} nodes), {el:.1f} s",
+                value_one_core=out[1][0], sample_one_core=f"{out[1][1]} step(s), {out[1][2]:.1f} s",
+                cpu_model=_cpu_model())
+
+
 def cpu_baseline(wl, budget_s, graded=False):
     """The FP64 oracle on the host cores: whole-grid steps of the same workload
-    (same grid, same mesh, same parameters) until about budget_s seconds have run."""
-    import numpy as np
+    (same grid, same mesh, same parameters) until about budget_s seconds have
+    run; then the same on one core."""
     from oracle import oracle as O
     from paper_2012_05537_amd import inputs
 
@@ -253,23 +290,16 @@ def cpu_baseline(wl, budget_s, graded=False):
     cfg = O.make_cfg(wl["n_el"], wl["p"], wl["dt"], wl["mu_inf"], gamma=wl["gamma"], prandtl=wl["Pr"],
                      widths=widths)
     rho, u, T = inputs.tgv_fields(*O.node_coords(cfg), wl["Ma"], wl["gamma"])
-    f, g = O.init_equilibrium(cfg, rho, u, T)
-    steps = 0
-    t0 = time.perf_counter()
-    while True:
-        f, g = O.step(cfg, f, g, 1)
-        steps += 1
-        el = time.perf_counter() - t0
-        if el > budget_s or el / steps * (steps + 1) > 2.0 * budget_s:
-            break
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return dict(value=O.num_nodes(cfg) * steps / el, unit="node-updates/s", cores=cores, kind="oracle",
-                sample=f"{steps} whole-grid FP64 oracle step(s) of the same workload "
-                       f"({O.num_nodes(cfg)} nodes), {el:.1f} s")
+    st = list(O.init_equilibrium(cfg, rho, u, T))
+
+    def step():
+        st[0], st[1] = O.step(cfg, st[0], st[1], 1)
+    return _time_oracle(O, step, O.num_nodes(cfg), budget_s, "oracle")
 
 
 def cpu_baseline_2d(wl, budget_s):
-    """The 2-D FP64 oracle on the host cores: whole-grid steps of the same workload."""
+    """The 2-D FP64 oracle on the host cores: whole-grid steps of the same
+    workload, then the same on one core."""
     from oracle import oracle2d as O
     from paper_2012_05537_amd import inputs
 
@@ -277,19 +307,11 @@ def cpu_baseline_2d(wl, budget_s):
                      length=wl["length"], viscosity_law=O.CONSTANT)
     x, y = O.node_coords(cfg)
     rho, u, T = (inputs.sod_fields if wl["name"] == "sod" else inputs.riemann_fields)(x, y)
-    f, g = O.init_equilibrium(cfg, rho, u, T)
-    steps = 0
-    t0 = time.perf_counter()
-    while True:
-        f, g = O.step(cfg, f, g, 1)
-        steps += 1
-        el = time.perf_counter() - t0
-        if el > budget_s or el / steps * (steps + 1) > 2.0 * budget_s:
-            break
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return dict(value=O.num_nodes(cfg) * steps / el, unit="node-updates/s", cores=cores, kind="oracle",
-                sample=f"{steps} whole-grid FP64 2-D oracle step(s) of the same workload "
-                       f"({O.num_nodes(cfg)} nodes), {el:.1f} s")
+    st = list(O.init_equilibrium(cfg, rho, u, T))
+
+    def step():
+        st[0], st[1] = O.step(cfg, st[0], st[1], 1)
+    return _time_oracle(O, step, O.num_nodes(cfg), budget_s, "2-D oracle")
 
 
 def workload_2d(name):
