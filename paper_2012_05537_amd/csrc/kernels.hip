@@ -17,9 +17,9 @@ namespace sllbm {
 // lanes per node (f on the even lane, g on the odd one), the values in
 // registers: D3Q45 in FP64, D2Q19 in FP32, and the cases that k_collide_lds
 // below does not take (N not a multiple of 16 / sizeof(S), an input not
-// 16-byte aligned).  in and out may be the same
-// buffer (each lane reads its values first).  NTH: non-temporal loads and
-// stores (states larger than the Infinity Cache).
+// 16-byte aligned).  in and out may be the same buffer (each lane reads its
+// values first).  NTH: non-temporal loads and stores (states larger than
+// the Infinity Cache).
 template <typename S, class L, bool NTH>
 __global__ void __launch_bounds__(256) k_collide(int64_t N, CollisionParams cp, const S *in, S *out)
 {
