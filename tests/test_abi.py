@@ -138,3 +138,22 @@ def test_bench_refuses_several_gpus():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_cpu_baseline_times_all_cores_then_one():
+    """bench.py's cpu_baseline (the oracle on the host; no GPU): the all-core
+    and one-core rates, the thread count it used, and the oracle's OpenMP
+    thread count restored afterwards."""
+    import os
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    sys.path.insert(0, root)
+    import bench
+    from oracle import oracle as O
+    from paper_2012_05537_amd import inputs
+    before = O._lib().omp_get_max_threads()
+    r = bench.cpu_baseline(inputs.workload("c1"), 0.2)
+    assert r["kind"] == "oracle" and r["unit"] == "node-updates/s"
+    assert r["value"] > 0 and r["value_one_core"] > 0
+    assert r["cores"] == before
+    assert O._lib().omp_get_max_threads() == before
