@@ -53,9 +53,10 @@ __global__ void __launch_bounds__(256) k_collide(int64_t N, CollisionParams cp, 
 }
 
 // DMA copy of 16 bytes per lane from g into LDS at l + 16 * lane (l is
-// wave-uniform).  A device function of its own: the 16-byte form exists on
-// gfx950 only, and the host pass drops the launch stub of a kernel whose
-// body names it.
+// wave-uniform).  AUX is the copy's cache-policy operand (2: non-temporal,
+// 0: the default policy).  A device function of its own: the 16-byte form
+// exists on gfx950 only, and the host pass drops the launch stub of a
+// kernel whose body names it.
 template <int AUX, typename T>
 __device__ __forceinline__ void dma16(const T *g, T *l)
 {
