@@ -38,7 +38,8 @@ namespace sllbm {
 
 namespace {
 
-__device__ __forceinline__ double pair_sum(double v) { return v + __shfl_xor(v, 1); }
+template <int XM>
+__device__ __forceinline__ double pair_sum(double v) { return v + __shfl_xor(v, XM); }
 
 __device__ __forceinline__ double viscosity_factor(const CollisionParams &cp, double T, double &dfac_dT)
 {
@@ -95,29 +96,17 @@ __device__ __forceinline__ double bder(const Bracket &b, double c)    // d b / d
 // Collision VJP: lam = J_C(X)^T mu, two lanes per node.  dmu_part[block]
 // receives the block's sum of dL/dmu_inf.
 // ---------------------------------------------------------------------------
-// Grid-stride over lane pairs; the whole block runs the same number of
-// iterations, so every shuffle partner is live.  mu and lam may be the same
-// buffer: each lane reads its 45 values before writing them.
-// NTH: non-temporal loads and stores (states larger than the Infinity Cache)
-template <typename S, bool NTH>
-__global__ void __launch_bounds__(256) k_collide_vjp(int64_t N, CollisionParams cp, const S *__restrict__ X,
-                                                     const S *mu, S *lam, double *__restrict__ dmu_part)
+// One lane of the collision VJP (its node's population is_g): X of the node
+// from X + off (stride N), the lane's adjoint inputs alpha_i from AL(i), the
+// partner lane l ^ XM; writes lambda of its population at lp (stride N) and
+// returns the node's dL/dmu_inf (counted on the f lane).  Inactive lanes (a
+// node past the end) compute on node 0 for their partner and write nothing.
+template <typename S, bool NTH, int XM, class Alpha>
+__device__ __forceinline__ double collide_vjp_lane(int64_t N, const CollisionParams &cp, const S *__restrict__ X,
+                                                   int64_t off, bool is_g, bool active, Alpha &&AL, S *lp)
 {
-    __shared__ double red[256];
-    double dmu_acc = 0.0;
-    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
-    for (int64_t t0 = blockIdx.x * static_cast<int64_t>(blockDim.x); t0 < 2 * N; t0 += stride) {
-    const int64_t t = t0 + threadIdx.x;
-    const int64_t n = t >> 1;
-    const int pop = static_cast<int>(t & 1);
-    const bool is_g = pop != 0;
-    const bool active = n < N;
-    const int64_t nn = active ? n : 0;
-    const int64_t off = static_cast<int64_t>(pop) * vs::Q * N + nn;
-
     // X enters only through its raw moments and sum alpha h, so it is dead
-    // before the sweep; alpha stays in registers
-    double al[vs::Q];
+    // before the sweep
     RawMoments<D3Q45> rm;
     double dot_ah = 0.0;
     {
@@ -125,18 +114,17 @@ __global__ void __launch_bounds__(256) k_collide_vjp(int64_t N, CollisionParams 
 #pragma unroll
         for (int i = 0; i < vs::Q; ++i) {
             h[i] = static_cast<double>(load_hint<NTH>(&X[off + static_cast<int64_t>(i) * N]));
-            al[i] = static_cast<double>(load_hint<NTH>(&mu[off + static_cast<int64_t>(i) * N]));
         }
         rm = raw_moments<D3Q45>(h);
 #pragma unroll
-        for (int i = 0; i < vs::Q; ++i) dot_ah = fma(al[i], h[i], dot_ah);
+        for (int i = 0; i < vs::Q; ++i) dot_ah = fma(AL(i), h[i], dot_ah);
     }
 
     // ---- forward quantities (as in collide_half) ----
     const double ktr = rm.m2[0] + rm.m2[3] + rm.m2[5];
-    const double p_m0 = __shfl_xor(rm.m0, 1);
-    const double p_j0 = __shfl_xor(rm.m1[0], 1), p_j1 = __shfl_xor(rm.m1[1], 1), p_j2 = __shfl_xor(rm.m1[2], 1);
-    const double p_tr = __shfl_xor(ktr, 1);
+    const double p_m0 = __shfl_xor(rm.m0, XM);
+    const double p_j0 = __shfl_xor(rm.m1[0], XM), p_j1 = __shfl_xor(rm.m1[1], XM), p_j2 = __shfl_xor(rm.m1[2], XM);
+    const double p_tr = __shfl_xor(ktr, XM);
     const double rho = is_g ? p_m0 : rm.m0;
     const double J[3] = {is_g ? p_j0 : rm.m1[0], is_g ? p_j1 : rm.m1[1], is_g ? p_j2 : rm.m1[2]};
     const double ir = 1.0 / rho;
@@ -181,10 +169,10 @@ __global__ void __launch_bounds__(256) k_collide_vjp(int64_t N, CollisionParams 
         const double w = vs::T.w[0];
         const double feq = w * rho * br[0].a0;
         const double heq = eqs * feq;
-        s_heq = fma(al[0], heq, s_heq);
-        s_eqT = fma(al[0], feq, s_eqT);
-        s_u2 = fma(al[0] * w * rho * eqs, br[0].d0u, s_u2);
-        s_th = fma(al[0] * w * rho * eqs, br[0].d0t, s_th);
+        s_heq = fma(AL(0), heq, s_heq);
+        s_eqT = fma(AL(0), feq, s_eqT);
+        s_u2 = fma(AL(0) * w * rho * eqs, br[0].d0u, s_u2);
+        s_th = fma(AL(0) * w * rho * eqs, br[0].d0t, s_th);
     }
 #pragma unroll
     for (int q = 0; q < 22; ++q) {
@@ -198,7 +186,7 @@ __global__ void __launch_bounds__(256) k_collide_vjp(int64_t N, CollisionParams 
         double hs = 0.0;
 #pragma unroll
         for (int m = 0; m < 10; ++m) hs = fma_nz(vs::H3.c[i][m], qb[m], hs);
-        const double ai = al[i], aj = al[j];
+        const double ai = AL(i), aj = AL(j);
         s_ka += (ai - aj) * hs;
         s_heq += ai * heq_i + aj * heq_j;
         s_eqT += ai * feq_i + aj * feq_j;
@@ -228,13 +216,13 @@ __global__ void __launch_bounds__(256) k_collide_vjp(int64_t N, CollisionParams 
     }
 
     // ---- pair totals (sum alpha (s h^eq - h) = s_heq - dot_ah) ----
-    const double S_om = pair_sum(s_heq - dot_ah), S_ka = pair_sum(s_ka);
-    const double S_heq = pair_sum(om * s_heq);
-    const double S_eqT = pair_sum(is_g ? om * cp.beta * s_eqT : 0.0);
-    const double S_u2 = pair_sum(om * s_u2), S_th = pair_sum(om * s_th);
+    const double S_om = pair_sum<XM>(s_heq - dot_ah), S_ka = pair_sum<XM>(s_ka);
+    const double S_heq = pair_sum<XM>(om * s_heq);
+    const double S_eqT = pair_sum<XM>(is_g ? om * cp.beta * s_eqT : 0.0);
+    const double S_u2 = pair_sum<XM>(om * s_u2), S_th = pair_sum<XM>(om * s_th);
     double U[3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) U[a] = pair_sum(om * ubar[a] + uq[a]);
+    for (int a = 0; a < 3; ++a) U[a] = pair_sum<XM>(om * ubar[a] + uq[a]);
 
     // omega = 1/tau, kappa = 1/tau - 1/tau_pr
     const double om_bar = S_om + S_ka;
@@ -275,12 +263,11 @@ __global__ void __launch_bounds__(256) k_collide_vjp(int64_t N, CollisionParams 
             Cu[c] = fma(abar[m], u[a] * u[b], Cu[c]);
             T0 = fma(abar[m], u[a] * u[b] * u[c], T0);
         }
-        S *lp = lam + off;
         asm volatile("" : "+v"(lp));      // fresh store addresses (the load addresses are not kept live)
         const double one_m = 1.0 - om;
         const double base_f = rho_bar, x2g = is_g ? 0.0 : 1.0, kg = is_g ? K_bar : 0.0;
         {   // rest velocity: xi = 0
-            double r = one_m * al[0] - T0 + kg;
+            double r = one_m * AL(0) - T0 + kg;
             if (!is_g) r += base_f;
             store_hint<NTH>(&lp[0], static_cast<S>(r));
         }
@@ -296,15 +283,95 @@ __global__ void __launch_bounds__(256) k_collide_vjp(int64_t N, CollisionParams 
             const double T1 = Cu[0] * x + Cu[1] * y + Cu[2] * z;
             const double jx = is_g ? 0.0 : J_bar[0] * x + J_bar[1] * y + J_bar[2] * z;
             const double common = kg + x2g * (base_f + K_bar * vs::T.x2[i]);
-            const double ri = one_m * al[i] + common + jx + (T3 - T2 + T1 - T0);
-            const double rj = one_m * al[j] + common - jx - (T3 + T2 + T1 + T0);
+            const double ri = one_m * AL(i) + common + jx + (T3 - T2 + T1 - T0);
+            const double rj = one_m * AL(j) + common - jx - (T3 + T2 + T1 + T0);
             store_hint<NTH>(&lp[static_cast<int64_t>(i) * N], static_cast<S>(ri));
             store_hint<NTH>(&lp[static_cast<int64_t>(j) * N], static_cast<S>(rj));
         }
     }
 
     // ---- dL/dmu_inf: mu = mu_inf * fac, counted once per node (f lane) ----
-    if (active && !is_g) dmu_acc += mu_bar * fac;
+    return active && !is_g ? mu_bar * fac : 0.0;
+}
+
+// Grid-stride over lane pairs; the whole block runs the same number of
+// iterations, so every shuffle partner is live.  mu and lam may be the same
+// buffer: each lane reads its 45 values before writing them.
+// NTH: non-temporal loads and stores (states larger than the Infinity Cache)
+template <typename S, bool NTH>
+__global__ void __launch_bounds__(256) k_collide_vjp(int64_t N, CollisionParams cp, const S *__restrict__ X,
+                                                     const S *mu, S *lam, double *__restrict__ dmu_part)
+{
+    __shared__ double red[256];
+    double dmu_acc = 0.0;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    for (int64_t t0 = blockIdx.x * static_cast<int64_t>(blockDim.x); t0 < 2 * N; t0 += stride) {
+        const int64_t t = t0 + threadIdx.x;
+        const int64_t n = t >> 1;
+        const int pop = static_cast<int>(t & 1);
+        const bool active = n < N;
+        const int64_t off = static_cast<int64_t>(pop) * vs::Q * N + (active ? n : 0);
+        double al[vs::Q];
+#pragma unroll
+        for (int i = 0; i < vs::Q; ++i) al[i] = static_cast<double>(load_hint<NTH>(&mu[off + static_cast<int64_t>(i) * N]));
+        dmu_acc += collide_vjp_lane<S, NTH, 1>(N, cp, X, off, pop != 0, active, [&](int i) { return al[i]; },
+                                               lam + off);
+    }
+    red[threadIdx.x] = dmu_acc;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) dmu_part[blockIdx.x] = red[0];
+}
+
+// DMA copy of 16 bytes per lane from g into LDS at l + 16 * lane (l is
+// wave-uniform; AUX 2: non-temporal).  Untyped, in a device function of its
+// own: the 16-byte form exists on gfx950 only.
+template <int AUX>
+__device__ __forceinline__ void dma16_adj(const void *g, void *l)
+{
+    __builtin_amdgcn_global_load_lds(g, l, 16, 0, AUX);
+}
+
+// The collision VJP in FP32 storage with the adjoint inputs alpha staged in
+// LDS: per iteration a block takes 128 consecutive nodes, copies their 90
+// rows of mu (row r = pop * 45 + i, 512 contiguous bytes) into LDS by 16-byte
+// DMA copies, and each lane reads its alpha_i from there (lane l of wave w:
+// node w * 32 + (l & 31), population l >> 5, partner l ^ 32).  256 VGPRs
+// and 38 spilled at two waves per SIMD, against 330 registers and one wave
+// for k_collide_vjp.  N % 4 == 0 and mu 16-byte aligned; mu and lam may be
+// the same buffer (every copy of an iteration lands before its writes, and
+// the next iteration's copies wait for all its reads).
+template <bool NTH>
+__global__ void __launch_bounds__(256, 2) k_collide_vjp_lds(int64_t N, CollisionParams cp,
+                                                            const float *__restrict__ X, const float *mu, float *lam,
+                                                            double *__restrict__ dmu_part)
+{
+    constexpr int NB = 128, ROWS = 2 * vs::Q;
+    __shared__ float tile[ROWS][NB];
+    __shared__ double red[256];
+    double dmu_acc = 0.0;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int pop = lane >> 5;
+    const int c = w * 32 + (lane & 31);
+    for (int64_t nb = static_cast<int64_t>(blockIdx.x) * NB; nb < N; nb += static_cast<int64_t>(gridDim.x) * NB) {
+        __syncthreads();                         // the previous nodes' reads of the tile are done
+        const int64_t col = nb + 4 * (lane & 31);
+        if (col < N) {
+            const float *src = mu + static_cast<int64_t>(lane >> 5) * N + col;
+            for (int m = w; m < ROWS / 2; m += 4)
+                dma16_adj<NTH ? 2 : 0>(src + static_cast<int64_t>(2 * m) * N, &tile[2 * m][0]);
+        }
+        __builtin_amdgcn_s_waitcnt(0);           // this wave's copies have landed
+        __syncthreads();                         // and every other wave's
+        const int64_t n = nb + c;
+        const bool active = n < N;
+        const int64_t off = static_cast<int64_t>(pop) * vs::Q * N + (active ? n : 0);
+        const float *sl = &tile[pop * vs::Q][c];
+        dmu_acc += collide_vjp_lane<float, NTH, 32>(N, cp, X, off, pop != 0, active,
+                                                    [&](int i) { return static_cast<double>(sl[i * NB]); }, lam + off);
     }
     red[threadIdx.x] = dmu_acc;
     __syncthreads();
@@ -775,13 +842,33 @@ hipError_t Launch<S>::collide_vjp(const Geometry &g, const CollisionParams &cp, 
                                   double *dmu_partials, int nblocks, double *dmu, hipStream_t st)
 {
     // lam <- J_C(X_n)^T lam in place
-    const int blocks = static_cast<int>(std::min<int64_t>((2 * g.nodes + 255) / 256, nblocks));
-    if (use_nontemporal(90 * g.nodes * static_cast<int64_t>(sizeof(S))))
-        hipLaunchKernelGGL((k_collide_vjp<S, true>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, g.nodes,
-                           cp, state_n, lam, lam, dmu_partials);
-    else
-        hipLaunchKernelGGL((k_collide_vjp<S, false>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, g.nodes,
-                           cp, state_n, lam, lam, dmu_partials);
+    const bool nt = use_nontemporal(90 * g.nodes * static_cast<int64_t>(sizeof(S)));
+    int blocks = 0;
+    bool staged = false;
+    if constexpr (sizeof(S) == 4) {
+        // FP32: alpha staged in LDS (measured per adjoint step: 3-5 % faster
+        // at 128^3 and 256^3 nodes, 8 % at 64^3; in FP64 the staged form
+        // spills 81 registers and is 17-20 % slower)
+        if (g.nodes % 4 == 0 && reinterpret_cast<uintptr_t>(lam) % 16 == 0) {
+            staged = true;
+            blocks = static_cast<int>(std::min<int64_t>((g.nodes + 127) / 128, nblocks));
+            if (nt)
+                hipLaunchKernelGGL((k_collide_vjp_lds<true>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st,
+                                   g.nodes, cp, state_n, lam, lam, dmu_partials);
+            else
+                hipLaunchKernelGGL((k_collide_vjp_lds<false>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st,
+                                   g.nodes, cp, state_n, lam, lam, dmu_partials);
+        }
+    }
+    if (!staged) {
+        blocks = static_cast<int>(std::min<int64_t>((2 * g.nodes + 255) / 256, nblocks));
+        if (nt)
+            hipLaunchKernelGGL((k_collide_vjp<S, true>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st,
+                               g.nodes, cp, state_n, lam, lam, dmu_partials);
+        else
+            hipLaunchKernelGGL((k_collide_vjp<S, false>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st,
+                               g.nodes, cp, state_n, lam, lam, dmu_partials);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (dmu) {
