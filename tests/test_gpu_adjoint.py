@@ -105,6 +105,34 @@ def test_adjoint_step_collision_vjp_elementwise(oracle, n_el, p, dt, mu, Ma, law
     assert abs(dmu.item() - dmu_ref) <= TOL_OP * max(abs(dmu_ref), 1e-300) * 10, (dmu.item(), dmu_ref)
 
 
+@pytest.mark.parametrize("n_el,p", [((5, 3, 3), 2), ((3, 3, 3), 3)])
+def test_adjoint_step_fp32_matches_fp64(oracle, n_el, p):
+    """FP32-mixed adjoint step against the FP64 one (itself pinned to the
+    complex-step oracle above) on the same, FP32-representable inputs: 360
+    nodes (the LDS-staged FP32 collision VJP with a ragged last block) and 729
+    (not a multiple of 4: the register form).  The FP32 path rounds S^T lam
+    and lam to FP32, so the bar is 1e-5 of the largest entry."""
+    _say(f"fp32 adjoint step n_el={n_el} p={p}")
+    c64, cfg = make_pair(oracle, n_el, p, 0.2, 0.004)
+    c32, _ = make_pair(oracle, n_el, p, 0.2, 0.004, precision=1)
+    f, g = _noisy_state(oracle, cfg, 0.8, 1.4, seed=7)
+    f, g = f.astype(np.float32).astype(np.float64), g.astype(np.float32).astype(np.float64)
+    rng = np.random.default_rng(8)
+    N = f.shape[1]
+    lf = rng.normal(size=(Q, N)).astype(np.float32).astype(np.float64)
+    lg = rng.normal(size=(Q, N)).astype(np.float32).astype(np.float64)
+    out = {}
+    for ctx in (c64, c32):
+        dmu = torch.zeros(1, dtype=torch.float64, device=ctx.device)
+        lam = ctx.adjoint_step(to_dev(ctx, f, g), to_dev(ctx, lf, lg), dmu=dmu)
+        torch.cuda.synchronize()
+        out[ctx.dtype] = (to_np(lam), dmu.item())
+    (F64, G64), d64 = out[torch.float64]
+    (F32, G32), d32 = out[torch.float32]
+    assert rel_err(F32, F64) < 1e-5 and rel_err(G32, G64) < 1e-5, (rel_err(F32, F64), rel_err(G32, G64))
+    assert abs(d32 - d64) <= 1e-5 * abs(d64), (d32, d64)
+
+
 def test_adjoint_step_accumulates_dmu(oracle):
     """dmu is added to, not overwritten."""
     ctx, cfg = make_pair(oracle, (2, 2, 2), 2, 0.3, 0.01)
