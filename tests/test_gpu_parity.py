@@ -316,16 +316,23 @@ def test_c2_full_grid_every_step_until_non_finite(oracle, cfl):
     ctx.close()
 
 
-def test_deterministic(oracle):
-    w, ctx, cfg = workload_pair(oracle, "c1")
-    tgv_init(oracle, ctx, cfg, w["Ma"], w["gamma"])
-    ctx.step(5)
-    a = ctx.get_state()
-    ta = ctx.totals()
-    tgv_init(oracle, ctx, cfg, w["Ma"], w["gamma"])
-    ctx.step(5)
-    assert torch.equal(a, ctx.get_state())
-    assert ta == ctx.totals()
+@pytest.mark.parametrize("precision", [0, 1])
+def test_deterministic(oracle, precision):
+    """Steps, totals and an adjoint step (with its dL/dmu_inf partial sums)
+    repeat bit for bit: no atomics, fixed reduction orders."""
+    w, ctx, cfg = workload_pair(oracle, "c1", precision=precision)
+    runs = []
+    for _ in range(2):
+        tgv_init(oracle, ctx, cfg, w["Ma"], w["gamma"])
+        ctx.step(5)
+        x = ctx.get_state()
+        dmu = torch.zeros(1, dtype=torch.float64, device=ctx.device)
+        lam = ctx.adjoint_step(x, x.clone(), dmu=dmu)
+        runs.append((x, ctx.totals(), lam, dmu.item()))
+    (a, ta, la, da), (b, tb, lb, db) = runs
+    assert torch.equal(a, b)
+    assert ta == tb
+    assert torch.equal(la, lb) and da == db
 
 
 def test_zero_steps_is_identity(oracle):
